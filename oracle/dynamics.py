@@ -1,0 +1,102 @@
+"""Dynamics of the two models, their RK4 discretization and its exact Jacobians.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Paper: Sec. II eq. (ocp) integrates the continuous dynamics over one step with
+4th-order Runge-Kutta; Sec. III-A takes A_i, B_i as the Jacobians of that
+discrete map at the nominal (x_i, u_i) and d_i as the linearization residual.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+QUAD, MARS = 1, 2
+
+
+def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Continuous-time dynamics x' = f(x, u).
+
+    Quadrotor point mass: p' = v, v' = u/m_s - g e3 - c ||v|| v  (drag isotropic and quadratic).
+    Powered descent (scaled units): r' = v, v' = T/m + g_vec, m' = -alpha Gamma.
+    The norm is written sqrt(v.v) so the function stays analytic for complex-step tests.
+    """
+    if inst["model"] == QUAD:
+        p, v = x[:3], x[3:6]
+        nv = np.sqrt(v @ v)
+        acc = u / inst["mscale"] - np.array([0.0, 0.0, inst["grav"]]) - inst["drag"] * nv * v
+        return np.concatenate([v, acc])
+    r, v, m = x[:3], x[3:6], x[6]
+    T, G = u[:3], u[3]
+    return np.concatenate([v, T / m + inst["gvec"], [-inst["alpha"] * G]])
+
+
+def jac_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Jacobians (df/dx, df/du) of ``f_cont``.
+
+    Drag term: d(c||v||v)/dv = c (||v|| I + v v^T / ||v||), taken as 0 at v = 0.
+    """
+    nx, nu = x.shape[0], u.shape[0]
+    Jx = np.zeros((nx, nx))
+    Ju = np.zeros((nx, nu))
+    if inst["model"] == QUAD:
+        v = x[3:6]
+        nv = np.sqrt(v @ v)
+        Jx[0:3, 3:6] = np.eye(3)
+        if nv > 0.0:
+            Jx[3:6, 3:6] = -inst["drag"] * (nv * np.eye(3) + np.outer(v, v) / nv)
+        Ju[3:6, 0:3] = np.eye(3) / inst["mscale"]
+        return Jx, Ju
+    m = x[6]
+    T = u[:3]
+    Jx[0:3, 3:6] = np.eye(3)
+    Jx[3:6, 6] = -T / (m * m)
+    Ju[3:6, 0:3] = np.eye(3) / m
+    Ju[6, 3] = -inst["alpha"]
+    return Jx, Ju
+
+
+def rk4(inst: dict, x: np.ndarray, u: np.ndarray, h: float | None = None) -> np.ndarray:
+    """Classical 4th-order Runge-Kutta step with zero-order-hold control."""
+    h = inst["h"] if h is None else h
+    k1 = f_cont(inst, x, u)
+    k2 = f_cont(inst, x + 0.5 * h * k1, u)
+    k3 = f_cont(inst, x + 0.5 * h * k2, u)
+    k4 = f_cont(inst, x + h * k3, u)
+    return x + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+def rk4_jac(inst: dict, x: np.ndarray, u: np.ndarray):
+    """Discrete map F = RK4(x, u) and its exact Jacobians A = dF/dx, B = dF/du.
+
+    Forward-mode chain rule through the four stages: with stage points
+    x1 = x, x2 = x + h/2 k1, x3 = x + h/2 k2, x4 = x + h k3 and stage sensitivities
+    S_j = dk_j/d(x,u), S_j = Jx(x_j) dx_j/d(x,u) + [0, Ju(x_j)].
+    Returns (F, A, B, d) with the residual d = F - A x - B u (Sec. III-A).
+    """
+    h = inst["h"]
+    nx, nu = x.shape[0], u.shape[0]
+    I = np.eye(nx)
+    Zu = np.zeros((nx, nu))
+    pts, sx, su = [], [], []
+    xs, dxs_x, dxs_u = x, I, Zu
+    coeffs = (0.5 * h, 0.5 * h, h)
+    ks = []
+    for j in range(4):
+        Jx, Ju = jac_cont(inst, xs, u)
+        k = f_cont(inst, xs, u)
+        Sx = Jx @ dxs_x
+        Su = Jx @ dxs_u + Ju
+        ks.append(k)
+        sx.append(Sx)
+        su.append(Su)
+        pts.append(xs)
+        if j < 3:
+            c = coeffs[j]
+            xs = x + c * k
+            dxs_x = I + c * Sx
+            dxs_u = c * Su
+    F = x + (h / 6.0) * (ks[0] + 2.0 * ks[1] + 2.0 * ks[2] + ks[3])
+    A = I + (h / 6.0) * (sx[0] + 2.0 * sx[1] + 2.0 * sx[2] + sx[3])
+    B = (h / 6.0) * (su[0] + 2.0 * su[1] + 2.0 * su[2] + su[3])
+    d = F - A @ x - B @ u
+    return F, A, B, d

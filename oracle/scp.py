@@ -1,0 +1,345 @@
+"""Outer SCP loop (Sec. III-A) around the consensus ADMM, with trust-region acceptance.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Per SCP iteration k (Fig. method_overview: linearize -> convex QP -> update nominal):
+  a2  A_i, B_i, d_i from the exact Jacobians of the RK4 map at the nominal (Sec. III-A)
+  a3  convex sets of eq. (qp_subproblem): trust box around the nominal intersected with the
+      hard bounds, boundary conditions of eq. (ocp) as degenerate boxes, obstacle spheres
+      linearized into half-spaces at the nominal, control ball / SOC / glide-slope cone
+  a4  Step-1 Hessians; ADMM primal state re-initialized from the nominal, duals carried over
+  a5-a9  ADMM iterations (oracle.admm)
+  a10 candidate = last physical iterate; merit ratio test; nominal and trust radius update
+      (the paper omits this logic and points to standard trust-region texts; the reading
+      here is the classic ratio test on an l1 merit function)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .admm import Group, QP, AdmmState, build_H, admm_run
+from .dynamics import rk4, rk4_jac, QUAD, MARS
+
+
+def default_params(**kw) -> dict:
+    """Solver parameters; the defaults are the fixed-budget settings of the workloads
+    (rho = 1 for all three penalties, always-accept steps, fixed trust radius)."""
+    p = dict(scp_iters=10, admm_iters=100, rho_eq=1.0, rho_dyn=1.0, rho_geo=1.0,
+             check_every=0, eps_p=0.0, eps_d=0.0,
+             eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
+             merit_w=1.0e3)
+    p.update(kw)
+    return p
+
+
+# ------------------------------------------------------------------------------------------
+# a2: linearization
+# ------------------------------------------------------------------------------------------
+
+def linearize(inst: dict, xbar: np.ndarray, ubar: np.ndarray):
+    """A_i, B_i, d_i for i < N at the nominal (first-order expansion of the RK4 map)."""
+    N, nx, nu = inst["N"], inst["nx"], inst["nu"]
+    A = np.zeros((N, nx, nx))
+    B = np.zeros((N, nx, nu))
+    d = np.zeros((N, nx))
+    for i in range(N):
+        _, A[i], B[i], d[i] = rk4_jac(inst, xbar[i], ubar[i])
+    return A, B, d
+
+
+def cost_qp(inst: dict, A, B, d) -> QP:
+    """Quadratic cost model of eq. (qp_subproblem).  The workloads' costs are already
+    quadratic (sum u'Ru/2 + terminal x'Qn x/2 + qn'x), so the expansion is exact."""
+    N, nx, nu = inst["N"], inst["nx"], inst["nu"]
+    Q = np.zeros((N + 1, nx, nx))
+    Q[:N] = np.diag(inst["Qr"])
+    Q[N] = np.diag(inst["Qn"])
+    q = np.zeros((N + 1, nx))
+    q[N] = inst["qn"]
+    R = np.broadcast_to(np.diag(inst["R"]), (N, nu, nu)).copy()
+    return QP(Q=Q, q=q, R=R, r=np.zeros((N, nu)), M=np.zeros((N, nx, nu)), A=A, B=B, d=d)
+
+
+# ------------------------------------------------------------------------------------------
+# a3: convexification
+# ------------------------------------------------------------------------------------------
+
+def _trust_box(center, delta, lo_h, hi_h):
+    """[center - delta, center + delta] intersected with [lo_h, hi_h]; if empty, the box
+    collapses onto the hard-box point nearest the nominal (the hard bounds win)."""
+    lo = np.maximum(center - delta, lo_h)
+    hi = np.minimum(center + delta, hi_h)
+    empty = lo > hi
+    if np.any(empty):
+        p = np.minimum(np.maximum(center, lo_h), hi_h)
+        lo = np.where(empty, p, lo)
+        hi = np.where(empty, p, hi)
+    return lo, hi
+
+
+def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_center=None):
+    """Constraint groups of the convex subproblem, in a fixed order.
+
+    x box (all nodes): node 0 lo = hi = x_init; nodes 1..N trust box around xbar intersected
+      with the hard state bounds; node N components selected by t_mask lo = hi = x_target.
+    u box (nodes 0..N-1): trust box around ubar intersected with the hard control bounds;
+      at node 0 the box is centred at ``u0_center`` when given (scenario groups share one
+      first-control set).
+    Quadrotor: control ball ||u|| <= u_ball (nodes 0..N-1), then one half-space per obstacle
+      at nodes 1..N: n'(p - c) >= r with n = (pbar - c)/||pbar - c|| (+e3 if ||pbar - c|| < 1e-9).
+    Powered descent: glide-slope cone ||(r_x, r_y)|| <= tan(86 deg) r_z at nodes 1..N, then
+      the SOC ||T|| <= Gamma at nodes 0..N-1.
+    """
+    N, nx, nu = inst["N"], inst["nx"], inst["nu"]
+    allx = np.ones(N + 1, dtype=bool)
+    xlo = np.zeros((N + 1, nx))
+    xhi = np.zeros((N + 1, nx))
+    xlo[0] = xhi[0] = inst["x_init"]
+    for i in range(1, N + 1):
+        xlo[i], xhi[i] = _trust_box(xbar[i], delta, inst["x_lo"], inst["x_hi"])
+    m = inst["t_mask"]
+    xlo[N, m] = inst["x_target"][m]
+    xhi[N, m] = inst["x_target"][m]
+    groups = [Group("x", tuple(range(nx)), "box", allx, lo=xlo, hi=xhi)]
+
+    uact = np.ones(N + 1, dtype=bool)
+    uact[N] = False
+    ulo = np.zeros((N + 1, nu))
+    uhi = np.zeros((N + 1, nu))
+    for i in range(N):
+        c = ubar[i] if (i > 0 or u0_center is None) else u0_center
+        ulo[i], uhi[i] = _trust_box(c, delta, inst["u_lo"], inst["u_hi"])
+    groups.append(Group("u", tuple(range(nu)), "box", uact, lo=ulo, hi=uhi))
+
+    inner = np.ones(N + 1, dtype=bool)
+    inner[0] = False
+    if inst["model"] == QUAD:
+        if math.isfinite(inst["u_ball"]):
+            groups.append(Group("u", (0, 1, 2), "ball", uact.copy(), radius=float(inst["u_ball"])))
+        for j in range(inst["obstacles"].shape[0]):
+            c, r = inst["obstacles"][j, :3], inst["obstacles"][j, 3]
+            a = np.zeros((N + 1, 3))
+            b = np.zeros(N + 1)
+            for i in range(1, N + 1):
+                dvec = xbar[i, :3] - c
+                nd = np.sqrt(dvec @ dvec)
+                nvec = dvec / nd if nd >= 1e-9 else np.array([0.0, 0.0, 1.0])
+                a[i] = nvec
+                b[i] = r + nvec @ c
+            groups.append(Group("x", (0, 1, 2), "halfspace", inner.copy(), a=a, b=b))
+    else:
+        groups.append(Group("x", (0, 1, 2), "cone", inner.copy(), kappa=float(inst["glide_tan"])))
+        groups.append(Group("u", (0, 1, 2, 3), "soc", uact.copy()))
+    return groups
+
+
+# ------------------------------------------------------------------------------------------
+# metrics and merit
+# ------------------------------------------------------------------------------------------
+
+def cost(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
+    """Objective of eq. (ocp) for the workloads: sum_i (x_i'Qr x_i + u_i'R u_i)/2 over i < N plus
+    x_N'Qn x_N/2 + qn'x_N + cN.  Summed in node order."""
+    N = inst["N"]
+    J = 0.0
+    for i in range(N):
+        J += 0.5 * float(x[i] @ (inst["Qr"] * x[i])) + 0.5 * float(u[i] @ (inst["R"] * u[i]))
+    J += 0.5 * float(x[N] @ (inst["Qn"] * x[N])) + float(inst["qn"] @ x[N]) + inst["cN"]
+    return J
+
+
+def defect(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
+    """Max over i < N of ||x_{i+1} - RK4(x_i, u_i)||_inf (nonlinear dynamics defect)."""
+    N = inst["N"]
+    if N == 0:
+        return 0.0
+    return float(max(np.max(np.abs(x[i + 1] - rk4(inst, x[i], u[i]))) for i in range(N)))
+
+
+def violation(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
+    """Max violation of the hard (unconvexified) constraints: state/control bounds, control
+    ball, obstacle spheres (penetration depth, nodes 1..N), SOC ||T|| <= Gamma, glide slope."""
+    N = inst["N"]
+    v = 0.0
+    v = max(v, float(np.max(np.maximum(0.0, inst["x_lo"] - x))), float(np.max(np.maximum(0.0, x - inst["x_hi"]))))
+    if N > 0:
+        v = max(v, float(np.max(np.maximum(0.0, inst["u_lo"] - u))), float(np.max(np.maximum(0.0, u - inst["u_hi"]))))
+    if inst["model"] == QUAD:
+        if N > 0 and math.isfinite(inst["u_ball"]):
+            v = max(v, float(np.max(np.sqrt(np.sum(u[:, :3] ** 2, axis=1)) - inst["u_ball"])))
+        for j in range(inst["obstacles"].shape[0]):
+            c, r = inst["obstacles"][j, :3], inst["obstacles"][j, 3]
+            dist = np.sqrt(np.sum((x[1:, :3] - c) ** 2, axis=1))
+            if dist.size:
+                v = max(v, float(np.max(r - dist)))
+    else:
+        if N > 0:
+            v = max(v, float(np.max(np.sqrt(np.sum(u[:, :3] ** 2, axis=1)) - u[:, 3])))
+        rxy = np.sqrt(x[1:, 0] ** 2 + x[1:, 1] ** 2)
+        if rxy.size:
+            v = max(v, float(np.max(rxy - inst["glide_tan"] * x[1:, 2])))
+    return max(v, 0.0)
+
+
+def boundary_error(inst: dict, x: np.ndarray) -> float:
+    """max(||x_0 - x_init||_inf, max |x_N - x_target| over the components selected by S)."""
+    e = float(np.max(np.abs(x[0] - inst["x_init"])))
+    m = inst["t_mask"]
+    if np.any(m):
+        e = max(e, float(np.max(np.abs(x[-1, m] - inst["x_target"][m]))))
+    return e
+
+
+def _merit_terms(inst, x, u, A=None, B=None, d=None):
+    """(J, sum_i ||x_{i+1} - F_i||_1) with F_i the RK4 map, or the affine model if A is given."""
+    N = inst["N"]
+    pen = 0.0
+    for i in range(N):
+        if A is None:
+            Fi = rk4(inst, x[i], u[i])
+        else:
+            Fi = A[i] @ x[i] + B[i] @ u[i] + d[i]
+        pen += float(np.sum(np.abs(x[i + 1] - Fi)))
+    return cost(inst, x, u), pen
+
+
+# ------------------------------------------------------------------------------------------
+# the SCP loop
+# ------------------------------------------------------------------------------------------
+
+@dataclass
+class Traj:
+    inst: dict
+    xbar: np.ndarray
+    ubar: np.ndarray
+    state: AdmmState | None = None
+    qp: QP | None = None
+    groups: list = field(default_factory=list)
+
+
+def init_traj(inst: dict) -> Traj:
+    return Traj(inst, np.array(inst["x_guess"], dtype=float, copy=True),
+                np.array(inst["u_guess"], dtype=float, copy=True))
+
+
+def _prepare(trajs: list[Traj], delta: float, rho):
+    """a2-a4 plus the primal re-initialization of R10 for every trajectory of one group."""
+    u0c = None
+    if len(trajs) > 1:
+        acc = np.zeros(trajs[0].inst["nu"])
+        for t in trajs:
+            acc = acc + t.ubar[0]
+        u0c = acc / len(trajs)
+    out = []
+    for t in trajs:
+        inst = t.inst
+        A, B, d = linearize(inst, t.xbar, t.ubar)
+        t.qp = cost_qp(inst, A, B, d)
+        t.groups = convexify(inst, t.xbar, t.ubar, delta, u0c)
+        N = inst["N"]
+        if t.state is None:
+            t.state = AdmmState.zeros(N, inst["nx"], inst["nu"], t.groups)
+        st = t.state
+        st.x[:] = t.xbar
+        st.u[:] = t.ubar
+        st.z[:] = t.xbar
+        st.z[0] = 0.0
+        for gi, g in enumerate(t.groups):
+            src = t.xbar if g.var == "x" else np.vstack([t.ubar, np.zeros((1, inst["nu"]))])
+            st.copy[gi][:] = 0.0
+            st.copy[gi][g.active] = src[g.active][:, list(g.comps)]
+        out.append((t.qp, t.groups, st, build_H(t.qp, t.groups, rho)))
+    return out
+
+
+def scp_group(trajs: list[Traj], params: dict, delta: float | None = None) -> dict:
+    """Solve one group of trajectories (a single trajectory, or scenarios sharing u_0).
+
+    Returns the group's info; the trajectories' nominals hold the solution.
+    """
+    rho = (params["rho_eq"], params["rho_dyn"], params["rho_geo"])
+    delta = trajs[0].inst["delta"] if delta is None else delta
+    coupled = len(trajs) > 1
+    iters_total = 0
+    n_accept = 0
+    rp = rd = float("nan")
+    status = 0
+    for k in range(params["scp_iters"]):
+        packs = _prepare(trajs, delta, rho)
+        it, rp, rd = admm_run(packs, rho, params["admm_iters"], params["check_every"],
+                              params["eps_p"], params["eps_d"], couple_u0=coupled)
+        iters_total += it
+        # a10: merit ratio test over the whole group (sums in trajectory order)
+        m_nom = m_new = m_mod = 0.0
+        w = params["merit_w"]
+        for t in trajs:
+            J0, p0 = _merit_terms(t.inst, t.xbar, t.ubar)
+            J1, p1 = _merit_terms(t.inst, t.state.x, t.state.u)
+            _, pm = _merit_terms(t.inst, t.state.x, t.state.u, t.qp.A, t.qp.B, t.qp.d)
+            m_nom += J0 + w * p0
+            m_new += J1 + w * p1
+            m_mod += J1 + w * pm
+        actual = m_nom - m_new
+        pred = m_nom - m_mod
+        ratio = actual / pred if pred > 0.0 else -math.inf
+        if not (math.isfinite(m_new) and math.isfinite(m_mod)):
+            ratio = math.nan
+            status |= 1
+        if ratio >= params["eta0"]:
+            n_accept += 1
+            for t in trajs:
+                t.xbar = t.state.x.copy()
+                t.ubar = t.state.u.copy()
+        if ratio < params["eta1"]:
+            delta = delta * params["shrink"]
+        elif ratio > params["eta2"]:
+            delta = min(delta * params["grow"], params["delta_max"])
+    return dict(admm_iters=iters_total, r_p=rp, r_d=rd, n_accept=n_accept, delta=delta, status=status)
+
+
+def scp_solve(insts: list[dict], params: dict | None = None):
+    """Solve every instance (grouping consecutive instances that share a ``group`` id >= 0).
+
+    Returns (list of (xbar, ubar), list of per-instance info dicts).
+    """
+    params = default_params() if params is None else params
+    sols, infos = [None] * len(insts), [None] * len(insts)
+    i = 0
+    while i < len(insts):
+        j = i + 1
+        if insts[i]["group"] >= 0:
+            while j < len(insts) and insts[j]["group"] == insts[i]["group"]:
+                j += 1
+        trajs = [init_traj(insts[k]) for k in range(i, j)]
+        ginfo = scp_group(trajs, params)
+        for k, t in zip(range(i, j), trajs):
+            inf = dict(ginfo)
+            inf.update(defect=defect(t.inst, t.xbar, t.ubar), cost=cost(t.inst, t.xbar, t.ubar),
+                       viol=violation(t.inst, t.xbar, t.ubar), bnd_err=boundary_error(t.inst, t.xbar))
+            sols[k] = (t.xbar, t.ubar)
+            infos[k] = inf
+        i = j
+    return sols, infos
+
+
+def shift_warm_start(traj: Traj):
+    """MPC warm start (Sec. IV-A.4): shift the trajectory and its ADMM state by one node,
+    repeating the last node, so the next solve starts from the previous tube."""
+    def sh(a):
+        b = np.array(a, copy=True)
+        b[:-1] = a[1:]
+        return b
+    traj.xbar = sh(traj.xbar)
+    traj.ubar = sh(traj.ubar)
+    st = traj.state
+    if st is not None:
+        st.lam = sh(st.lam)
+        st.mu = sh(st.mu)
+        st.lam[0] = 0.0
+        st.mu[0] = 0.0
+        for gi in range(len(st.dual)):
+            st.dual[gi] = sh(st.dual[gi])
+    return traj

@@ -1,0 +1,206 @@
+"""Seeded synthetic problem instances for the SCP + consensus-ADMM hot path.
+
+This module only draws random problem data and writes it out as plain
+numpy arrays.  It holds none of the solver's arithmetic: no dynamics, no
+linearization, no projections.  Both the CPU oracle (``oracle/``) and the
+GPU binding consume the instance dictionaries it returns; neither shares any
+other code with the other.
+
+Every instance is a ``dict`` with the physical problem in solver units:
+
+``model``       1 = quadrotor point mass (nx=6, nu=3), 2 = 3-DOF powered descent (nx=7, nu=4)
+``N``           number of intervals (N+1 state nodes, N control nodes)
+``h``           step size T/N
+``x_init``      initial state (boundary condition x_0 = x_init, eq. (ocp))
+``x_target``    terminal target, ``t_mask`` selects the fixed components (S in eq. (ocp))
+``Qr``, ``R``   diagonals of the running state / control Hessians
+``Qn``, ``qn``, ``cN``  terminal cost 0.5 x'diag(Qn)x + qn'x + cN
+``x_lo``/``x_hi``/``u_lo``/``u_hi``  hard bounds (+-inf where absent)
+``u_ball``      radius of the control ball ||u|| <= u_ball (quadrotor; inf = none)
+``delta``       trust-region radius (l-inf box around the nominal)
+``drag``, ``mscale``, ``grav``  quadrotor drag coefficient, mass scale, gravity
+``obstacles``   (K, 4) sphere centres and radii (quadrotor)
+``alpha``, ``gvec``, ``glide_tan``  powered-descent mass-flow coefficient, gravity vector,
+                tangent of the glide-slope half angle
+``x_guess``, ``u_guess``  initial nominal trajectory, shapes (N+1, nx) and (N, nu)
+``group``       scenario group id; trajectories of one group share their first control
+                by consensus (robust MPC, Sec. IV-A.4 of the paper)
+
+RNG: ``numpy.random.Generator(PCG64(1000*config + instance))`` with a fixed draw
+order (start, goal, obstacles; or r0, v0; then per-scenario parameters).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+QUAD = 1
+MARS = 2
+NX = {QUAD: 6, MARS: 7}
+NU = {QUAD: 3, MARS: 4}
+KMAX = 8  # most obstacles one quadrotor instance may carry
+
+G_EARTH = 9.81
+
+# Powered-descent scaling: length 1000 m, time 10 s, mass 1905 kg (force unit 19050 N).
+MARS_L, MARS_TAU, MARS_M = 1000.0, 10.0, 1905.0
+MARS_F = MARS_M * MARS_L / MARS_TAU ** 2
+MARS_G = 3.7114
+MARS_ISP_G0 = 225.0 * 9.807
+
+
+def _rng(config: int, instance: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(1000 * config + instance))
+
+
+def quad_instance(config: int, instance: int, N: int = 30, K: int = 4, T: float = 5.0,
+                  delta: float = 1.0, drag: float = 0.1, mscale: float = 1.0,
+                  rng: np.random.Generator | None = None) -> dict:
+    """Quadrotor point mass p' = v, v' = u/m - g e3 - c|v|v with K spherical obstacles.
+
+    Cost sum ||u||^2 + 100 ||x_N - x_goal||^2, |u_j| <= 15, ||u|| <= 20.
+    Start and goal are redrawn while they sit within r + 0.25 of an obstacle.
+    """
+    if not 0 <= K <= KMAX:
+        raise ValueError(f"K must be in [0, {KMAX}]")
+    g = rng if rng is not None else _rng(config, instance)
+    start = g.uniform(-5.0, 5.0, 3)
+    goal = g.uniform(-5.0, 5.0, 3)
+    obs = np.zeros((K, 4))
+    for j in range(K):
+        obs[j, :3] = g.uniform(-3.0, 3.0, 3)
+        obs[j, 3] = g.uniform(0.5, 1.0)
+
+    def clear(p):
+        return all(np.linalg.norm(p - obs[j, :3]) >= obs[j, 3] + 0.25 for j in range(K))
+
+    while not clear(start):
+        start = g.uniform(-5.0, 5.0, 3)
+    while not clear(goal):
+        goal = g.uniform(-5.0, 5.0, 3)
+
+    nx, nu = 6, 3
+    x_goal = np.concatenate([goal, np.zeros(3)])
+    s = np.linspace(0.0, 1.0, N + 1)[:, None]
+    x_guess = np.zeros((N + 1, nx))
+    x_guess[:, :3] = start + s * (goal - start)
+    x_guess[:, 3:] = (goal - start) / T
+    u_guess = np.tile(np.array([0.0, 0.0, G_EARTH]), (N, 1))
+    inf = math.inf
+    return dict(
+        model=QUAD, N=N, h=T / N, nx=nx, nu=nu,
+        x_init=np.concatenate([start, np.zeros(3)]),
+        x_target=x_goal.copy(), t_mask=np.zeros(nx, dtype=bool),
+        Qr=np.zeros(nx), R=np.full(nu, 2.0),
+        Qn=np.full(nx, 200.0), qn=-200.0 * x_goal, cN=100.0 * float(x_goal @ x_goal),
+        x_lo=np.full(nx, -inf), x_hi=np.full(nx, inf),
+        u_lo=np.full(nu, -15.0), u_hi=np.full(nu, 15.0), u_ball=20.0,
+        delta=delta, drag=drag, mscale=mscale, grav=G_EARTH,
+        obstacles=obs, alpha=0.0, gvec=np.array([0.0, 0.0, -G_EARTH]), glide_tan=inf,
+        x_guess=x_guess, u_guess=u_guess, group=-1,
+    )
+
+
+def mars_instance(config: int, instance: int, N: int = 60, tf: float = 50.0,
+                  delta: float = 1.0, rng: np.random.Generator | None = None) -> dict:
+    """3-DOF powered descent r' = v, v' = T/m + g, m' = -Gamma/(Isp g0), in scaled units.
+
+    SOC ||T|| <= Gamma, 3000 N <= Gamma <= 13000 N, glide-slope half angle 86 deg,
+    r_N = 0 and v_N = 0, cost -m_N, m_0 = 1905 kg.
+    """
+    g = rng if rng is not None else _rng(config, instance)
+    r0 = np.array([g.uniform(-500.0, 500.0), g.uniform(-500.0, 500.0), g.uniform(1200.0, 1800.0)])
+    v0 = g.uniform(-50.0, 50.0, 3)
+    nx, nu = 7, 4
+    tf_s = tf / MARS_TAU
+    gz = MARS_G * MARS_TAU ** 2 / MARS_L
+    x_init = np.concatenate([r0 / MARS_L, v0 * MARS_TAU / MARS_L, [1.0]])
+    s = np.linspace(0.0, 1.0, N + 1)[:, None]
+    x_guess = np.zeros((N + 1, nx))
+    x_guess[:, :6] = (1.0 - s) * x_init[:6]
+    x_guess[:, 6] = 1.0
+    u_guess = np.tile(np.array([0.0, 0.0, gz, gz]), (N, 1))
+    inf = math.inf
+    t_mask = np.array([True] * 6 + [False])
+    return dict(
+        model=MARS, N=N, h=tf_s / N, nx=nx, nu=nu,
+        x_init=x_init, x_target=np.zeros(nx), t_mask=t_mask,
+        Qr=np.zeros(nx), R=np.zeros(nu),
+        Qn=np.zeros(nx), qn=np.array([0.0] * 6 + [-1.0]), cN=0.0,
+        x_lo=np.full(nx, -inf), x_hi=np.full(nx, inf),
+        u_lo=np.array([-inf, -inf, -inf, 3000.0 / MARS_F]),
+        u_hi=np.array([inf, inf, inf, 13000.0 / MARS_F]), u_ball=inf,
+        delta=delta, drag=0.0, mscale=1.0, grav=gz,
+        obstacles=np.zeros((0, 4)),
+        alpha=MARS_TAU * MARS_F / (MARS_M * MARS_ISP_G0),
+        gvec=np.array([0.0, 0.0, -gz]), glide_tan=math.tan(math.radians(86.0)),
+        x_guess=x_guess, u_guess=u_guess, group=-1,
+    )
+
+
+def with_scenarios(base: dict, S: int, rng: np.random.Generator, group: int) -> list[dict]:
+    """S copies of a quadrotor instance with drag ~ U[0.05, 0.2] and mass scale ~ U[0.9, 1.1].
+
+    All copies share x_init, goal and obstacles and form one consensus group.
+    """
+    out = []
+    for _ in range(S):
+        c = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+        c["drag"] = float(rng.uniform(0.05, 0.2))
+        c["mscale"] = float(rng.uniform(0.9, 1.1))
+        c["group"] = group
+        out.append(c)
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# Workloads (shapes of the paper's quadrotor and powered-descent experiments)
+# ---------------------------------------------------------------------------------------------
+
+def config0() -> list[dict]:
+    """Single quadrotor instance, N=30, T=5 s, 4 obstacles (solved in FP64)."""
+    return [quad_instance(0, 0, N=30, K=4, T=5.0)]
+
+
+def config1(n_inst: int = 1024, first: int = 0) -> list[dict]:
+    """Independent quadrotor instances, N=50, T=5 s, 8 obstacles each (FP32 batch)."""
+    return [quad_instance(1, i, N=50, K=8, T=5.0) for i in range(first, first + n_inst)]
+
+
+def config2(n_inst: int = 4096, first: int = 0) -> list[dict]:
+    """Powered-descent Monte Carlo, N=60, tf=50 s."""
+    return [mars_instance(2, i, N=60, tf=50.0) for i in range(first, first + n_inst)]
+
+
+def config3(n_inst: int = 2048, first: int = 0) -> list[dict]:
+    """Uneven mix: half quadrotor (8 obstacles, T=5 s), half powered descent (tf=50 s),
+    horizons N ~ U{20..120}, order given by a seeded permutation."""
+    perm = np.random.Generator(np.random.PCG64(3000 + 999_999)).permutation(n_inst)
+    out = []
+    for i in range(first, first + n_inst):
+        g = _rng(3, i)
+        N = int(g.integers(20, 121))
+        if perm[i] % 2 == 0:
+            out.append(quad_instance(3, i, N=N, K=8, T=5.0, rng=g))
+        else:
+            out.append(mars_instance(3, i, N=N, tf=50.0, rng=g))
+    return out
+
+
+def config4_request(session: int, S: int = 16, N: int | None = None) -> list[dict]:
+    """One robust-MPC request: S scenarios of a quadrotor (4 obstacles, N ~ U{30..80})
+    sharing the first control.  Drag and mass scale are drawn per scenario."""
+    g = _rng(4, session)
+    if N is None:
+        N = int(g.integers(30, 81))
+    base = quad_instance(4, session, N=N, K=4, T=5.0, rng=g)
+    return with_scenarios(base, S, g, group=session)
+
+
+def horizon_mix_stats(insts: list[dict]) -> dict:
+    """Counts used to state the workload in results (nodes, models)."""
+    nodes = sum(d["N"] + 1 for d in insts)
+    return dict(instances=len(insts), nodes=nodes,
+                quad=sum(d["model"] == QUAD for d in insts),
+                mars=sum(d["model"] == MARS for d in insts))
