@@ -1,0 +1,236 @@
+"""Benchmark of the SCP + consensus-ADMM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096] [--no-cpu-baseline]
+
+One step = one full batched solve of the workload (linearization, convexification, factorization,
+ADMM iterations, acceptance and metrics for every instance) through the C ABI, persistent form,
+with the problem already resident in HBM.  Prints one JSON line.
+
+Default workload: 1024 independent quadrotor point-mass instances, N = 50, 8 obstacles, fixed
+budget of 15 SCP x 200 ADMM iterations, rho = 1, FP32.  ``value`` is the whole-job throughput
+(solves/s) at that fixed budget; the solves meeting the defect bound 1e-5 are reported next to it
+as goodput.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+# The CPU baseline runs the oracle in single-threaded worker processes.
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import scpgen  # noqa: E402
+
+METRIC = "SCP solves/s at defect<=1e-5; p50/p99 latency, persistent-served vs plain"
+PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (packed issue)
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def workload(name: str):
+    if name == "quad1024":
+        return dict(name=name, insts=scpgen.config1(1024), scp=15, admm=200, rho=1.0, prec="f32",
+                    desc="quadrotor point-mass batch: 1024 instances, N=50, 8 obstacles, 15 SCP x 200 ADMM, "
+                         "rho=1, trust region 1, FP32")
+    if name == "mars4096":
+        return dict(name=name, insts=scpgen.config2(4096), scp=15, admm=200, rho=1.0, prec="f32",
+                    desc="3-DOF powered-descent Monte Carlo: 4096 instances, N=60, 15 SCP x 200 ADMM, rho=1, FP32")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def flops_per_node_iter(model: int, K: int) -> int:
+    """Algorithmic flops of one ADMM iteration (Steps 1-4) at one interior node, FMA = 2.
+
+    Step 1: w (3 nx), A'w (2 nx nxr), B'w (2 nx nu), x right-hand side (4 nx), mirror terms (3 C),
+    two triangular solves (2 n^2), A x (2 nx nxr), B u (2 nx nu), d_dyn (2 nx).
+    Step 2: 6 nx.  Step 3: box clamps 4 n, ball 17, half-space 20 each, glide cone 21, SOC 25.
+    Step 4: 6 nx + 3 C.  Quantities constant within an SCP iteration are not counted again.
+    """
+    if model == scpgen.QUAD:
+        nx, nxr, nu = 6, 3, 3
+        C = 12 + 3 * K
+        s3 = 4 * (nx + nu) + 17 + 20 * K
+    else:
+        nx, nxr, nu = 7, 4, 4
+        C = 18
+        s3 = 4 * (nx + nu) + 21 + 25
+    n = nx + nu
+    s1 = 3 * nx + 2 * nx * nxr + 2 * nx * nu + 4 * nx + 3 * C + 2 * n * n + 2 * nx * nxr + 2 * nx * nu + 2 * nx
+    return s1 + 6 * nx + s3 + 6 * nx + 3 * C
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_10711_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _oracle_worker(args):
+    inst, scp_iters, admm_iters, rho = args
+    import oracle
+    p = oracle.default_params(scp_iters=scp_iters, admm_iters=admm_iters, rho_eq=rho, rho_dyn=rho, rho_geo=rho)
+    t = oracle.init_traj(inst)
+    oracle.scp.scp_group([t], p)
+    return oracle.defect(inst, t.xbar, t.ubar)
+
+
+def cpu_baseline(wl, sample: int, cores: int) -> dict:
+    """The FP64 oracle (as it stands) on a sample of the workload, one process per core.
+    Runs before the GPU is touched (worker processes are forked from a GPU-free parent)."""
+    import multiprocessing as mp
+    insts = wl["insts"][:sample]
+    args = [(d, wl["scp"], wl["admm"], wl["rho"]) for d in insts]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        defects = pool.map(_oracle_worker, args, chunksize=1)
+    dt = time.perf_counter() - t0
+    return {"value": round(sample / dt, 3), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {sample} instances of the workload, full {wl['scp']}x{wl['admm']} budget, FP64 NumPy, "
+                      f"{cores} single-threaded worker processes, {dt:.1f} s wall",
+            "defect_p50": float(np.median(defects))}
+
+
+def load_pmc(wl_name: str, khash: str):
+    """HBM traffic of the persistent kernel from the committed rocprofv3 counter summary, if the
+    kernel sources are unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_persistent_{wl_name}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != khash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="quad1024")
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (instances shard across GPUs "
+              "with no communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    wl = workload(a.workload)
+    cores = min(os.cpu_count() or 1, 16)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_sample, cores)
+
+    import torch
+    from paper_2603_10711_amd import binding as B
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    insts = wl["insts"]
+    prob = B.Problem(insts, precision=wl["prec"], block=a.block, device="cuda:0")
+    prm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], form="persistent")
+    stream = prob.stream
+    for _ in range(a.warmup):
+        prob.solve(prm)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        starts[k].record(stream)
+        prob.solve(prm)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    _, _, info = prob.result()
+    info = info.cpu().numpy()
+    n = len(insts)
+    defect = info[:, 6]
+    good = int(np.sum(defect <= 1e-5))
+    ms_per_step = wall / a.steps * 1e3
+    solves_per_s = n * a.steps / wall
+    node_iters = sum((d["N"] + 1) for d in insts) * wl["scp"] * wl["admm"]
+    flops = sum((d["N"] + 1) * flops_per_node_iter(d["model"], d["obstacles"].shape[0]) for d in insts) \
+        * wl["scp"] * wl["admm"]
+    kernel_ms = float(np.mean(step_ms))
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    khash = kernel_source_hash()
+    traffic = load_pmc(wl["name"], khash)
+    prob.close()
+
+    # plain form (state in HBM, host-enqueued kernels) on the same workload
+    plain = None
+    if a.plain_steps > 0:
+        pp = B.Problem(insts, precision=wl["prec"], device="cuda:0")
+        pprm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], form="plain")
+        pp.solve(pprm)
+        torch.cuda.synchronize()
+        ps = [torch.cuda.Event(enable_timing=True) for _ in range(a.plain_steps)]
+        pe = [torch.cuda.Event(enable_timing=True) for _ in range(a.plain_steps)]
+        t1 = time.perf_counter()
+        for k in range(a.plain_steps):
+            ps[k].record(pp.stream)
+            pp.solve(pprm)
+            pe[k].record(pp.stream)
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - t1
+        pms = np.array([s.elapsed_time(e) for s, e in zip(ps, pe)])
+        plain = {"solves_per_s": round(n * a.plain_steps / pwall, 1), "ms_per_step": round(pwall / a.plain_steps * 1e3, 3),
+                 "latency_ms_p50": round(float(np.percentile(pms, 50)), 3),
+                 "latency_ms_p99": round(float(np.percentile(pms, 99)), 3)}
+        pp.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(solves_per_s, 1),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl["prec"] == "f32" else "f64",
+        "data": "synthetic (seeded generator of the workload's shapes and distributions)",
+        "config": {"workload": wl["desc"], "form": "persistent", "instances": n, "nodes": int(sum(d["N"] + 1 for d in insts)),
+                   "block": a.block or "auto"},
+        "goodput_solves_per_s": round(good * a.steps / wall, 1),
+        "defect_le_1e-5": f"{good}/{n}",
+        "defect_p50": float(np.median(defect)),
+        "defect_max": float(np.max(defect)),
+        "latency_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "node_admm_iters_per_s": round(node_iters * a.steps / wall, 1),
+        "plain": plain,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS if wl["prec"] == "f32" else PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / (PEAK_FP32_TFLOPS if wl["prec"] == "f32" else PEAK_FP64_TFLOPS), 4),
+                     "traffic": traffic, "kernel": "k_persistent", "flops_per_launch": flops,
+                     "kernel_ms": round(kernel_ms, 4)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

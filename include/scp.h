@@ -1,0 +1,235 @@
+/*
+ * scp.h - C ABI of the MI355X (gfx950) library for the data-parallel hot path of
+ * GPU-native sequential convex programming with consensus ADMM (arXiv 2603.10711).
+ *
+ * The library solves batches of discrete optimal control problems of the form of the
+ * paper's eq. (ocp) (Sec. II): RK4-discretized nonlinear dynamics x_{i+1} = f(x_i, u_i),
+ * boundary conditions x_0 = x_init and S x_N = x_target, convex sets on x_i and u_i.
+ * Each SCP iteration (Sec. III-A) linearizes the dynamics around the nominal trajectory and
+ * solves the convex subproblem eq. (qp_subproblem) with the temporally split consensus ADMM
+ * of Sec. III-B (per-node dense Cholesky solves, closed-form consensus update, analytic
+ * projections, dual ascent).
+ *
+ * General conventions
+ *  - Every call returns scp_status (SCP_OK = 0) and never throws.  On error the handle's
+ *    message is available from scp_last_error().
+ *  - Device memory: the caller owns it.  scp_problem_device_bytes() gives the size of the
+ *    arena that scp_problem_create() needs; the caller allocates it (e.g. a torch uint8 tensor)
+ *    and keeps it alive until scp_problem_destroy().  The library never calls hipMalloc.
+ *  - Streams: every call after create enqueues work on the hip stream given at create time
+ *    and returns without synchronizing; results live in device memory.
+ *  - Numerical failures are not call errors: they are per-trajectory status bits in the info
+ *    record (SCP_ST_*), and the other trajectories of the batch are unaffected.
+ *  - Thread compatibility: one handle must not be used from two host threads at once.
+ *    Different handles are independent.
+ */
+#ifndef SCP_MI355X_H
+#define SCP_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCP_OK = 0,
+    SCP_ERR_ARG = 1,          /* invalid argument (sizes, ids, NULL pointers, arena too small) */
+    SCP_ERR_NOMEM = 2,        /* host allocation failed */
+    SCP_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed */
+    SCP_ERR_STATE = 4,        /* call out of order (e.g. admm_solve before scp_linearize) */
+    SCP_ERR_UNSUPPORTED = 5   /* valid request this build cannot serve (e.g. block size) */
+} scp_status;
+
+/* Dynamics models (hand-derived device functions; a problem names a model id). */
+typedef enum {
+    SCP_MODEL_QUAD_PM = 1,    /* quadrotor point mass, nx=6 (p, v), nu=3 (u):
+                                 p' = v, v' = u/m_s - g e3 - c |v| v                        */
+    SCP_MODEL_MARS3DOF = 2    /* 3-DOF powered descent in scaled units, nx=7 (r, v, m),
+                                 nu=4 (T, Gamma): r' = v, v' = T/m + g_vec, m' = -alpha Gamma */
+} scp_model;
+
+typedef enum { SCP_F32 = 0, SCP_F64 = 1 } scp_precision;
+
+typedef enum {
+    SCP_FORM_PLAIN = 0,       /* state in HBM; host-enqueued kernels per ADMM iteration       */
+    SCP_FORM_PERSISTENT = 1   /* one kernel per SCP iteration (or per solve); every node's
+                                 factor and ADMM state stay in registers/LDS                    */
+} scp_form;
+
+#define SCP_MAX_NX 7
+#define SCP_MAX_NU 4
+#define SCP_MAX_OBS 8
+#define SCP_MAX_N 1023        /* largest horizon N (intervals) of one trajectory */
+
+/*
+ * Per-trajectory parameter record: SCP_PARAM_STRIDE doubles, in solver units.
+ * Vectors are stored at the given offset with SCP_MAX_NX / SCP_MAX_NU slots; unused
+ * trailing slots are ignored.  +-HUGE_VAL marks an absent bound.
+ */
+enum {
+    SCP_P_H = 0,              /* step size T/N                                              */
+    SCP_P_XINIT = 1,          /* [7] initial state, x_0 = x_init (eq. ocp)                  */
+    SCP_P_XTGT = 8,           /* [7] terminal target                                        */
+    SCP_P_TMASK = 15,         /* [7] 1.0 where x_N is fixed to the target (selection S)     */
+    SCP_P_QR = 22,            /* [7] diagonal of the running state Hessian Q_i, i < N       */
+    SCP_P_QN = 29,            /* [7] diagonal of the terminal Hessian Q_N                   */
+    SCP_P_QNV = 36,           /* [7] terminal gradient q_N                                  */
+    SCP_P_CN = 43,            /* constant of the terminal cost (reported cost only)         */
+    SCP_P_R = 44,             /* [4] diagonal of the control Hessian R_i                    */
+    SCP_P_XLO = 48,           /* [7] hard state lower bounds                                */
+    SCP_P_XHI = 55,           /* [7] hard state upper bounds                                */
+    SCP_P_ULO = 62,           /* [4] hard control lower bounds                              */
+    SCP_P_UHI = 66,           /* [4] hard control upper bounds                              */
+    SCP_P_UBALL = 70,         /* control ball radius ||u|| <= r (quadrotor; HUGE_VAL = none)*/
+    SCP_P_DELTA = 71,         /* initial trust-region radius (l-inf box around the nominal) */
+    SCP_P_DRAG = 72,          /* quadrotor drag coefficient c                               */
+    SCP_P_MSCALE = 73,        /* quadrotor mass scale m_s                                   */
+    SCP_P_GRAV = 74,          /* quadrotor gravity g                                        */
+    SCP_P_ALPHA = 75,         /* powered descent mass-flow coefficient alpha                */
+    SCP_P_GVEC = 76,          /* [3] powered descent gravity vector                         */
+    SCP_P_GLIDE = 79,         /* tan of the glide-slope half angle (powered descent)        */
+    SCP_P_NOBS = 80,          /* number of spherical obstacles K <= SCP_MAX_OBS (quadrotor) */
+    SCP_P_OBS = 81,           /* [8 x 4] obstacle centre (3) and radius (1)                 */
+    SCP_PARAM_STRIDE = 113
+};
+
+/*
+ * Per-trajectory info record written to device memory by scp_solve / admm_solve
+ * (SCP_INFO_FIELDS doubles per trajectory).
+ */
+enum {
+    SCP_I_ADMM_ITERS = 0,     /* ADMM iterations run (summed over SCP iterations)           */
+    SCP_I_RP = 1,             /* last primal residual (inf-norm)                            */
+    SCP_I_RD = 2,             /* last dual residual (inf-norm)                              */
+    SCP_I_NACCEPT = 3,        /* accepted SCP steps                                         */
+    SCP_I_DELTA = 4,          /* trust radius after the last SCP iteration                  */
+    SCP_I_STATUS = 5,         /* SCP_ST_* bits                                              */
+    SCP_I_DEFECT = 6,         /* max_i ||x_{i+1} - RK4(x_i, u_i)||_inf of the returned nominal */
+    SCP_I_COST = 7,           /* objective of eq. (ocp) at the returned nominal             */
+    SCP_I_VIOL = 8,           /* max violation of the hard (unconvexified) constraints      */
+    SCP_I_BNDERR = 9,         /* boundary-condition error                                   */
+    SCP_I_MERIT = 10,         /* merit of the last candidate                                */
+    SCP_I_RATIO = 11,         /* last actual/predicted merit reduction ratio                */
+    SCP_INFO_FIELDS = 12
+};
+
+/* status bits of SCP_I_STATUS */
+#define SCP_ST_NONFINITE 1    /* a non-finite iterate or merit was produced                 */
+#define SCP_ST_BADPIVOT 2     /* non-positive Cholesky pivot (H_i not positive definite)   */
+#define SCP_ST_EMPTYSET 4     /* a hard box has lo > hi                                     */
+#define SCP_ST_CONVERGED 8    /* ADMM residual test passed in the last SCP iteration        */
+
+typedef struct {
+    int32_t n_traj;           /* number of trajectories, >= 1                              */
+    scp_precision prec;       /* arithmetic of every kernel of this problem                 */
+    const int32_t* model;     /* [n_traj] scp_model                                         */
+    const int32_t* horizon;   /* [n_traj] N, 1 <= N <= SCP_MAX_N                            */
+    const int32_t* group;     /* [n_traj] consensus group id, or -1; members of one group
+                                 are consecutive and share model and N; their first
+                                 controls are averaged at every ADMM iteration (scenario
+                                 MPC, Sec. IV-A.4).  NULL = every trajectory alone.          */
+    const double* params;     /* [n_traj * SCP_PARAM_STRIDE] records, see SCP_P_*           */
+    const double* x_guess;    /* initial nominal states, rows of SCP_MAX_NX doubles, (N+1)
+                                 rows per trajectory, trajectories concatenated             */
+    const double* u_guess;    /* initial nominal controls, rows of SCP_MAX_NU doubles, N
+                                 rows per trajectory                                        */
+    int32_t block;            /* workgroup size of the persistent kernel: 64, 128 or 256
+                                 (0 = smallest that holds the longest trajectory or group) */
+} scp_problem_desc;
+
+typedef struct {
+    double rho_eq, rho_dyn, rho_geo;  /* penalties of eq. (augmented_lagrangian), > 0        */
+    int32_t max_iters;                /* ADMM iterations per call / per SCP iteration       */
+    int32_t check_every;              /* residual test cadence c (0 = never stop early)     */
+    double eps_prim, eps_dual;        /* stop when r_p <= eps_prim and r_d <= eps_dual      */
+} admm_params;
+
+typedef struct {
+    int32_t scp_iters;                /* SCP iterations                                      */
+    admm_params admm;
+    double eta0;                      /* accept a step if ratio >= eta0 (-HUGE_VAL: always) */
+    double eta1, eta2;                /* shrink below eta1, grow above eta2                 */
+    double shrink, grow, delta_max;   /* trust-radius update factors and cap                */
+    double merit_w;                   /* weight of the l1 dynamics defect in the merit      */
+    scp_form form;                    /* plain (HBM state) or persistent kernel             */
+    int32_t scp_per_launch;           /* persistent form: SCP iterations per kernel launch
+                                         (0 = all in one launch)                            */
+} scp_params;
+
+typedef struct scp_problem scp_problem;
+
+/* HBM footprint in bytes of the arena scp_problem_create() needs for this description;
+ * 0 if the description is invalid.  Pure host computation. */
+size_t scp_problem_device_bytes(const scp_problem_desc* desc);
+
+/* Validate the description, lay out the arena, upload problem data and initial nominal
+ * (converted to the problem precision), and return a handle.  arena_dev must hold at
+ * least scp_problem_device_bytes(desc) bytes of device memory, 256-byte aligned.  The
+ * upload is enqueued on hip_stream (a hipStream_t, NULL = default stream) and the call
+ * waits for it.  Errors: SCP_ERR_ARG (bad description or arena), SCP_ERR_HIP. */
+scp_status scp_problem_create(const scp_problem_desc* desc, void* arena_dev, size_t arena_bytes,
+                              void* hip_stream, scp_problem** out);
+
+/* Release host resources of the handle; never frees arena_dev.  NULL is ignored. */
+void scp_problem_destroy(scp_problem* p);
+
+/* Steps a2-a4 at the current nominal (Sec. III-A; Sec. III-B Step 1 factorization):
+ * RK4 linearization with exact Jacobians, convexified constraint sets (trust box with the
+ * current radius, boundary equalities, obstacle half-spaces), Step-1 Hessians and their
+ * unpivoted Cholesky factors, and re-initialization of the ADMM primal state from the
+ * nominal (duals are carried).  Uses rho from the last admm_params given to admm_solve or
+ * scp_solve, or rho = 1 before any.  Async on the handle's stream. */
+scp_status scp_linearize(scp_problem* p, const admm_params* prm);
+
+/* Steps a5-a9: up to prm->max_iters ADMM iterations (Steps 1-4) on the subproblem built by
+ * the last scp_linearize, continuing from the state in the arena, with the residual test
+ * every prm->check_every iterations (per trajectory / consensus group).  The penalties must
+ * equal those given to scp_linearize (SCP_ERR_ARG otherwise).  Plain form.  Async. */
+scp_status admm_solve(scp_problem* p, const admm_params* prm);
+
+/* Steps a2-a10 repeated prm->scp_iters times from the current nominal, including the merit
+ * ratio test, nominal update and trust-radius update, then the metrics of the final
+ * nominal (defect, cost, violation, boundary error) into the info records.  Async. */
+scp_status scp_solve(scp_problem* p, const scp_params* prm);
+
+/* Copy the nominal trajectory and info to caller device buffers (device-to-device, async):
+ * x_dev gets rows of SCP_MAX_NX values per node (all trajectories concatenated, N+1 rows
+ * each), u_dev rows of SCP_MAX_NU values (N+1 rows per trajectory, the last row zero), both
+ * in the problem precision; info_dev gets SCP_INFO_FIELDS doubles per trajectory.  Any of
+ * the three may be NULL. */
+scp_status scp_get_result(const scp_problem* p, void* x_dev, void* u_dev, void* info_dev);
+
+/* Field ids of scp_get_field: the ADMM iterates and linearization data of every node. */
+typedef enum {
+    SCP_FIELD_XBAR = 0, SCP_FIELD_UBAR = 1, SCP_FIELD_X = 2, SCP_FIELD_U = 3,
+    SCP_FIELD_Z = 4, SCP_FIELD_LAM = 5, SCP_FIELD_MU = 6, SCP_FIELD_DDYN = 7,
+    SCP_FIELD_COPY = 8, SCP_FIELD_DUAL = 9, SCP_FIELD_A = 10, SCP_FIELD_B = 11,
+    SCP_FIELD_D = 12, SCP_FIELD_BOXLO = 13, SCP_FIELD_BOXHI = 14, SCP_FIELD_HS = 15,
+    SCP_FIELD_COUNT = 16
+} scp_field;
+
+/* Width (values per node) of a field: XBAR/X/Z/LAM/MU/DDYN/D 7, UBAR/U 4, COPY/DUAL 36,
+ * A 49 (row-major 7x7), B 28 (row-major 7x4), BOXLO/BOXHI 11 (x then u), HS 32
+ * (a_x, a_y, a_z, b per obstacle).  0 for an invalid id. */
+int32_t scp_field_width(int32_t field);
+
+/* Copy one field of every node (trajectories concatenated, N+1 rows each, scp_field_width
+ * values per row, problem precision) to dst_dev.  Mirror copies and duals are packed per
+ * model in a fixed group order: quadrotor [x box 6][u box 3][ball 3][half-space k: 3 each],
+ * powered descent [x box 7][u box 4][glide cone 3][SOC 4].  Async. */
+scp_status scp_get_field(const scp_problem* p, int32_t field, void* dst_dev);
+
+/* Total nodes (sum of N+1) and the node offset of trajectory t (for slicing results). */
+int64_t scp_problem_nodes(const scp_problem* p);
+int64_t scp_traj_node_offset(const scp_problem* p, int32_t t);
+
+/* Message of the last failed call on this handle ("" if none); for p == NULL, the last
+ * error of a failed scp_problem_create in this thread. */
+const char* scp_last_error(const scp_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCP_MI355X_H */

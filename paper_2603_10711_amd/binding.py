@@ -1,0 +1,241 @@
+"""ctypes binding of libscp.so (the C ABI in include/scp.h).
+
+Argument marshalling only: problem dictionaries (as produced by ``scpgen``) are packed into
+the C parameter records, device memory comes from PyTorch (one uint8 tensor per problem, the
+"arena"), and every computation runs in the HIP kernels of the library.  There is no CPU
+fallback: if the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscp.so")
+
+# --- constants mirrored from include/scp.h ------------------------------------------------
+SCP_OK = 0
+QUAD, MARS = 1, 2
+F32, F64 = 0, 1
+FORM_PLAIN, FORM_PERSISTENT = 0, 1
+MAX_NX, MAX_NU, MAX_OBS = 7, 4, 8
+P = dict(H=0, XINIT=1, XTGT=8, TMASK=15, QR=22, QN=29, QNV=36, CN=43, R=44, XLO=48, XHI=55, ULO=62, UHI=66,
+         UBALL=70, DELTA=71, DRAG=72, MSCALE=73, GRAV=74, ALPHA=75, GVEC=76, GLIDE=79, NOBS=80, OBS=81)
+PARAM_STRIDE = 113
+INFO = dict(admm_iters=0, r_p=1, r_d=2, n_accept=3, delta=4, status=5, defect=6, cost=7, viol=8, bnd_err=9,
+            merit=10, ratio=11)
+INFO_FIELDS = 12
+ST_NONFINITE, ST_BADPIVOT, ST_EMPTYSET, ST_CONVERGED = 1, 2, 4, 8
+FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9, A=10, B=11, d=12, boxlo=13,
+              boxhi=14, hs=15)
+SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_destroy", "scp_linearize", "admm_solve",
+           "scp_solve", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
+           "scp_traj_node_offset", "scp_last_error"]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("n_traj", c_int32), ("prec", c_int32), ("model", POINTER(c_int32)), ("horizon", POINTER(c_int32)),
+                ("group", POINTER(c_int32)), ("params", POINTER(c_double)), ("x_guess", POINTER(c_double)),
+                ("u_guess", POINTER(c_double)), ("block", c_int32)]
+
+
+class AdmmParams(ctypes.Structure):
+    _fields_ = [("rho_eq", c_double), ("rho_dyn", c_double), ("rho_geo", c_double), ("max_iters", c_int32),
+                ("check_every", c_int32), ("eps_prim", c_double), ("eps_dual", c_double)]
+
+
+class ScpParams(ctypes.Structure):
+    _fields_ = [("scp_iters", c_int32), ("admm", AdmmParams), ("eta0", c_double), ("eta1", c_double),
+                ("eta2", c_double), ("shrink", c_double), ("grow", c_double), ("delta_max", c_double),
+                ("merit_w", c_double), ("form", c_int32), ("scp_per_launch", c_int32)]
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libscp.so and declare its signatures.  Raises if the library is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run paper_2603_10711_amd.build)")
+    lib = ctypes.CDLL(path)
+    lib.scp_problem_device_bytes.argtypes = [POINTER(ProblemDesc)]
+    lib.scp_problem_device_bytes.restype = c_size_t
+    lib.scp_problem_create.argtypes = [POINTER(ProblemDesc), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
+    lib.scp_problem_create.restype = c_int32
+    lib.scp_problem_destroy.argtypes = [c_void_p]
+    lib.scp_problem_destroy.restype = None
+    lib.scp_linearize.argtypes = [c_void_p, POINTER(AdmmParams)]
+    lib.scp_linearize.restype = c_int32
+    lib.admm_solve.argtypes = [c_void_p, POINTER(AdmmParams)]
+    lib.admm_solve.restype = c_int32
+    lib.scp_solve.argtypes = [c_void_p, POINTER(ScpParams)]
+    lib.scp_solve.restype = c_int32
+    lib.scp_get_result.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.scp_get_result.restype = c_int32
+    lib.scp_field_width.argtypes = [c_int32]
+    lib.scp_field_width.restype = c_int32
+    lib.scp_get_field.argtypes = [c_void_p, c_int32, c_void_p]
+    lib.scp_get_field.restype = c_int32
+    lib.scp_problem_nodes.argtypes = [c_void_p]
+    lib.scp_problem_nodes.restype = c_int64
+    lib.scp_traj_node_offset.argtypes = [c_void_p, c_int32]
+    lib.scp_traj_node_offset.restype = c_int64
+    lib.scp_last_error.argtypes = [c_void_p]
+    lib.scp_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def param_record(inst: dict) -> np.ndarray:
+    """Pack one problem dictionary into the SCP_PARAM_STRIDE-double C record."""
+    r = np.zeros(PARAM_STRIDE)
+    nx, nu = inst["nx"], inst["nu"]
+    r[P["H"]] = inst["h"]
+    r[P["XINIT"]:P["XINIT"] + nx] = inst["x_init"]
+    r[P["XTGT"]:P["XTGT"] + nx] = inst["x_target"]
+    r[P["TMASK"]:P["TMASK"] + nx] = np.asarray(inst["t_mask"], dtype=float)
+    r[P["QR"]:P["QR"] + nx] = inst["Qr"]
+    r[P["QN"]:P["QN"] + nx] = inst["Qn"]
+    r[P["QNV"]:P["QNV"] + nx] = inst["qn"]
+    r[P["CN"]] = inst["cN"]
+    r[P["R"]:P["R"] + nu] = inst["R"]
+    r[P["XLO"]:P["XLO"] + nx] = inst["x_lo"]
+    r[P["XHI"]:P["XHI"] + nx] = inst["x_hi"]
+    r[P["ULO"]:P["ULO"] + nu] = inst["u_lo"]
+    r[P["UHI"]:P["UHI"] + nu] = inst["u_hi"]
+    r[P["UBALL"]] = inst["u_ball"]
+    r[P["DELTA"]] = inst["delta"]
+    r[P["DRAG"]] = inst["drag"]
+    r[P["MSCALE"]] = inst["mscale"]
+    r[P["GRAV"]] = inst["grav"]
+    r[P["ALPHA"]] = inst["alpha"]
+    r[P["GVEC"]:P["GVEC"] + 3] = inst["gvec"]
+    r[P["GLIDE"]] = inst["glide_tan"]
+    obs = np.asarray(inst["obstacles"], dtype=float).reshape(-1, 4)
+    r[P["NOBS"]] = obs.shape[0]          # the library rejects counts above MAX_OBS
+    keep = obs[:MAX_OBS].ravel()
+    r[P["OBS"]:P["OBS"] + keep.size] = keep
+    return r
+
+
+def admm_params(rho=1.0, iters=100, check_every=0, eps=0.0, rho_dyn=None, rho_geo=None, eps_dual=None) -> AdmmParams:
+    return AdmmParams(rho, rho if rho_dyn is None else rho_dyn, rho if rho_geo is None else rho_geo, iters,
+                      check_every, eps, eps if eps_dual is None else eps_dual)
+
+
+def scp_params(scp_iters=10, admm_iters=100, rho=1.0, check_every=0, eps=0.0, form="persistent",
+               scp_per_launch=0, eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
+               merit_w=1.0e3, rho_dyn=None, rho_geo=None) -> ScpParams:
+    f = FORM_PERSISTENT if form == "persistent" else FORM_PLAIN
+    return ScpParams(scp_iters, admm_params(rho, admm_iters, check_every, eps, rho_dyn, rho_geo), eta0, eta1, eta2,
+                     shrink, grow, delta_max, merit_w, f, scp_per_launch)
+
+
+class ScpError(RuntimeError):
+    pass
+
+
+class Problem:
+    """A batch of trajectories resident on the GPU (one arena tensor), driven through the C ABI."""
+
+    def __init__(self, insts: list[dict], precision: str = "f32", block: int = 0, device: str = "cuda",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.insts = insts
+        self.n_traj = len(insts)
+        self.prec = F32 if precision == "f32" else F64
+        self.dtype = torch.float32 if self.prec == F32 else torch.float64
+        model = np.array([d["model"] for d in insts], dtype=np.int32)
+        horizon = np.array([d["N"] for d in insts], dtype=np.int32)
+        group = np.array([d.get("group", -1) for d in insts], dtype=np.int32)
+        params = np.concatenate([param_record(d) for d in insts])
+        xg = np.concatenate([self._pad(d["x_guess"], MAX_NX) for d in insts])
+        ug = np.concatenate([self._pad(d["u_guess"], MAX_NU) for d in insts])
+        self._keep = (model, horizon, group, params, xg, ug)
+        desc = ProblemDesc(self.n_traj, self.prec, model.ctypes.data_as(POINTER(c_int32)),
+                           horizon.ctypes.data_as(POINTER(c_int32)), group.ctypes.data_as(POINTER(c_int32)),
+                           params.ctypes.data_as(POINTER(c_double)), xg.ctypes.data_as(POINTER(c_double)),
+                           ug.ctypes.data_as(POINTER(c_double)), block)
+        nbytes = self.lib.scp_problem_device_bytes(byref(desc))
+        if nbytes == 0:
+            h = c_void_p()
+            st = self.lib.scp_problem_create(byref(desc), None, 0, None, byref(h))
+            raise ScpError(f"invalid problem description: {self.lib.scp_last_error(None).decode()}")
+        self.nbytes = nbytes
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        h = c_void_p()
+        st = self.lib.scp_problem_create(byref(desc), c_void_p(self.arena.data_ptr()), nbytes,
+                                         c_void_p(self.stream.cuda_stream), byref(h))
+        if st != SCP_OK:
+            raise ScpError(f"scp_problem_create failed ({st}): {self.lib.scp_last_error(None).decode()}")
+        self.h = h
+        self.n_nodes = int(self.lib.scp_problem_nodes(h))
+        self.offsets = np.array([self.lib.scp_traj_node_offset(h, t) for t in range(self.n_traj)], dtype=np.int64)
+
+    @staticmethod
+    def _pad(a, w):
+        a = np.asarray(a, dtype=float)
+        out = np.zeros((a.shape[0], w))
+        out[:, :a.shape[1]] = a
+        return out
+
+    def _check(self, st, what):
+        if st != SCP_OK:
+            raise ScpError(f"{what} failed ({st}): {self.lib.scp_last_error(self.h).decode()}")
+
+    def linearize(self, prm: AdmmParams | None = None):
+        self._check(self.lib.scp_linearize(self.h, byref(prm) if prm is not None else None), "scp_linearize")
+
+    def admm(self, prm: AdmmParams):
+        self._check(self.lib.admm_solve(self.h, byref(prm)), "admm_solve")
+
+    def solve(self, prm: ScpParams):
+        self._check(self.lib.scp_solve(self.h, byref(prm)), "scp_solve")
+
+    def field(self, name: str):
+        fid = FIELDS[name]
+        w = self.lib.scp_field_width(fid)
+        out = self.torch.empty((self.n_nodes, w), dtype=self.dtype, device=self.arena.device)
+        self._check(self.lib.scp_get_field(self.h, fid, c_void_p(out.data_ptr())), "scp_get_field")
+        return out
+
+    def result(self):
+        """(x, u, info) as device tensors: x (nodes, 7), u (nodes, 4), info (n_traj, 12) float64."""
+        t = self.torch
+        x = t.empty((self.n_nodes, MAX_NX), dtype=self.dtype, device=self.arena.device)
+        u = t.empty((self.n_nodes, MAX_NU), dtype=self.dtype, device=self.arena.device)
+        info = t.empty((self.n_traj, INFO_FIELDS), dtype=t.float64, device=self.arena.device)
+        self._check(self.lib.scp_get_result(self.h, c_void_p(x.data_ptr()), c_void_p(u.data_ptr()),
+                                            c_void_p(info.data_ptr())), "scp_get_result")
+        return x, u, info
+
+    def split(self, arr: np.ndarray, t: int, width: int | None = None, controls: bool = False) -> np.ndarray:
+        """Rows of trajectory t from a node-major array (controls: the first N rows)."""
+        N = self.insts[t]["N"]
+        o = self.offsets[t]
+        rows = arr[o:o + N + (0 if controls else 1)]
+        return rows if width is None else rows[:, :width]
+
+    def info_dicts(self, info: np.ndarray) -> list[dict]:
+        return [{k: float(info[t, v]) for k, v in INFO.items()} for t in range(self.n_traj)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.scp_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

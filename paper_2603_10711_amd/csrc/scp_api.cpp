@@ -1,0 +1,552 @@
+// Host side of the C ABI declared in include/scp.h: validation, arena layout, packing of
+// trajectories into persistent-kernel workgroups, upload, and the launch sequences of the
+// plain and persistent forms.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/scp.h"
+#include "scp_launch.hpp"
+#include "scp_layout.hpp"
+
+using namespace scp;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int n_traj = 0, n_nodes = 0, P = 0;
+    int models = 0, kmax = 0;
+    int block = 0, n_wg = 0;
+    bool persistent_ok = false;
+    int n_groups = 0;
+    size_t esz = 4;
+    // byte offsets inside the arena
+    size_t o_traj, o_node_traj, o_lane, o_groups, o_params, o_planes, o_rt, o_info, o_flags, o_red, total;
+    std::vector<int> traj;       // n_traj * TR_FIELDS
+    std::vector<int> node_traj;  // P
+    std::vector<int> lane;       // n_wg * block + n_wg (per-workgroup model ids)
+    std::vector<int> groups;     // first trajectory of each multi-member group
+};
+
+bool valid_model(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_MARS3DOF; }
+int model_nx(int m) { return m == SCP_MODEL_QUAD_PM ? 6 : 7; }
+int model_nu(int m) { return m == SCP_MODEL_QUAD_PM ? 3 : 4; }
+
+// Pack units (single trajectories or whole consensus groups) of one model into workgroups of
+// `block` lanes, first-fit decreasing by size.  Returns false if a unit does not fit.
+struct Unit {
+    int first_traj, n_traj, lanes, model;
+};
+
+bool pack(const std::vector<Unit>& units, const std::vector<int>& traj_off, const std::vector<int>& horizon,
+          int block, std::vector<int>& lane, std::vector<int>& wg_model, int& n_wg) {
+    lane.clear();
+    wg_model.clear();
+    n_wg = 0;
+    for (int model : {SCP_MODEL_QUAD_PM, SCP_MODEL_MARS3DOF}) {
+        std::vector<int> idx;
+        for (int u = 0; u < (int)units.size(); ++u)
+            if (units[u].model == model) idx.push_back(u);
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return units[a].lanes > units[b].lanes; });
+        std::vector<int> fill;  // used lanes of this model's workgroups
+        std::vector<int> wgs;   // global workgroup index
+        for (int u : idx) {
+            const Unit& un = units[u];
+            if (un.lanes > block) return false;
+            int w = -1;
+            for (int q = 0; q < (int)fill.size(); ++q)
+                if (fill[q] + un.lanes <= block) {
+                    w = q;
+                    break;
+                }
+            if (w < 0) {
+                w = (int)fill.size();
+                fill.push_back(0);
+                wgs.push_back(n_wg++);
+                lane.resize((size_t)n_wg * block, -1);
+                wg_model.push_back(model);
+            }
+            int base = wgs[w] * block + fill[w];
+            for (int t = un.first_traj; t < un.first_traj + un.n_traj; ++t)
+                for (int i = 0; i <= horizon[t]; ++i) lane[base++] = traj_off[t] + i;
+            fill[w] += un.lanes;
+        }
+    }
+    return true;
+}
+
+bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
+    if (!d) { err = "desc is NULL"; return false; }
+    if (d->n_traj < 1) { err = "n_traj must be >= 1"; return false; }
+    if (d->prec != SCP_F32 && d->prec != SCP_F64) { err = "invalid precision"; return false; }
+    if (!d->model || !d->horizon || !d->params || !d->x_guess || !d->u_guess) { err = "NULL array in desc"; return false; }
+    if (d->block != 0 && d->block != 64 && d->block != 128 && d->block != 256) { err = "block must be 0, 64, 128 or 256"; return false; }
+    L.n_traj = d->n_traj;
+    L.esz = d->prec == SCP_F32 ? 4 : 8;
+    L.traj.assign((size_t)L.n_traj * TR_FIELDS, 0);
+    std::vector<int> traj_off(L.n_traj), horizon(L.n_traj);
+    long long off = 0;
+    for (int t = 0; t < L.n_traj; ++t) {
+        const int m = d->model[t], N = d->horizon[t];
+        if (!valid_model(m)) { err = "invalid model id at trajectory " + std::to_string(t); return false; }
+        if (N < 1 || N > SCP_MAX_N) { err = "horizon out of range at trajectory " + std::to_string(t); return false; }
+        const double* prm = d->params + (size_t)t * SCP_PARAM_STRIDE;
+        const double K = prm[SCP_P_NOBS];
+        if (m == SCP_MODEL_QUAD_PM && !(K >= 0 && K <= SCP_MAX_OBS && K == std::floor(K))) {
+            err = "obstacle count out of range at trajectory " + std::to_string(t);
+            return false;
+        }
+        if (!(prm[SCP_P_H] > 0) || !std::isfinite(prm[SCP_P_H])) { err = "step size must be positive"; return false; }
+        if (!(prm[SCP_P_DELTA] > 0)) { err = "trust radius must be positive"; return false; }
+        int* r = &L.traj[(size_t)t * TR_FIELDS];
+        r[TR_MODEL] = m;
+        r[TR_N] = N;
+        r[TR_OFF] = (int)off;
+        r[TR_K] = m == SCP_MODEL_QUAD_PM ? (int)K : 0;
+        r[TR_BALL] = (m == SCP_MODEL_QUAD_PM && std::isfinite(prm[SCP_P_UBALL])) ? 1 : 0;
+        r[TR_GFIRST] = t;
+        r[TR_GSIZE] = 1;
+        r[TR_MEMBER] = 0;
+        traj_off[t] = (int)off;
+        horizon[t] = N;
+        off += N + 1;
+        L.models |= (m == SCP_MODEL_QUAD_PM) ? 1 : 2;
+        L.kmax = std::max(L.kmax, r[TR_K]);
+        if (off > (1LL << 30)) { err = "too many nodes"; return false; }
+    }
+    L.n_nodes = (int)off;
+    L.P = (int)((off + 255) / 256 * 256);
+    // consensus groups
+    std::vector<Unit> units;
+    int t = 0;
+    while (t < L.n_traj) {
+        int e = t + 1;
+        const int gid = d->group ? d->group[t] : -1;
+        if (gid >= 0) {
+            while (e < L.n_traj && d->group[e] == gid) ++e;
+            for (int q = t; q < e; ++q) {
+                if (d->model[q] != d->model[t] || d->horizon[q] != d->horizon[t]) {
+                    err = "members of a consensus group must share model and horizon";
+                    return false;
+                }
+            }
+            for (int q = e; q < L.n_traj; ++q)
+                if (d->group[q] == gid) {
+                    err = "members of a consensus group must be consecutive";
+                    return false;
+                }
+        }
+        for (int q = t; q < e; ++q) {
+            int* r = &L.traj[(size_t)q * TR_FIELDS];
+            r[TR_GFIRST] = t;
+            r[TR_GSIZE] = e - t;
+            r[TR_MEMBER] = q - t;
+        }
+        if (e - t > 1) L.groups.push_back(t);
+        units.push_back({t, e - t, (e - t) * (horizon[t] + 1), d->model[t]});
+        t = e;
+    }
+    L.n_groups = (int)L.groups.size();
+    L.node_traj.assign(L.P, -1);
+    for (int q = 0; q < L.n_traj; ++q)
+        for (int i = 0; i <= horizon[q]; ++i) L.node_traj[traj_off[q] + i] = q;
+    // persistent-kernel packing: requested block, or the candidate with the fewest idle lanes
+    int max_unit = 0;
+    for (auto& u : units) max_unit = std::max(max_unit, u.lanes);
+    std::vector<int> cands = d->block ? std::vector<int>{d->block} : std::vector<int>{64, 128, 256};
+    if (d->prec == SCP_F64) cands.erase(std::remove(cands.begin(), cands.end(), 256), cands.end());
+    long best_idle = -1;
+    for (int b : cands) {
+        if (max_unit > b) continue;
+        std::vector<int> lane, wgm;
+        int nwg = 0;
+        if (!pack(units, traj_off, horizon, b, lane, wgm, nwg)) continue;
+        const long idle = (long)nwg * b - L.n_nodes;
+        if (best_idle < 0 || idle < best_idle) {
+            best_idle = idle;
+            L.block = b;
+            L.n_wg = nwg;
+            L.lane = lane;
+            L.lane.insert(L.lane.end(), wgm.begin(), wgm.end());
+        }
+    }
+    L.persistent_ok = best_idle >= 0;
+    if (!L.persistent_ok) {
+        L.block = 0;
+        L.n_wg = 0;
+        L.lane.assign(1, -1);
+    }
+    // arena
+    size_t o = 0;
+    L.o_traj = o; o = align_up(o + L.traj.size() * 4);
+    L.o_node_traj = o; o = align_up(o + (size_t)L.P * 4);
+    L.o_lane = o; o = align_up(o + L.lane.size() * 4);
+    L.o_groups = o; o = align_up(o + std::max<size_t>(1, L.groups.size()) * 4);
+    L.o_params = o; o = align_up(o + (size_t)L.n_traj * SCP_PARAM_STRIDE * L.esz);
+    L.o_planes = o; o = align_up(o + (size_t)NPLANES * L.P * L.esz);
+    L.o_rt = o; o = align_up(o + (size_t)L.n_traj * RT_FIELDS * L.esz);
+    L.o_info = o; o = align_up(o + (size_t)L.n_traj * SCP_INFO_FIELDS * 8);
+    L.o_flags = o; o = align_up(o + (size_t)L.n_traj * FL_FIELDS * 4);
+    L.o_red = o; o = align_up(o + (size_t)L.n_traj * 2 * 8);
+    L.total = o;
+    return true;
+}
+
+template <class T>
+Dev<T> make_dev(const Layout& L, char* base) {
+    Dev<T> dv;
+    dv.traj = reinterpret_cast<const int*>(base + L.o_traj);
+    dv.node_traj = reinterpret_cast<const int*>(base + L.o_node_traj);
+    dv.lane_node = reinterpret_cast<const int*>(base + L.o_lane);
+    dv.params = reinterpret_cast<const T*>(base + L.o_params);
+    dv.planes = reinterpret_cast<T*>(base + L.o_planes);
+    dv.rt = reinterpret_cast<T*>(base + L.o_rt);
+    dv.info = reinterpret_cast<double*>(base + L.o_info);
+    dv.flags = reinterpret_cast<int*>(base + L.o_flags);
+    dv.red = reinterpret_cast<unsigned long long*>(base + L.o_red);
+    dv.n_traj = L.n_traj;
+    dv.P = L.P;
+    dv.n_nodes = L.n_nodes;
+    dv.n_groups = L.n_groups;
+    dv.groups = reinterpret_cast<const int*>(base + L.o_groups);
+    return dv;
+}
+
+}  // namespace
+
+struct scp_problem {
+    Layout L;
+    scp_precision prec;
+    hipStream_t stream = nullptr;
+    char* arena = nullptr;
+    Dev<float> df;
+    Dev<double> dd;
+    bool linearized = false;
+    double lin_rho[3] = {1.0, 1.0, 1.0};
+    std::string err;
+};
+
+namespace {
+
+template <class T>
+KParams<T> kparams(const admm_params* a, const scp_params* s) {
+    KParams<T> k{};
+    k.rho_eq = T(a->rho_eq);
+    k.rho_dyn = T(a->rho_dyn);
+    k.rho_geo = T(a->rho_geo);
+    k.eps_p = T(a->eps_prim);
+    k.eps_d = T(a->eps_dual);
+    k.max_iters = a->max_iters;
+    k.check_every = a->check_every;
+    if (s) {
+        k.eta0 = T(s->eta0);
+        k.eta1 = T(s->eta1);
+        k.eta2 = T(s->eta2);
+        k.shrink = T(s->shrink);
+        k.grow = T(s->grow);
+        k.delta_max = T(s->delta_max);
+        k.merit_w = T(s->merit_w);
+    }
+    k.n_scp = 1;
+    return k;
+}
+
+scp_status fail(scp_problem* p, scp_status st, const std::string& msg) {
+    if (p) p->err = msg;
+    return st;
+}
+
+scp_status hip_check(scp_problem* p, hipError_t e, const char* what) {
+    if (e == hipSuccess) return SCP_OK;
+    return fail(p, SCP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool admm_valid(const admm_params* a, std::string& err) {
+    if (!a) { err = "admm params NULL"; return false; }
+    if (!(a->rho_eq > 0) || !(a->rho_dyn > 0) || !(a->rho_geo > 0)) { err = "penalties must be positive"; return false; }
+    if (a->max_iters < 0 || a->check_every < 0) { err = "iteration counts must be >= 0"; return false; }
+    return true;
+}
+
+template <class T>
+scp_status run_plain_admm(scp_problem* p, const Dev<T>& dv, const KParams<T>& kp) {
+    const Layout& L = p->L;
+    for (int j = 1; j <= kp.max_iters; ++j) {
+        const bool check = (kp.check_every > 0 && j % kp.check_every == 0) || j == kp.max_iters;
+        const int test = kp.check_every > 0 && j % kp.check_every == 0;
+        hipError_t e = launch_plain<T>(PlainOp::Step1, dv, kp, L.models, L.kmax, 0, j, p->stream);
+        if (e == hipSuccess) e = launch_plain<T>(PlainOp::Step234, dv, kp, L.models, L.kmax, check ? 1 : 0, j, p->stream);
+        if (e == hipSuccess && check) e = launch_plain<T>(PlainOp::Resid, dv, kp, L.models, L.kmax, test, j, p->stream);
+        if (e != hipSuccess) return hip_check(p, e, "ADMM kernel launch");
+    }
+    return SCP_OK;
+}
+
+template <class T>
+scp_status do_linearize(scp_problem* p, const admm_params* a) {
+    const Dev<T>& dv = *reinterpret_cast<const Dev<T>*>(p->prec == SCP_F32 ? (const void*)&p->df : (const void*)&p->dd);
+    KParams<T> kp = kparams<T>(a, nullptr);
+    hipError_t e = launch_plain<T>(PlainOp::Lin, dv, kp, p->L.models, p->L.kmax, 0, 0, p->stream);
+    return hip_check(p, e, "linearize launch");
+}
+
+template <class T>
+scp_status do_admm(scp_problem* p, const admm_params* a) {
+    const Dev<T>& dv = *reinterpret_cast<const Dev<T>*>(p->prec == SCP_F32 ? (const void*)&p->df : (const void*)&p->dd);
+    KParams<T> kp = kparams<T>(a, nullptr);
+    return run_plain_admm<T>(p, dv, kp);
+}
+
+template <class T>
+scp_status do_solve(scp_problem* p, const scp_params* s) {
+    const Dev<T>& dv = *reinterpret_cast<const Dev<T>*>(p->prec == SCP_F32 ? (const void*)&p->df : (const void*)&p->dd);
+    const Layout& L = p->L;
+    KParams<T> kp = kparams<T>(&s->admm, s);
+    kp.has_groups = L.n_groups > 0 ? 1 : 0;
+    hipError_t e = launch_plain<T>(PlainOp::Reset, dv, kp, L.models, L.kmax, 1, 0, p->stream);
+    if (e != hipSuccess) return hip_check(p, e, "reset launch");
+    if (s->form == SCP_FORM_PLAIN) {
+        for (int k = 0; k < s->scp_iters; ++k) {
+            e = launch_plain<T>(PlainOp::Lin, dv, kp, L.models, L.kmax, 0, 0, p->stream);
+            if (e != hipSuccess) return hip_check(p, e, "linearize launch");
+            scp_status st = run_plain_admm<T>(p, dv, kp);
+            if (st != SCP_OK) return st;
+            e = launch_plain<T>(PlainOp::Accept, dv, kp, L.models, L.kmax, 0, 0, p->stream);
+            if (e != hipSuccess) return hip_check(p, e, "accept launch");
+        }
+        e = launch_plain<T>(PlainOp::Metrics, dv, kp, L.models, L.kmax, 0, 0, p->stream);
+        return hip_check(p, e, "metrics launch");
+    }
+    if (!L.persistent_ok) return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory or consensus group exceeds 256 nodes; use the plain form");
+    const int per = s->scp_per_launch > 0 ? s->scp_per_launch : std::max(1, s->scp_iters);
+    int done = 0;
+    if (s->scp_iters == 0) {
+        kp.n_scp = 0;
+        kp.reset_info = 1;
+        kp.final_metrics = 1;
+        e = launch_persistent<T>(dv, kp, L.n_wg, L.block, L.models, L.kmax, p->stream);
+        return hip_check(p, e, "persistent launch");
+    }
+    while (done < s->scp_iters) {
+        const int n = std::min(per, s->scp_iters - done);
+        kp.n_scp = n;
+        kp.reset_info = done == 0 ? 1 : 0;
+        kp.final_metrics = (done + n == s->scp_iters) ? 1 : 0;
+        e = launch_persistent<T>(dv, kp, L.n_wg, L.block, L.models, L.kmax, p->stream);
+        if (e != hipSuccess) return hip_check(p, e, "persistent launch");
+        done += n;
+    }
+    return SCP_OK;
+}
+
+template <class T>
+void stage_problem(const scp_problem_desc* d, const Layout& L, std::vector<char>& img_params, std::vector<char>& img_nom,
+                   std::vector<char>& img_rt) {
+    img_params.assign((size_t)L.n_traj * SCP_PARAM_STRIDE * sizeof(T), 0);
+    T* prm = reinterpret_cast<T*>(img_params.data());
+    for (size_t k = 0; k < (size_t)L.n_traj * SCP_PARAM_STRIDE; ++k) prm[k] = T(d->params[k]);
+    // nominal planes XBAR (7) and UBAR (4): contiguous block of 11 planes
+    img_nom.assign((size_t)(SCP_MAX_NX + SCP_MAX_NU) * L.P * sizeof(T), 0);
+    T* nom = reinterpret_cast<T*>(img_nom.data());
+    long long xrow = 0, urow = 0;
+    for (int t = 0; t < L.n_traj; ++t) {
+        const int N = L.traj[(size_t)t * TR_FIELDS + TR_N], off = L.traj[(size_t)t * TR_FIELDS + TR_OFF];
+        for (int i = 0; i <= N; ++i, ++xrow)
+            for (int r = 0; r < SCP_MAX_NX; ++r) nom[(size_t)(PL_XBAR + r) * L.P + off + i] = T(d->x_guess[xrow * SCP_MAX_NX + r]);
+        for (int i = 0; i < N; ++i, ++urow)
+            for (int r = 0; r < SCP_MAX_NU; ++r) nom[(size_t)(PL_UBAR + r) * L.P + off + i] = T(d->u_guess[urow * SCP_MAX_NU + r]);
+    }
+    img_rt.assign((size_t)L.n_traj * RT_FIELDS * sizeof(T), 0);
+    T* rt = reinterpret_cast<T*>(img_rt.data());
+    for (int t = 0; t < L.n_traj; ++t) rt[t * RT_FIELDS + RT_DELTA] = T(d->params[(size_t)t * SCP_PARAM_STRIDE + SCP_P_DELTA]);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t scp_problem_device_bytes(const scp_problem_desc* desc) {
+    Layout L;
+    std::string err;
+    if (!build_layout(desc, L, err)) return 0;
+    return L.total;
+}
+
+scp_status scp_problem_create(const scp_problem_desc* desc, void* arena_dev, size_t arena_bytes, void* hip_stream,
+                              scp_problem** out) {
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "out is NULL";
+        return SCP_ERR_ARG;
+    }
+    *out = nullptr;
+    scp_problem* p = new (std::nothrow) scp_problem();
+    if (!p) {
+        g_create_error = "host allocation failed";
+        return SCP_ERR_NOMEM;
+    }
+    std::string err;
+    if (!build_layout(desc, p->L, err)) {
+        g_create_error = err;
+        delete p;
+        return SCP_ERR_ARG;
+    }
+    if (!arena_dev || arena_bytes < p->L.total || (reinterpret_cast<uintptr_t>(arena_dev) % kAlign) != 0) {
+        g_create_error = "arena missing, too small (need " + std::to_string(p->L.total) + " bytes) or not 256-byte aligned";
+        delete p;
+        return SCP_ERR_ARG;
+    }
+    p->prec = desc->prec;
+    p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    p->arena = reinterpret_cast<char*>(arena_dev);
+    const Layout& L = p->L;
+    std::vector<char> img_params, img_nom, img_rt;
+    if (p->prec == SCP_F32) stage_problem<float>(desc, L, img_params, img_nom, img_rt);
+    else stage_problem<double>(desc, L, img_params, img_nom, img_rt);
+    hipError_t e = hipMemsetAsync(p->arena, 0, L.total, p->stream);
+    auto cp = [&](size_t off, const void* src, size_t n) {
+        if (e == hipSuccess && n) e = hipMemcpyAsync(p->arena + off, src, n, hipMemcpyHostToDevice, p->stream);
+    };
+    cp(L.o_traj, L.traj.data(), L.traj.size() * 4);
+    cp(L.o_node_traj, L.node_traj.data(), L.node_traj.size() * 4);
+    cp(L.o_lane, L.lane.data(), L.lane.size() * 4);
+    if (!L.groups.empty()) cp(L.o_groups, L.groups.data(), L.groups.size() * 4);
+    cp(L.o_params, img_params.data(), img_params.size());
+    cp(L.o_planes, img_nom.data(), img_nom.size());
+    cp(L.o_rt, img_rt.data(), img_rt.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        g_create_error = std::string("upload failed: ") + hipGetErrorString(e);
+        delete p;
+        return SCP_ERR_HIP;
+    }
+    p->df = make_dev<float>(L, p->arena);
+    p->dd = make_dev<double>(L, p->arena);
+    *out = p;
+    return SCP_OK;
+}
+
+void scp_problem_destroy(scp_problem* p) { delete p; }
+
+scp_status scp_linearize(scp_problem* p, const admm_params* prm) {
+    if (!p) return SCP_ERR_ARG;
+    admm_params def{1.0, 1.0, 1.0, 0, 0, 0.0, 0.0};
+    const admm_params* a = prm ? prm : &def;
+    std::string err;
+    if (!admm_valid(a, err)) return fail(p, SCP_ERR_ARG, err);
+    scp_status st = p->prec == SCP_F32 ? do_linearize<float>(p, a) : do_linearize<double>(p, a);
+    if (st == SCP_OK) {
+        p->linearized = true;
+        p->lin_rho[0] = a->rho_eq;
+        p->lin_rho[1] = a->rho_dyn;
+        p->lin_rho[2] = a->rho_geo;
+    }
+    return st;
+}
+
+scp_status admm_solve(scp_problem* p, const admm_params* prm) {
+    if (!p) return SCP_ERR_ARG;
+    std::string err;
+    if (!admm_valid(prm, err)) return fail(p, SCP_ERR_ARG, err);
+    if (!p->linearized) return fail(p, SCP_ERR_STATE, "admm_solve before scp_linearize");
+    if (prm->rho_eq != p->lin_rho[0] || prm->rho_dyn != p->lin_rho[1] || prm->rho_geo != p->lin_rho[2])
+        return fail(p, SCP_ERR_ARG, "penalties differ from those the factors were built with");
+    return p->prec == SCP_F32 ? do_admm<float>(p, prm) : do_admm<double>(p, prm);
+}
+
+scp_status scp_solve(scp_problem* p, const scp_params* prm) {
+    if (!p) return SCP_ERR_ARG;
+    if (!prm) return fail(p, SCP_ERR_ARG, "scp params NULL");
+    std::string err;
+    if (!admm_valid(&prm->admm, err)) return fail(p, SCP_ERR_ARG, err);
+    if (prm->scp_iters < 0) return fail(p, SCP_ERR_ARG, "scp_iters must be >= 0");
+    if (prm->form != SCP_FORM_PLAIN && prm->form != SCP_FORM_PERSISTENT) return fail(p, SCP_ERR_ARG, "invalid form");
+    scp_status st = p->prec == SCP_F32 ? do_solve<float>(p, prm) : do_solve<double>(p, prm);
+    if (st == SCP_OK) {
+        p->linearized = false;
+    }
+    return st;
+}
+
+int32_t scp_field_width(int32_t field) {
+    switch (field) {
+        case SCP_FIELD_XBAR: case SCP_FIELD_X: case SCP_FIELD_Z: case SCP_FIELD_LAM: case SCP_FIELD_MU:
+        case SCP_FIELD_DDYN: case SCP_FIELD_D: return 7;
+        case SCP_FIELD_UBAR: case SCP_FIELD_U: return 4;
+        case SCP_FIELD_COPY: case SCP_FIELD_DUAL: return 36;
+        case SCP_FIELD_A: return 49;
+        case SCP_FIELD_B: return 28;
+        case SCP_FIELD_BOXLO: case SCP_FIELD_BOXHI: return 11;
+        case SCP_FIELD_HS: return 32;
+        default: return 0;
+    }
+}
+
+scp_status scp_get_field(const scp_problem* cp, int32_t field, void* dst_dev) {
+    scp_problem* p = const_cast<scp_problem*>(cp);
+    if (!p) return SCP_ERR_ARG;
+    const int w = scp_field_width(field);
+    if (!w || !dst_dev) return fail(p, SCP_ERR_ARG, "invalid field id or NULL destination");
+    int plane = 0, mode = 0;
+    switch (field) {
+        case SCP_FIELD_XBAR: plane = PL_XBAR; break;
+        case SCP_FIELD_UBAR: plane = PL_UBAR; break;
+        case SCP_FIELD_X: plane = PL_X; break;
+        case SCP_FIELD_U: plane = PL_U; break;
+        case SCP_FIELD_Z: plane = PL_Z; break;
+        case SCP_FIELD_LAM: plane = PL_LAM; break;
+        case SCP_FIELD_MU: plane = PL_MU; break;
+        case SCP_FIELD_DDYN: plane = PL_DD; break;
+        case SCP_FIELD_COPY: plane = PL_CP; break;
+        case SCP_FIELD_DUAL: plane = PL_DU; break;
+        case SCP_FIELD_A: plane = PL_AR; mode = 1; break;
+        case SCP_FIELD_B: plane = PL_B; mode = 2; break;
+        case SCP_FIELD_D: plane = PL_D; break;
+        case SCP_FIELD_BOXLO: plane = PL_LO; mode = 3; break;
+        case SCP_FIELD_BOXHI: plane = PL_HI; mode = 3; break;
+        case SCP_FIELD_HS: plane = PL_HS; break;
+    }
+    hipError_t e = p->prec == SCP_F32
+                       ? launch_gather<float>(p->df, plane, w, mode, reinterpret_cast<float*>(dst_dev), p->stream)
+                       : launch_gather<double>(p->dd, plane, w, mode, reinterpret_cast<double*>(dst_dev), p->stream);
+    return hip_check(p, e, "gather launch");
+}
+
+scp_status scp_get_result(const scp_problem* cp, void* x_dev, void* u_dev, void* info_dev) {
+    scp_problem* p = const_cast<scp_problem*>(cp);
+    if (!p) return SCP_ERR_ARG;
+    scp_status st = SCP_OK;
+    if (x_dev) st = scp_get_field(p, SCP_FIELD_XBAR, x_dev);
+    if (st == SCP_OK && u_dev) st = scp_get_field(p, SCP_FIELD_UBAR, u_dev);
+    if (st == SCP_OK && info_dev) {
+        hipError_t e = hipMemcpyAsync(info_dev, p->arena + p->L.o_info, (size_t)p->L.n_traj * SCP_INFO_FIELDS * 8,
+                                      hipMemcpyDeviceToDevice, p->stream);
+        st = hip_check(p, e, "info copy");
+    }
+    return st;
+}
+
+int64_t scp_problem_nodes(const scp_problem* p) { return p ? p->L.n_nodes : 0; }
+
+int64_t scp_traj_node_offset(const scp_problem* p, int32_t t) {
+    if (!p || t < 0 || t >= p->L.n_traj) return -1;
+    return p->L.traj[(size_t)t * TR_FIELDS + TR_OFF];
+}
+
+const char* scp_last_error(const scp_problem* p) {
+    if (!p) return g_create_error.c_str();
+    return p->err.c_str();
+}
+
+}  // extern "C"

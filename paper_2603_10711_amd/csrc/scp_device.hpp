@@ -1,0 +1,987 @@
+// Per-node device routines of the SCP + consensus-ADMM hot path (gfx950).
+//
+// Every routine works on one trajectory node held in registers: the caller (a plain-form kernel
+// that streams the node from HBM, or the persistent kernel that keeps it resident) owns the
+// storage.  Arrays are sized by compile-time model traits and indexed with compile-time
+// constants only (all loops are unrolled), so they live in VGPRs.
+//
+// Paper references (arXiv 2603.10711):
+//   dynamics + RK4            Sec. II eq. (ocp)
+//   linearization             Sec. III-A (A_i, B_i Jacobians of the discrete map, d_i residual)
+//   convex sets / trust box   Sec. III-A eq. (qp_subproblem), Sec. II prox-friendly sets
+//   Step 1 (H_i, Cholesky)    Sec. III-B.3 block formulas of H_i and the unpivoted factorization
+//   Step 2 (z average)        Sec. III-B.3 closed-form weighted average
+//   Step 3 (projections)      Sec. III-B.3 proximal step / clamp
+//   Step 4 (duals)            Sec. III-B.3 dual ascent
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/scp.h"
+
+namespace scp {
+
+// ------------------------------------------------------------------------------------------
+// model traits
+// ------------------------------------------------------------------------------------------
+// Mirror-copy layout (one copy with its own dual per constraint group):
+//   quadrotor       [x box: NX][u box: NU][ball: 3][half-space k: 3 each, k < KM]
+//   powered descent [x box: NX][u box: NU][glide cone on r: 3][SOC on (T, Gamma): 4]
+// The first three state components (position) never enter the dynamics of either model, so
+// the first three columns of A are the unit vectors e_0..e_2 exactly; only the other
+// NXR = NX - 3 columns are stored ("Ar").
+
+template <int KM_>
+struct Quad {
+    static constexpr int ID = SCP_MODEL_QUAD_PM;
+    static constexpr int NX = 6, NU = 3, NN = 9, NXR = 3, KM = KM_;
+    static constexpr int C_XBOX = 0, C_UBOX = 6, C_BALL = 9, C_HS = 12;
+    static constexpr int C = 12 + 3 * KM_;
+    static constexpr int NHS = KM_ > 0 ? 4 * KM_ : 1;
+};
+
+struct Mars {
+    static constexpr int ID = SCP_MODEL_MARS3DOF;
+    static constexpr int NX = 7, NU = 4, NN = 11, NXR = 4, KM = 0;
+    static constexpr int C_XBOX = 0, C_UBOX = 7, C_CONE = 11, C_SOC = 14;
+    static constexpr int C = 18;
+    static constexpr int NHS = 1;
+};
+
+template <class M>
+__host__ __device__ constexpr int NU_OF() { return M::NU; }
+
+template <class M>
+struct Dims {
+    static constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR;
+    static constexpr int NL = NN * (NN + 1) / 2;
+};
+
+__host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+template <class T>
+struct Rho {
+    T eq, dyn, geo, inv_geo, inv_sum;
+};
+
+// ------------------------------------------------------------------------------------------
+// scalar helpers (NaN-propagating max; the comparisons keep a NaN once it appears)
+// ------------------------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T nmax(T a, T b) { return (b > a || b != b) ? b : a; }
+template <class T>
+__device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+__device__ __forceinline__ float tsqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double tsqrt(double a) { return sqrt(a); }
+template <class T>
+__device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
+template <class T>
+__device__ __forceinline__ T tmaxv(T a, T b) { return b > a ? b : a; }
+
+// ------------------------------------------------------------------------------------------
+// continuous dynamics and their directional derivative (JVP)
+// ------------------------------------------------------------------------------------------
+// prm points at the trajectory's parameter record (SCP_P_* offsets) in the problem precision.
+
+template <class M, class T>
+__device__ __forceinline__ void f_cont(const T* __restrict__ prm, const T* x, const T* u, T* f) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        // p' = v, v' = u/m_s - g e3 - c ||v|| v
+        const T c = prm[SCP_P_DRAG], ms = prm[SCP_P_MSCALE], g = prm[SCP_P_GRAV];
+        const T nv = tsqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
+        f[0] = x[3]; f[1] = x[4]; f[2] = x[5];
+        f[3] = u[0] / ms - c * nv * x[3];
+        f[4] = u[1] / ms - c * nv * x[4];
+        f[5] = (u[2] / ms - g) - c * nv * x[5];
+    } else {
+        // r' = v, v' = T/m + g_vec, m' = -alpha Gamma
+        const T m = x[6];
+        f[0] = x[3]; f[1] = x[4]; f[2] = x[5];
+        f[3] = u[0] / m + prm[SCP_P_GVEC + 0];
+        f[4] = u[1] / m + prm[SCP_P_GVEC + 1];
+        f[5] = u[2] / m + prm[SCP_P_GVEC + 2];
+        f[6] = -prm[SCP_P_ALPHA] * u[3];
+    }
+}
+
+// df = (df/dx) dx + (df/du) du at (x, u)
+template <class M, class T>
+__device__ __forceinline__ void f_jvp(const T* __restrict__ prm, const T* x, const T* u, const T* dx,
+                                      const T* du, T* df) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        // d(c||v||v) = c (||v|| dv + v (v.dv)/||v||), zero at v = 0
+        const T c = prm[SCP_P_DRAG], ms = prm[SCP_P_MSCALE];
+        const T nv = tsqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
+        const T vdv = x[3] * dx[3] + x[4] * dx[4] + x[5] * dx[5];
+        const T q = nv > T(0) ? vdv / nv : T(0);
+        df[0] = dx[3]; df[1] = dx[4]; df[2] = dx[5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) df[3 + k] = du[k] / ms - c * (nv * dx[3 + k] + x[3 + k] * q);
+    } else {
+        const T m = x[6];
+        const T dm = dx[6];
+        df[0] = dx[3]; df[1] = dx[4]; df[2] = dx[5];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) df[3 + k] = du[k] / m - u[k] / (m * m) * dm;
+        df[6] = -prm[SCP_P_ALPHA] * du[3];
+    }
+}
+
+// RK4 step F(x, u) with zero-order-hold control.
+template <class M, class T>
+__device__ __forceinline__ void rk4(const T* __restrict__ prm, const T* x, const T* u, T* F) {
+    constexpr int NX = M::NX;
+    const T h = prm[SCP_P_H];
+    T k1[NX], k2[NX], k3[NX], k4[NX], xs[NX];
+    f_cont<M, T>(prm, x, u, k1);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) xs[r] = x[r] + T(0.5) * h * k1[r];
+    f_cont<M, T>(prm, xs, u, k2);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) xs[r] = x[r] + T(0.5) * h * k2[r];
+    f_cont<M, T>(prm, xs, u, k3);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) xs[r] = x[r] + h * k3[r];
+    f_cont<M, T>(prm, xs, u, k4);
+    const T h6 = h / T(6);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) F[r] = x[r] + h6 * (((k1[r] + T(2) * k2[r]) + T(2) * k3[r]) + k4[r]);
+}
+
+// Linearization of the RK4 map at (x, u): F, the non-unit columns Ar of A = dF/dx (columns
+// 3..NX-1), B = dF/du and d = F - A x - B u.  Forward-mode chain rule through the stages: for
+// every input direction e, s_j = J(x_j) (e + c_j s_{j-1}) with stage points x_j and
+// c = (0, h/2, h/2, h); the column is e + h/6 (s_1 + 2 s_2 + 2 s_3 + s_4).
+template <class M, class T>
+__device__ __forceinline__ void linearize(const T* __restrict__ prm, const T* x, const T* u, T* F,
+                                          T* Ar, T* B, T* d) {
+    constexpr int NX = M::NX, NU = M::NU, NXR = M::NXR;
+    const T h = prm[SCP_P_H];
+    T xs[4][NX], k[4][NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) xs[0][r] = x[r];
+    f_cont<M, T>(prm, xs[0], u, k[0]);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) xs[1][r] = x[r] + T(0.5) * h * k[0][r];
+    f_cont<M, T>(prm, xs[1], u, k[1]);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) xs[2][r] = x[r] + T(0.5) * h * k[1][r];
+    f_cont<M, T>(prm, xs[2], u, k[2]);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) xs[3][r] = x[r] + h * k[2][r];
+    f_cont<M, T>(prm, xs[3], u, k[3]);
+    const T h6 = h / T(6);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) F[r] = x[r] + h6 * (((k[0][r] + T(2) * k[1][r]) + T(2) * k[2][r]) + k[3][r]);
+
+#pragma unroll
+    for (int col = 3; col < NX + NU; ++col) {
+        T e[NX], eu[NU], s[4][NX], dx[NX];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) e[r] = (r == col) ? T(1) : T(0);
+#pragma unroll
+        for (int r = 0; r < NU; ++r) eu[r] = (NX + r == col) ? T(1) : T(0);
+        f_jvp<M, T>(prm, xs[0], u, e, eu, s[0]);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dx[r] = e[r] + T(0.5) * h * s[0][r];
+        f_jvp<M, T>(prm, xs[1], u, dx, eu, s[1]);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dx[r] = e[r] + T(0.5) * h * s[1][r];
+        f_jvp<M, T>(prm, xs[2], u, dx, eu, s[2]);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dx[r] = e[r] + h * s[2][r];
+        f_jvp<M, T>(prm, xs[3], u, dx, eu, s[3]);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+            const T v = e[r] + h6 * (((s[0][r] + T(2) * s[1][r]) + T(2) * s[2][r]) + s[3][r]);
+            if (col < NX) Ar[r * NXR + (col - 3)] = v;
+            else B[r * NU + (col - NX)] = v;
+        }
+    }
+    // d = F - A x - B u  (A x includes the unit columns)
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        T ax = (r < 3) ? x[r] : T(0);
+#pragma unroll
+        for (int c = 0; c < NXR; ++c) ax = ax + Ar[r * NXR + c] * x[3 + c];
+        T bu = T(0);
+#pragma unroll
+        for (int c = 0; c < NU; ++c) bu = bu + B[r * NU + c] * u[c];
+        d[r] = (F[r] - ax) - bu;
+    }
+}
+
+// y = A x  (A = [e_0 e_1 e_2 | Ar])
+template <class M, class T>
+__device__ __forceinline__ void a_mul(const T* Ar, const T* x, T* y) {
+    constexpr int NX = M::NX, NXR = M::NXR;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        T s = (r < 3) ? x[r] : T(0);
+#pragma unroll
+        for (int c = 0; c < NXR; ++c) s = s + Ar[r * NXR + c] * x[3 + c];
+        y[r] = s;
+    }
+}
+
+// y = A^T w
+template <class M, class T>
+__device__ __forceinline__ void at_mul(const T* Ar, const T* w, T* y) {
+    constexpr int NX = M::NX, NXR = M::NXR;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y[k] = w[k];
+#pragma unroll
+    for (int c = 0; c < NXR; ++c) {
+        T s = T(0);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) s = s + Ar[r * NXR + c] * w[r];
+        y[3 + c] = s;
+    }
+}
+
+// y = B^T w
+template <class M, class T>
+__device__ __forceinline__ void bt_mul(const T* B, const T* w, T* y) {
+    constexpr int NX = M::NX, NU = M::NU;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+        T s = T(0);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) s = s + B[r * NU + c] * w[r];
+        y[c] = s;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// projections (exact closed forms)
+// ------------------------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T clampv(T v, T lo, T hi) { return tmin(tmaxv(v, lo), hi); }
+
+// {y : a'y >= b}
+template <class T>
+__device__ __forceinline__ void proj_halfspace(const T* a, T b, T* v) {
+    const T av = (a[0] * v[0] + a[1] * v[1]) + a[2] * v[2];
+    const T aa = (a[0] * a[0] + a[1] * a[1]) + a[2] * a[2];
+    const T t = tmaxv(T(0), b - av) / aa;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = v[k] + t * a[k];
+}
+
+// {y : ||y|| <= r}, 3-vector
+template <class T>
+__device__ __forceinline__ void proj_ball3(T r, T* v) {
+    const T nv = tsqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    const T s = nv > r ? r / nv : T(1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = v[k] * s;
+}
+
+// {(y, s) : ||y|| <= kappa s}, y of length M-1
+template <int M, class T>
+__device__ __forceinline__ void proj_cone(T kappa, T* v) {
+    T yy = T(0);
+#pragma unroll
+    for (int k = 0; k < M - 1; ++k) yy = yy + v[k] * v[k];
+    const T ny = tsqrt(yy);
+    const T s = v[M - 1];
+    const bool inside = ny <= kappa * s;
+    const bool polar = !inside && (kappa * ny <= -s);
+    if (!inside) {
+        if (polar) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) v[k] = T(0);
+        } else {
+            const T c = (kappa * ny + s) / (T(1) + kappa * kappa);
+            const T f = c * kappa / ny;
+#pragma unroll
+            for (int k = 0; k < M - 1; ++k) v[k] = f * v[k];
+            v[M - 1] = c;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// node data
+// ------------------------------------------------------------------------------------------
+// Per-SCP-iteration constants of one node.
+template <class M, class T>
+struct NodeConst {
+    static constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NL = Dims<M>::NL;
+    T L[NL];        // packed lower Cholesky factor of H_i, diagonal slots hold 1/L_kk
+    T Ar[NX * NXR]; // non-unit columns of A_i (zero at node N)
+    T B[NX * NU];   // B_i (zero at node N)
+    T d[NX];        // d_i (zero at node N)
+    T lo[NN], hi[NN];   // box group bounds: x components then u components
+    T hs[M::NHS];   // quadrotor half-spaces: (a_x, a_y, a_z, b) per obstacle
+    T g0[NX];       // constant part of the Step-1 right-hand side: -q_i (x part)
+};
+
+// ADMM iterates of one node.
+template <class M, class T>
+struct NodeState {
+    static constexpr int NX = M::NX, NU = M::NU, C = M::C;
+    T x[NX], u[NU];
+    T z[NX], lam[NX], mu[NX];
+    T dd[NX];       // d_dyn,i = A_i x_i + B_i u_i + d_i
+    T cp[C], du[C]; // mirror copies and their duals (zero where the group is absent)
+};
+
+// Node identity inside its trajectory.
+struct NodeId {
+    int i, N, K;    // node index, horizon, obstacle count
+    bool ball;      // quadrotor ball group present
+    __device__ bool first() const { return i == 0; }
+    __device__ bool last() const { return i == N; }
+};
+
+// Group activity at a node: x box everywhere; u groups at i < N; half-spaces and the glide
+// cone at i >= 1.
+template <class M>
+__device__ __forceinline__ bool group_active(const NodeId& id, int g) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        if (g == 0) return true;                         // x box
+        if (g == 1) return !id.last();                   // u box
+        if (g == 2) return !id.last() && id.ball;        // ball
+        return !id.first() && (g - 3) < id.K;            // half-space g-3
+    } else {
+        if (g == 0) return true;
+        if (g == 1) return !id.last();
+        if (g == 2) return !id.first();                  // glide cone
+        return !id.last();                               // SOC
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a3: convexified sets
+// ------------------------------------------------------------------------------------------
+// Trust box [c - delta, c + delta] cut by the hard box [lh, hh]; an empty cut collapses onto
+// the hard-box point nearest the centre.  Returns true if the hard box itself is empty.
+template <class T>
+__device__ __forceinline__ bool trust_box(T c, T delta, T lh, T hh, T& lo, T& hi) {
+    T l = tmaxv(c - delta, lh);
+    T u = tmin(c + delta, hh);
+    if (l > u) {
+        const T p = tmin(tmaxv(c, lh), hh);
+        l = p;
+        u = p;
+    }
+    lo = l;
+    hi = u;
+    return lh > hh;
+}
+
+// Box bounds, half-spaces and g0 of one node.  ucenter: centre of the control trust box
+// (the nominal control, or the scenario mean at node 0 of a consensus group).
+template <class M, class T>
+__device__ __forceinline__ int convexify(const T* __restrict__ prm, const NodeId& id, const T* xbar,
+                                         const T* ucenter, T delta, NodeConst<M, T>& nc) {
+    constexpr int NX = M::NX, NU = M::NU;
+    int st = 0;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        T lo, hi;
+        if (trust_box(xbar[r], delta, prm[SCP_P_XLO + r], prm[SCP_P_XHI + r], lo, hi)) st |= SCP_ST_EMPTYSET;
+        if (id.first()) {
+            lo = prm[SCP_P_XINIT + r];
+            hi = lo;
+        }
+        if (id.last() && prm[SCP_P_TMASK + r] != T(0)) {
+            lo = prm[SCP_P_XTGT + r];
+            hi = lo;
+        }
+        nc.lo[r] = lo;
+        nc.hi[r] = hi;
+        nc.g0[r] = id.last() ? -prm[SCP_P_QNV + r] : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+        T lo, hi;
+        if (trust_box(ucenter[r], delta, prm[SCP_P_ULO + r], prm[SCP_P_UHI + r], lo, hi)) st |= SCP_ST_EMPTYSET;
+        nc.lo[NX + r] = id.last() ? T(0) : lo;
+        nc.hi[NX + r] = id.last() ? T(0) : hi;
+    }
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+#pragma unroll
+        for (int j = 0; j < M::KM; ++j) {
+            T a0 = T(0), a1 = T(0), a2 = T(0), b = T(0);
+            if (j < id.K && !id.first()) {
+                const T* o = prm + SCP_P_OBS + 4 * j;
+                const T d0 = xbar[0] - o[0], d1 = xbar[1] - o[1], d2 = xbar[2] - o[2];
+                const T nd = tsqrt((d0 * d0 + d1 * d1) + d2 * d2);
+                if (nd >= T(1e-9)) {
+                    a0 = d0 / nd; a1 = d1 / nd; a2 = d2 / nd;
+                } else {
+                    a2 = T(1);
+                }
+                b = o[3] + ((a0 * o[0] + a1 * o[1]) + a2 * o[2]);
+            }
+            nc.hs[4 * j + 0] = a0;
+            nc.hs[4 * j + 1] = a1;
+            nc.hs[4 * j + 2] = a2;
+            nc.hs[4 * j + 3] = b;
+        }
+    }
+    return st;
+}
+
+// number of groups covering each component (D_x, D_u of the Step-1 Hessian)
+template <class M, class T>
+__device__ __forceinline__ void group_counts(const NodeId& id, T* Dx, T* Du) {
+    constexpr int NX = M::NX, NU = M::NU;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) Dx[r] = T(1);
+#pragma unroll
+    for (int r = 0; r < NU; ++r) Du[r] = T(1);
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        if (!id.first()) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Dx[r] = Dx[r] + T(id.K);
+        }
+        if (id.ball) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Du[r] = Du[r] + T(1);
+        }
+    } else {
+        if (!id.first()) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Dx[r] = Dx[r] + T(1);
+        }
+#pragma unroll
+        for (int r = 0; r < NU; ++r) Du[r] = Du[r] + T(1);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a4: Step-1 Hessian and its unpivoted Cholesky factor
+// ------------------------------------------------------------------------------------------
+// H11 = Q_i + rho_eq 1{i>0} I + rho_geo D_x + rho_dyn A'A
+// H12 = rho_dyn A'B  (no cross cost term for the models here)
+// H22 = R + rho_geo D_u + rho_dyn B'B  (i < N);  at node N the control block is I (unused).
+// Returns SCP_ST_BADPIVOT if a pivot is not positive (the pivot is then replaced by 1 so the
+// node stays finite; the status bit marks the trajectory).
+template <class M, class T>
+__device__ __forceinline__ int assemble_factor(const T* __restrict__ prm, const NodeId& id, const Rho<T>& rho,
+                                               NodeConst<M, T>& nc) {
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR;
+    T Dx[NX], Du[NU];
+    group_counts<M, T>(id, Dx, Du);
+    const T rdyn = id.last() ? T(0) : rho.dyn;
+    T* H = nc.L;  // factor in place
+    // A'A, A'B, B'B with A = [E | Ar]
+#pragma unroll
+    for (int r = 0; r < NN; ++r) {
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            T p = T(0);
+            if (r < NX && c < NX) {
+                // (A'A)_{rc}
+                if (r < 3 && c < 3) {
+                    p = (r == c) ? T(1) : T(0);
+                } else if (c < 3) {
+                    p = nc.Ar[c * NXR + (r - 3)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) p = p + nc.Ar[k * NXR + (r - 3)] * nc.Ar[k * NXR + (c - 3)];
+                }
+            } else if (r >= NX && c < NX) {
+                // (A'B)_{c, r-NX}
+                if (c < 3) {
+                    p = nc.B[c * NU + (r - NX)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) p = p + nc.Ar[k * NXR + (c - 3)] * nc.B[k * NU + (r - NX)];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NX; ++k) p = p + nc.B[k * NU + (r - NX)] * nc.B[k * NU + (c - NX)];
+            }
+            T v;
+            if (r == c) {
+                if (r < NX) {
+                    const T q = id.last() ? prm[SCP_P_QN + r] : prm[SCP_P_QR + r];
+                    v = ((q + (id.first() ? T(0) : rho.eq)) + rho.geo * Dx[r]) + rdyn * p;
+                } else if (id.last()) {
+                    v = T(1);
+                } else {
+                    v = (prm[SCP_P_R + (r - NX)] + rho.geo * Du[r - NX]) + rdyn * p;
+                }
+            } else {
+                v = (r >= NX && id.last()) ? T(0) : rdyn * p;
+            }
+            H[tri(r, c)] = v;
+        }
+    }
+    int st = 0;
+#pragma unroll
+    for (int c = 0; c < NN; ++c) {
+        T s = H[tri(c, c)];
+#pragma unroll
+        for (int k = 0; k < c; ++k) s = s - H[tri(c, k)] * H[tri(c, k)];
+        if (!(s > T(0))) {
+            st |= SCP_ST_BADPIVOT;
+            s = T(1);
+        }
+        const T inv = T(1) / tsqrt(s);
+        H[tri(c, c)] = inv;
+#pragma unroll
+        for (int r = c + 1; r < NN; ++r) {
+            T a = H[tri(r, c)];
+#pragma unroll
+            for (int k = 0; k < c; ++k) a = a - H[tri(r, k)] * H[tri(c, k)];
+            H[tri(r, c)] = a * inv;
+        }
+    }
+    return st;
+}
+
+// Solve L L' xi = g in place (forward then backward substitution).
+template <class M, class T>
+__device__ __forceinline__ void chol_solve(const T* L, T* g) {
+    constexpr int NN = M::NN;
+#pragma unroll
+    for (int r = 0; r < NN; ++r) {
+        T s = g[r];
+#pragma unroll
+        for (int k = 0; k < r; ++k) s = s - L[tri(r, k)] * g[k];
+        g[r] = s * L[tri(r, r)];
+    }
+#pragma unroll
+    for (int r = NN - 1; r >= 0; --r) {
+        T s = g[r];
+#pragma unroll
+        for (int k = r + 1; k < NN; ++k) s = s - L[tri(k, r)] * g[k];
+        g[r] = s * L[tri(r, r)];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a5: Step 1 (physical layer)
+// ------------------------------------------------------------------------------------------
+// g_x = -q_i + 1{i>0}(rho_eq z_i - lambda_i) + 1{i<N} A_i' w_i + sum_g (rho_geo xhat^g - nu_x^g)
+// g_u =         1{i<N} B_i' w_i + sum_g (rho_geo uhat^g - nu_u^g),  w_i = mu_{i+1} + rho_dyn (z_{i+1} - d_i)
+// then x, u from the cached factor and d_dyn,i = A_i x_i + B_i u_i + d_i.
+// Absent groups hold exactly zero copies and duals, so summing over all slots is exact.
+template <class M, class T>
+__device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
+                                      NodeState<M, T>& s, const T* znext, const T* munext) {
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN;
+    T w[NX], g[NN], tx[NX], tu[NU];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) w[r] = id.last() ? T(0) : munext[r] + rho.dyn * (znext[r] - nc.d[r]);
+    at_mul<M, T>(nc.Ar, w, tx);
+    bt_mul<M, T>(nc.B, w, tu);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        T v = nc.g0[r];
+        if (!id.first()) v = v + (rho.eq * s.z[r] - s.lam[r]);
+        if (!id.last()) v = v + tx[r];
+        g[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) g[NX + r] = id.last() ? T(0) : tu[r];
+    // mirror terms, group order
+#pragma unroll
+    for (int r = 0; r < NX; ++r) g[r] = g[r] + (rho.geo * s.cp[M::C_XBOX + r] - s.du[M::C_XBOX + r]);
+#pragma unroll
+    for (int r = 0; r < NU; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_UBOX + r] - s.du[M::C_UBOX + r]);
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_BALL + r] - s.du[M::C_BALL + r]);
+#pragma unroll
+        for (int j = 0; j < M::KM; ++j)
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                g[r] = g[r] + (rho.geo * s.cp[M::C_HS + 3 * j + r] - s.du[M::C_HS + 3 * j + r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) g[r] = g[r] + (rho.geo * s.cp[M::C_CONE + r] - s.du[M::C_CONE + r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_SOC + r] - s.du[M::C_SOC + r]);
+    }
+    chol_solve<M, T>(nc.L, g);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s.x[r] = g[r];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) s.u[r] = id.last() ? T(0) : g[NX + r];
+    T ax[NX];
+    a_mul<M, T>(nc.Ar, s.x, ax);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        T bu = T(0);
+#pragma unroll
+        for (int c = 0; c < NU; ++c) bu = bu + nc.B[r * NU + c] * s.u[c];
+        s.dd[r] = id.last() ? T(0) : (ax[r] + bu) + nc.d[r];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a6: Step 2 (dynamic layer), i >= 1
+// ------------------------------------------------------------------------------------------
+template <class M, class T>
+__device__ __forceinline__ void step2(const NodeId& id, const Rho<T>& rho, NodeState<M, T>& s, const T* ddprev) {
+    if (id.first()) return;
+#pragma unroll
+    for (int r = 0; r < M::NX; ++r)
+        s.z[r] = (((rho.eq * s.x[r] + s.lam[r]) + rho.dyn * ddprev[r]) - s.mu[r]) * rho.inv_sum;
+}
+
+// ------------------------------------------------------------------------------------------
+// a7: Step 3 (geometric layer): copy^g = projection of (var^g + nu^g / rho_geo)
+// ------------------------------------------------------------------------------------------
+// The u copies at node 0 of a consensus group are averaged afterwards by the caller.
+template <class M, class T>
+__device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
+                                      NodeState<M, T>& s, T ball_r, T kappa) {
+    constexpr int NX = M::NX, NU = M::NU;
+    // x box
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+        s.cp[M::C_XBOX + r] = clampv(s.x[r] + s.du[M::C_XBOX + r] * rho.inv_geo, nc.lo[r], nc.hi[r]);
+    // u box
+    {
+        const bool act = !id.last();
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            const T v = clampv(s.u[r] + s.du[M::C_UBOX + r] * rho.inv_geo, nc.lo[NX + r], nc.hi[NX + r]);
+            s.cp[M::C_UBOX + r] = act ? v : T(0);
+        }
+    }
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        {
+            T v[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[r] = s.u[r] + s.du[M::C_BALL + r] * rho.inv_geo;
+            proj_ball3(ball_r, v);
+            const bool act = !id.last() && id.ball;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_BALL + r] = act ? v[r] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < M::KM; ++j) {
+            T v[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[r] = s.x[r] + s.du[M::C_HS + 3 * j + r] * rho.inv_geo;
+            proj_halfspace(&nc.hs[4 * j], nc.hs[4 * j + 3], v);
+            const bool act = !id.first() && j < id.K;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_HS + 3 * j + r] = act ? v[r] : T(0);
+        }
+    } else {
+        {
+            T v[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[r] = s.x[r] + s.du[M::C_CONE + r] * rho.inv_geo;
+            proj_cone<3>(kappa, v);
+            const bool act = !id.first();
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_CONE + r] = act ? v[r] : T(0);
+        }
+        {
+            T v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = s.u[r] + s.du[M::C_SOC + r] * rho.inv_geo;
+            proj_cone<4>(T(1), v);
+            const bool act = !id.last();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s.cp[M::C_SOC + r] = act ? v[r] : T(0);
+        }
+    }
+}
+
+// variable component feeding mirror slot k (x or u), and the group of slot k
+template <class M>
+__device__ __forceinline__ constexpr int slot_group(int k) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        return k < M::C_UBOX ? 0 : k < M::C_BALL ? 1 : k < M::C_HS ? 2 : 3 + (k - M::C_HS) / 3;
+    } else {
+        return k < M::C_UBOX ? 0 : k < M::C_CONE ? 1 : k < M::C_SOC ? 2 : 3;
+    }
+}
+template <class M>
+__device__ __forceinline__ constexpr bool slot_is_u(int k) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        return k >= M::C_UBOX && k < M::C_HS;
+    } else {
+        return (k >= M::C_UBOX && k < M::C_CONE) || k >= M::C_SOC;
+    }
+}
+template <class M>
+__device__ __forceinline__ constexpr int slot_comp(int k) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        return k < M::C_UBOX ? k : k < M::C_BALL ? k - M::C_UBOX : k < M::C_HS ? k - M::C_BALL : (k - M::C_HS) % 3;
+    } else {
+        return k < M::C_UBOX ? k : k < M::C_CONE ? k - M::C_UBOX : k < M::C_SOC ? k - M::C_CONE : k - M::C_SOC;
+    }
+}
+
+template <class M, class T>
+__device__ __forceinline__ T slot_var(const NodeState<M, T>& s, int k) {
+    return slot_is_u<M>(k) ? s.u[slot_comp<M>(k)] : s.x[slot_comp<M>(k)];
+}
+
+// ------------------------------------------------------------------------------------------
+// a8: Step 4 (dual ascent)
+// ------------------------------------------------------------------------------------------
+template <class M, class T>
+__device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeState<M, T>& s, const T* ddprev) {
+    if (!id.first()) {
+#pragma unroll
+        for (int r = 0; r < M::NX; ++r) {
+            s.lam[r] = s.lam[r] + rho.eq * (s.x[r] - s.z[r]);
+            s.mu[r] = s.mu[r] + rho.dyn * (s.z[r] - ddprev[r]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) {
+        const bool act = group_active<M>(id, slot_group<M>(k));
+        const T v = s.du[k] + rho.geo * (slot_var<M, T>(s, k) - s.cp[k]);
+        s.du[k] = act ? v : T(0);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a9: residual pieces
+// ------------------------------------------------------------------------------------------
+// primal: max |x - z|, |z - d_dyn,i-1| (i >= 1), |var - copy| (active groups)
+template <class M, class T>
+__device__ __forceinline__ T primal_res(const NodeId& id, const NodeState<M, T>& s, const T* ddprev) {
+    T m = T(0);
+    if (!id.first()) {
+#pragma unroll
+        for (int r = 0; r < M::NX; ++r) {
+            m = nmax(m, tabs(s.x[r] - s.z[r]));
+            m = nmax(m, tabs(s.z[r] - ddprev[r]));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) {
+        if (group_active<M>(id, slot_group<M>(k))) m = nmax(m, tabs(slot_var<M, T>(s, k) - s.cp[k]));
+    }
+    return m;
+}
+
+// dual: max |s_i| with s_x = rho_eq dz_i + rho_dyn A'dz_{i+1} + rho_geo sum dxhat,
+//                      s_u = rho_dyn B'dz_{i+1} + rho_geo sum duhat
+// dcp holds copy - copy_old per slot; dz = z - z_old of this node; dznext of node i+1.
+template <class M, class T>
+__device__ __forceinline__ T dual_res(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
+                                      const T* dz, const T* dznext, const T* dcp) {
+    constexpr int NX = M::NX, NU = M::NU;
+    T sx[NX], su[NU], tx[NX], tu[NU];
+    T w[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) w[r] = id.last() ? T(0) : dznext[r];
+    at_mul<M, T>(nc.Ar, w, tx);
+    bt_mul<M, T>(nc.B, w, tu);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        T v = T(0);
+        if (!id.first()) v = v + rho.eq * dz[r];
+        if (!id.last()) v = v + rho.dyn * tx[r];
+        sx[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) su[r] = id.last() ? T(0) : rho.dyn * tu[r];
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) {
+        if (!group_active<M>(id, slot_group<M>(k))) continue;
+        const T v = rho.geo * dcp[k];
+        if (slot_is_u<M>(k)) su[slot_comp<M>(k)] = su[slot_comp<M>(k)] + v;
+        else sx[slot_comp<M>(k)] = sx[slot_comp<M>(k)] + v;
+    }
+    T m = T(0);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) m = nmax(m, tabs(sx[r]));
+    if (!id.last()) {
+#pragma unroll
+        for (int r = 0; r < NU; ++r) m = nmax(m, tabs(su[r]));
+    }
+    return m;
+}
+
+// index of slot k among the u slots (scratch addressing)
+template <class M>
+__device__ __forceinline__ constexpr int slot_comp_u(int k) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        return k - M::C_UBOX;   // ubox 0..2, ball 3..5
+    } else {
+        return k < M::C_CONE ? k - M::C_UBOX : NU_OF<M>() + (k - M::C_SOC);
+    }
+}
+
+// node-local part of the dual-residual vector: x part rho_eq dz (i >= 1) + rho_geo sum dxhat,
+// u part rho_geo sum duhat (active groups, slot order).  skip_u: leave the u slots out (node 0
+// of a consensus group, finished after the scenario average).
+template <class M, class T>
+__device__ __forceinline__ void dual_res_own(const NodeId& id, const Rho<T>& rho, const T* dz, const T* dcp, T* sp,
+                                             bool skip_u) {
+    constexpr int NX = M::NX, NU = M::NU;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) sp[r] = id.first() ? T(0) : rho.eq * dz[r];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) sp[NX + r] = T(0);
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) {
+        if (!group_active<M>(id, slot_group<M>(k))) continue;
+        if (slot_is_u<M>(k)) {
+            if (!skip_u) sp[NX + slot_comp<M>(k)] = sp[NX + slot_comp<M>(k)] + rho.geo * dcp[k];
+        } else {
+            sp[slot_comp<M>(k)] = sp[slot_comp<M>(k)] + rho.geo * dcp[k];
+        }
+    }
+}
+
+// add the neighbour term rho_dyn [A B]' dz_{i+1} and return the inf-norm
+template <class M, class T>
+__device__ __forceinline__ T dual_res_finish(const NodeId& id, const Rho<T>& rho, const T* Ar, const T* B, const T* sp,
+                                             const T* dznext) {
+    constexpr int NX = M::NX, NU = M::NU;
+    T w[NX], tx[NX], tu[NU];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) w[r] = id.last() ? T(0) : dznext[r];
+    at_mul<M, T>(Ar, w, tx);
+    bt_mul<M, T>(B, w, tu);
+    T m = T(0);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) m = nmax(m, tabs(id.last() ? sp[r] : sp[r] + rho.dyn * tx[r]));
+    if (!id.last()) {
+#pragma unroll
+        for (int r = 0; r < NU; ++r) m = nmax(m, tabs(sp[NX + r] + rho.dyn * tu[r]));
+    }
+    return m;
+}
+
+// primal residual without the u slots (node 0 of a consensus group)
+template <class M, class T>
+__device__ __forceinline__ T primal_res_skip_u(const NodeId& id, const NodeState<M, T>& s, const T* ddprev) {
+    T m = T(0);
+    if (!id.first()) {
+#pragma unroll
+        for (int r = 0; r < M::NX; ++r) {
+            m = nmax(m, tabs(s.x[r] - s.z[r]));
+            m = nmax(m, tabs(s.z[r] - ddprev[r]));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) {
+        if (slot_is_u<M>(k)) continue;
+        if (group_active<M>(id, slot_group<M>(k))) m = nmax(m, tabs(slot_var<M, T>(s, k) - s.cp[k]));
+    }
+    return m;
+}
+
+// order-preserving bit pattern of a non-negative residual (NaN sorts above every number)
+template <class T>
+__device__ __forceinline__ unsigned long long res_bits(T v) {
+    return (unsigned long long)__double_as_longlong((double)v);
+}
+__device__ __forceinline__ double bits_res(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// trust-region ratio test on the merit (reading of the omitted update logic, Sec. III-A)
+template <class T>
+struct AcceptOut {
+    bool accept, nonfinite;
+    T ratio, delta;
+};
+
+template <class T>
+__device__ __forceinline__ AcceptOut<T> accept_rule(T eta0, T eta1, T eta2, T shrink, T grow, T dmax, T mnom, T mnew,
+                                                    T mmod, T delta) {
+    AcceptOut<T> a;
+    const T actual = mnom - mnew;
+    const T pred = mnom - mmod;
+    T ratio = pred > T(0) ? actual / pred : -T(INFINITY);
+    a.nonfinite = !(__builtin_isfinite(mnew) && __builtin_isfinite(mmod));
+    if (a.nonfinite) ratio = T(NAN);
+    a.accept = ratio >= eta0;
+    if (ratio < eta1) delta = delta * shrink;
+    else if (ratio > eta2) delta = tmin(delta * grow, dmax);
+    a.ratio = ratio;
+    a.delta = delta;
+    return a;
+}
+
+// ------------------------------------------------------------------------------------------
+// a10: merit terms and metrics of one node
+// ------------------------------------------------------------------------------------------
+// running/terminal cost of one node: 0.5 x'Qr x + 0.5 u'R u (i < N) or 0.5 x'Qn x + qn'x + cN
+template <class M, class T>
+__device__ __forceinline__ T node_cost(const T* __restrict__ prm, const NodeId& id, const T* x, const T* u) {
+    constexpr int NX = M::NX, NU = M::NU;
+    if (id.last()) {
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) a = a + x[r] * (prm[SCP_P_QN + r] * x[r]);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) b = b + prm[SCP_P_QNV + r] * x[r];
+        return (T(0.5) * a + b) + prm[SCP_P_CN];
+    }
+    T a = T(0), b = T(0);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) a = a + x[r] * (prm[SCP_P_QR + r] * x[r]);
+#pragma unroll
+    for (int r = 0; r < NU; ++r) b = b + u[r] * (prm[SCP_P_R + r] * u[r]);
+    return T(0.5) * a + T(0.5) * b;
+}
+
+// max violation of the hard constraints at one node (oracle's definition)
+template <class M, class T>
+__device__ __forceinline__ T node_violation(const T* __restrict__ prm, const NodeId& id, const T* x, const T* u) {
+    constexpr int NX = M::NX, NU = M::NU;
+    T v = T(0);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        v = nmax(v, prm[SCP_P_XLO + r] - x[r]);
+        v = nmax(v, x[r] - prm[SCP_P_XHI + r]);
+    }
+    if (!id.last()) {
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            v = nmax(v, prm[SCP_P_ULO + r] - u[r]);
+            v = nmax(v, u[r] - prm[SCP_P_UHI + r]);
+        }
+    }
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        if (!id.last() && id.ball) {
+            const T nu = tsqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+            v = nmax(v, nu - prm[SCP_P_UBALL]);
+        }
+        if (!id.first()) {
+            for (int j = 0; j < id.K; ++j) {
+                const T* o = prm + SCP_P_OBS + 4 * j;
+                const T d0 = x[0] - o[0], d1 = x[1] - o[1], d2 = x[2] - o[2];
+                v = nmax(v, o[3] - tsqrt((d0 * d0 + d1 * d1) + d2 * d2));
+            }
+        }
+    } else {
+        if (!id.last()) {
+            const T nt = tsqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+            v = nmax(v, nt - u[3]);
+        }
+        if (!id.first()) {
+            const T rxy = tsqrt(x[0] * x[0] + x[1] * x[1]);
+            v = nmax(v, rxy - prm[SCP_P_GLIDE] * x[2]);
+        }
+    }
+    return v;
+}
+
+// boundary error at one node
+template <class M, class T>
+__device__ __forceinline__ T node_bnd_err(const T* __restrict__ prm, const NodeId& id, const T* x) {
+    T e = T(0);
+    if (id.first()) {
+#pragma unroll
+        for (int r = 0; r < M::NX; ++r) e = nmax(e, tabs(x[r] - prm[SCP_P_XINIT + r]));
+    }
+    if (id.last()) {
+#pragma unroll
+        for (int r = 0; r < M::NX; ++r)
+            if (prm[SCP_P_TMASK + r] != T(0)) e = nmax(e, tabs(x[r] - prm[SCP_P_XTGT + r]));
+    }
+    return e;
+}
+
+}  // namespace scp

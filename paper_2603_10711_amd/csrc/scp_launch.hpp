@@ -1,0 +1,26 @@
+// Host-side launchers of the kernels (defined next to the kernels, called by the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "scp_layout.hpp"
+
+namespace scp {
+
+enum class PlainOp { Lin, Step1, Step234, Resid, Accept, Metrics, Reset };
+
+// models: bit 0 quadrotor present, bit 1 powered descent present; kmax: largest obstacle count.
+template <class T>
+hipError_t launch_plain(PlainOp op, const Dev<T>& dv, const KParams<T>& kp, int models, int kmax, int check, int j,
+                        hipStream_t s);
+
+template <class T>
+hipError_t launch_gather(const Dev<T>& dv, int plane, int width, int mode, T* out, hipStream_t s);
+
+// Persistent form: one workgroup per entry of the lane table, n_wg workgroups of `block`
+// lanes.  Runs kp.n_scp SCP iterations.
+template <class T>
+hipError_t launch_persistent(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int block, int models, int kmax,
+                             hipStream_t s);
+
+}  // namespace scp

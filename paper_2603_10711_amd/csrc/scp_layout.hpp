@@ -1,0 +1,84 @@
+// Arena layout shared by the host API and the kernels.
+//
+// Node data is stored component-plane major ("SoA"): value k of node g lives at
+// planes[k * P + g], P = node count padded to a multiple of 256, so consecutive lanes of a
+// wavefront touch consecutive addresses.  Plane blocks are sized for the largest model
+// (nx = 7, nu = 4, 36 mirror slots); smaller models use a prefix of each block.
+#pragma once
+
+#include <stdint.h>
+
+namespace scp {
+
+enum Plane : int {
+    PL_XBAR = 0,     // 7  nominal state
+    PL_UBAR = 7,     // 4  nominal control (row N zero)
+    PL_X = 11,       // 7  physical state
+    PL_U = 18,       // 4  physical control
+    PL_Z = 22,       // 7  dynamic auxiliary z
+    PL_LAM = 29,     // 7  lambda
+    PL_MU = 36,      // 7  mu
+    PL_DD = 43,      // 7  d_dyn = A x + B u + d
+    PL_CP = 50,      // 36 mirror copies
+    PL_DU = 86,      // 36 mirror duals
+    PL_AR = 122,     // 28 non-unit columns of A (row-major NX x NXR)
+    PL_B = 150,      // 28 B (row-major NX x NU)
+    PL_D = 178,      // 7  d
+    PL_L = 185,      // 66 packed Cholesky factor (diagonal slots hold reciprocals)
+    PL_LO = 251,     // 11 box lower bounds (x then u)
+    PL_HI = 262,     // 11 box upper bounds
+    PL_HS = 273,     // 32 half-spaces (a_x, a_y, a_z, b) per obstacle
+    PL_G0 = 305,     // 7  constant Step-1 right-hand side (x part)
+    PL_DZ = 312,     // 7  z - z_old (residual iterations)
+    PL_SP = 319,     // 11 node-local part of the dual residual vector
+    PL_RP = 330,     // 1  node primal residual
+    PL_MER = 331,    // 8  merit / metric terms of one node
+    NPLANES = 339
+};
+
+// merit / metric term slots inside PL_MER
+enum : int { MER_COST_NOM = 0, MER_PEN_NOM = 1, MER_COST_NEW = 2, MER_PEN_NEW = 3, MER_PEN_MOD = 4,
+             MER_DEFECT = 5, MER_VIOL = 6, MER_BND = 7 };
+
+// per-trajectory integer record
+enum : int { TR_MODEL = 0, TR_N = 1, TR_OFF = 2, TR_GFIRST = 3, TR_GSIZE = 4, TR_K = 5, TR_BALL = 6,
+             TR_MEMBER = 7, TR_FIELDS = 8 };
+
+// per-trajectory runtime values (problem precision)
+enum : int { RT_DELTA = 0, RT_FIELDS = 2 };
+
+// per-trajectory integer flags
+enum : int { FL_DONE = 0, FL_ITERS = 1, FL_ACCEPT = 2, FL_STATUS = 3, FL_FIELDS = 4 };
+
+template <class T>
+struct Dev {
+    const int* traj;       // [n_traj * TR_FIELDS]
+    const int* node_traj;  // [P] trajectory of each node, -1 for padding
+    const int* lane_node;  // [n_wg * block] node of each persistent-kernel lane, -1 idle
+    const T* params;       // [n_traj * SCP_PARAM_STRIDE]
+    T* planes;             // [NPLANES * P]
+    T* rt;                 // [n_traj * RT_FIELDS]
+    double* info;          // [n_traj * SCP_INFO_FIELDS]
+    int* flags;            // [n_traj * FL_FIELDS]
+    unsigned long long* red;  // [n_traj * 2] atomic max slots (r_p, r_d as double bit patterns)
+    int n_traj;
+    int P;
+    int n_nodes;
+    int n_groups;          // number of consensus groups with more than one member
+    const int* groups;     // [n_groups] first trajectory of each such group
+};
+
+template <class T>
+struct KParams {
+    T rho_eq, rho_dyn, rho_geo;
+    T eps_p, eps_d;
+    T eta0, eta1, eta2, shrink, grow, delta_max, merit_w;
+    int max_iters, check_every;
+    int n_scp;        // SCP iterations this launch (persistent form)
+    int final_metrics;
+    int reset_info;
+    int has_groups;
+    int iter_base;    // plain form: index of the first ADMM iteration of this launch batch
+};
+
+}  // namespace scp

@@ -1,0 +1,636 @@
+// Plain form of the hot path: one thread per node, every array in HBM, one kernel launch per
+// ADMM phase.  This is the comparison baseline for the persistent kernel and the path behind
+// the scp_linearize / admm_solve entry points.
+#include "scp_device.hpp"
+#include "scp_launch.hpp"
+#include "scp_layout.hpp"
+
+namespace scp {
+
+template <int NV, class T>
+__device__ __forceinline__ void ldp(const T* __restrict__ pl, int P, int g, T* v) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = pl[(size_t)k * P + g];
+}
+template <int NV, class T>
+__device__ __forceinline__ void stp(T* __restrict__ pl, int P, int g, const T* v) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) pl[(size_t)k * P + g] = v[k];
+}
+
+template <class T>
+__device__ __forceinline__ T* PL(const Dev<T>& dv, int plane) { return dv.planes + (size_t)plane * dv.P; }
+
+// Resolve the node handled by this thread: returns the trajectory or -1.
+template <class M, class T>
+__device__ __forceinline__ int node_of(const Dev<T>& dv, int g, NodeId& id, const T*& prm) {
+    if (g >= dv.n_nodes) return -1;
+    const int tr = dv.node_traj[g];
+    if (tr < 0) return -1;
+    const int* rec = dv.traj + tr * TR_FIELDS;
+    if (rec[TR_MODEL] != M::ID) return -1;
+    id.i = g - rec[TR_OFF];
+    id.N = rec[TR_N];
+    id.K = rec[TR_K];
+    id.ball = rec[TR_BALL] != 0;
+    prm = dv.params + (size_t)tr * SCP_PARAM_STRIDE;
+    return tr;
+}
+
+template <class M, class T>
+__device__ __forceinline__ void load_const(const Dev<T>& dv, int g, NodeConst<M, T>& nc) {
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR;
+    const int P = dv.P;
+    ldp<Dims<M>::NL>(PL(dv, PL_L), P, g, nc.L);
+    ldp<NX * NXR>(PL(dv, PL_AR), P, g, nc.Ar);
+    ldp<NX * NU>(PL(dv, PL_B), P, g, nc.B);
+    ldp<NX>(PL(dv, PL_D), P, g, nc.d);
+    ldp<NN>(PL(dv, PL_LO), P, g, nc.lo);
+    ldp<NN>(PL(dv, PL_HI), P, g, nc.hi);
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    ldp<NX>(PL(dv, PL_G0), P, g, nc.g0);
+}
+
+// ------------------------------------------------------------------------------------------
+// a2-a4 + primal re-initialization + nominal merit terms
+// ------------------------------------------------------------------------------------------
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_lin(Dev<T> dv, KParams<T> kp) {
+    constexpr int NX = M::NX, NU = M::NU, NXR = M::NXR;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    NodeId id;
+    const T* prm;
+    const int tr = node_of<M>(dv, g, id, prm);
+    if (tr < 0) return;
+    const int P = dv.P;
+    const int* rec = dv.traj + tr * TR_FIELDS;
+    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    NodeConst<M, T> nc;
+    T xbar[NX], ubar[NU], F[NX];
+    ldp<NX>(PL(dv, PL_XBAR), P, g, xbar);
+    ldp<NU>(PL(dv, PL_UBAR), P, g, ubar);
+    if (!id.last()) {
+        linearize<M, T>(prm, xbar, ubar, F, nc.Ar, nc.B, nc.d);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NX * NXR; ++k) nc.Ar[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < NX * NU; ++k) nc.B[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < NX; ++k) nc.d[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < NU; ++k) ubar[k] = T(0);
+    }
+    // control trust-box centre: scenario mean of the first nominal controls inside a group
+    T uc[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) uc[k] = ubar[k];
+    const int gsize = rec[TR_GSIZE];
+    if (id.first() && gsize > 1) {
+        const int g0 = dv.traj[rec[TR_GFIRST] * TR_FIELDS + TR_OFF];
+        const int stride = id.N + 1;
+        T acc[NU];
+#pragma unroll
+        for (int k = 0; k < NU; ++k) acc[k] = T(0);
+        for (int m = 0; m < gsize; ++m) {
+            T um[NU];
+            ldp<NU>(PL(dv, PL_UBAR), P, g0 + m * stride, um);
+#pragma unroll
+            for (int k = 0; k < NU; ++k) acc[k] = acc[k] + um[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NU; ++k) uc[k] = acc[k] / T(gsize);
+    }
+    const T delta = dv.rt[tr * RT_FIELDS + RT_DELTA];
+    int st = convexify<M, T>(prm, id, xbar, uc, delta, nc);
+    st |= assemble_factor<M, T>(prm, id, rho, nc);
+    // merit terms of the nominal
+    T pen = T(0);
+    if (!id.last()) {
+        T xn[NX];
+        ldp<NX>(PL(dv, PL_XBAR), P, g + 1, xn);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) pen = pen + tabs(xn[r] - F[r]);
+    }
+    PL(dv, PL_MER)[(size_t)MER_COST_NOM * P + g] = node_cost<M, T>(prm, id, xbar, ubar);
+    PL(dv, PL_MER)[(size_t)MER_PEN_NOM * P + g] = pen;
+    // primal re-initialization from the nominal (duals carried)
+    NodeState<M, T> s;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        s.x[r] = xbar[r];
+        s.z[r] = id.first() ? T(0) : xbar[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) s.u[r] = ubar[r];
+#pragma unroll
+    for (int k = 0; k < M::C; ++k)
+        s.cp[k] = group_active<M>(id, slot_group<M>(k)) ? slot_var<M, T>(s, k) : T(0);
+    stp<Dims<M>::NL>(PL(dv, PL_L), P, g, nc.L);
+    stp<NX * NXR>(PL(dv, PL_AR), P, g, nc.Ar);
+    stp<NX * NU>(PL(dv, PL_B), P, g, nc.B);
+    stp<NX>(PL(dv, PL_D), P, g, nc.d);
+    stp<M::NN>(PL(dv, PL_LO), P, g, nc.lo);
+    stp<M::NN>(PL(dv, PL_HI), P, g, nc.hi);
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) stp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    stp<NX>(PL(dv, PL_G0), P, g, nc.g0);
+    stp<NX>(PL(dv, PL_X), P, g, s.x);
+    stp<NU>(PL(dv, PL_U), P, g, s.u);
+    stp<NX>(PL(dv, PL_Z), P, g, s.z);
+    stp<M::C>(PL(dv, PL_CP), P, g, s.cp);
+    if (st) atomicOr(&dv.flags[tr * FL_FIELDS + FL_STATUS], st);
+    if (id.first()) {
+        dv.flags[tr * FL_FIELDS + FL_DONE] = 0;
+        dv.flags[tr * FL_FIELDS + FL_ITERS] = 0;
+        dv.red[2 * tr] = 0ull;
+        dv.red[2 * tr + 1] = 0ull;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a5: Step 1
+// ------------------------------------------------------------------------------------------
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_step1(Dev<T> dv, KParams<T> kp) {
+    constexpr int NX = M::NX, NU = M::NU;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    NodeId id;
+    const T* prm;
+    const int tr = node_of<M>(dv, g, id, prm);
+    if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
+    const int P = dv.P;
+    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    NodeConst<M, T> nc;
+    load_const<M, T>(dv, g, nc);
+    NodeState<M, T> s;
+    ldp<NX>(PL(dv, PL_Z), P, g, s.z);
+    ldp<NX>(PL(dv, PL_LAM), P, g, s.lam);
+    ldp<M::C>(PL(dv, PL_CP), P, g, s.cp);
+    ldp<M::C>(PL(dv, PL_DU), P, g, s.du);
+    T zn[NX], mn[NX];
+    if (!id.last()) {
+        ldp<NX>(PL(dv, PL_Z), P, g + 1, zn);
+        ldp<NX>(PL(dv, PL_MU), P, g + 1, mn);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) zn[r] = mn[r] = T(0);
+    }
+    step1<M, T>(id, rho, nc, s, zn, mn);
+    stp<NX>(PL(dv, PL_X), P, g, s.x);
+    stp<NU>(PL(dv, PL_U), P, g, s.u);
+    stp<NX>(PL(dv, PL_DD), P, g, s.dd);
+}
+
+// ------------------------------------------------------------------------------------------
+// a6-a8: Steps 2-4 (+ node-local residual pieces on check iterations)
+// ------------------------------------------------------------------------------------------
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_step234(Dev<T> dv, KParams<T> kp, int check) {
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    NodeId id;
+    const T* prm;
+    const int tr = node_of<M>(dv, g, id, prm);
+    if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
+    const int P = dv.P;
+    const bool grouped0 = id.first() && dv.traj[tr * TR_FIELDS + TR_GSIZE] > 1;
+    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    NodeConst<M, T> nc;
+    ldp<NN>(PL(dv, PL_LO), P, g, nc.lo);
+    ldp<NN>(PL(dv, PL_HI), P, g, nc.hi);
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    NodeState<M, T> s;
+    ldp<NX>(PL(dv, PL_X), P, g, s.x);
+    ldp<NU>(PL(dv, PL_U), P, g, s.u);
+    ldp<NX>(PL(dv, PL_Z), P, g, s.z);
+    ldp<NX>(PL(dv, PL_LAM), P, g, s.lam);
+    ldp<NX>(PL(dv, PL_MU), P, g, s.mu);
+    ldp<M::C>(PL(dv, PL_CP), P, g, s.cp);
+    ldp<M::C>(PL(dv, PL_DU), P, g, s.du);
+    T dp[NX];
+    if (!id.first()) ldp<NX>(PL(dv, PL_DD), P, g - 1, dp);
+    else {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dp[r] = T(0);
+    }
+    T zold[NX], cpold[M::C];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) zold[r] = s.z[r];
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) cpold[k] = s.cp[k];
+    const T ball_r = prm[SCP_P_UBALL], kappa = prm[SCP_P_GLIDE];
+    step2<M, T>(id, rho, s, dp);
+    step3<M, T>(id, rho, nc, s, ball_r, kappa);
+    if (grouped0) {
+        // node 0 of a consensus group: u copies are averaged by k_group, which also
+        // finishes Step 4 and the residual pieces of those slots; keep the old copies.
+#pragma unroll
+        for (int k = 0; k < M::C; ++k)
+            if (slot_is_u<M>(k)) PL(dv, PL_MER)[(size_t)slot_comp_u<M>(k) * P + g] = cpold[k];
+    }
+    // Step 4 (skip the u slots of a grouped node 0: k_group does them after averaging)
+    if (!id.first()) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+            s.lam[r] = s.lam[r] + rho.eq * (s.x[r] - s.z[r]);
+            s.mu[r] = s.mu[r] + rho.dyn * (s.z[r] - dp[r]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) {
+        if (grouped0 && slot_is_u<M>(k)) continue;
+        const bool act = group_active<M>(id, slot_group<M>(k));
+        const T v = s.du[k] + rho.geo * (slot_var<M, T>(s, k) - s.cp[k]);
+        s.du[k] = act ? v : T(0);
+    }
+    stp<NX>(PL(dv, PL_Z), P, g, s.z);
+    stp<NX>(PL(dv, PL_LAM), P, g, s.lam);
+    stp<NX>(PL(dv, PL_MU), P, g, s.mu);
+    stp<M::C>(PL(dv, PL_CP), P, g, s.cp);
+    stp<M::C>(PL(dv, PL_DU), P, g, s.du);
+    if (check) {
+        T dz[NX], dcp[M::C], sp[NN];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dz[r] = s.z[r] - zold[r];
+#pragma unroll
+        for (int k = 0; k < M::C; ++k) dcp[k] = (grouped0 && slot_is_u<M>(k)) ? T(0) : s.cp[k] - cpold[k];
+        dual_res_own<M, T>(id, rho, dz, dcp, sp, grouped0);
+        T rp = grouped0 ? primal_res_skip_u<M, T>(id, s, dp) : primal_res<M, T>(id, s, dp);
+        stp<NX>(PL(dv, PL_DZ), P, g, dz);
+        stp<NN>(PL(dv, PL_SP), P, g, sp);
+        PL(dv, PL_RP)[g] = rp;
+    }
+}
+
+// node 0 of every consensus group: average the projected first-control copies over the
+// scenarios (fixed order), then Step 4 and residual pieces of those slots.  One thread per group.
+template <class M, class T>
+__global__ void k_group(Dev<T> dv, KParams<T> kp, int check) {
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= dv.n_groups) return;
+    const int t0 = dv.groups[q];
+    const int* rec = dv.traj + t0 * TR_FIELDS;
+    if (rec[TR_MODEL] != M::ID || dv.flags[t0 * FL_FIELDS + FL_DONE]) return;
+    const int S = rec[TR_GSIZE];
+    const int P = dv.P;
+    const T rho_geo = kp.rho_geo;
+    T acc[M::C];
+#pragma unroll
+    for (int k = 0; k < M::C; ++k) acc[k] = T(0);
+    for (int m = 0; m < S; ++m) {
+        const int g = dv.traj[(t0 + m) * TR_FIELDS + TR_OFF];
+#pragma unroll
+        for (int k = 0; k < M::C; ++k)
+            if (slot_is_u<M>(k)) acc[k] = acc[k] + PL(dv, PL_CP)[(size_t)k * P + g];
+    }
+    for (int m = 0; m < S; ++m) {
+        const int tr = t0 + m;
+        const int g = dv.traj[tr * TR_FIELDS + TR_OFF];
+        NodeId id;
+        id.i = 0;
+        id.N = rec[TR_N];
+        id.K = dv.traj[tr * TR_FIELDS + TR_K];
+        id.ball = dv.traj[tr * TR_FIELDS + TR_BALL] != 0;
+        T u[NU], sp[NN];
+        ldp<NU>(PL(dv, PL_U), P, g, u);
+        if (check) ldp<NN>(PL(dv, PL_SP), P, g, sp);
+        T rp = check ? PL(dv, PL_RP)[g] : T(0);
+#pragma unroll
+        for (int k = 0; k < M::C; ++k) {
+            if (!slot_is_u<M>(k)) continue;
+            const bool act = group_active<M>(id, slot_group<M>(k));
+            const T mean = act ? acc[k] / T(S) : T(0);
+            const T old = PL(dv, PL_MER)[(size_t)slot_comp_u<M>(k) * P + g];
+            const T var = u[slot_comp<M>(k)];
+            T du = PL(dv, PL_DU)[(size_t)k * P + g];
+            du = act ? du + rho_geo * (var - mean) : T(0);
+            PL(dv, PL_CP)[(size_t)k * P + g] = mean;
+            PL(dv, PL_DU)[(size_t)k * P + g] = du;
+            if (check && act) {
+                sp[NX + slot_comp<M>(k)] = sp[NX + slot_comp<M>(k)] + rho_geo * (mean - old);
+                rp = nmax(rp, tabs(var - mean));
+            }
+        }
+        if (check) {
+            stp<NN>(PL(dv, PL_SP), P, g, sp);
+            PL(dv, PL_RP)[g] = rp;
+        }
+    }
+}
+
+// a9: finish the dual residual with the neighbour term and reduce per trajectory.
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_resid(Dev<T> dv, KParams<T> kp) {
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    NodeId id;
+    const T* prm;
+    const int tr = node_of<M>(dv, g, id, prm);
+    if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
+    const int P = dv.P;
+    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    T Ar[NX * NXR], B[NX * NU], sp[NN], dzn[NX];
+    ldp<NX * NXR>(PL(dv, PL_AR), P, g, Ar);
+    ldp<NX * NU>(PL(dv, PL_B), P, g, B);
+    ldp<NN>(PL(dv, PL_SP), P, g, sp);
+    if (!id.last()) ldp<NX>(PL(dv, PL_DZ), P, g + 1, dzn);
+    else {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dzn[r] = T(0);
+    }
+    const T rd = dual_res_finish<M, T>(id, rho, Ar, B, sp, dzn);
+    const T rp = PL(dv, PL_RP)[g];
+    atomicMax(&dv.red[2 * tr], res_bits(rp));
+    atomicMax(&dv.red[2 * tr + 1], res_bits(rd));
+}
+
+// per trajectory (group leader): residual test, convergence mask, info.
+template <class T>
+__global__ void k_check(Dev<T> dv, KParams<T> kp, int j, int test) {
+    const int tr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tr >= dv.n_traj) return;
+    const int* rec = dv.traj + tr * TR_FIELDS;
+    if (rec[TR_MEMBER] != 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
+    const int S = rec[TR_GSIZE];
+    unsigned long long bp = 0ull, bd = 0ull;
+    for (int m = 0; m < S; ++m) {
+        bp = max(bp, dv.red[2 * (tr + m)]);
+        bd = max(bd, dv.red[2 * (tr + m) + 1]);
+        dv.red[2 * (tr + m)] = 0ull;
+        dv.red[2 * (tr + m) + 1] = 0ull;
+    }
+    const T rp = T(bits_res(bp)), rd = T(bits_res(bd));
+    const bool conv = test && (rp <= kp.eps_p) && (rd <= kp.eps_d);
+    for (int m = 0; m < S; ++m) {
+        double* inf = dv.info + (size_t)(tr + m) * SCP_INFO_FIELDS;
+        inf[SCP_I_RP] = (double)rp;
+        inf[SCP_I_RD] = (double)rd;
+        if (conv) {
+            dv.flags[(tr + m) * FL_FIELDS + FL_DONE] = 1;
+            dv.flags[(tr + m) * FL_FIELDS + FL_ITERS] = j;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a10: merit terms of the candidate, ratio test, nominal update
+// ------------------------------------------------------------------------------------------
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_acc_nodes(Dev<T> dv, KParams<T> kp) {
+    constexpr int NX = M::NX, NU = M::NU;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    NodeId id;
+    const T* prm;
+    const int tr = node_of<M>(dv, g, id, prm);
+    if (tr < 0) return;
+    const int P = dv.P;
+    T x[NX], u[NU], dd[NX];
+    ldp<NX>(PL(dv, PL_X), P, g, x);
+    ldp<NU>(PL(dv, PL_U), P, g, u);
+    T pen = T(0), pmod = T(0);
+    if (!id.last()) {
+        T xn[NX], F[NX];
+        ldp<NX>(PL(dv, PL_DD), P, g, dd);
+        ldp<NX>(PL(dv, PL_X), P, g + 1, xn);
+        rk4<M, T>(prm, x, u, F);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) pen = pen + tabs(xn[r] - F[r]);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) pmod = pmod + tabs(xn[r] - dd[r]);
+    }
+    PL(dv, PL_MER)[(size_t)MER_COST_NEW * P + g] = node_cost<M, T>(prm, id, x, u);
+    PL(dv, PL_MER)[(size_t)MER_PEN_NEW * P + g] = pen;
+    PL(dv, PL_MER)[(size_t)MER_PEN_MOD * P + g] = pmod;
+}
+
+template <class T>
+__global__ void k_acc_traj(Dev<T> dv, KParams<T> kp) {
+    const int tr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tr >= dv.n_traj) return;
+    const int* rec = dv.traj + tr * TR_FIELDS;
+    if (rec[TR_MEMBER] != 0) return;
+    const int S = rec[TR_GSIZE];
+    const int P = dv.P;
+    const T* mer = dv.planes + (size_t)PL_MER * P;
+    T mnom = T(0), mnew = T(0), mmod = T(0);
+    for (int m = 0; m < S; ++m) {
+        const int* r = dv.traj + (tr + m) * TR_FIELDS;
+        const int off = r[TR_OFF], n = r[TR_N] + 1;
+        T J0 = T(0), p0 = T(0), J1 = T(0), p1 = T(0), pm = T(0);
+        for (int i = 0; i < n; ++i) {
+            J0 = J0 + mer[(size_t)MER_COST_NOM * P + off + i];
+            J1 = J1 + mer[(size_t)MER_COST_NEW * P + off + i];
+        }
+        for (int i = 0; i + 1 < n; ++i) {
+            p0 = p0 + mer[(size_t)MER_PEN_NOM * P + off + i];
+            p1 = p1 + mer[(size_t)MER_PEN_NEW * P + off + i];
+            pm = pm + mer[(size_t)MER_PEN_MOD * P + off + i];
+        }
+        mnom = mnom + (J0 + kp.merit_w * p0);
+        mnew = mnew + (J1 + kp.merit_w * p1);
+        mmod = mmod + (J1 + kp.merit_w * pm);
+    }
+    const AcceptOut<T> a = accept_rule<T>(kp.eta0, kp.eta1, kp.eta2, kp.shrink, kp.grow, kp.delta_max, mnom, mnew,
+                                          mmod, dv.rt[tr * RT_FIELDS + RT_DELTA]);
+    for (int m = 0; m < S; ++m) {
+        const int t = tr + m;
+        double* inf = dv.info + (size_t)t * SCP_INFO_FIELDS;
+        int* fl = dv.flags + t * FL_FIELDS;
+        const int iters = fl[FL_DONE] ? fl[FL_ITERS] : kp.max_iters;
+        inf[SCP_I_ADMM_ITERS] += (double)iters;
+        inf[SCP_I_NACCEPT] += a.accept ? 1.0 : 0.0;
+        inf[SCP_I_RATIO] = (double)a.ratio;
+        inf[SCP_I_MERIT] = (double)mnew;
+        inf[SCP_I_DELTA] = (double)a.delta;
+        int st = fl[FL_STATUS] | (a.nonfinite ? SCP_ST_NONFINITE : 0);
+        if (fl[FL_DONE]) st |= SCP_ST_CONVERGED;
+        else st &= ~SCP_ST_CONVERGED;
+        fl[FL_STATUS] = st;
+        inf[SCP_I_STATUS] = (double)st;
+        fl[FL_ACCEPT] = a.accept ? 1 : 0;
+        dv.rt[t * RT_FIELDS + RT_DELTA] = a.delta;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_acc_apply(Dev<T> dv) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= dv.n_nodes) return;
+    const int tr = dv.node_traj[g];
+    if (tr < 0 || !dv.flags[tr * FL_FIELDS + FL_ACCEPT]) return;
+    const int P = dv.P;
+#pragma unroll
+    for (int r = 0; r < SCP_MAX_NX; ++r) PL(dv, PL_XBAR)[(size_t)r * P + g] = PL(dv, PL_X)[(size_t)r * P + g];
+#pragma unroll
+    for (int r = 0; r < SCP_MAX_NU; ++r) PL(dv, PL_UBAR)[(size_t)r * P + g] = PL(dv, PL_U)[(size_t)r * P + g];
+}
+
+// metrics of the nominal: per node, then per trajectory in node order
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_met_nodes(Dev<T> dv) {
+    constexpr int NX = M::NX, NU = M::NU;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    NodeId id;
+    const T* prm;
+    const int tr = node_of<M>(dv, g, id, prm);
+    if (tr < 0) return;
+    const int P = dv.P;
+    T x[NX], u[NU];
+    ldp<NX>(PL(dv, PL_XBAR), P, g, x);
+    ldp<NU>(PL(dv, PL_UBAR), P, g, u);
+    T dfc = T(0);
+    if (!id.last()) {
+        T xn[NX], F[NX];
+        ldp<NX>(PL(dv, PL_XBAR), P, g + 1, xn);
+        rk4<M, T>(prm, x, u, F);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dfc = nmax(dfc, tabs(xn[r] - F[r]));
+    }
+    PL(dv, PL_MER)[(size_t)MER_DEFECT * P + g] = dfc;
+    PL(dv, PL_MER)[(size_t)MER_COST_NEW * P + g] = node_cost<M, T>(prm, id, x, u);
+    PL(dv, PL_MER)[(size_t)MER_VIOL * P + g] = node_violation<M, T>(prm, id, x, u);
+    PL(dv, PL_MER)[(size_t)MER_BND * P + g] = node_bnd_err<M, T>(prm, id, x);
+}
+
+template <class T>
+__global__ void k_met_traj(Dev<T> dv) {
+    const int tr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tr >= dv.n_traj) return;
+    const int* rec = dv.traj + tr * TR_FIELDS;
+    const int off = rec[TR_OFF], n = rec[TR_N] + 1, P = dv.P;
+    const T* mer = dv.planes + (size_t)PL_MER * P;
+    T J = T(0), dfc = T(0), vi = T(0), be = T(0);
+    for (int i = 0; i < n; ++i) {
+        J = J + mer[(size_t)MER_COST_NEW * P + off + i];
+        dfc = nmax(dfc, mer[(size_t)MER_DEFECT * P + off + i]);
+        vi = nmax(vi, mer[(size_t)MER_VIOL * P + off + i]);
+        be = nmax(be, mer[(size_t)MER_BND * P + off + i]);
+    }
+    double* inf = dv.info + (size_t)tr * SCP_INFO_FIELDS;
+    inf[SCP_I_COST] = (double)J;
+    inf[SCP_I_DEFECT] = (double)dfc;
+    inf[SCP_I_VIOL] = (double)vi;
+    inf[SCP_I_BNDERR] = (double)be;
+}
+
+template <class T>
+__global__ void k_reset(Dev<T> dv, int reset_delta) {
+    const int tr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tr >= dv.n_traj) return;
+    double* inf = dv.info + (size_t)tr * SCP_INFO_FIELDS;
+#pragma unroll
+    for (int k = 0; k < SCP_INFO_FIELDS; ++k) inf[k] = 0.0;
+    int* fl = dv.flags + tr * FL_FIELDS;
+    fl[FL_DONE] = 0;
+    fl[FL_ITERS] = 0;
+    fl[FL_ACCEPT] = 0;
+    fl[FL_STATUS] = 0;
+    dv.red[2 * tr] = 0ull;
+    dv.red[2 * tr + 1] = 0ull;
+    if (reset_delta) dv.rt[tr * RT_FIELDS + RT_DELTA] = dv.params[(size_t)tr * SCP_PARAM_STRIDE + SCP_P_DELTA];
+    inf[SCP_I_DELTA] = (double)dv.rt[tr * RT_FIELDS + RT_DELTA];
+}
+
+// gather one field of every node into a dense [node][width] array
+template <class T>
+__global__ __launch_bounds__(256) void k_gather(Dev<T> dv, int plane, int width, int mode, T* out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= dv.n_nodes) return;
+    const int tr = dv.node_traj[g];
+    const int model = dv.traj[tr * TR_FIELDS + TR_MODEL];
+    const int P = dv.P;
+    T* o = out + (size_t)g * width;
+    if (mode == 1) {
+        // dense A from the stored non-unit columns
+        const int nx = model == SCP_MODEL_QUAD_PM ? 6 : 7, nxr = nx - 3;
+        const int N = dv.traj[tr * TR_FIELDS + TR_N], i = g - dv.traj[tr * TR_FIELDS + TR_OFF];
+        for (int r = 0; r < 7; ++r)
+            for (int c = 0; c < 7; ++c) {
+                T v = T(0);
+                if (r < nx && c < nx) {
+                    if (c < 3) v = (i < N && r == c) ? T(1) : T(0);
+                    else v = PL(dv, PL_AR)[(size_t)(r * nxr + (c - 3)) * P + g];
+                }
+                o[r * 7 + c] = v;
+            }
+    } else if (mode == 2) {
+        const int nx = model == SCP_MODEL_QUAD_PM ? 6 : 7, nu = nx == 6 ? 3 : 4;
+        for (int r = 0; r < 7; ++r)
+            for (int c = 0; c < 4; ++c)
+                o[r * 4 + c] = (r < nx && c < nu) ? PL(dv, PL_B)[(size_t)(r * nu + c) * P + g] : T(0);
+    } else if (mode == 3) {
+        // box bounds: x part then u part at fixed offsets 0..6 / 7..10
+        const int nx = model == SCP_MODEL_QUAD_PM ? 6 : 7, nu = nx == 6 ? 3 : 4;
+        for (int k = 0; k < 11; ++k) {
+            T v = T(0);
+            if (k < 7 && k < nx) v = PL(dv, plane)[(size_t)k * P + g];
+            if (k >= 7 && k - 7 < nu) v = PL(dv, plane)[(size_t)(nx + k - 7) * P + g];
+            o[k] = v;
+        }
+    } else {
+        for (int k = 0; k < width; ++k) o[k] = PL(dv, plane)[(size_t)k * P + g];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static inline dim3 grid_for(int n) { return dim3((n + 255) / 256); }
+
+template <class T>
+hipError_t launch_plain(PlainOp op, const Dev<T>& dv, const KParams<T>& kp, int models, int kmax, int check,
+                        int j, hipStream_t s) {
+    const dim3 gn = grid_for(dv.n_nodes), gt = grid_for(dv.n_traj), gg = grid_for(dv.n_groups > 0 ? dv.n_groups : 1);
+    const dim3 b(256);
+    auto each = [&](auto launch_model) {
+        if (models & 1) {
+            if (kmax <= 4) launch_model(Quad<4>{});
+            else launch_model(Quad<8>{});
+        }
+        if (models & 2) launch_model(Mars{});
+    };
+    switch (op) {
+        case PlainOp::Lin:
+            each([&](auto m) { hipLaunchKernelGGL((k_lin<decltype(m), T>), gn, b, 0, s, dv, kp); });
+            break;
+        case PlainOp::Step1:
+            each([&](auto m) { hipLaunchKernelGGL((k_step1<decltype(m), T>), gn, b, 0, s, dv, kp); });
+            break;
+        case PlainOp::Step234:
+            each([&](auto m) { hipLaunchKernelGGL((k_step234<decltype(m), T>), gn, b, 0, s, dv, kp, check); });
+            if (dv.n_groups > 0)
+                each([&](auto m) { hipLaunchKernelGGL((k_group<decltype(m), T>), gg, b, 0, s, dv, kp, check); });
+            break;
+        case PlainOp::Resid:
+            each([&](auto m) { hipLaunchKernelGGL((k_resid<decltype(m), T>), gn, b, 0, s, dv, kp); });
+            hipLaunchKernelGGL((k_check<T>), gt, b, 0, s, dv, kp, j, check);
+            break;
+        case PlainOp::Accept:
+            each([&](auto m) { hipLaunchKernelGGL((k_acc_nodes<decltype(m), T>), gn, b, 0, s, dv, kp); });
+            hipLaunchKernelGGL((k_acc_traj<T>), gt, b, 0, s, dv, kp);
+            hipLaunchKernelGGL((k_acc_apply<T>), gn, b, 0, s, dv);
+            break;
+        case PlainOp::Metrics:
+            each([&](auto m) { hipLaunchKernelGGL((k_met_nodes<decltype(m), T>), gn, b, 0, s, dv); });
+            hipLaunchKernelGGL((k_met_traj<T>), gt, b, 0, s, dv);
+            break;
+        case PlainOp::Reset:
+            hipLaunchKernelGGL((k_reset<T>), gt, b, 0, s, dv, check);
+            break;
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_gather(const Dev<T>& dv, int plane, int width, int mode, T* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_gather<T>), grid_for(dv.n_nodes), dim3(256), 0, s, dv, plane, width, mode, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_plain<float>(PlainOp, const Dev<float>&, const KParams<float>&, int, int, int, int, hipStream_t);
+template hipError_t launch_plain<double>(PlainOp, const Dev<double>&, const KParams<double>&, int, int, int, int, hipStream_t);
+template hipError_t launch_gather<float>(const Dev<float>&, int, int, int, float*, hipStream_t);
+template hipError_t launch_gather<double>(const Dev<double>&, int, int, int, double*, hipStream_t);
+
+}  // namespace scp

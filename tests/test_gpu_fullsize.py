@@ -1,0 +1,106 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+Quadrotor batch: 1024 instances, N = 50, 8 obstacles, 15 SCP x 200 ADMM, FP32, persistent form.
+Powered descent: 4096 instances, N = 60, 15 x 200, FP32.
+* sampled instances after the first SCP iteration of the full batch: FP32 vs oracle at 1e-4;
+* sampled instances at the full budget: FP64 mode vs oracle at 1e-9;
+* every sampled trajectory of the full FP32 batch is bitwise equal to the same trajectory solved
+  alone (placement independence), and plain and persistent forms agree to 1e-4 after SCP 1;
+* properties that hold at any size: finite iterates, boundary conditions, metrics consistent.
+"""
+import numpy as np
+import pytest
+
+import scpgen
+import oracle
+from _parity import FIELDS, compare, gpu_fields, oracle_scp, rel_err
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = [0, 333, 1023]
+
+
+@pytest.fixture(scope="module")
+def B(lib):
+    from paper_2603_10711_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def quad_batch():
+    return scpgen.config1(1024)
+
+
+def test_quad_full_batch_first_scp_iteration(B, quad_batch):
+    print("quad 1024 x 51, 1 x 200 fp32 persistent", flush=True)
+    prob = B.Problem(quad_batch, precision="f32")
+    prob.solve(B.scp_params(1, 200))
+    f = gpu_fields(prob)
+    sample = [quad_batch[i] for i in SAMPLE]
+    trajs, _ = oracle_scp(sample, 1, 200)
+    worst = compare(prob, f, sample, trajs, idx=SAMPLE)
+    print(worst, flush=True)
+    assert max(worst.values()) < 1e-4
+    plain = B.Problem(quad_batch, precision="f32")
+    plain.solve(B.scp_params(1, 200, form="plain"))
+    fp = gpu_fields(plain, ("xbar", "lam", "dual"))
+    for k in fp:
+        assert rel_err(fp[k][:prob.n_nodes], f[k][:prob.n_nodes]) < 1e-4
+    prob.close()
+    plain.close()
+
+
+def test_quad_full_budget_fp64_samples(B, quad_batch):
+    sample = [quad_batch[i] for i in SAMPLE]
+    print("quad samples 15 x 200 fp64 persistent", flush=True)
+    prob = B.Problem(sample, precision="f64")
+    prob.solve(B.scp_params(15, 200))
+    f = gpu_fields(prob)
+    trajs, oinfo = oracle_scp(sample, 15, 200)
+    worst = compare(prob, f, sample, trajs)
+    print(worst, flush=True)
+    assert max(worst.values()) < 1e-9
+    prob.close()
+
+
+def test_quad_full_budget_batch_invariance(B, quad_batch):
+    print("quad 1024 15 x 200 fp32 persistent vs alone", flush=True)
+    prob = B.Problem(quad_batch, precision="f32")
+    prob.solve(B.scp_params(15, 200))
+    x, u, info = prob.result()
+    x, u, info = x.cpu().numpy(), u.cpu().numpy(), info.cpu().numpy()
+    assert np.all(np.isfinite(x[:prob.n_nodes])) and np.all(np.isfinite(info))
+    assert np.all(info[:, 0] == 3000) and np.all(info[:, 3] == 15)
+    for i in SAMPLE:
+        alone = B.Problem([quad_batch[i]], precision="f32")
+        alone.solve(B.scp_params(15, 200))
+        xa, ua, ia = (a.cpu().numpy() for a in alone.result())
+        o = prob.offsets[i]
+        n = quad_batch[i]["N"] + 1
+        np.testing.assert_array_equal(xa[:n], x[o:o + n])
+        np.testing.assert_array_equal(ua[:n], u[o:o + n])
+        np.testing.assert_array_equal(ia[0], info[i])
+        alone.close()
+    # metrics recomputed by the oracle from the returned FP32 trajectory (in FP64)
+    for i in SAMPLE:
+        d = quad_batch[i]
+        o, N = prob.offsets[i], d["N"]
+        xs, us = x[o:o + N + 1, :6].astype(float), u[o:o + N, :3].astype(float)
+        assert abs(info[i, 6] - oracle.defect(d, xs, us)) < 1e-4 * max(1.0, oracle.defect(d, xs, us))
+        assert abs(info[i, 7] - oracle.cost(d, xs, us)) < 1e-5 * abs(oracle.cost(d, xs, us))
+    prob.close()
+
+
+def test_mars_full_batch(B):
+    insts = scpgen.config2(4096)
+    print("mars 4096 x 61 fp32 persistent 1 x 200", flush=True)
+    prob = B.Problem(insts, precision="f32")
+    prob.solve(B.scp_params(1, 200))
+    f = gpu_fields(prob)
+    idx = [0, 2047, 4095]
+    sample = [insts[i] for i in idx]
+    trajs, _ = oracle_scp(sample, 1, 200)
+    worst = compare(prob, f, sample, trajs, idx=idx)
+    print(worst, flush=True)
+    assert max(worst.values()) < 1e-4
+    prob.close()

@@ -1,0 +1,110 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header declares, and its
+host-side validation rejects bad descriptions without touching a GPU."""
+import ctypes
+import os
+import re
+from ctypes import POINTER, byref, c_double, c_int32, c_void_p
+
+import numpy as np
+import pytest
+
+import scpgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2603_10711_amd import binding
+    binding.load()
+    return binding
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "scp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_]+)\s*\([^;{]*\)\s*;", txt)) - {"sizeof"})
+
+
+def test_library_exports_every_declared_symbol(B):
+    names = _header_functions()
+    assert len(names) >= 12
+    lib = B.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.SYMBOLS) == names
+
+
+def _desc(B, insts, prec=0, block=0, group=None):
+    model = np.array([d["model"] for d in insts], dtype=np.int32)
+    hz = np.array([d["N"] for d in insts], dtype=np.int32)
+    grp = np.array([d.get("group", -1) for d in insts] if group is None else group, dtype=np.int32)
+    params = np.concatenate([B.param_record(d) for d in insts])
+    xg = np.concatenate([B.Problem._pad(d["x_guess"], 7) for d in insts])
+    ug = np.concatenate([B.Problem._pad(d["u_guess"], 4) for d in insts])
+    keep = (model, hz, grp, params, xg, ug)
+    d = B.ProblemDesc(len(insts), prec, model.ctypes.data_as(POINTER(c_int32)), hz.ctypes.data_as(POINTER(c_int32)),
+                      grp.ctypes.data_as(POINTER(c_int32)), params.ctypes.data_as(POINTER(c_double)),
+                      xg.ctypes.data_as(POINTER(c_double)), ug.ctypes.data_as(POINTER(c_double)), block)
+    return d, keep
+
+
+def test_device_bytes_and_field_widths(B):
+    lib = B.load()
+    d, keep = _desc(B, scpgen.config1(8))
+    n32 = lib.scp_problem_device_bytes(byref(d))
+    d64, keep2 = _desc(B, scpgen.config1(8), prec=1)
+    n64 = lib.scp_problem_device_bytes(byref(d64))
+    assert n32 > 0 and n64 > 1.9 * n32 * 0.9
+    assert [lib.scp_field_width(i) for i in range(16)] == [7, 4, 7, 4, 7, 7, 7, 7, 36, 36, 49, 28, 7, 11, 11, 32]
+    assert lib.scp_field_width(99) == 0
+
+
+@pytest.mark.parametrize("case", ["model", "horizon", "obstacles", "block", "group_gap", "group_shape", "delta"])
+def test_invalid_descriptions_rejected_on_host(B, case):
+    lib = B.load()
+    insts = scpgen.config1(3)
+    group = None
+    block = 0
+    if case == "model":
+        insts[1] = dict(insts[1], model=9)
+    elif case == "horizon":
+        insts[2] = dict(insts[2], N=0)
+    elif case == "obstacles":
+        insts[0] = dict(insts[0], obstacles=np.zeros((9, 4)))
+    elif case == "block":
+        block = 96
+    elif case == "group_gap":
+        group = [5, -1, 5]
+    elif case == "group_shape":
+        insts[1] = dict(scpgen.quad_instance(1, 1, N=20), group=4)
+        insts[0] = dict(insts[0], group=4)
+        group = [4, 4, -1]
+    elif case == "delta":
+        insts[0] = dict(insts[0], delta=0.0)
+    if case == "horizon":
+        insts[2]["x_guess"] = insts[2]["x_guess"][:1]
+        insts[2]["u_guess"] = insts[2]["u_guess"][:0]
+    d, keep = _desc(B, insts, block=block, group=group)
+    assert lib.scp_problem_device_bytes(byref(d)) == 0
+    h = c_void_p()
+    st = lib.scp_problem_create(byref(d), None, 0, None, byref(h))
+    assert st == 1 and not h.value
+    assert len(lib.scp_last_error(None)) > 0
+
+
+def test_arena_too_small_is_rejected(B):
+    lib = B.load()
+    d, keep = _desc(B, scpgen.config1(2))
+    h = c_void_p()
+    st = lib.scp_problem_create(byref(d), c_void_p(256), 512, None, byref(h))
+    assert st == 1 and b"too small" in lib.scp_last_error(None)
+
+
+def test_null_handles_are_safe(B):
+    lib = B.load()
+    assert lib.scp_linearize(None, None) == 1
+    assert lib.admm_solve(None, None) == 1
+    assert lib.scp_solve(None, None) == 1
+    assert lib.scp_problem_nodes(None) == 0
+    lib.scp_problem_destroy(None)
