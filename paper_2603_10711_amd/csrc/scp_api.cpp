@@ -161,20 +161,27 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     L.node_traj.assign(L.P, -1);
     for (int q = 0; q < L.n_traj; ++q)
         for (int i = 0; i <= horizon[q]; ++i) L.node_traj[traj_off[q] + i] = q;
-    // persistent-kernel packing: requested block, or the candidate with the fewest idle lanes
+    // persistent-kernel packing: the requested block, or the candidate with the lowest cost
+    // estimate.  The kernel runs one wave per SIMD (1024 SIMDs on the chip); waves of one
+    // workgroup wait for each other at every exchange barrier, so at equal wave rounds a
+    // smaller workgroup wins, and the idle-lane count breaks ties.
     int max_unit = 0;
     for (auto& u : units) max_unit = std::max(max_unit, u.lanes);
     std::vector<int> cands = d->block ? std::vector<int>{d->block} : std::vector<int>{64, 128, 256};
     if (d->prec == SCP_F64) cands.erase(std::remove(cands.begin(), cands.end(), 256), cands.end());
     long best_idle = -1;
+    double best_score = 0.0;
     for (int b : cands) {
         if (max_unit > b) continue;
         std::vector<int> lane, wgm;
         int nwg = 0;
         if (!pack(units, traj_off, horizon, b, lane, wgm, nwg)) continue;
         const long idle = (long)nwg * b - L.n_nodes;
-        if (best_idle < 0 || idle < best_idle) {
+        const double waves = (double)nwg * (b / 64);
+        const double score = std::ceil(waves / 1024.0) * (1.0 + 0.05 * (b / 64 - 1));
+        if (best_idle < 0 || score < best_score || (score == best_score && idle < best_idle)) {
             best_idle = idle;
+            best_score = score;
             L.block = b;
             L.n_wg = nwg;
             L.lane = lane;

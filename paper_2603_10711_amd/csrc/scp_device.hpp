@@ -74,10 +74,34 @@ template <class T>
 __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
 __device__ __forceinline__ float tsqrt(float a) { return sqrtf(a); }
 __device__ __forceinline__ double tsqrt(double a) { return sqrt(a); }
-template <class T>
-__device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
-template <class T>
-__device__ __forceinline__ T tmaxv(T a, T b) { return b > a ? b : a; }
+// min / max / clamp map to single VALU instructions (v_min, v_max, v_med3)
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float tmaxv(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double tmaxv(double a, double b) { return __builtin_fmax(a, b); }
+// 1/sqrt(a): one hardware reciprocal square root in FP32 (about 1 ulp), exact division in FP64
+__device__ __forceinline__ float trsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
+__device__ __forceinline__ double trsqrt(double a) { return 1.0 / sqrt(a); }
+
+// ------------------------------------------------------------------------------------------
+// wavefront neighbour exchange (DPP wave shifts, no LDS): lane t receives the value of lane
+// t+1 (lane_next) or t-1 (lane_prev); the lane without a neighbour receives 0.  Called with
+// the whole wavefront active.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ float lane_next(float v) { return __builtin_bit_cast(float, dpp_next_i(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float lane_prev(float v) { return __builtin_bit_cast(float, dpp_prev_i(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double lane_next(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_next_i((int)(b & 0xffffffffll)), hi = dpp_next_i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double lane_prev(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_prev_i((int)(b & 0xffffffffll)), hi = dpp_prev_i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 // ------------------------------------------------------------------------------------------
 // continuous dynamics and their directional derivative (JVP)
@@ -256,50 +280,45 @@ __device__ __forceinline__ void bt_mul(const T* B, const T* w, T* y) {
 // ------------------------------------------------------------------------------------------
 // projections (exact closed forms)
 // ------------------------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ T clampv(T v, T lo, T hi) { return tmin(tmaxv(v, lo), hi); }
+// box clamp; lo <= hi holds for every convexified box (an empty cut collapses to a point)
+__device__ __forceinline__ float clampv(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
+__device__ __forceinline__ double clampv(double v, double lo, double hi) { return tmin(tmaxv(v, lo), hi); }
 
-// {y : a'y >= b}
+// {y : a'y >= b} with a unit normal a (the obstacle normals are normalized when the sets are
+// built), so the projection v + max(0, b - a'v)/||a||^2 a needs no division.
 template <class T>
 __device__ __forceinline__ void proj_halfspace(const T* a, T b, T* v) {
     const T av = (a[0] * v[0] + a[1] * v[1]) + a[2] * v[2];
-    const T aa = (a[0] * a[0] + a[1] * a[1]) + a[2] * a[2];
-    const T t = tmaxv(T(0), b - av) / aa;
+    const T t = tmaxv(T(0), b - av);
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[k] = v[k] + t * a[k];
 }
 
-// {y : ||y|| <= r}, 3-vector
+// {y : ||y|| <= r}, 3-vector: v min(1, r/||v||)
 template <class T>
 __device__ __forceinline__ void proj_ball3(T r, T* v) {
-    const T nv = tsqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
-    const T s = nv > r ? r / nv : T(1);
+    const T vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+    const T s = vv > r * r ? r * trsqrt(vv) : T(1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[k] = v[k] * s;
 }
 
-// {(y, s) : ||y|| <= kappa s}, y of length M-1
+// {(y, s) : ||y|| <= kappa s}, y of length M-1; inv1k2 = 1/(1 + kappa^2)
 template <int M, class T>
-__device__ __forceinline__ void proj_cone(T kappa, T* v) {
+__device__ __forceinline__ void proj_cone(T kappa, T inv1k2, T* v) {
     T yy = T(0);
 #pragma unroll
     for (int k = 0; k < M - 1; ++k) yy = yy + v[k] * v[k];
-    const T ny = tsqrt(yy);
+    const T rny = trsqrt(yy);          // 1/||y|| (inf at y = 0; then the point is inside or polar)
+    const T ny = yy * rny;
     const T s = v[M - 1];
-    const bool inside = ny <= kappa * s;
-    const bool polar = !inside && (kappa * ny <= -s);
-    if (!inside) {
-        if (polar) {
+    const bool inside = (yy == T(0)) ? (s >= T(0)) : (ny <= kappa * s);
+    const bool polar = !inside && (yy == T(0) || kappa * ny <= -s);
+    const T c = (kappa * ny + s) * inv1k2;
+    const T f = polar ? T(0) : (inside ? T(1) : c * kappa * rny);
 #pragma unroll
-            for (int k = 0; k < M; ++k) v[k] = T(0);
-        } else {
-            const T c = (kappa * ny + s) / (T(1) + kappa * kappa);
-            const T f = c * kappa / ny;
-#pragma unroll
-            for (int k = 0; k < M - 1; ++k) v[k] = f * v[k];
-            v[M - 1] = c;
-        }
-    }
+    for (int k = 0; k < M - 1; ++k) v[k] = f * v[k];
+    v[M - 1] = polar ? T(0) : (inside ? s : c);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -633,7 +652,7 @@ __device__ __forceinline__ void step2(const NodeId& id, const Rho<T>& rho, NodeS
 // The u copies at node 0 of a consensus group are averaged afterwards by the caller.
 template <class M, class T>
 __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
-                                      NodeState<M, T>& s, T ball_r, T kappa) {
+                                      NodeState<M, T>& s, T ball_r, T kappa, T inv1k2) {
     constexpr int NX = M::NX, NU = M::NU;
     // x box
 #pragma unroll
@@ -673,7 +692,7 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
             T v[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) v[r] = s.x[r] + s.du[M::C_CONE + r] * rho.inv_geo;
-            proj_cone<3>(kappa, v);
+            proj_cone<3>(kappa, inv1k2, v);
             const bool act = !id.first();
 #pragma unroll
             for (int r = 0; r < 3; ++r) s.cp[M::C_CONE + r] = act ? v[r] : T(0);
@@ -682,7 +701,7 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
             T v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = s.u[r] + s.du[M::C_SOC + r] * rho.inv_geo;
-            proj_cone<4>(T(1), v);
+            proj_cone<4>(T(1), T(0.5), v);
             const bool act = !id.last();
 #pragma unroll
             for (int r = 0; r < 4; ++r) s.cp[M::C_SOC + r] = act ? v[r] : T(0);

