@@ -2,9 +2,10 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096] [--no-cpu-baseline]
 
-One step = one full batched solve of the workload (linearization, convexification, factorization,
-ADMM iterations, acceptance and metrics for every instance) through the C ABI, persistent form,
-with the problem already resident in HBM.  Prints one JSON line.
+One step = one full batched solve of the workload from its initial guess (reset of the resident
+state, then linearization, convexification, factorization, ADMM iterations, acceptance and metrics
+for every instance) through the C ABI, persistent form, with the problem already resident in HBM.
+Prints one JSON line.
 
 Default workload: 1024 independent quadrotor point-mass instances, N = 50, 8 obstacles, fixed
 budget of 15 SCP x 200 ADMM iterations, rho = 1, FP32.  ``value`` is the whole-job throughput
@@ -149,6 +150,7 @@ def main(argv=None):
     prm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], form="persistent")
     stream = prob.stream
     for _ in range(a.warmup):
+        prob.reset()
         prob.solve(prm)
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
@@ -157,6 +159,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     for k in range(a.steps):
         starts[k].record(stream)
+        prob.reset()          # every step is a fresh solve from the initial guess
         prob.solve(prm)
         ends[k].record(stream)
     torch.cuda.synchronize()
@@ -183,6 +186,7 @@ def main(argv=None):
     if a.plain_steps > 0:
         pp = B.Problem(insts, precision=wl["prec"], device="cuda:0")
         pprm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], form="plain")
+        pp.reset()
         pp.solve(pprm)
         torch.cuda.synchronize()
         ps = [torch.cuda.Event(enable_timing=True) for _ in range(a.plain_steps)]
@@ -190,6 +194,7 @@ def main(argv=None):
         t1 = time.perf_counter()
         for k in range(a.plain_steps):
             ps[k].record(pp.stream)
+            pp.reset()
             pp.solve(pprm)
             pe[k].record(pp.stream)
         torch.cuda.synchronize()

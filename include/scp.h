@@ -194,6 +194,11 @@ scp_status admm_solve(scp_problem* p, const admm_params* prm);
  * nominal (defect, cost, violation, boundary error) into the info records.  Async. */
 scp_status scp_solve(scp_problem* p, const scp_params* prm);
 
+/* Restore the initial guess given at create time as the nominal, set every ADMM iterate and
+ * dual to zero, the trust radius to its initial value and the info records to zero: the next
+ * scp_solve is then a fresh solve (instead of a warm start from the last one).  Async. */
+scp_status scp_reset(scp_problem* p);
+
 /* Copy the nominal trajectory and info to caller device buffers (device-to-device, async):
  * x_dev gets rows of SCP_MAX_NX values per node (all trajectories concatenated, N+1 rows
  * each), u_dev rows of SCP_MAX_NU values (N+1 rows per trajectory, the last row zero), both

@@ -33,7 +33,7 @@ ST_NONFINITE, ST_BADPIVOT, ST_EMPTYSET, ST_CONVERGED = 1, 2, 4, 8
 FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9, A=10, B=11, d=12, boxlo=13,
               boxhi=14, hs=15)
 SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_destroy", "scp_linearize", "admm_solve",
-           "scp_solve", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
+           "scp_solve", "scp_reset", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
            "scp_traj_node_offset", "scp_last_error"]
 
 
@@ -77,6 +77,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.admm_solve.restype = c_int32
     lib.scp_solve.argtypes = [c_void_p, POINTER(ScpParams)]
     lib.scp_solve.restype = c_int32
+    lib.scp_reset.argtypes = [c_void_p]
+    lib.scp_reset.restype = c_int32
     lib.scp_get_result.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     lib.scp_get_result.restype = c_int32
     lib.scp_field_width.argtypes = [c_int32]
@@ -201,6 +203,10 @@ class Problem:
 
     def solve(self, prm: ScpParams):
         self._check(self.lib.scp_solve(self.h, byref(prm)), "scp_solve")
+
+    def reset(self):
+        """Back to the initial guess with zero duals: the next solve starts fresh."""
+        self._check(self.lib.scp_reset(self.h), "scp_reset")
 
     def field(self, name: str):
         fid = FIELDS[name]

@@ -431,6 +431,7 @@ scp_status scp_problem_create(const scp_problem_desc* desc, void* arena_dev, siz
     if (!L.groups.empty()) cp(L.o_groups, L.groups.data(), L.groups.size() * 4);
     cp(L.o_params, img_params.data(), img_params.size());
     cp(L.o_planes, img_nom.data(), img_nom.size());
+    cp(L.o_planes + (size_t)PL_XG * L.P * L.esz, img_nom.data(), img_nom.size());   // kept for scp_reset
     cp(L.o_rt, img_rt.data(), img_rt.size());
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
@@ -484,6 +485,20 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
         p->linearized = false;
     }
     return st;
+}
+
+scp_status scp_reset(scp_problem* p) {
+    if (!p) return SCP_ERR_ARG;
+    hipError_t e;
+    if (p->prec == SCP_F32) {
+        KParams<float> kp{};
+        e = launch_plain<float>(PlainOp::ResetState, p->df, kp, p->L.models, p->L.kmax, 1, 0, p->stream);
+    } else {
+        KParams<double> kp{};
+        e = launch_plain<double>(PlainOp::ResetState, p->dd, kp, p->L.models, p->L.kmax, 1, 0, p->stream);
+    }
+    p->linearized = false;
+    return hip_check(p, e, "reset launch");
 }
 
 int32_t scp_field_width(int32_t field) {

@@ -7,7 +7,7 @@
 
 namespace scp {
 
-enum class PlainOp { Lin, Step1, Step234, Resid, Accept, Metrics, Reset };
+enum class PlainOp { Lin, Step1, Step234, Resid, Accept, Metrics, Reset, ResetState };
 
 // models: bit 0 quadrotor present, bit 1 powered descent present; kmax: largest obstacle count.
 template <class T>

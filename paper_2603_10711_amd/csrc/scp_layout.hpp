@@ -33,7 +33,9 @@ enum Plane : int {
     PL_SP = 319,     // 11 node-local part of the dual residual vector
     PL_RP = 330,     // 1  node primal residual
     PL_MER = 331,    // 8  merit / metric terms of one node
-    NPLANES = 339
+    PL_XG = 339,     // 7  initial guess of the states (restored by scp_reset)
+    PL_UG = 346,     // 4  initial guess of the controls
+    NPLANES = 350
 };
 
 // merit / metric term slots inside PL_MER

@@ -533,6 +533,19 @@ __global__ void k_reset(Dev<T> dv, int reset_delta) {
     inf[SCP_I_DELTA] = (double)dv.rt[tr * RT_FIELDS + RT_DELTA];
 }
 
+// restore the initial guess as the nominal and clear every ADMM iterate and dual
+template <class T>
+__global__ __launch_bounds__(256) void k_reset_state(Dev<T> dv) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= dv.n_nodes) return;
+    const int P = dv.P;
+#pragma unroll
+    for (int r = 0; r < SCP_MAX_NX; ++r) PL(dv, PL_XBAR)[(size_t)r * P + g] = PL(dv, PL_XG)[(size_t)r * P + g];
+#pragma unroll
+    for (int r = 0; r < SCP_MAX_NU; ++r) PL(dv, PL_UBAR)[(size_t)r * P + g] = PL(dv, PL_UG)[(size_t)r * P + g];
+    for (int k = PL_X; k < PL_AR; ++k) dv.planes[(size_t)k * P + g] = T(0);   // x, u, z, lambda, mu, d_dyn, copies, duals
+}
+
 // gather one field of every node into a dense [node][width] array
 template <class T>
 __global__ __launch_bounds__(256) void k_gather(Dev<T> dv, int plane, int width, int mode, T* out) {
@@ -618,6 +631,10 @@ hipError_t launch_plain(PlainOp op, const Dev<T>& dv, const KParams<T>& kp, int 
             break;
         case PlainOp::Reset:
             hipLaunchKernelGGL((k_reset<T>), gt, b, 0, s, dv, check);
+            break;
+        case PlainOp::ResetState:
+            hipLaunchKernelGGL((k_reset_state<T>), gn, b, 0, s, dv);
+            hipLaunchKernelGGL((k_reset<T>), gt, b, 0, s, dv, 1);
             break;
     }
     return hipGetLastError();

@@ -1,0 +1,95 @@
+"""Summarize rocprofv3 CSV output into the short text files kept under profiles/.
+
+    python -m paper_2603_10711_amd.profile_summary stats <kernel_stats.csv> <out.md> --cmd "<command>"
+    python -m paper_2603_10711_amd.profile_summary pmc <fetch dir> <write dir> <copy fetch dir> <copy write dir> \
+        <workload> <out.json> --cmd "<command>"
+
+``pmc`` scales FETCH_SIZE / WRITE_SIZE of k_persistent by what the same counters read for a
+1 GiB device copy (copy_probe.py) and records the hash of the kernel sources the counters were
+taken with; bench.py reports the traffic only while that hash still matches.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stats(csv_path: str, out: str, cmd: str, top: int = 14) -> None:
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = ["# rocprofv3 kernel statistics", "", f"Command: `{cmd}`", "",
+             f"Kernel sources hash: `{kernel_source_hash()}`", "",
+             "| kernel | calls | avg (us) | min (us) | max (us) | total (ms) | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 110:
+            name = name[:107] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _counter(dirpath: str, kernel_prefix: str):
+    path = glob.glob(os.path.join(dirpath, "*counter_collection.csv"))[0]
+    vals = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    for k, v in vals.items():
+        if k.startswith(kernel_prefix):
+            return sum(v) / len(v), k
+    raise SystemExit(f"no kernel {kernel_prefix} in {path}")
+
+
+def pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, out, cmd) -> None:
+    copy_bytes = 1 << 30
+    cf, _ = _counter(copy_fetch_dir, "__amd_rocclr_copyBuffer")
+    cw, _ = _counter(copy_write_dir, "__amd_rocclr_copyBuffer")
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    kf, name = _counter(fetch_dir, "void scp::k_persistent")
+    kw, _ = _counter(write_dir, "void scp::k_persistent")
+    d = {"kernel": name, "workload": workload, "kernel_hash": kernel_source_hash(), "command": cmd,
+         "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
+         "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
+                              "fetch_scale": f_scale, "write_scale": w_scale},
+         "hbm_read_bytes_per_launch": kf * 1024.0 * f_scale, "hbm_write_bytes_per_launch": kw * 1024.0 * w_scale}
+    d["hbm_bytes_per_launch"] = d["hbm_read_bytes_per_launch"] + d["hbm_write_bytes_per_launch"]
+    json.dump(d, open(out, "w"), indent=1)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("out")
+    s.add_argument("--cmd", required=True)
+    p = sub.add_parser("pmc")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "workload", "out"):
+        p.add_argument(k)
+    p.add_argument("--cmd", required=True)
+    a = ap.parse_args(argv)
+    if a.mode == "stats":
+        stats(a.csv, a.out, a.cmd)
+    else:
+        pmc(a.fetch, a.write, a.copy_fetch, a.copy_write, a.workload, a.out, a.cmd)
+
+
+if __name__ == "__main__":
+    main()

@@ -231,3 +231,24 @@ def test_invalid_arguments_are_errors(B):
         p2.solve(B.scp_params(1, 5, form="persistent"))
     p2.solve(B.scp_params(1, 5, form="plain"))
     p2.close()
+
+
+def test_reset_then_solve_equals_fresh_solve(B):
+    """scp_reset restores the initial guess and clears the state: a second solve after a reset is
+    bitwise equal to the first solve of a fresh problem (both forms)."""
+    insts = scpgen.config1(4) + [scpgen.mars_instance(2, 3, N=30)]
+    for form in ["persistent", "plain"]:
+        _say("reset", form)
+        fresh = B.Problem(insts, precision="f32")
+        fresh.solve(B.scp_params(3, 40, form=form))
+        x1, u1, i1 = (a.cpu().numpy() for a in fresh.result())
+        fresh.solve(B.scp_params(3, 40, form=form))          # warm start: different result
+        x2, _, _ = (a.cpu().numpy() for a in fresh.result())
+        assert not np.array_equal(x1, x2)
+        fresh.reset()
+        fresh.solve(B.scp_params(3, 40, form=form))
+        x3, u3, i3 = (a.cpu().numpy() for a in fresh.result())
+        np.testing.assert_array_equal(x3, x1)
+        np.testing.assert_array_equal(u3, u1)
+        np.testing.assert_array_equal(i3, i1)
+        fresh.close()
