@@ -1,6 +1,6 @@
 """Benchmark of the SCP + consensus-ADMM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096|mix2048] [--no-cpu-baseline]
 
 One step = one full batched solve of the workload from its initial guess (reset of the resident
 state, then linearization, convexification, factorization, ADMM iterations, acceptance and metrics
@@ -11,6 +11,10 @@ Default workload: 1024 independent quadrotor point-mass instances, N = 50, 8 obs
 budget of 15 SCP x 200 ADMM iterations, rho = 1, FP32.  ``value`` is the whole-job throughput
 (solves/s) at that fixed budget; the solves meeting the defect bound 1e-5 are reported next to it
 as goodput.
+
+mix2048: 2048 uneven instances (half quadrotor, half powered descent, N ~ U{20..120}) in one
+persistent kernel with per-instance residual stopping at 1e-4 (caps 15 SCP x 200 ADMM); the
+library's autotuner picks workgroup size, packing and residual-test cadence first, untimed.
 """
 from __future__ import annotations
 
@@ -47,6 +51,11 @@ def workload(name: str):
     if name == "mars4096":
         return dict(name=name, insts=scpgen.config2(4096), scp=15, admm=200, rho=1.0, prec="f32",
                     desc="3-DOF powered-descent Monte Carlo: 4096 instances, N=60, 15 SCP x 200 ADMM, rho=1, FP32")
+    if name == "mix2048":
+        return dict(name=name, insts=scpgen.config3(2048), scp=15, admm=200, rho=1.0, prec="f32", eps=1e-4,
+                    cadences=(1, 5, 10, 25),
+                    desc="uneven batch: 2048 instances, 50% quadrotor (8 obstacles) / 50% powered descent, "
+                         "N ~ U{20..120}, residual stop 1e-4, caps 15 SCP x 200 ADMM, rho=1, FP32, autotuned")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -81,9 +90,10 @@ def kernel_source_hash() -> str:
 
 
 def _oracle_worker(args):
-    inst, scp_iters, admm_iters, rho = args
+    inst, scp_iters, admm_iters, rho, check_every, eps = args
     import oracle
-    p = oracle.default_params(scp_iters=scp_iters, admm_iters=admm_iters, rho_eq=rho, rho_dyn=rho, rho_geo=rho)
+    p = oracle.default_params(scp_iters=scp_iters, admm_iters=admm_iters, rho_eq=rho, rho_dyn=rho, rho_geo=rho,
+                              check_every=check_every, eps_p=eps, eps_d=eps)
     t = oracle.init_traj(inst)
     oracle.scp.scp_group([t], p)
     return oracle.defect(inst, t.xbar, t.ubar)
@@ -91,17 +101,20 @@ def _oracle_worker(args):
 
 def cpu_baseline(wl, sample: int, cores: int) -> dict:
     """The FP64 oracle (as it stands) on a sample of the workload, one process per core.
-    Runs before the GPU is touched (worker processes are forked from a GPU-free parent)."""
+    Runs before the GPU is touched (worker processes are forked from a GPU-free parent).  With a
+    residual stop, the oracle tests every 10 iterations."""
     import multiprocessing as mp
     insts = wl["insts"][:sample]
-    args = [(d, wl["scp"], wl["admm"], wl["rho"]) for d in insts]
+    eps = wl.get("eps", 0.0)
+    args = [(d, wl["scp"], wl["admm"], wl["rho"], 10 if eps > 0 else 0, eps) for d in insts]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         defects = pool.map(_oracle_worker, args, chunksize=1)
     dt = time.perf_counter() - t0
+    stop = f", residual stop {eps:g} tested every 10 iterations" if eps > 0 else ""
     return {"value": round(sample / dt, 3), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {sample} instances of the workload, full {wl['scp']}x{wl['admm']} budget, FP64 NumPy, "
+            "sample": f"first {sample} instances of the workload, {wl['scp']}x{wl['admm']} budget{stop}, FP64 NumPy, "
                       f"{cores} single-threaded worker processes, {dt:.1f} s wall",
             "defect_p50": float(np.median(defects))}
 
@@ -144,10 +157,21 @@ def main(argv=None):
     from paper_2603_10711_amd import binding as B
 
     torch.cuda.init()
-    dev = torch.device("cuda:0")
     insts = wl["insts"]
-    prob = B.Problem(insts, precision=wl["prec"], block=a.block, device="cuda:0")
-    prm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], form="persistent")
+    eps = wl.get("eps", 0.0)
+    check = 0
+    block, pack = a.block, B.PACK_ALIGNED
+    tune = None
+    if "cadences" in wl:
+        prm0 = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], eps=eps, form="persistent")
+        t_tune = time.perf_counter()
+        best, table = B.autotune(insts, prm0, cadences=wl["cadences"], reps=2, precision=wl["prec"], device="cuda:0")
+        tune = {"best": best, "table": table, "seconds": round(time.perf_counter() - t_tune, 2)}
+        check = best["check_every"]
+        if not a.block:
+            block, pack = best["block"], B.PACK_DENSE if best["pack"] == "dense" else B.PACK_ALIGNED
+    prob = B.Problem(insts, precision=wl["prec"], block=block, pack=pack, device="cuda:0")
+    prm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], check_every=check, eps=eps, form="persistent")
     stream = prob.stream
     for _ in range(a.warmup):
         prob.reset()
@@ -172,9 +196,12 @@ def main(argv=None):
     good = int(np.sum(defect <= 1e-5))
     ms_per_step = wall / a.steps * 1e3
     solves_per_s = n * a.steps / wall
-    node_iters = sum((d["N"] + 1) for d in insts) * wl["scp"] * wl["admm"]
-    flops = sum((d["N"] + 1) * flops_per_node_iter(d["model"], d["obstacles"].shape[0]) for d in insts) \
-        * wl["scp"] * wl["admm"]
+    # ADMM iterations actually run per instance (the whole budget unless the residual test stopped it)
+    iters = info[:, 0]
+    node_iters = float(sum((d["N"] + 1) * it for d, it in zip(insts, iters)))
+    flops = float(sum((d["N"] + 1) * it * flops_per_node_iter(d["model"], d["obstacles"].shape[0])
+                      for d, it in zip(insts, iters)))
+    converged = int(np.sum((info[:, 5].astype(np.int64) & B.ST_CONVERGED) != 0))
     kernel_ms = float(np.mean(step_ms))
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     khash = kernel_source_hash()
@@ -184,8 +211,9 @@ def main(argv=None):
     # plain form (state in HBM, host-enqueued kernels) on the same workload
     plain = None
     if a.plain_steps > 0:
-        pp = B.Problem(insts, precision=wl["prec"], device="cuda:0")
-        pprm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], form="plain")
+        pp = B.Problem(insts, precision=wl["prec"], device="cuda:0", stream=torch.cuda.Stream())
+        pprm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], check_every=check, eps=eps, form="plain",
+                            graph=True)
         pp.reset()
         pp.solve(pprm)
         torch.cuda.synchronize()
@@ -201,6 +229,7 @@ def main(argv=None):
         pwall = time.perf_counter() - t1
         pms = np.array([s.elapsed_time(e) for s, e in zip(ps, pe)])
         plain = {"solves_per_s": round(n * a.plain_steps / pwall, 1), "ms_per_step": round(pwall / a.plain_steps * 1e3, 3),
+                 "launches": "one hipGraph replay per solve (captured on the first call)",
                  "latency_ms_p50": round(float(np.percentile(pms, 50)), 3),
                  "latency_ms_p99": round(float(np.percentile(pms, 99)), 3)}
         pp.close()
@@ -219,7 +248,8 @@ def main(argv=None):
         "dtype": "f32" if wl["prec"] == "f32" else "f64",
         "data": "synthetic (seeded generator of the workload's shapes and distributions)",
         "config": {"workload": wl["desc"], "form": "persistent", "instances": n, "nodes": int(sum(d["N"] + 1 for d in insts)),
-                   "block": a.block or "auto"},
+                   "block": block or "auto", "pack": "dense" if pack == B.PACK_DENSE else "aligned",
+                   "check_every": check},
         "goodput_solves_per_s": round(good * a.steps / wall, 1),
         "defect_le_1e-5": f"{good}/{n}",
         "defect_p50": float(np.median(defect)),
@@ -227,6 +257,8 @@ def main(argv=None):
         "latency_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
         "latency_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
         "node_admm_iters_per_s": round(node_iters * a.steps / wall, 1),
+        "converged": f"{converged}/{n}",
+        "autotune": tune,
         "plain": plain,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS if wl["prec"] == "f32" else PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / (PEAK_FP32_TFLOPS if wl["prec"] == "f32" else PEAK_FP64_TFLOPS), 4),

@@ -58,6 +58,8 @@ typedef enum {
                                  factor and ADMM state stay in registers/LDS                    */
 } scp_form;
 
+typedef enum { SCP_PACK_ALIGNED = 0, SCP_PACK_DENSE = 1 } scp_pack;
+
 #define SCP_MAX_NX 7
 #define SCP_MAX_NU 4
 #define SCP_MAX_OBS 8
@@ -137,6 +139,12 @@ typedef struct {
                                  rows per trajectory                                        */
     int32_t block;            /* workgroup size of the persistent kernel: 64, 128 or 256
                                  (0 = smallest that holds the longest trajectory or group) */
+    int32_t pack;             /* SCP_PACK_ALIGNED: a trajectory of at most 64 nodes never
+                                 straddles a wavefront, so workgroups without longer ones
+                                 exchange neighbour values inside the wavefront;
+                                 SCP_PACK_DENSE: first-fit over the whole workgroup (fewer
+                                 idle lanes, LDS exchange when the workgroup has several
+                                 wavefronts).  Results do not depend on it.               */
 } scp_problem_desc;
 
 typedef struct {
@@ -156,6 +164,11 @@ typedef struct {
     scp_form form;                    /* plain (HBM state) or persistent kernel             */
     int32_t scp_per_launch;           /* persistent form: SCP iterations per kernel launch
                                          (0 = all in one launch)                            */
+    int32_t graph;                    /* 1: the first call with these parameters captures its
+                                         whole launch sequence into a hipGraph kept by the
+                                         handle, later calls with equal parameters replay it.
+                                         Needs a stream other than the legacy default stream
+                                         (SCP_ERR_HIP otherwise).  0: direct launches.        */
 } scp_params;
 
 typedef struct scp_problem scp_problem;
@@ -230,8 +243,44 @@ scp_status scp_get_field(const scp_problem* p, int32_t field, void* dst_dev);
 int64_t scp_problem_nodes(const scp_problem* p);
 int64_t scp_traj_node_offset(const scp_problem* p, int32_t t);
 
+/* Host-side plan of the persistent form for a description (pure host computation, no
+ * device access): plan[0] workgroup size, plan[1] workgroups, plan[2] workgroups whose
+ * trajectories straddle a wavefront (LDS neighbour exchange), plan[3] idle lanes.  If
+ * lane_table is not NULL and lane_cap >= plan[0] * plan[1], it receives the node index
+ * (trajectory offset + node) of every lane, -1 for idle lanes.  plan[0] = 0 if no block
+ * holds the longest trajectory or group (the persistent form is then unavailable).
+ * Errors: SCP_ERR_ARG (invalid description, NULL plan). */
+scp_status scp_plan(const scp_problem_desc* desc, int32_t plan[4], int32_t* lane_table, size_t lane_cap);
+
+/* Autotuner of the persistent form (the knobs do not change what is computed, except the
+ * residual-test cadence, which decides at which iteration a converged trajectory stops). */
+typedef struct {
+    int32_t block;        /* workgroup size                                          */
+    int32_t pack;         /* scp_pack                                                */
+    int32_t check_every;  /* residual-test cadence c                                 */
+    int32_t valid;        /* 0 if the candidate does not fit (no timing)             */
+    double ms;            /* mean wall time of one fresh solve on the device, in ms  */
+} scp_tune_entry;
+
+/* Largest arena any candidate of scp_autotune needs (pure host computation); 0 if the
+ * description is invalid. */
+size_t scp_autotune_device_bytes(const scp_problem_desc* desc);
+
+/* Time every candidate (block in {64, 128, 256} (FP64: {64, 128}), pack in {aligned, dense},
+ * check_every in cadences[0..n_cad-1]) on the description's own problem: each candidate
+ * builds the problem in arena_dev, runs one untimed fresh solve with prm (form forced to
+ * persistent) and then `reps` timed fresh solves (HIP events on hip_stream).  Writes up to
+ * table_cap entries to table (n_out = number of candidates) and the fastest valid one to
+ * best.  Synchronizes the stream; the arena's contents are undefined afterwards.  Results are
+ * cached per process, keyed by the description's shape (precision, models, horizons, groups)
+ * and the parameters: a repeated call returns the cached best with *n_out = 0.
+ * Errors: SCP_ERR_ARG, SCP_ERR_HIP, SCP_ERR_UNSUPPORTED (no candidate fits). */
+scp_status scp_autotune(const scp_problem_desc* desc, const scp_params* prm, const int32_t* cadences, int32_t n_cad,
+                        int32_t reps, void* arena_dev, size_t arena_bytes, void* hip_stream,
+                        scp_tune_entry* table, int32_t table_cap, int32_t* n_out, scp_tune_entry* best);
+
 /* Message of the last failed call on this handle ("" if none); for p == NULL, the last
- * error of a failed scp_problem_create in this thread. */
+ * error of a failed scp_problem_create, scp_plan or scp_autotune in this thread. */
 const char* scp_last_error(const scp_problem* p);
 
 #ifdef __cplusplus

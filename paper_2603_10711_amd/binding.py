@@ -22,6 +22,7 @@ SCP_OK = 0
 QUAD, MARS = 1, 2
 F32, F64 = 0, 1
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
+PACK_ALIGNED, PACK_DENSE = 0, 1
 MAX_NX, MAX_NU, MAX_OBS = 7, 4, 8
 P = dict(H=0, XINIT=1, XTGT=8, TMASK=15, QR=22, QN=29, QNV=36, CN=43, R=44, XLO=48, XHI=55, ULO=62, UHI=66,
          UBALL=70, DELTA=71, DRAG=72, MSCALE=73, GRAV=74, ALPHA=75, GVEC=76, GLIDE=79, NOBS=80, OBS=81)
@@ -34,13 +35,13 @@ FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9
               boxhi=14, hs=15)
 SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_destroy", "scp_linearize", "admm_solve",
            "scp_solve", "scp_reset", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
-           "scp_traj_node_offset", "scp_last_error"]
+           "scp_traj_node_offset", "scp_plan", "scp_autotune_device_bytes", "scp_autotune", "scp_last_error"]
 
 
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("n_traj", c_int32), ("prec", c_int32), ("model", POINTER(c_int32)), ("horizon", POINTER(c_int32)),
                 ("group", POINTER(c_int32)), ("params", POINTER(c_double)), ("x_guess", POINTER(c_double)),
-                ("u_guess", POINTER(c_double)), ("block", c_int32)]
+                ("u_guess", POINTER(c_double)), ("block", c_int32), ("pack", c_int32)]
 
 
 class AdmmParams(ctypes.Structure):
@@ -51,7 +52,16 @@ class AdmmParams(ctypes.Structure):
 class ScpParams(ctypes.Structure):
     _fields_ = [("scp_iters", c_int32), ("admm", AdmmParams), ("eta0", c_double), ("eta1", c_double),
                 ("eta2", c_double), ("shrink", c_double), ("grow", c_double), ("delta_max", c_double),
-                ("merit_w", c_double), ("form", c_int32), ("scp_per_launch", c_int32)]
+                ("merit_w", c_double), ("form", c_int32), ("scp_per_launch", c_int32), ("graph", c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("block", c_int32), ("pack", c_int32), ("check_every", c_int32), ("valid", c_int32),
+                ("ms", c_double)]
+
+    def as_dict(self) -> dict:
+        return dict(block=self.block, pack="dense" if self.pack == PACK_DENSE else "aligned",
+                    check_every=self.check_every, valid=bool(self.valid), ms=self.ms)
 
 
 _LIB = None
@@ -89,6 +99,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scp_problem_nodes.restype = c_int64
     lib.scp_traj_node_offset.argtypes = [c_void_p, c_int32]
     lib.scp_traj_node_offset.restype = c_int64
+    lib.scp_plan.argtypes = [POINTER(ProblemDesc), POINTER(c_int32), POINTER(c_int32), c_size_t]
+    lib.scp_plan.restype = c_int32
+    lib.scp_autotune_device_bytes.argtypes = [POINTER(ProblemDesc)]
+    lib.scp_autotune_device_bytes.restype = c_size_t
+    lib.scp_autotune.argtypes = [POINTER(ProblemDesc), POINTER(ScpParams), POINTER(c_int32), c_int32, c_int32,
+                                 c_void_p, c_size_t, c_void_p, POINTER(TuneEntry), c_int32, POINTER(c_int32),
+                                 POINTER(TuneEntry)]
+    lib.scp_autotune.restype = c_int32
     lib.scp_last_error.argtypes = [c_void_p]
     lib.scp_last_error.restype = ctypes.c_char_p
     _LIB = lib
@@ -134,10 +152,76 @@ def admm_params(rho=1.0, iters=100, check_every=0, eps=0.0, rho_dyn=None, rho_ge
 
 def scp_params(scp_iters=10, admm_iters=100, rho=1.0, check_every=0, eps=0.0, form="persistent",
                scp_per_launch=0, eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
-               merit_w=1.0e3, rho_dyn=None, rho_geo=None) -> ScpParams:
+               merit_w=1.0e3, rho_dyn=None, rho_geo=None, graph=False) -> ScpParams:
     f = FORM_PERSISTENT if form == "persistent" else FORM_PLAIN
     return ScpParams(scp_iters, admm_params(rho, admm_iters, check_every, eps, rho_dyn, rho_geo), eta0, eta1, eta2,
-                     shrink, grow, delta_max, merit_w, f, scp_per_launch)
+                     shrink, grow, delta_max, merit_w, f, scp_per_launch, 1 if graph else 0)
+
+
+def _pad(a, w):
+    a = np.asarray(a, dtype=float)
+    out = np.zeros((a.shape[0], w))
+    out[:, :a.shape[1]] = a
+    return out
+
+
+def make_desc(insts: list[dict], prec: int = F32, block: int = 0, pack: int = PACK_ALIGNED):
+    """The C description of a batch; the second value keeps its arrays alive."""
+    model = np.array([d["model"] for d in insts], dtype=np.int32)
+    horizon = np.array([d["N"] for d in insts], dtype=np.int32)
+    group = np.array([d.get("group", -1) for d in insts], dtype=np.int32)
+    params = np.concatenate([param_record(d) for d in insts])
+    xg = np.concatenate([_pad(d["x_guess"], MAX_NX) for d in insts])
+    ug = np.concatenate([_pad(d["u_guess"], MAX_NU) for d in insts])
+    keep = (model, horizon, group, params, xg, ug)
+    desc = ProblemDesc(len(insts), prec, model.ctypes.data_as(POINTER(c_int32)),
+                       horizon.ctypes.data_as(POINTER(c_int32)), group.ctypes.data_as(POINTER(c_int32)),
+                       params.ctypes.data_as(POINTER(c_double)), xg.ctypes.data_as(POINTER(c_double)),
+                       ug.ctypes.data_as(POINTER(c_double)), block, pack)
+    return desc, keep
+
+
+def plan(insts: list[dict], precision: str = "f32", block: int = 0, pack: int = PACK_ALIGNED,
+         lanes: bool = False) -> dict:
+    """Host-side persistent-kernel plan of a batch (no GPU needed)."""
+    lib = load()
+    desc, keep = make_desc(insts, F32 if precision == "f32" else F64, block, pack)
+    out = (c_int32 * 4)()
+    st = lib.scp_plan(byref(desc), out, None, 0)
+    if st != SCP_OK:
+        raise ScpError(f"scp_plan failed ({st}): {lib.scp_last_error(None).decode()}")
+    res = dict(block=out[0], n_wg=out[1], lds_wg=out[2], idle=out[3])
+    if lanes and out[0]:
+        n = out[0] * out[1]
+        tab = np.empty(n, dtype=np.int32)
+        st = lib.scp_plan(byref(desc), out, tab.ctypes.data_as(POINTER(c_int32)), n)
+        if st != SCP_OK:
+            raise ScpError(f"scp_plan failed ({st}): {lib.scp_last_error(None).decode()}")
+        res["lanes"] = tab.reshape(out[1], out[0])
+    return res
+
+
+def autotune(insts: list[dict], prm: ScpParams, cadences=(1, 5, 10, 25), reps: int = 3, precision: str = "f32",
+             device: str = "cuda", stream=None):
+    """Run the library's autotuner on this batch; returns (best, table) as dictionaries."""
+    import torch
+    lib = load()
+    desc, keep = make_desc(insts, F32 if precision == "f32" else F64)
+    nbytes = lib.scp_autotune_device_bytes(byref(desc))
+    if nbytes == 0:
+        raise ScpError("invalid problem description for autotune")
+    arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream(arena.device)
+    cad = (c_int32 * len(cadences))(*cadences)
+    cap = 6 * len(cadences)
+    table = (TuneEntry * cap)()
+    n = c_int32(0)
+    best = TuneEntry()
+    st = lib.scp_autotune(byref(desc), byref(prm), cad, len(cadences), reps, c_void_p(arena.data_ptr()), nbytes,
+                          c_void_p(s.cuda_stream), table, cap, byref(n), byref(best))
+    if st != SCP_OK:
+        raise ScpError(f"scp_autotune failed ({st}): {lib.scp_last_error(None).decode()}")
+    return best.as_dict(), [table[i].as_dict() for i in range(min(n.value, cap))]
 
 
 class ScpError(RuntimeError):
@@ -148,7 +232,7 @@ class Problem:
     """A batch of trajectories resident on the GPU (one arena tensor), driven through the C ABI."""
 
     def __init__(self, insts: list[dict], precision: str = "f32", block: int = 0, device: str = "cuda",
-                 stream=None):
+                 stream=None, pack: int = PACK_ALIGNED):
         import torch
         self.torch = torch
         self.lib = load()
@@ -156,17 +240,7 @@ class Problem:
         self.n_traj = len(insts)
         self.prec = F32 if precision == "f32" else F64
         self.dtype = torch.float32 if self.prec == F32 else torch.float64
-        model = np.array([d["model"] for d in insts], dtype=np.int32)
-        horizon = np.array([d["N"] for d in insts], dtype=np.int32)
-        group = np.array([d.get("group", -1) for d in insts], dtype=np.int32)
-        params = np.concatenate([param_record(d) for d in insts])
-        xg = np.concatenate([self._pad(d["x_guess"], MAX_NX) for d in insts])
-        ug = np.concatenate([self._pad(d["u_guess"], MAX_NU) for d in insts])
-        self._keep = (model, horizon, group, params, xg, ug)
-        desc = ProblemDesc(self.n_traj, self.prec, model.ctypes.data_as(POINTER(c_int32)),
-                           horizon.ctypes.data_as(POINTER(c_int32)), group.ctypes.data_as(POINTER(c_int32)),
-                           params.ctypes.data_as(POINTER(c_double)), xg.ctypes.data_as(POINTER(c_double)),
-                           ug.ctypes.data_as(POINTER(c_double)), block)
+        desc, self._keep = make_desc(insts, self.prec, block, pack)
         nbytes = self.lib.scp_problem_device_bytes(byref(desc))
         if nbytes == 0:
             h = c_void_p()
@@ -175,6 +249,8 @@ class Problem:
         self.nbytes = nbytes
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        if self.stream != torch.cuda.current_stream(self.arena.device):
+            self.arena.record_stream(self.stream)
         h = c_void_p()
         st = self.lib.scp_problem_create(byref(desc), c_void_p(self.arena.data_ptr()), nbytes,
                                          c_void_p(self.stream.cuda_stream), byref(h))
@@ -186,10 +262,7 @@ class Problem:
 
     @staticmethod
     def _pad(a, w):
-        a = np.asarray(a, dtype=float)
-        out = np.zeros((a.shape[0], w))
-        out[:, :a.shape[1]] = a
-        return out
+        return _pad(a, w)
 
     def _check(self, st, what):
         if st != SCP_OK:
@@ -213,7 +286,14 @@ class Problem:
         w = self.lib.scp_field_width(fid)
         out = self.torch.empty((self.n_nodes, w), dtype=self.dtype, device=self.arena.device)
         self._check(self.lib.scp_get_field(self.h, fid, c_void_p(out.data_ptr())), "scp_get_field")
+        self._join()
         return out
+
+    def _join(self):
+        """Order the caller's current stream after the work enqueued on the problem's stream."""
+        cur = self.torch.cuda.current_stream(self.arena.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     def result(self):
         """(x, u, info) as device tensors: x (nodes, 7), u (nodes, 4), info (n_traj, 12) float64."""
@@ -223,6 +303,7 @@ class Problem:
         info = t.empty((self.n_traj, INFO_FIELDS), dtype=t.float64, device=self.arena.device)
         self._check(self.lib.scp_get_result(self.h, c_void_p(x.data_ptr()), c_void_p(u.data_ptr()),
                                             c_void_p(info.data_ptr())), "scp_get_result")
+        self._join()
         return x, u, info
 
     def split(self, arr: np.ndarray, t: int, width: int | None = None, controls: bool = False) -> np.ndarray:

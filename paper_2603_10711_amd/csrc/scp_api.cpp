@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -35,7 +37,7 @@ struct Layout {
     size_t o_traj, o_node_traj, o_lane, o_groups, o_params, o_planes, o_rt, o_info, o_flags, o_red, total;
     std::vector<int> traj;       // n_traj * TR_FIELDS
     std::vector<int> node_traj;  // P
-    std::vector<int> lane;       // n_wg * block + n_wg (per-workgroup model ids)
+    std::vector<int> lane;       // n_wg * block lanes, then per workgroup: model id | wavefront-crossing flag << 8
     std::vector<int> groups;     // first trajectory of each multi-member group
 };
 
@@ -49,38 +51,75 @@ struct Unit {
     int first_traj, n_traj, lanes, model;
 };
 
+// Aligned packing: a unit of at most 64 lanes never straddles a wavefront boundary and a longer
+// unit starts on one.  Dense packing: first fit over the whole workgroup.  A workgroup in which
+// no unit straddles a wavefront boundary gets wg_cross = 0 and exchanges neighbour values with
+// wavefront shifts; the others exchange them through LDS.
 bool pack(const std::vector<Unit>& units, const std::vector<int>& traj_off, const std::vector<int>& horizon,
-          int block, std::vector<int>& lane, std::vector<int>& wg_model, int& n_wg) {
+          int block, bool aligned, std::vector<int>& lane, std::vector<int>& wg_model, std::vector<int>& wg_cross,
+          int& n_wg) {
+    constexpr int W = 64;
+    const int nw = aligned ? block / W : 1;   // fill slots per workgroup
+    const int cap = aligned ? W : block;      // lanes per fill slot
     lane.clear();
     wg_model.clear();
+    wg_cross.clear();
     n_wg = 0;
     for (int model : {SCP_MODEL_QUAD_PM, SCP_MODEL_MARS3DOF}) {
         std::vector<int> idx;
         for (int u = 0; u < (int)units.size(); ++u)
             if (units[u].model == model) idx.push_back(u);
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return units[a].lanes > units[b].lanes; });
-        std::vector<int> fill;  // used lanes of this model's workgroups
-        std::vector<int> wgs;   // global workgroup index
+        std::vector<std::vector<int>> fill;  // used lanes of every fill slot of this model's workgroups
+        std::vector<int> wgs;                // global workgroup index
+        auto new_wg = [&]() {
+            fill.emplace_back(nw, 0);
+            wgs.push_back(n_wg++);
+            lane.resize((size_t)n_wg * block, -1);
+            wg_model.push_back(model);
+            wg_cross.push_back(0);
+            return (int)fill.size() - 1;
+        };
         for (int u : idx) {
             const Unit& un = units[u];
             if (un.lanes > block) return false;
-            int w = -1;
-            for (int q = 0; q < (int)fill.size(); ++q)
-                if (fill[q] + un.lanes <= block) {
-                    w = q;
-                    break;
-                }
-            if (w < 0) {
-                w = (int)fill.size();
-                fill.push_back(0);
-                wgs.push_back(n_wg++);
-                lane.resize((size_t)n_wg * block, -1);
-                wg_model.push_back(model);
+            int wq = -1, wv = -1;
+            if (un.lanes <= cap) {
+                for (int q = 0; q < (int)fill.size() && wq < 0; ++q)
+                    for (int v = 0; v < nw; ++v)
+                        if (fill[q][v] + un.lanes <= cap) {
+                            wq = q;
+                            wv = v;
+                            break;
+                        }
+            } else {
+                const int k = (un.lanes + cap - 1) / cap;  // fill slots spanned, all empty
+                for (int q = 0; q < (int)fill.size() && wq < 0; ++q)
+                    for (int v = 0; v + k <= nw; ++v) {
+                        bool empty = true;
+                        for (int e = v; e < v + k; ++e) empty = empty && fill[q][e] == 0;
+                        if (empty) {
+                            wq = q;
+                            wv = v;
+                            break;
+                        }
+                    }
             }
-            int base = wgs[w] * block + fill[w];
+            if (wq < 0) {
+                wq = new_wg();
+                wv = 0;
+            }
+            const int off = wv * cap + fill[wq][wv];  // lane offset inside the workgroup
+            if (off / W != (off + un.lanes - 1) / W) wg_cross[wgs[wq]] = 1;
+            int base = wgs[wq] * block + off;
             for (int t = un.first_traj; t < un.first_traj + un.n_traj; ++t)
                 for (int i = 0; i <= horizon[t]; ++i) lane[base++] = traj_off[t] + i;
-            fill[w] += un.lanes;
+            int rest = un.lanes;
+            for (int v = wv; rest > 0; ++v) {
+                const int take = std::min(rest, cap - fill[wq][v]);
+                fill[wq][v] += take;
+                rest -= take;
+            }
         }
     }
     return true;
@@ -92,6 +131,7 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     if (d->prec != SCP_F32 && d->prec != SCP_F64) { err = "invalid precision"; return false; }
     if (!d->model || !d->horizon || !d->params || !d->x_guess || !d->u_guess) { err = "NULL array in desc"; return false; }
     if (d->block != 0 && d->block != 64 && d->block != 128 && d->block != 256) { err = "block must be 0, 64, 128 or 256"; return false; }
+    if (d->pack != SCP_PACK_ALIGNED && d->pack != SCP_PACK_DENSE) { err = "pack must be SCP_PACK_ALIGNED or SCP_PACK_DENSE"; return false; }
     L.n_traj = d->n_traj;
     L.esz = d->prec == SCP_F32 ? 4 : 8;
     L.traj.assign((size_t)L.n_traj * TR_FIELDS, 0);
@@ -173,9 +213,9 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     double best_score = 0.0;
     for (int b : cands) {
         if (max_unit > b) continue;
-        std::vector<int> lane, wgm;
+        std::vector<int> lane, wgm, wgc;
         int nwg = 0;
-        if (!pack(units, traj_off, horizon, b, lane, wgm, nwg)) continue;
+        if (!pack(units, traj_off, horizon, b, d->pack == SCP_PACK_ALIGNED, lane, wgm, wgc, nwg)) continue;
         const long idle = (long)nwg * b - L.n_nodes;
         const double waves = (double)nwg * (b / 64);
         const double score = std::ceil(waves / 1024.0) * (1.0 + 0.05 * (b / 64 - 1));
@@ -185,7 +225,7 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
             L.block = b;
             L.n_wg = nwg;
             L.lane = lane;
-            L.lane.insert(L.lane.end(), wgm.begin(), wgm.end());
+            for (int w = 0; w < nwg; ++w) L.lane.push_back(wgm[w] | (wgc[w] << 8));
         }
     }
     L.persistent_ok = best_idle >= 0;
@@ -242,6 +282,11 @@ struct scp_problem {
     bool linearized = false;
     double lin_rho[3] = {1.0, 1.0, 1.0};
     std::string err;
+    // scp_solve launch sequences captured into graphs, keyed by their parameters
+    std::vector<std::pair<scp_params, hipGraphExec_t>> graphs;
+    ~scp_problem() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    }
 };
 
 namespace {
@@ -284,6 +329,16 @@ bool admm_valid(const admm_params* a, std::string& err) {
     if (!(a->rho_eq > 0) || !(a->rho_dyn > 0) || !(a->rho_geo > 0)) { err = "penalties must be positive"; return false; }
     if (a->max_iters < 0 || a->check_every < 0) { err = "iteration counts must be >= 0"; return false; }
     return true;
+}
+
+bool same_params(const scp_params& a, const scp_params& b) {
+    return a.scp_iters == b.scp_iters && a.admm.rho_eq == b.admm.rho_eq && a.admm.rho_dyn == b.admm.rho_dyn &&
+           a.admm.rho_geo == b.admm.rho_geo && a.admm.max_iters == b.admm.max_iters &&
+           a.admm.check_every == b.admm.check_every && a.admm.eps_prim == b.admm.eps_prim &&
+           a.admm.eps_dual == b.admm.eps_dual && std::memcmp(&a.eta0, &b.eta0, sizeof(double)) == 0 &&
+           a.eta1 == b.eta1 && a.eta2 == b.eta2 && a.shrink == b.shrink && a.grow == b.grow &&
+           std::memcmp(&a.delta_max, &b.delta_max, sizeof(double)) == 0 && a.merit_w == b.merit_w &&
+           a.form == b.form && a.scp_per_launch == b.scp_per_launch;
 }
 
 template <class T>
@@ -377,6 +432,29 @@ void stage_problem(const scp_problem_desc* d, const Layout& L, std::vector<char>
     img_rt.assign((size_t)L.n_traj * RT_FIELDS * sizeof(T), 0);
     T* rt = reinterpret_cast<T*>(img_rt.data());
     for (int t = 0; t < L.n_traj; ++t) rt[t * RT_FIELDS + RT_DELTA] = T(d->params[(size_t)t * SCP_PARAM_STRIDE + SCP_P_DELTA]);
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, scp_tune_entry> g_tune_cache;
+
+// Cache key of the autotuner: problem shape (precision, model, horizon, obstacle count and group
+// layout of every trajectory), the solve parameters and the cadence list.
+std::string tune_key(const scp_problem_desc* d, const scp_params* q, const std::vector<int>& cads) {
+    std::string k = std::to_string(d->prec) + "|" + std::to_string(d->n_traj) + "|";
+    for (int t = 0; t < d->n_traj; ++t) {
+        const int K = (int)d->params[(size_t)t * SCP_PARAM_STRIDE + SCP_P_NOBS];
+        const int same = (d->group && t > 0 && d->group[t] >= 0 && d->group[t] == d->group[t - 1]) ? 1 : 0;
+        k += std::to_string(d->model[t]) + "," + std::to_string(d->horizon[t]) + "," + std::to_string(K) + "," +
+             std::to_string(same) + ";";
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "|%d|%.17g,%.17g,%.17g,%d,%.17g,%.17g|%.17g,%.17g,%.17g,%.17g,%.17g,%.17g,%.17g|%d|",
+                  q->scp_iters, q->admm.rho_eq, q->admm.rho_dyn, q->admm.rho_geo, q->admm.max_iters,
+                  q->admm.eps_prim, q->admm.eps_dual, q->eta0, q->eta1, q->eta2, q->shrink, q->grow, q->delta_max,
+                  q->merit_w, q->scp_per_launch);
+    k += buf;
+    for (int c : cads) k += std::to_string(c) + ",";
+    return k;
 }
 
 }  // namespace
@@ -480,7 +558,39 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
     if (!admm_valid(&prm->admm, err)) return fail(p, SCP_ERR_ARG, err);
     if (prm->scp_iters < 0) return fail(p, SCP_ERR_ARG, "scp_iters must be >= 0");
     if (prm->form != SCP_FORM_PLAIN && prm->form != SCP_FORM_PERSISTENT) return fail(p, SCP_ERR_ARG, "invalid form");
-    scp_status st = p->prec == SCP_F32 ? do_solve<float>(p, prm) : do_solve<double>(p, prm);
+    if (prm->graph != 0 && prm->graph != 1) return fail(p, SCP_ERR_ARG, "graph must be 0 or 1");
+    if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok)
+        return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory or consensus group exceeds 256 nodes; use the plain form");
+    scp_status st = SCP_OK;
+    if (!prm->graph) {
+        st = p->prec == SCP_F32 ? do_solve<float>(p, prm) : do_solve<double>(p, prm);
+    } else {
+        hipGraphExec_t exec = nullptr;
+        for (auto& g : p->graphs)
+            if (same_params(g.first, *prm)) exec = g.second;
+        if (!exec) {
+            hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();  // the launch checks that follow must not see this error
+                return hip_check(p, e, "graph capture (the stream must not be the legacy default stream)");
+            }
+            st = p->prec == SCP_F32 ? do_solve<float>(p, prm) : do_solve<double>(p, prm);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(p->stream, &graph);
+            if (st != SCP_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return hip_check(p, e, "graph capture");
+            }
+            p->graphs.emplace_back(*prm, exec);
+        }
+        st = hip_check(p, hipGraphLaunch(exec, p->stream), "graph launch");
+    }
     if (st == SCP_OK) {
         p->linearized = false;
     }
@@ -564,6 +674,144 @@ int64_t scp_problem_nodes(const scp_problem* p) { return p ? p->L.n_nodes : 0; }
 int64_t scp_traj_node_offset(const scp_problem* p, int32_t t) {
     if (!p || t < 0 || t >= p->L.n_traj) return -1;
     return p->L.traj[(size_t)t * TR_FIELDS + TR_OFF];
+}
+
+scp_status scp_plan(const scp_problem_desc* desc, int32_t plan[4], int32_t* lane_table, size_t lane_cap) {
+    g_create_error.clear();
+    if (!plan) {
+        g_create_error = "plan is NULL";
+        return SCP_ERR_ARG;
+    }
+    Layout L;
+    std::string err;
+    if (!build_layout(desc, L, err)) {
+        g_create_error = err;
+        return SCP_ERR_ARG;
+    }
+    const size_t lanes = (size_t)L.n_wg * L.block;
+    int cross = 0;
+    for (int w = 0; w < L.n_wg; ++w) cross += (L.lane[lanes + w] >> 8) & 1;
+    plan[0] = L.persistent_ok ? L.block : 0;
+    plan[1] = L.n_wg;
+    plan[2] = cross;
+    plan[3] = L.persistent_ok ? (int32_t)((long long)lanes - L.n_nodes) : 0;
+    if (lane_table && L.persistent_ok && lane_cap >= lanes) std::memcpy(lane_table, L.lane.data(), lanes * sizeof(int32_t));
+    return SCP_OK;
+}
+
+size_t scp_autotune_device_bytes(const scp_problem_desc* desc) {
+    if (!desc) return 0;
+    size_t best = 0;
+    for (int b : {64, 128, 256})
+        for (int pk : {SCP_PACK_ALIGNED, SCP_PACK_DENSE}) {
+            scp_problem_desc d = *desc;
+            d.block = b;
+            d.pack = pk;
+            Layout L;
+            std::string err;
+            if (!build_layout(&d, L, err)) return 0;
+            best = std::max(best, L.total);
+        }
+    return best;
+}
+
+scp_status scp_autotune(const scp_problem_desc* desc, const scp_params* prm, const int32_t* cadences, int32_t n_cad,
+                        int32_t reps, void* arena_dev, size_t arena_bytes, void* hip_stream, scp_tune_entry* table,
+                        int32_t table_cap, int32_t* n_out, scp_tune_entry* best) {
+    g_create_error.clear();
+    auto bad = [](const std::string& m, scp_status st = SCP_ERR_ARG) {
+        g_create_error = m;
+        return st;
+    };
+    if (!desc || !prm || !n_out || !best) return bad("NULL argument");
+    if (reps < 1) return bad("reps must be >= 1");
+    if (n_cad < 0 || (n_cad > 0 && !cadences)) return bad("invalid cadence list");
+    std::string err;
+    if (!admm_valid(&prm->admm, err)) return bad(err);
+    if (prm->scp_iters < 0) return bad("scp_iters must be >= 0");
+    {
+        Layout L;
+        if (!build_layout(desc, L, err)) return bad(err);
+    }
+    std::vector<int> cads(cadences, cadences + n_cad);
+    if (cads.empty()) cads.push_back(prm->admm.check_every);
+    for (int c : cads)
+        if (c < 0) return bad("cadences must be >= 0");
+    *n_out = 0;
+    const std::string key = tune_key(desc, prm, cads);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *best = it->second;
+            return SCP_OK;
+        }
+    }
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipError_t e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    scp_status st = SCP_OK;
+    int count = 0;
+    bool found = false;
+    scp_tune_entry b{};
+    for (int blk : {64, 128, 256}) {
+        for (int pk : {SCP_PACK_ALIGNED, SCP_PACK_DENSE}) {
+            if (e != hipSuccess || st != SCP_OK) break;
+            if (blk == 64 && pk == SCP_PACK_DENSE) continue;  // one wavefront: both packings coincide
+            scp_problem_desc d = *desc;
+            d.block = blk;
+            d.pack = pk;
+            Layout L;
+            const bool fits = build_layout(&d, L, err) && L.persistent_ok && L.total <= arena_bytes;
+            scp_problem* p = nullptr;
+            if (fits) {
+                st = scp_problem_create(&d, arena_dev, arena_bytes, hip_stream, &p);
+                if (st != SCP_OK) break;
+            }
+            for (int c : cads) {
+                scp_tune_entry en{blk, pk, c, 0, 0.0};
+                if (p) {
+                    scp_params q = *prm;
+                    q.form = SCP_FORM_PERSISTENT;
+                    q.graph = 0;
+                    q.admm.check_every = c;
+                    st = scp_reset(p);
+                    if (st == SCP_OK) st = scp_solve(p, &q);
+                    if (st == SCP_OK) e = hipEventRecord(ev0, stream);
+                    for (int r = 0; r < reps && st == SCP_OK && e == hipSuccess; ++r) {
+                        st = scp_reset(p);
+                        if (st == SCP_OK) st = scp_solve(p, &q);
+                    }
+                    if (st == SCP_OK && e == hipSuccess) e = hipEventRecord(ev1, stream);
+                    if (st == SCP_OK && e == hipSuccess) e = hipEventSynchronize(ev1);
+                    float ms = 0.f;
+                    if (st == SCP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+                    if (st != SCP_OK) g_create_error = p->err;
+                    if (st != SCP_OK || e != hipSuccess) break;
+                    en.valid = 1;
+                    en.ms = (double)ms / reps;
+                    if (!found || en.ms < b.ms) {
+                        b = en;
+                        found = true;
+                    }
+                }
+                if (table && count < table_cap) table[count] = en;
+                ++count;
+            }
+            scp_problem_destroy(p);
+        }
+    }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    *n_out = count;
+    if (st != SCP_OK) return st;
+    if (e != hipSuccess) return bad(std::string("autotune timing: ") + hipGetErrorString(e), SCP_ERR_HIP);
+    if (!found) return bad("no candidate workgroup size holds the longest trajectory or group", SCP_ERR_UNSUPPORTED);
+    *best = b;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = b;
+    return SCP_OK;
 }
 
 const char* scp_last_error(const scp_problem* p) {

@@ -30,12 +30,13 @@ struct Shared {
     int st[BLOCK];                 // per-trajectory status bits at the first lane
 };
 
-template <class M, class T, int BLOCK>
+// WAVE1: no trajectory of this workgroup straddles a wavefront boundary, so neighbour values
+// move with DPP wavefront shifts instead of LDS and the two exchange barriers of every ADMM
+// iteration disappear.  The per-trajectory reductions still go through LDS.
+template <class M, class T, int BLOCK, bool WAVE1>
 __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK>& sh,
                                                 const int t, const int gn) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, C = M::C;
-    // one-wavefront workgroups exchange neighbour values with DPP wave shifts instead of LDS
-    constexpr bool WAVE1 = (BLOCK == 64);
     const int P = dv.P;
     const bool valid = gn >= 0;
     NodeId id{0, 0, 0, false};
@@ -474,19 +475,33 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
 }
 
+template <class M, class T, int BLOCK>
+__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK>& sh, const int t,
+                                         const int gn, const bool cross) {
+    if constexpr (BLOCK == 64) {
+        persistent_body<M, T, BLOCK, true>(dv, kp, sh, t, gn);
+    } else {
+        if (cross) persistent_body<M, T, BLOCK, false>(dv, kp, sh, t, gn);
+        else persistent_body<M, T, BLOCK, true>(dv, kp, sh, t, gn);
+    }
+}
+
 // MODELS: 1 quadrotor only, 2 powered descent only, 3 both (each workgroup holds one model).
+// wg_info[w] = model id | (1 << 8 if a trajectory of workgroup w straddles a wavefront).
 template <class T, int BLOCK, int MODELS, int KM>
-__global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp, const int* __restrict__ wg_model) {
+__global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp, const int* __restrict__ wg_info) {
     __shared__ Shared<T, BLOCK> sh;
     const int t = threadIdx.x;
     const int gn = dv.lane_node[(size_t)blockIdx.x * BLOCK + t];
+    const int wi = wg_info[blockIdx.x];
+    const bool cross = (wi >> 8) & 1;
     if constexpr (MODELS == 1) {
-        persistent_body<Quad<KM>, T, BLOCK>(dv, kp, sh, t, gn);
+        body_for<Quad<KM>, T, BLOCK>(dv, kp, sh, t, gn, cross);
     } else if constexpr (MODELS == 2) {
-        persistent_body<Mars, T, BLOCK>(dv, kp, sh, t, gn);
+        body_for<Mars, T, BLOCK>(dv, kp, sh, t, gn, cross);
     } else {
-        if (wg_model[blockIdx.x] == SCP_MODEL_QUAD_PM) persistent_body<Quad<KM>, T, BLOCK>(dv, kp, sh, t, gn);
-        else persistent_body<Mars, T, BLOCK>(dv, kp, sh, t, gn);
+        if ((wi & 0xff) == SCP_MODEL_QUAD_PM) body_for<Quad<KM>, T, BLOCK>(dv, kp, sh, t, gn, cross);
+        else body_for<Mars, T, BLOCK>(dv, kp, sh, t, gn, cross);
     }
 }
 
@@ -509,7 +524,7 @@ static hipError_t launch_block(const Dev<T>& dv, const KParams<T>& kp, int n_wg,
 template <class T>
 hipError_t launch_persistent(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int block, int models, int kmax,
                              hipStream_t s) {
-    const int* wg_model = dv.lane_node + (size_t)n_wg * block;  // per-workgroup model ids follow the lane table
+    const int* wg_model = dv.lane_node + (size_t)n_wg * block;  // per-workgroup records follow the lane table
     switch (block) {
         case 64: return launch_block<T, 64>(dv, kp, n_wg, models, kmax, wg_model, s);
         case 128: return launch_block<T, 128>(dv, kp, n_wg, models, kmax, wg_model, s);

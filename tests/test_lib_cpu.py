@@ -35,18 +35,10 @@ def test_library_exports_every_declared_symbol(B):
     assert sorted(B.SYMBOLS) == names
 
 
-def _desc(B, insts, prec=0, block=0, group=None):
-    model = np.array([d["model"] for d in insts], dtype=np.int32)
-    hz = np.array([d["N"] for d in insts], dtype=np.int32)
-    grp = np.array([d.get("group", -1) for d in insts] if group is None else group, dtype=np.int32)
-    params = np.concatenate([B.param_record(d) for d in insts])
-    xg = np.concatenate([B.Problem._pad(d["x_guess"], 7) for d in insts])
-    ug = np.concatenate([B.Problem._pad(d["u_guess"], 4) for d in insts])
-    keep = (model, hz, grp, params, xg, ug)
-    d = B.ProblemDesc(len(insts), prec, model.ctypes.data_as(POINTER(c_int32)), hz.ctypes.data_as(POINTER(c_int32)),
-                      grp.ctypes.data_as(POINTER(c_int32)), params.ctypes.data_as(POINTER(c_double)),
-                      xg.ctypes.data_as(POINTER(c_double)), ug.ctypes.data_as(POINTER(c_double)), block)
-    return d, keep
+def _desc(B, insts, prec=0, block=0, group=None, pack=0):
+    if group is not None:
+        insts = [dict(d, group=g) for d, g in zip(insts, group)]
+    return B.make_desc(insts, prec, block, pack)
 
 
 def test_device_bytes_and_field_widths(B):
@@ -60,12 +52,14 @@ def test_device_bytes_and_field_widths(B):
     assert lib.scp_field_width(99) == 0
 
 
-@pytest.mark.parametrize("case", ["model", "horizon", "obstacles", "block", "group_gap", "group_shape", "delta"])
+@pytest.mark.parametrize("case", ["model", "horizon", "obstacles", "block", "pack", "group_gap", "group_shape",
+                                  "delta"])
 def test_invalid_descriptions_rejected_on_host(B, case):
     lib = B.load()
     insts = scpgen.config1(3)
     group = None
     block = 0
+    pack = 0
     if case == "model":
         insts[1] = dict(insts[1], model=9)
     elif case == "horizon":
@@ -74,6 +68,8 @@ def test_invalid_descriptions_rejected_on_host(B, case):
         insts[0] = dict(insts[0], obstacles=np.zeros((9, 4)))
     elif case == "block":
         block = 96
+    elif case == "pack":
+        pack = 2
     elif case == "group_gap":
         group = [5, -1, 5]
     elif case == "group_shape":
@@ -85,7 +81,7 @@ def test_invalid_descriptions_rejected_on_host(B, case):
     if case == "horizon":
         insts[2]["x_guess"] = insts[2]["x_guess"][:1]
         insts[2]["u_guess"] = insts[2]["u_guess"][:0]
-    d, keep = _desc(B, insts, block=block, group=group)
+    d, keep = _desc(B, insts, block=block, group=group, pack=pack)
     assert lib.scp_problem_device_bytes(byref(d)) == 0
     h = c_void_p()
     st = lib.scp_problem_create(byref(d), None, 0, None, byref(h))

@@ -1,0 +1,97 @@
+"""Host-side packing of trajectories into persistent-kernel workgroups (no GPU needed).
+
+The plan must place every node of every trajectory exactly once, keep each trajectory (and each
+consensus group) contiguous inside one workgroup, and, in aligned mode, never let a trajectory of
+at most 64 nodes straddle a wavefront.  Workgroups flagged for the LDS exchange are exactly the
+ones in which some trajectory straddles a wavefront.
+"""
+import numpy as np
+import pytest
+
+import scpgen
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2603_10711_amd import binding
+    try:
+        binding.load()
+    except RuntimeError as e:
+        pytest.skip(str(e))
+    return binding
+
+
+def _check_plan(insts, pl):
+    block, n_wg, lanes = pl["block"], pl["n_wg"], pl["lanes"]
+    assert lanes.shape == (n_wg, block)
+    offs = np.cumsum([0] + [d["N"] + 1 for d in insts])
+    nodes = lanes[lanes >= 0]
+    assert np.array_equal(np.sort(nodes), np.arange(offs[-1]))          # every node exactly once
+    assert pl["idle"] == n_wg * block - offs[-1]
+    straddle = np.zeros(n_wg, dtype=bool)
+    where = {int(g): (w, l) for w in range(n_wg) for l, g in enumerate(lanes[w]) if g >= 0}
+    for t, d in enumerate(insts):
+        w0, l0 = where[int(offs[t])]
+        for i in range(d["N"] + 1):
+            assert where[int(offs[t] + i)] == (w0, l0 + i)                 # contiguous, one workgroup
+        if l0 // 64 != (l0 + d["N"]) // 64:
+            straddle[w0] = True
+    return straddle
+
+
+@pytest.mark.parametrize("block", [128, 256])
+@pytest.mark.parametrize("pack", [0, 1])
+def test_uneven_mix_plan_invariants(B, block, pack):
+    insts = scpgen.config3(300)
+    pl = B.plan(insts, block=block, pack=pack, lanes=True)
+    assert pl["block"] == block
+    straddle = _check_plan(insts, pl)
+    assert pl["lds_wg"] == int(straddle.sum())
+    if pack == 0:
+        offs = np.cumsum([0] + [d["N"] + 1 for d in insts])
+        for t, d in enumerate(insts):
+            if d["N"] + 1 <= 64:
+                w = np.argwhere(pl["lanes"] == offs[t])[0]
+                assert w[1] // 64 == (w[1] + d["N"]) // 64
+    # one model per workgroup
+    model = np.repeat([d["model"] for d in insts], [d["N"] + 1 for d in insts])
+    for w in range(pl["n_wg"]):
+        row = pl["lanes"][w]
+        assert len(set(model[row[row >= 0]])) == 1
+
+
+def test_short_trajectories_alone_use_wavefront_exchange(B):
+    """Trajectories of at most 64 nodes, aligned packing: no workgroup needs the LDS exchange even
+    at 256 lanes; dense packing of the same batch does straddle."""
+    insts = [scpgen.quad_instance(1, i, N=20 + (i * 13) % 40, K=2) for i in range(40)]
+    al = B.plan(insts, block=256, pack=0, lanes=True)
+    _check_plan(insts, al)
+    assert al["lds_wg"] == 0
+    de = B.plan(insts, block=256, pack=1, lanes=True)
+    _check_plan(insts, de)
+    assert de["lds_wg"] > 0 and de["idle"] <= al["idle"]
+
+
+def test_groups_stay_whole_and_auto_block(B):
+    reqs = scpgen.config4_request(0, S=3, N=30) + scpgen.config4_request(1, S=2, N=50)
+    pl = B.plan(reqs, lanes=True)
+    assert pl["block"] == 128                       # a 3 x 31 group needs more than one wavefront
+    _check_plan(reqs, pl)
+    lanes = pl["lanes"]
+    w0 = np.argwhere(lanes == 0)[0][0]
+    assert set(range(93)) <= set(lanes[w0][lanes[w0] >= 0].tolist())
+    assert B.plan(scpgen.config1(64))["block"] == 64
+    too_long = [scpgen.quad_instance(0, 0, N=300, K=1)]
+    assert B.plan(too_long)["block"] == 0           # persistent form unavailable
+
+
+def test_autotune_arena_covers_every_candidate(B):
+    from ctypes import byref
+    lib = B.load()
+    insts = scpgen.config3(64)
+    d, keep = B.make_desc(insts)
+    auto = lib.scp_autotune_device_bytes(byref(d))
+    for blk in (64, 128, 256):
+        for pk in (0, 1):
+            d2, keep2 = B.make_desc(insts, 0, blk, pk)
+            assert lib.scp_problem_device_bytes(byref(d2)) <= auto
