@@ -28,4 +28,4 @@ from .dynamics import f_cont, jac_cont, rk4, rk4_jac  # noqa: F401
 from .sets import proj_box, proj_halfspace, proj_ball, proj_soc, proj_cone  # noqa: F401
 from .admm import Group, QP, AdmmState, build_H, admm_run, residuals  # noqa: F401
 from .scp import (linearize, convexify, scp_solve, default_params, defect, cost,  # noqa: F401
-                  violation, boundary_error, Traj, init_traj, shift_warm_start)
+                  violation, boundary_error, Traj, init_traj, shift_warm_start, mpc_session)

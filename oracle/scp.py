@@ -325,21 +325,66 @@ def scp_solve(insts: list[dict], params: dict | None = None):
     return sols, infos
 
 
-def shift_warm_start(traj: Traj):
-    """MPC warm start (Sec. IV-A.4): shift the trajectory and its ADMM state by one node,
-    repeating the last node, so the next solve starts from the previous tube."""
-    def sh(a):
-        b = np.array(a, copy=True)
+def shift_warm_start(trajs: list[Traj], next_insts: list[dict] | None = None) -> list[Traj]:
+    """MPC warm start of the next request of a session (Sec. IV-A.4, receding horizon).
+
+    Reading (the paper gives no formula): the next request starts one node later along the
+    previous solution of every scenario.
+      * state-indexed rows (nominal x, lambda, mu, duals of state groups; N+1 rows): row i takes
+        row i+1 for i < N, row N is repeated;
+      * control-indexed rows (nominal u, duals of control groups; rows 0..N-1): row i takes row
+        i+1 for i < N-1, row N-1 is repeated;
+      * lambda_0 = mu_0 = 0 (node 0 has no dynamic coupling), and every dual at a node where its
+        group does not exist is 0;
+      * the new initial state, for every scenario, is the previous scenario-0 nominal at node 1.
+    The trust radius and the iteration records start afresh (the caller's scp_group does so).
+    Returns new Traj objects; their instances are next_insts (the next request's data, same
+    shapes) or copies of the previous ones, with the new x_init.  The inputs are unchanged.
+    """
+    x_init = np.array(trajs[0].xbar[1], dtype=float, copy=True)
+
+    def sh_x(a):
+        b = np.array(a, dtype=float, copy=True)
         b[:-1] = a[1:]
         return b
-    traj.xbar = sh(traj.xbar)
-    traj.ubar = sh(traj.ubar)
-    st = traj.state
-    if st is not None:
-        st.lam = sh(st.lam)
-        st.mu = sh(st.mu)
-        st.lam[0] = 0.0
-        st.mu[0] = 0.0
-        for gi in range(len(st.dual)):
-            st.dual[gi] = sh(st.dual[gi])
-    return traj
+
+    def sh_u(a, N):
+        b = np.array(a, dtype=float, copy=True)
+        b[:N - 1] = a[1:N]
+        return b
+
+    out = []
+    for k, t in enumerate(trajs):
+        inst = dict(t.inst if next_insts is None else next_insts[k])
+        inst["x_init"] = x_init.copy()
+        N = inst["N"]
+        nt = Traj(inst, sh_x(t.xbar), sh_u(t.ubar, N))
+        st = t.state
+        if st is not None:
+            ns = AdmmState(np.array(st.x, copy=True), np.array(st.u, copy=True), np.array(st.z, copy=True),
+                           sh_x(st.lam), sh_x(st.mu), np.array(st.ddyn, copy=True),
+                           [np.array(c, copy=True) for c in st.copy], [])
+            ns.lam[0] = 0.0
+            ns.mu[0] = 0.0
+            for g, d in zip(t.groups, st.dual):
+                nd = sh_x(d) if g.var == "x" else sh_u(d, N)
+                nd[~g.active] = 0.0
+                ns.dual.append(nd)
+            nt.state = ns
+            nt.groups = t.groups
+        out.append(nt)
+    return out
+
+
+def mpc_session(requests: list[list[dict]], params: dict) -> list[tuple[list[Traj], dict]]:
+    """Solve the requests of one MPC session in order: the first from its initial guess, each
+    later one warm-started from the previous solution (shift_warm_start).  Returns, per request,
+    the solved trajectories and the group info."""
+    out = []
+    prev = None
+    for req in requests:
+        trajs = [init_traj(d) for d in req] if prev is None else shift_warm_start(prev, req)
+        info = scp_group(trajs, params)
+        out.append((trajs, info))
+        prev = trajs
+    return out
