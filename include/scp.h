@@ -122,6 +122,9 @@ enum {
 #define SCP_ST_BADPIVOT 2     /* non-positive Cholesky pivot (H_i not positive definite)   */
 #define SCP_ST_EMPTYSET 4     /* a hard box has lo > hi                                     */
 #define SCP_ST_CONVERGED 8    /* ADMM residual test passed in the last SCP iteration        */
+#define SCP_ST_SYNC 16        /* a consensus group spanning several workgroups waited too
+                                 long at its group barrier (its workgroups were not all
+                                 resident); the group's results are invalid               */
 
 typedef struct {
     int32_t n_traj;           /* number of trajectories, >= 1                              */
@@ -131,7 +134,10 @@ typedef struct {
     const int32_t* group;     /* [n_traj] consensus group id, or -1; members of one group
                                  are consecutive and share model and N; their first
                                  controls are averaged at every ADMM iteration (scenario
-                                 MPC, Sec. IV-A.4).  NULL = every trajectory alone.          */
+                                 MPC, Sec. IV-A.4).  NULL = every trajectory alone.  In the
+                                 persistent form a group larger than one workgroup spans
+                                 several (at most 64 members, each member whole in one
+                                 workgroup), coupled by a barrier in device memory.         */
     const double* params;     /* [n_traj * SCP_PARAM_STRIDE] records, see SCP_P_*           */
     const double* x_guess;    /* initial nominal states, rows of SCP_MAX_NX doubles, (N+1)
                                  rows per trajectory, trajectories concatenated             */
@@ -245,12 +251,13 @@ int64_t scp_traj_node_offset(const scp_problem* p, int32_t t);
 
 /* Host-side plan of the persistent form for a description (pure host computation, no
  * device access): plan[0] workgroup size, plan[1] workgroups, plan[2] workgroups whose
- * trajectories straddle a wavefront (LDS neighbour exchange), plan[3] idle lanes.  If
+ * trajectories straddle a wavefront (LDS neighbour exchange), plan[3] idle lanes, plan[4]
+ * consensus groups spanning several workgroups.  If
  * lane_table is not NULL and lane_cap >= plan[0] * plan[1], it receives the node index
  * (trajectory offset + node) of every lane, -1 for idle lanes.  plan[0] = 0 if no block
  * holds the longest trajectory or group (the persistent form is then unavailable).
  * Errors: SCP_ERR_ARG (invalid description, NULL plan). */
-scp_status scp_plan(const scp_problem_desc* desc, int32_t plan[4], int32_t* lane_table, size_t lane_cap);
+scp_status scp_plan(const scp_problem_desc* desc, int32_t plan[5], int32_t* lane_table, size_t lane_cap);
 
 /* Autotuner of the persistent form (the knobs do not change what is computed, except the
  * residual-test cadence, which decides at which iteration a converged trajectory stops). */

@@ -30,7 +30,7 @@ PARAM_STRIDE = 113
 INFO = dict(admm_iters=0, r_p=1, r_d=2, n_accept=3, delta=4, status=5, defect=6, cost=7, viol=8, bnd_err=9,
             merit=10, ratio=11)
 INFO_FIELDS = 12
-ST_NONFINITE, ST_BADPIVOT, ST_EMPTYSET, ST_CONVERGED = 1, 2, 4, 8
+ST_NONFINITE, ST_BADPIVOT, ST_EMPTYSET, ST_CONVERGED, ST_SYNC = 1, 2, 4, 8, 16
 FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9, A=10, B=11, d=12, boxlo=13,
               boxhi=14, hs=15)
 SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_destroy", "scp_linearize", "admm_solve",
@@ -186,11 +186,11 @@ def plan(insts: list[dict], precision: str = "f32", block: int = 0, pack: int = 
     """Host-side persistent-kernel plan of a batch (no GPU needed)."""
     lib = load()
     desc, keep = make_desc(insts, F32 if precision == "f32" else F64, block, pack)
-    out = (c_int32 * 4)()
+    out = (c_int32 * 5)()
     st = lib.scp_plan(byref(desc), out, None, 0)
     if st != SCP_OK:
         raise ScpError(f"scp_plan failed ({st}): {lib.scp_last_error(None).decode()}")
-    res = dict(block=out[0], n_wg=out[1], lds_wg=out[2], idle=out[3])
+    res = dict(block=out[0], n_wg=out[1], lds_wg=out[2], idle=out[3], spanning=out[4])
     if lanes and out[0]:
         n = out[0] * out[1]
         tab = np.empty(n, dtype=np.int32)

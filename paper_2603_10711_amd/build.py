@@ -21,7 +21,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libscp.so")
 
-SOURCES = ["scp_plain.hip", "scp_persistent.hip", "scp_api.cpp"]
+# largest translation units first, so the parallel build ends early
+SOURCES = ["scp_persistent_f64_span.hip", "scp_persistent_f64.hip", "scp_persistent_f32_span.hip",
+           "scp_persistent_f32.hip", "scp_plain.hip", "scp_persistent.hip", "scp_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -46,7 +48,8 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(jobs: int = 3, verbose: bool = False) -> str:
+def build(jobs: int = 0, verbose: bool = False) -> str:
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
@@ -63,7 +66,7 @@ def build(jobs: int = 3, verbose: bool = False) -> str:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=3)
+    ap.add_argument("--jobs", type=int, default=0)
     ap.add_argument("--verbose", action="store_true")
     a = ap.parse_args(argv)
     print(build(a.jobs, a.verbose))

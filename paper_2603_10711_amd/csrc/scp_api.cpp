@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/scp.h"
+#include "scp_host.hpp"
 #include "scp_launch.hpp"
 #include "scp_layout.hpp"
 
@@ -22,24 +23,6 @@ using namespace scp;
 namespace {
 
 thread_local std::string g_create_error;
-
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    int n_traj = 0, n_nodes = 0, P = 0;
-    int models = 0, kmax = 0;
-    int block = 0, n_wg = 0;
-    bool persistent_ok = false;
-    int n_groups = 0;
-    size_t esz = 4;
-    // byte offsets inside the arena
-    size_t o_traj, o_node_traj, o_lane, o_groups, o_params, o_planes, o_rt, o_info, o_flags, o_red, total;
-    std::vector<int> traj;       // n_traj * TR_FIELDS
-    std::vector<int> node_traj;  // P
-    std::vector<int> lane;       // n_wg * block lanes, then per workgroup: model id | wavefront-crossing flag << 8
-    std::vector<int> groups;     // first trajectory of each multi-member group
-};
 
 bool valid_model(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_MARS3DOF; }
 int model_nx(int m) { return m == SCP_MODEL_QUAD_PM ? 6 : 7; }
@@ -51,79 +34,112 @@ struct Unit {
     int first_traj, n_traj, lanes, model;
 };
 
+struct Packed {
+    std::vector<int> lane;      // n_wg * block node indices, -1 idle
+    std::vector<int> wg_info;   // n_wg: model | WG_CROSS | WG_SPAN
+    std::vector<int> wg_group;  // 2 * n_wg: spanning group slot, workgroups of that group
+    int n_wg = 0;
+    int n_gslots = 0;
+};
+
 // Aligned packing: a unit of at most 64 lanes never straddles a wavefront boundary and a longer
 // unit starts on one.  Dense packing: first fit over the whole workgroup.  A workgroup in which
-// no unit straddles a wavefront boundary gets wg_cross = 0 and exchanges neighbour values with
-// wavefront shifts; the others exchange them through LDS.
+// no unit straddles a wavefront boundary exchanges neighbour values with wavefront shifts; the
+// others (WG_CROSS) exchange them through LDS.  A consensus group larger than one workgroup is
+// split by member over workgroups of its own (WG_SPAN), each member whole in one workgroup.
 bool pack(const std::vector<Unit>& units, const std::vector<int>& traj_off, const std::vector<int>& horizon,
-          int block, bool aligned, std::vector<int>& lane, std::vector<int>& wg_model, std::vector<int>& wg_cross,
-          int& n_wg) {
+          int block, bool aligned, Packed& out) {
     constexpr int W = 64;
     const int nw = aligned ? block / W : 1;   // fill slots per workgroup
     const int cap = aligned ? W : block;      // lanes per fill slot
-    lane.clear();
-    wg_model.clear();
-    wg_cross.clear();
-    n_wg = 0;
+    out = Packed{};
+    struct Wg {
+        std::vector<int> fill;
+        int index;
+    };
+    auto new_wg = [&](std::vector<Wg>& set, int model, int extra) {
+        set.push_back(Wg{std::vector<int>(nw, 0), out.n_wg++});
+        out.lane.resize((size_t)out.n_wg * block, -1);
+        out.wg_info.push_back(model | extra);
+        out.wg_group.push_back(0);
+        out.wg_group.push_back(0);
+        return (int)set.size() - 1;
+    };
+    // first free position for `lanes` lanes in workgroup q of `set`; returns the fill slot or -1
+    auto find_slot = [&](const Wg& g, int lanes) {
+        if (lanes <= cap) {
+            for (int v = 0; v < nw; ++v)
+                if (g.fill[v] + lanes <= cap) return v;
+            return -1;
+        }
+        const int k = (lanes + cap - 1) / cap;  // fill slots spanned, all empty
+        for (int v = 0; v + k <= nw; ++v) {
+            bool empty = true;
+            for (int e = v; e < v + k; ++e) empty = empty && g.fill[e] == 0;
+            if (empty) return v;
+        }
+        return -1;
+    };
+    auto place = [&](Wg& g, int v, int first_traj, int n_traj, int lanes) {
+        const int off = v * cap + g.fill[v];  // lane offset inside the workgroup
+        if (off / W != (off + lanes - 1) / W) out.wg_info[g.index] |= WG_CROSS;
+        int base = g.index * block + off;
+        for (int t = first_traj; t < first_traj + n_traj; ++t)
+            for (int i = 0; i <= horizon[t]; ++i) out.lane[base++] = traj_off[t] + i;
+        int rest = lanes;
+        for (int e = v; rest > 0; ++e) {
+            const int take = std::min(rest, cap - g.fill[e]);
+            g.fill[e] += take;
+            rest -= take;
+        }
+    };
     for (int model : {SCP_MODEL_QUAD_PM, SCP_MODEL_MARS3DOF}) {
         std::vector<int> idx;
         for (int u = 0; u < (int)units.size(); ++u)
             if (units[u].model == model) idx.push_back(u);
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return units[a].lanes > units[b].lanes; });
-        std::vector<std::vector<int>> fill;  // used lanes of every fill slot of this model's workgroups
-        std::vector<int> wgs;                // global workgroup index
-        auto new_wg = [&]() {
-            fill.emplace_back(nw, 0);
-            wgs.push_back(n_wg++);
-            lane.resize((size_t)n_wg * block, -1);
-            wg_model.push_back(model);
-            wg_cross.push_back(0);
-            return (int)fill.size() - 1;
-        };
+        std::vector<Wg> shared;  // this model's workgroups open to any unit
         for (int u : idx) {
             const Unit& un = units[u];
-            if (un.lanes > block) return false;
-            int wq = -1, wv = -1;
-            if (un.lanes <= cap) {
-                for (int q = 0; q < (int)fill.size() && wq < 0; ++q)
-                    for (int v = 0; v < nw; ++v)
-                        if (fill[q][v] + un.lanes <= cap) {
-                            wq = q;
-                            wv = v;
-                            break;
-                        }
-            } else {
-                const int k = (un.lanes + cap - 1) / cap;  // fill slots spanned, all empty
-                for (int q = 0; q < (int)fill.size() && wq < 0; ++q)
-                    for (int v = 0; v + k <= nw; ++v) {
-                        bool empty = true;
-                        for (int e = v; e < v + k; ++e) empty = empty && fill[q][e] == 0;
-                        if (empty) {
-                            wq = q;
-                            wv = v;
-                            break;
-                        }
-                    }
+            if (un.lanes <= block) {
+                int q = -1, v = -1;
+                for (int c = 0; c < (int)shared.size() && q < 0; ++c) {
+                    v = find_slot(shared[c], un.lanes);
+                    if (v >= 0) q = c;
+                }
+                if (q < 0) {
+                    q = new_wg(shared, model, 0);
+                    v = find_slot(shared[q], un.lanes);
+                }
+                place(shared[q], v, un.first_traj, un.n_traj, un.lanes);
+                continue;
             }
-            if (wq < 0) {
-                wq = new_wg();
-                wv = 0;
+            // spanning consensus group: members over workgroups of its own
+            const int L = horizon[un.first_traj] + 1;
+            if (un.n_traj < 2 || L > block || un.n_traj > GX_MEMBERS) return false;
+            std::vector<Wg> own;
+            const int slot = out.n_gslots++;
+            for (int m = 0; m < un.n_traj; ++m) {
+                int q = (int)own.size() - 1, v = q >= 0 ? find_slot(own[q], L) : -1;
+                if (v < 0) {
+                    q = new_wg(own, model, WG_SPAN);
+                    v = find_slot(own[q], L);
+                }
+                place(own[q], v, un.first_traj + m, 1, L);
             }
-            const int off = wv * cap + fill[wq][wv];  // lane offset inside the workgroup
-            if (off / W != (off + un.lanes - 1) / W) wg_cross[wgs[wq]] = 1;
-            int base = wgs[wq] * block + off;
-            for (int t = un.first_traj; t < un.first_traj + un.n_traj; ++t)
-                for (int i = 0; i <= horizon[t]; ++i) lane[base++] = traj_off[t] + i;
-            int rest = un.lanes;
-            for (int v = wv; rest > 0; ++v) {
-                const int take = std::min(rest, cap - fill[wq][v]);
-                fill[wq][v] += take;
-                rest -= take;
+            if ((int)own.size() > GX_MAX_WG) return false;
+            for (const Wg& g : own) {
+                out.wg_group[2 * g.index] = slot;
+                out.wg_group[2 * g.index + 1] = (int)own.size();
             }
         }
     }
     return true;
 }
+
+}  // namespace
+
+namespace scp {
 
 bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     if (!d) { err = "desc is NULL"; return false; }
@@ -205,33 +221,33 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     // estimate.  The kernel runs one wave per SIMD (1024 SIMDs on the chip); waves of one
     // workgroup wait for each other at every exchange barrier, so at equal wave rounds a
     // smaller workgroup wins, and the idle-lane count breaks ties.
-    int max_unit = 0;
-    for (auto& u : units) max_unit = std::max(max_unit, u.lanes);
     std::vector<int> cands = d->block ? std::vector<int>{d->block} : std::vector<int>{64, 128, 256};
     if (d->prec == SCP_F64) cands.erase(std::remove(cands.begin(), cands.end(), 256), cands.end());
     long best_idle = -1;
     double best_score = 0.0;
     for (int b : cands) {
-        if (max_unit > b) continue;
-        std::vector<int> lane, wgm, wgc;
-        int nwg = 0;
-        if (!pack(units, traj_off, horizon, b, d->pack == SCP_PACK_ALIGNED, lane, wgm, wgc, nwg)) continue;
-        const long idle = (long)nwg * b - L.n_nodes;
-        const double waves = (double)nwg * (b / 64);
-        const double score = std::ceil(waves / 1024.0) * (1.0 + 0.05 * (b / 64 - 1));
+        Packed pk;
+        if (!pack(units, traj_off, horizon, b, d->pack == SCP_PACK_ALIGNED, pk)) continue;
+        const long idle = (long)pk.n_wg * b - L.n_nodes;
+        const double waves = (double)pk.n_wg * (b / 64);
+        // spanning groups pay a group barrier per ADMM iteration: fewer workgroups per group win
+        const double score = std::ceil(waves / 1024.0) * (1.0 + 0.05 * (b / 64 - 1)) + (pk.n_gslots ? 64.0 / b : 0.0);
         if (best_idle < 0 || score < best_score || (score == best_score && idle < best_idle)) {
             best_idle = idle;
             best_score = score;
             L.block = b;
-            L.n_wg = nwg;
-            L.lane = lane;
-            for (int w = 0; w < nwg; ++w) L.lane.push_back(wgm[w] | (wgc[w] << 8));
+            L.n_wg = pk.n_wg;
+            L.n_gslots = pk.n_gslots;
+            L.lane = pk.lane;
+            L.lane.insert(L.lane.end(), pk.wg_info.begin(), pk.wg_info.end());
+            L.lane.insert(L.lane.end(), pk.wg_group.begin(), pk.wg_group.end());
         }
     }
     L.persistent_ok = best_idle >= 0;
     if (!L.persistent_ok) {
         L.block = 0;
         L.n_wg = 0;
+        L.n_gslots = 0;
         L.lane.assign(1, -1);
     }
     // arena
@@ -246,6 +262,8 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     L.o_info = o; o = align_up(o + (size_t)L.n_traj * SCP_INFO_FIELDS * 8);
     L.o_flags = o; o = align_up(o + (size_t)L.n_traj * FL_FIELDS * 4);
     L.o_red = o; o = align_up(o + (size_t)L.n_traj * 2 * 8);
+    L.o_gsync = o; o = align_up(o + (size_t)L.n_gslots * GX_SYNC_STRIDE * 4);
+    L.o_gx = o; o = align_up(o + (size_t)L.n_gslots * 2 * GX_MEMBERS * GX_WIDTH * L.esz);
     L.total = o;
     return true;
 }
@@ -267,10 +285,20 @@ Dev<T> make_dev(const Layout& L, char* base) {
     dv.n_nodes = L.n_nodes;
     dv.n_groups = L.n_groups;
     dv.groups = reinterpret_cast<const int*>(base + L.o_groups);
+    const int* lanes = reinterpret_cast<const int*>(base + L.o_lane);
+    dv.wg_list = nullptr;
+    dv.wg_info = lanes + (size_t)L.n_wg * L.block;
+    dv.wg_group = dv.wg_info + L.n_wg;
+    dv.gsync = reinterpret_cast<unsigned*>(base + L.o_gsync);
+    dv.gx = reinterpret_cast<T*>(base + L.o_gx);
+    dv.n_gslots = L.n_gslots;
     return dv;
 }
 
-}  // namespace
+template Dev<float> make_dev<float>(const Layout&, char*);
+template Dev<double> make_dev<double>(const Layout&, char*);
+
+}  // namespace scp
 
 struct scp_problem {
     Layout L;
@@ -390,7 +418,9 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
         e = launch_plain<T>(PlainOp::Metrics, dv, kp, L.models, L.kmax, 0, 0, p->stream);
         return hip_check(p, e, "metrics launch");
     }
-    if (!L.persistent_ok) return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory or consensus group exceeds 256 nodes; use the plain form");
+    if (!L.persistent_ok)
+        return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory exceeds 256 nodes or a consensus group more than 64 members; "
+                                            "use the plain form");
     const int per = s->scp_per_launch > 0 ? s->scp_per_launch : std::max(1, s->scp_iters);
     int done = 0;
     if (s->scp_iters == 0) {
@@ -560,7 +590,8 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
     if (prm->form != SCP_FORM_PLAIN && prm->form != SCP_FORM_PERSISTENT) return fail(p, SCP_ERR_ARG, "invalid form");
     if (prm->graph != 0 && prm->graph != 1) return fail(p, SCP_ERR_ARG, "graph must be 0 or 1");
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok)
-        return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory or consensus group exceeds 256 nodes; use the plain form");
+        return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory exceeds 256 nodes or a consensus group more than 64 members; "
+                                            "use the plain form");
     scp_status st = SCP_OK;
     if (!prm->graph) {
         st = p->prec == SCP_F32 ? do_solve<float>(p, prm) : do_solve<double>(p, prm);
@@ -676,7 +707,7 @@ int64_t scp_traj_node_offset(const scp_problem* p, int32_t t) {
     return p->L.traj[(size_t)t * TR_FIELDS + TR_OFF];
 }
 
-scp_status scp_plan(const scp_problem_desc* desc, int32_t plan[4], int32_t* lane_table, size_t lane_cap) {
+scp_status scp_plan(const scp_problem_desc* desc, int32_t plan[5], int32_t* lane_table, size_t lane_cap) {
     g_create_error.clear();
     if (!plan) {
         g_create_error = "plan is NULL";
@@ -690,11 +721,12 @@ scp_status scp_plan(const scp_problem_desc* desc, int32_t plan[4], int32_t* lane
     }
     const size_t lanes = (size_t)L.n_wg * L.block;
     int cross = 0;
-    for (int w = 0; w < L.n_wg; ++w) cross += (L.lane[lanes + w] >> 8) & 1;
+    for (int w = 0; w < L.n_wg; ++w) cross += (L.lane[lanes + w] & WG_CROSS) ? 1 : 0;
     plan[0] = L.persistent_ok ? L.block : 0;
     plan[1] = L.n_wg;
     plan[2] = cross;
     plan[3] = L.persistent_ok ? (int32_t)((long long)lanes - L.n_nodes) : 0;
+    plan[4] = L.n_gslots;
     if (lane_table && L.persistent_ok && lane_cap >= lanes) std::memcpy(lane_table, L.lane.data(), lanes * sizeof(int32_t));
     return SCP_OK;
 }

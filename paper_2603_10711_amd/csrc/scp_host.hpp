@@ -1,0 +1,40 @@
+// Host-side planning shared by the problem API and the server: validation of a description,
+// packing of trajectories into persistent-kernel workgroups, and the arena layout.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/scp.h"
+#include "scp_layout.hpp"
+
+namespace scp {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int n_traj = 0, n_nodes = 0, P = 0;
+    int models = 0, kmax = 0;
+    int block = 0, n_wg = 0;
+    bool persistent_ok = false;
+    int n_groups = 0;
+    size_t esz = 4;
+    // byte offsets inside the arena
+    size_t o_traj, o_node_traj, o_lane, o_groups, o_params, o_planes, o_rt, o_info, o_flags, o_red, total;
+    std::vector<int> traj;       // n_traj * TR_FIELDS
+    std::vector<int> node_traj;  // P
+    std::vector<int> lane;       // n_wg * block lanes, then wg_info [n_wg], then wg_group [2 n_wg]
+    std::vector<int> groups;     // first trajectory of each multi-member group
+    int n_gslots = 0;            // consensus groups spanning several workgroups
+    size_t o_gsync = 0, o_gx = 0;
+};
+
+// Validate the description and lay out its arena (packing included).
+bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err);
+
+// Device views of an arena laid out by build_layout.
+template <class T>
+Dev<T> make_dev(const Layout& L, char* base);
+
+}  // namespace scp

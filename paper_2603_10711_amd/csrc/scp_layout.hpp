@@ -52,6 +52,17 @@ enum : int { RT_DELTA = 0, RT_FIELDS = 2 };
 // per-trajectory integer flags
 enum : int { FL_DONE = 0, FL_ITERS = 1, FL_ACCEPT = 2, FL_STATUS = 3, FL_FIELDS = 4 };
 
+// Consensus groups larger than one workgroup ("spanning groups") get whole workgroups of their
+// own and exchange their per-member values through HBM records: two buffers (alternating by
+// the parity of the group barrier), GX_MEMBERS member rows of GX_WIDTH values each.  The
+// group barrier counts workgroup arrivals in one 32-bit word per 128-byte line.
+constexpr int GX_MEMBERS = 64;
+constexpr int GX_WIDTH = 8;
+constexpr int GX_SYNC_STRIDE = 32;
+constexpr int GX_MAX_WG = 64;
+// per-workgroup record: model id | straddling flag << 8 | spanning-group flag << 9
+enum : int { WG_CROSS = 1 << 8, WG_SPAN = 1 << 9 };
+
 template <class T>
 struct Dev {
     const int* traj;       // [n_traj * TR_FIELDS]
@@ -68,6 +79,13 @@ struct Dev {
     int n_nodes;
     int n_groups;          // number of consensus groups with more than one member
     const int* groups;     // [n_groups] first trajectory of each such group
+    // persistent form
+    const int* wg_list;    // [grid] lane-table workgroup of each launched workgroup (NULL: identity)
+    const int* wg_info;    // [n_wg] model | WG_CROSS | WG_SPAN
+    const int* wg_group;   // [n_wg * 2] spanning group slot and its workgroup count (WG_SPAN only)
+    unsigned* gsync;       // [n_gslots * GX_SYNC_STRIDE] barrier arrival counters
+    T* gx;                 // [n_gslots * 2 * GX_MEMBERS * GX_WIDTH] exchange records
+    int n_gslots;
 };
 
 template <class T>

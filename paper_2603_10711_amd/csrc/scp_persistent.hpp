@@ -1,0 +1,683 @@
+// Persistent form of the hot path.
+//
+// One workgroup holds whole trajectories (and whole consensus groups), one lane per node.  For
+// the SCP iterations of a launch every node keeps its linearization, Cholesky factor, box and
+// half-space data and all ADMM iterates in registers; the only traffic between nodes is the
+// neighbour exchange of the consensus step (d_dyn from node i-1, z and mu from node i+1) and
+// the per-trajectory reductions, both through LDS.  HBM is touched once at launch start (nominal
+// and duals) and once at the end (state write-back).
+//
+// Barriers per ADMM iteration: one after Step 1 (d_dyn published), one after Step 4 (z, mu
+// published); consensus groups add one for the first-control average, residual iterations
+// add three for the dual-residual neighbour term and the per-trajectory test.
+//
+// A consensus group too large for one workgroup spans several workgroups that hold nothing
+// else.  Its four couplings (scenario mean of the nominal first control at the start of an SCP
+// iteration, first-control copy average in every ADMM iteration, group residual test, group
+// merit test) go through per-member records in HBM and a group barrier across those
+// workgroups.  Every sum runs over members in member order, as in the single-workgroup case,
+// so the results do not depend on whether a group spans workgroups.
+#pragma once
+
+#include "scp_device.hpp"
+#include "scp_launch.hpp"
+#include "scp_layout.hpp"
+
+namespace scp {
+
+template <class T, int BLOCK>
+struct Shared {
+    T ex[2 * SCP_MAX_NX][BLOCK];   // z, mu of every node (backward exchange); x / xbar at accept
+    T fw[SCP_MAX_NX][BLOCK];       // d_dyn of every node (forward exchange)
+    T dz[SCP_MAX_NX][BLOCK];       // z - z_old (dual-residual neighbour term)
+    T zo[SCP_MAX_NX][BLOCK];       // own z before Steps 2-3 on residual iterations
+    T cpo[36][BLOCK];              // own copies before Step 3 on residual iterations
+    T red[8][BLOCK];               // per-node terms for fixed-order trajectory sums
+    T ucp[8][BLOCK];               // node-0 u copies of consensus groups
+    unsigned long long mx[2][BLOCK];  // per-trajectory residual maxima, slot = first lane
+    int flag[BLOCK];               // per-trajectory flags at the group leader lane
+    int st[BLOCK];                 // per-trajectory status bits at the first lane
+    int sync_fail;                 // a spanning-group barrier timed out
+};
+
+// Spanning consensus group of a workgroup (on = false for every other workgroup).
+struct Span {
+    bool on;
+    int slot;  // group slot: barrier counter and exchange records
+    int nwg;   // workgroups of the group
+};
+
+// Polls of a group barrier before it is declared failed (about a second); the barrier then
+// stops waiting, so every workgroup still reaches the end of the kernel.
+constexpr int kSpinLimit = 1 << 20;
+
+template <class T>
+__device__ __forceinline__ T* gx_row(const Dev<T>& dv, const Span& sp, unsigned nbar, int member) {
+    return dv.gx + ((size_t)(sp.slot * 2 + (int)(nbar & 1u)) * GX_MEMBERS + member) * GX_WIDTH;
+}
+
+template <class T>
+__device__ __forceinline__ T gx_read(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier over the workgroups of a spanning group.  Each thread makes its exchange-record stores
+// visible at agent scope, the workgroup arrives once (release), thread 0 waits until all
+// workgroups of the group have arrived as often as this one (acquire), then the workgroup
+// proceeds.  nbar counts the group barriers this workgroup has passed in this launch.
+template <class T, int BLOCK>
+__device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK>& sh, const Span& sp, unsigned& nbar,
+                                           const int t) {
+    __threadfence();
+    __syncthreads();
+    nbar += 1u;
+    if (t == 0) {
+        unsigned* c = dv.gsync + (size_t)sp.slot * GX_SYNC_STRIDE;
+        __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (!sh.sync_fail) {
+            const unsigned target = nbar * (unsigned)sp.nwg;
+            int spins = 0;
+            while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    sh.sync_fail = 1;
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// WAVE1: no trajectory of this workgroup straddles a wavefront boundary, so neighbour values
+// move with DPP wavefront shifts instead of LDS and the two exchange barriers of every ADMM
+// iteration disappear.  The per-trajectory reductions still go through LDS.
+template <class M, class T, int BLOCK, bool WAVE1, bool SPAN>
+__device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK>& sh,
+                                                const int t, const int gn, const Span span_in) {
+    // SPAN: this kernel variant may hold spanning groups (compiled out of the other variant)
+    const Span span{SPAN && span_in.on, span_in.slot, span_in.nwg};
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, C = M::C;
+    const int P = dv.P;
+    const bool valid = gn >= 0;
+    NodeId id{0, 0, 0, false};
+    int tr = 0, tb = t, lb = t, S = 1, mem = 0;
+    unsigned nbar = 0;
+    const T* prm = dv.params;
+    if (valid) {
+        tr = dv.node_traj[gn];
+        const int* rec = dv.traj + tr * TR_FIELDS;
+        id.i = gn - rec[TR_OFF];
+        id.N = rec[TR_N];
+        id.K = rec[TR_K];
+        id.ball = rec[TR_BALL] != 0;
+        tb = t - id.i;
+        S = rec[TR_GSIZE];
+        mem = rec[TR_MEMBER];
+        // members of a spanning group lead themselves; their group reductions go through HBM
+        lb = span.on ? tb : tb - mem * (id.N + 1);
+        prm = dv.params + (size_t)tr * SCP_PARAM_STRIDE;
+    }
+    const bool first_lane = valid && id.first();
+    const bool leader = first_lane && lb == tb;
+    const Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    const T ball_r = valid ? prm[SCP_P_UBALL] : T(0);
+    const T kappa = valid ? prm[SCP_P_GLIDE] : T(1);
+    const T inv1k2 = T(1) / (T(1) + kappa * kappa);
+    T delta = valid ? dv.rt[tr * RT_FIELDS + RT_DELTA] : T(0);
+
+    T xbar[NX], ubar[NU];
+    NodeState<M, T> s;
+    NodeConst<M, T> nc;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        xbar[r] = valid ? dv.planes[(size_t)(PL_XBAR + r) * P + gn] : T(0);
+        s.lam[r] = valid ? dv.planes[(size_t)(PL_LAM + r) * P + gn] : T(0);
+        s.mu[r] = valid ? dv.planes[(size_t)(PL_MU + r) * P + gn] : T(0);
+        s.z[r] = T(0);
+        s.dd[r] = T(0);
+        s.x[r] = T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+        ubar[r] = (valid && !id.last()) ? dv.planes[(size_t)(PL_UBAR + r) * P + gn] : T(0);
+        s.u[r] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        s.du[k] = valid ? dv.planes[(size_t)(PL_DU + k) * P + gn] : T(0);
+        s.cp[k] = T(0);
+    }
+    int status = 0;
+    int n_acc = 0, iters_sum = 0;
+    T rp_last = T(0), rd_last = T(0), ratio_last = T(0), merit_last = T(0);
+    bool conv_last = false;
+    if (t < BLOCK) {
+        sh.mx[0][t] = 0ull;
+        sh.mx[1][t] = 0ull;
+        sh.st[t] = 0;
+    }
+    if (t == 0) sh.sync_fail = 0;
+
+    for (int k = 0; k < kp.n_scp; ++k) {
+        // ---------------- a2: linearization at the nominal ----------------
+        T F[NX];
+        if (valid && !id.last()) {
+            linearize<M, T>(prm, xbar, ubar, F, nc.Ar, nc.B, nc.d);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NX * NXR; ++q) nc.Ar[q] = T(0);
+#pragma unroll
+            for (int q = 0; q < NX * NU; ++q) nc.B[q] = T(0);
+#pragma unroll
+            for (int q = 0; q < NX; ++q) nc.d[q] = F[q] = T(0);
+        }
+        // nominal merit terms and the scenario mean of the first controls
+        T xn0[NX];
+        if constexpr (WAVE1) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) xn0[r] = lane_next(xbar[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) sh.ex[r][t] = xbar[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NU; ++r) sh.red[r][t] = ubar[r];
+        __syncthreads();
+        if constexpr (!WAVE1) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) xn0[r] = sh.ex[r][t + 1 < BLOCK ? t + 1 : t];
+        }
+        T uc[NU];
+#pragma unroll
+        for (int r = 0; r < NU; ++r) uc[r] = ubar[r];
+        T pen_nom = T(0);
+        if (valid) {
+            if (!id.last()) {
+#pragma unroll
+                for (int r = 0; r < NX; ++r) pen_nom = pen_nom + tabs(xn0[r] - F[r]);
+            }
+            if (id.first() && S > 1 && !span.on) {
+                T acc[NU];
+#pragma unroll
+                for (int r = 0; r < NU; ++r) acc[r] = T(0);
+                for (int m = 0; m < S; ++m) {
+                    const int lm = lb + m * (id.N + 1);
+#pragma unroll
+                    for (int r = 0; r < NU; ++r) acc[r] = acc[r] + sh.red[r][lm];
+                }
+#pragma unroll
+                for (int r = 0; r < NU; ++r) uc[r] = acc[r] / T(S);
+            }
+        }
+        if (span.on) {
+            const bool g0 = valid && id.first();
+            const unsigned b = nbar;
+            if (g0) {
+                T* row = gx_row(dv, span, b, mem);
+#pragma unroll
+                for (int r = 0; r < NU; ++r) row[r] = ubar[r];
+            }
+            group_sync(dv, sh, span, nbar, t);
+            if (g0) {
+                T acc[NU];
+#pragma unroll
+                for (int r = 0; r < NU; ++r) acc[r] = T(0);
+                for (int m = 0; m < S; ++m) {
+                    const T* row = gx_row(dv, span, b, m);
+#pragma unroll
+                    for (int r = 0; r < NU; ++r) acc[r] = acc[r] + gx_read(row + r);
+                }
+#pragma unroll
+                for (int r = 0; r < NU; ++r) uc[r] = acc[r] / T(S);
+            }
+        }
+        const T cost_nom = valid ? node_cost<M, T>(prm, id, xbar, ubar) : T(0);
+        __syncthreads();
+
+        // ---------------- a3 / a4: convex sets, Step-1 factor ----------------
+        if (valid) {
+            status |= convexify<M, T>(prm, id, xbar, uc, delta, nc);
+            status |= assemble_factor<M, T>(prm, id, rho, nc);
+        }
+        // primal re-initialization from the nominal; duals carried
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+            s.x[r] = xbar[r];
+            s.z[r] = id.first() ? T(0) : xbar[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NU; ++r) s.u[r] = ubar[r];
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+            s.cp[q] = (valid && group_active<M>(id, slot_group<M>(q))) ? slot_var<M, T>(s, q) : T(0);
+        if constexpr (!WAVE1) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) {
+                sh.ex[r][t] = s.z[r];
+                sh.ex[NX + r][t] = s.mu[r];
+            }
+        }
+        bool done = !valid;
+        int iters_here = kp.max_iters;
+        bool conv_here = false;
+        __syncthreads();
+
+        // ---------------- a5-a9: ADMM iterations ----------------
+        for (int j = 1; j <= kp.max_iters; ++j) {
+            const bool check = (kp.check_every > 0 && j % kp.check_every == 0) || j == kp.max_iters;
+            T zn[NX], mn[NX];
+            if constexpr (WAVE1) {
+#pragma unroll
+                for (int r = 0; r < NX; ++r) {
+                    zn[r] = lane_next(s.z[r]);
+                    mn[r] = lane_next(s.mu[r]);
+                }
+            }
+            if (!done) {
+#pragma unroll
+                for (int r = 0; r < NX; ++r) {
+                    if constexpr (!WAVE1) {
+                        zn[r] = id.last() ? T(0) : sh.ex[r][t + 1];
+                        mn[r] = id.last() ? T(0) : sh.ex[NX + r][t + 1];
+                    } else {
+                        zn[r] = id.last() ? T(0) : zn[r];
+                        mn[r] = id.last() ? T(0) : mn[r];
+                    }
+                }
+                step1<M, T>(id, rho, nc, s, zn, mn);
+                if constexpr (!WAVE1) {
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) sh.fw[r][t] = s.dd[r];
+                }
+            }
+            T dp[NX];
+            if constexpr (WAVE1) {
+#pragma unroll
+                for (int r = 0; r < NX; ++r) {
+                    const T v = lane_prev(s.dd[r]);
+                    dp[r] = (!done && !id.first()) ? v : T(0);
+                }
+            } else {
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < NX; ++r) dp[r] = (!done && !id.first()) ? sh.fw[r][t - 1] : T(0);
+            }
+            if (!done) {
+                if (check) {
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) sh.zo[r][t] = s.z[r];
+#pragma unroll
+                    for (int q = 0; q < C; ++q) sh.cpo[q][t] = s.cp[q];
+                }
+                step2<M, T>(id, rho, s, dp);
+                step3<M, T>(id, rho, nc, s, ball_r, kappa, inv1k2);
+            }
+            if (span.on) {
+                // scenario consensus across workgroups
+                const bool g0 = !done && id.first();
+                const unsigned b = nbar;
+                if (g0) {
+                    T* row = gx_row(dv, span, b, mem);
+#pragma unroll
+                    for (int q = 0; q < C; ++q)
+                        if (slot_is_u<M>(q)) row[slot_comp_u<M>(q)] = s.cp[q];
+                }
+                group_sync(dv, sh, span, nbar, t);
+                if (g0) {
+#pragma unroll
+                    for (int q = 0; q < C; ++q) {
+                        if (!slot_is_u<M>(q)) continue;
+                        T acc = T(0);
+                        for (int m = 0; m < S; ++m) acc = acc + gx_read(gx_row(dv, span, b, m) + slot_comp_u<M>(q));
+                        s.cp[q] = group_active<M>(id, slot_group<M>(q)) ? acc / T(S) : T(0);
+                    }
+                }
+            } else if (kp.has_groups) {
+                // scenario consensus: node-0 u copies replaced by their scenario mean
+                const bool g0 = !done && id.first() && S > 1;
+                if (g0) {
+#pragma unroll
+                    for (int q = 0; q < C; ++q)
+                        if (slot_is_u<M>(q)) sh.ucp[slot_comp_u<M>(q)][t] = s.cp[q];
+                }
+                __syncthreads();
+                if (g0) {
+#pragma unroll
+                    for (int q = 0; q < C; ++q) {
+                        if (!slot_is_u<M>(q)) continue;
+                        T acc = T(0);
+                        for (int m = 0; m < S; ++m) acc = acc + sh.ucp[slot_comp_u<M>(q)][lb + m * (id.N + 1)];
+                        s.cp[q] = group_active<M>(id, slot_group<M>(q)) ? acc / T(S) : T(0);
+                    }
+                }
+            }
+            if (!done) {
+                step4<M, T>(id, rho, s, dp);
+                if constexpr (!WAVE1) {
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) {
+                        sh.ex[r][t] = s.z[r];
+                        sh.ex[NX + r][t] = s.mu[r];
+                    }
+                }
+            }
+            if (check) {
+                T rp = T(0), sp[NN], dz[NX];
+#pragma unroll
+                for (int r = 0; r < NX; ++r) dz[r] = T(0);
+                if (!done) {
+                    T dcp[C];
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) {
+                        dz[r] = s.z[r] - sh.zo[r][t];
+                        if constexpr (!WAVE1) sh.dz[r][t] = dz[r];
+                    }
+#pragma unroll
+                    for (int q = 0; q < C; ++q) dcp[q] = s.cp[q] - sh.cpo[q][t];
+                    dual_res_own<M, T>(id, rho, dz, dcp, sp, false);
+                    rp = primal_res<M, T>(id, s, dp);
+                }
+                T dzn[NX];
+                if constexpr (WAVE1) {
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) dzn[r] = lane_next(dz[r]);
+                }
+                __syncthreads();
+                if (!done) {
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) {
+                        if constexpr (WAVE1) dzn[r] = id.last() ? T(0) : dzn[r];
+                        else dzn[r] = id.last() ? T(0) : sh.dz[r][t + 1];
+                    }
+                    const T rd = dual_res_finish<M, T>(id, rho, nc.Ar, nc.B, sp, dzn);
+                    atomicMax(&sh.mx[0][tb], res_bits(rp));
+                    atomicMax(&sh.mx[1][tb], res_bits(rd));
+                }
+                __syncthreads();
+                const bool test = kp.check_every > 0 && j % kp.check_every == 0;
+                if (!span.on) {
+                    if (!done && leader) {
+                        unsigned long long bp = 0ull, bd = 0ull;
+                        for (int m = 0; m < S; ++m) {
+                            const int lm = lb + m * (id.N + 1);
+                            bp = max(bp, sh.mx[0][lm]);
+                            bd = max(bd, sh.mx[1][lm]);
+                            sh.mx[0][lm] = 0ull;
+                            sh.mx[1][lm] = 0ull;
+                        }
+                        const T grp = T(bits_res(bp)), grd = T(bits_res(bd));
+                        sh.flag[lb] = (test && grp <= kp.eps_p && grd <= kp.eps_d) ? 1 : 0;
+                        sh.red[0][lb] = grp;
+                        sh.red[1][lb] = grd;
+                    }
+                } else {
+                    // member maxima to HBM; the group maximum is the same in every workgroup
+                    const unsigned b = nbar;
+                    if (!done && leader) {
+                        T* row = gx_row(dv, span, b, mem);
+                        row[0] = T(bits_res(sh.mx[0][tb]));
+                        row[1] = T(bits_res(sh.mx[1][tb]));
+                        sh.mx[0][tb] = 0ull;
+                        sh.mx[1][tb] = 0ull;
+                    }
+                    group_sync(dv, sh, span, nbar, t);
+                    if (!done && leader) {
+                        T grp = T(0), grd = T(0);
+                        for (int m = 0; m < S; ++m) {
+                            const T* row = gx_row(dv, span, b, m);
+                            grp = nmax(grp, gx_read(row));
+                            grd = nmax(grd, gx_read(row + 1));
+                        }
+                        sh.flag[lb] = (test && grp <= kp.eps_p && grd <= kp.eps_d) ? 1 : 0;
+                        sh.red[0][lb] = grp;
+                        sh.red[1][lb] = grd;
+                    }
+                }
+                __syncthreads();
+                if (!done) {
+                    rp_last = sh.red[0][lb];
+                    rd_last = sh.red[1][lb];
+                    if (sh.flag[lb]) {
+                        done = true;
+                        conv_here = true;
+                        iters_here = j;
+                    }
+                }
+                if (!__syncthreads_or(done ? 0 : 1)) break;
+            }
+            if constexpr (!WAVE1) __syncthreads();
+        }
+
+        // ---------------- a10: merit ratio test and nominal update ----------------
+        T xn1[NX];
+        if constexpr (WAVE1) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) xn1[r] = lane_next(s.x[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) sh.ex[r][t] = s.x[r];
+        }
+        __syncthreads();
+        if constexpr (!WAVE1) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) xn1[r] = sh.ex[r][t + 1 < BLOCK ? t + 1 : t];
+        }
+        T cost_new = T(0), pen_new = T(0), pen_mod = T(0);
+        if (valid) {
+            cost_new = node_cost<M, T>(prm, id, s.x, s.u);
+            if (!id.last()) {
+                T Fx[NX];
+                rk4<M, T>(prm, s.x, s.u, Fx);
+#pragma unroll
+                for (int r = 0; r < NX; ++r) pen_new = pen_new + tabs(xn1[r] - Fx[r]);
+#pragma unroll
+                for (int r = 0; r < NX; ++r) pen_mod = pen_mod + tabs(xn1[r] - s.dd[r]);
+            }
+        }
+        sh.red[0][t] = cost_nom;
+        sh.red[1][t] = pen_nom;
+        sh.red[2][t] = cost_new;
+        sh.red[3][t] = pen_new;
+        sh.red[4][t] = pen_mod;
+        __syncthreads();
+        // member merit terms (nominal, candidate, model); a spanning group sums them over HBM
+        const int S_here = span.on ? 1 : S;
+        T mnom = T(0), mnew = T(0), mmod = T(0);
+        if (leader) {
+            for (int m = 0; m < S_here; ++m) {
+                const int base = lb + m * (id.N + 1);
+                T J0 = T(0), p0 = T(0), J1 = T(0), p1 = T(0), pm = T(0);
+                for (int i = 0; i <= id.N; ++i) {
+                    J0 = J0 + sh.red[0][base + i];
+                    J1 = J1 + sh.red[2][base + i];
+                }
+                for (int i = 0; i < id.N; ++i) {
+                    p0 = p0 + sh.red[1][base + i];
+                    p1 = p1 + sh.red[3][base + i];
+                    pm = pm + sh.red[4][base + i];
+                }
+                const T vnom = J0 + kp.merit_w * p0, vnew = J1 + kp.merit_w * p1, vmod = J1 + kp.merit_w * pm;
+                if (span.on) {
+                    T* row = gx_row(dv, span, nbar, mem);
+                    row[0] = vnom;
+                    row[1] = vnew;
+                    row[2] = vmod;
+                } else {
+                    mnom = mnom + vnom;
+                    mnew = mnew + vnew;
+                    mmod = mmod + vmod;
+                }
+            }
+        }
+        if (span.on) {
+            const unsigned b = nbar;
+            group_sync(dv, sh, span, nbar, t);
+            if (leader) {
+                for (int m = 0; m < S; ++m) {
+                    const T* row = gx_row(dv, span, b, m);
+                    mnom = mnom + gx_read(row);
+                    mnew = mnew + gx_read(row + 1);
+                    mmod = mmod + gx_read(row + 2);
+                }
+            }
+        }
+        if (leader) {
+            const AcceptOut<T> a = accept_rule<T>(kp.eta0, kp.eta1, kp.eta2, kp.shrink, kp.grow, kp.delta_max, mnom,
+                                                  mnew, mmod, delta);
+            sh.flag[lb] = (a.accept ? 1 : 0) | (a.nonfinite ? 2 : 0);
+            sh.red[5][lb] = a.delta;
+            sh.red[6][lb] = a.ratio;
+            sh.red[7][lb] = mnew;
+        }
+        __syncthreads();
+        if (valid) {
+            const int f = sh.flag[lb];
+            delta = sh.red[5][lb];
+            ratio_last = sh.red[6][lb];
+            merit_last = sh.red[7][lb];
+            if (f & 2) status |= SCP_ST_NONFINITE;
+            if (f & 1) {
+#pragma unroll
+                for (int r = 0; r < NX; ++r) xbar[r] = s.x[r];
+#pragma unroll
+                for (int r = 0; r < NU; ++r) ubar[r] = s.u[r];
+                n_acc += 1;
+            }
+            iters_sum += iters_here;
+            conv_last = conv_here;
+        }
+        __syncthreads();
+    }
+
+    // ---------------- metrics of the final nominal ----------------
+    T m_cost = T(0), m_def = T(0), m_viol = T(0), m_bnd = T(0);
+    if (kp.final_metrics) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) sh.ex[r][t] = xbar[r];
+        __syncthreads();
+        if (valid) {
+            if (!id.last()) {
+                T Fx[NX];
+                rk4<M, T>(prm, xbar, ubar, Fx);
+#pragma unroll
+                for (int r = 0; r < NX; ++r) m_def = nmax(m_def, tabs(sh.ex[r][t + 1] - Fx[r]));
+            }
+            m_cost = node_cost<M, T>(prm, id, xbar, ubar);
+            m_viol = node_violation<M, T>(prm, id, xbar, ubar);
+            m_bnd = node_bnd_err<M, T>(prm, id, xbar);
+        }
+        sh.red[0][t] = m_cost;
+        sh.red[1][t] = m_def;
+        sh.red[2][t] = m_viol;
+        sh.red[3][t] = m_bnd;
+        __syncthreads();
+    }
+    if (span.on && sh.sync_fail) status |= SCP_ST_SYNC;
+    if (valid && status) atomicOr(&sh.st[tb], status);
+    __syncthreads();
+
+    // ---------------- write-back ----------------
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+            dv.planes[(size_t)(PL_XBAR + r) * P + gn] = xbar[r];
+            dv.planes[(size_t)(PL_X + r) * P + gn] = s.x[r];
+            dv.planes[(size_t)(PL_Z + r) * P + gn] = s.z[r];
+            dv.planes[(size_t)(PL_LAM + r) * P + gn] = s.lam[r];
+            dv.planes[(size_t)(PL_MU + r) * P + gn] = s.mu[r];
+            dv.planes[(size_t)(PL_DD + r) * P + gn] = s.dd[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NU; ++r) {
+            dv.planes[(size_t)(PL_UBAR + r) * P + gn] = ubar[r];
+            dv.planes[(size_t)(PL_U + r) * P + gn] = s.u[r];
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            dv.planes[(size_t)(PL_CP + q) * P + gn] = s.cp[q];
+            dv.planes[(size_t)(PL_DU + q) * P + gn] = s.du[q];
+        }
+    }
+    if (first_lane) {
+        dv.rt[tr * RT_FIELDS + RT_DELTA] = delta;
+        double* inf = dv.info + (size_t)tr * SCP_INFO_FIELDS;
+        int st = sh.st[tb];
+        if (!kp.reset_info) st |= (int)inf[SCP_I_STATUS] & ~SCP_ST_CONVERGED;
+        if (conv_last) st |= SCP_ST_CONVERGED;
+        const double it0 = kp.reset_info ? 0.0 : inf[SCP_I_ADMM_ITERS];
+        const double na0 = kp.reset_info ? 0.0 : inf[SCP_I_NACCEPT];
+        inf[SCP_I_ADMM_ITERS] = it0 + (double)iters_sum;
+        inf[SCP_I_NACCEPT] = na0 + (double)n_acc;
+        inf[SCP_I_RP] = (double)rp_last;
+        inf[SCP_I_RD] = (double)rd_last;
+        inf[SCP_I_DELTA] = (double)delta;
+        inf[SCP_I_STATUS] = (double)st;
+        inf[SCP_I_RATIO] = (double)ratio_last;
+        inf[SCP_I_MERIT] = (double)merit_last;
+        if (kp.final_metrics) {
+            T J = T(0), df = T(0), vi = T(0), be = T(0);
+            for (int i = 0; i <= id.N; ++i) {
+                J = J + sh.red[0][tb + i];
+                df = nmax(df, sh.red[1][tb + i]);
+                vi = nmax(vi, sh.red[2][tb + i]);
+                be = nmax(be, sh.red[3][tb + i]);
+            }
+            inf[SCP_I_COST] = (double)J;
+            inf[SCP_I_DEFECT] = (double)df;
+            inf[SCP_I_VIOL] = (double)vi;
+            inf[SCP_I_BNDERR] = (double)be;
+        }
+    }
+}
+
+template <class M, class T, int BLOCK, bool SPAN>
+__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK>& sh, const int t,
+                                         const int gn, const bool cross, const Span& sp) {
+    if constexpr (BLOCK == 64) {
+        persistent_body<M, T, BLOCK, true, SPAN>(dv, kp, sh, t, gn, sp);
+    } else {
+        if (cross) persistent_body<M, T, BLOCK, false, SPAN>(dv, kp, sh, t, gn, sp);
+        else persistent_body<M, T, BLOCK, true, SPAN>(dv, kp, sh, t, gn, sp);
+    }
+}
+
+// MODELS: 1 quadrotor only, 2 powered descent only, 3 both (each workgroup holds one model).
+// SPAN: the launch has consensus groups spanning several workgroups.
+template <class T, int BLOCK, int MODELS, int KM, bool SPAN>
+__global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) {
+    __shared__ Shared<T, BLOCK> sh;
+    const int t = threadIdx.x;
+    const int w = dv.wg_list ? dv.wg_list[blockIdx.x] : (int)blockIdx.x;
+    const int gn = dv.lane_node[(size_t)w * BLOCK + t];
+    const int wi = dv.wg_info[w];
+    const bool cross = (wi & WG_CROSS) != 0;
+    Span sp{false, 0, 1};
+    if (wi & WG_SPAN) sp = Span{true, dv.wg_group[2 * w], dv.wg_group[2 * w + 1]};
+    if constexpr (MODELS == 1) {
+        body_for<Quad<KM>, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
+    } else if constexpr (MODELS == 2) {
+        body_for<Mars, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
+    } else {
+        if ((wi & 0xff) == SCP_MODEL_QUAD_PM) body_for<Quad<KM>, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
+        else body_for<Mars, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
+    }
+}
+
+// Launch of the persistent kernel variant for BLOCK and SPAN (instantiated per precision and
+// variant in their own translation units, compiled in parallel).
+template <class T, int BLOCK, bool SPAN>
+void launch_models(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int models, int kmax, hipStream_t s) {
+    const dim3 g(n_wg), b(BLOCK);
+    if (models == 1) {
+        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 4, SPAN>), g, b, 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 8, SPAN>), g, b, 0, s, dv, kp);
+    } else if (models == 2) {
+        hipLaunchKernelGGL((k_persistent<T, BLOCK, 2, 0, SPAN>), g, b, 0, s, dv, kp);
+    } else {
+        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 4, SPAN>), g, b, 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 8, SPAN>), g, b, 0, s, dv, kp);
+    }
+}
+
+}  // namespace scp

@@ -95,3 +95,28 @@ def test_autotune_arena_covers_every_candidate(B):
         for pk in (0, 1):
             d2, keep2 = B.make_desc(insts, 0, blk, pk)
             assert lib.scp_problem_device_bytes(byref(d2)) <= auto
+
+
+@pytest.mark.parametrize("N", [30, 50, 64, 80])
+@pytest.mark.parametrize("block,pack", [(128, 0), (256, 0), (256, 1)])
+def test_scenario_request_spans_workgroups(B, N, block, pack):
+    """A 16-scenario request is larger than one workgroup: its members go to workgroups of their
+    own (one spanning group), each member whole in one workgroup."""
+    req = scpgen.config4_request(0, S=16, N=N)
+    other = [scpgen.quad_instance(4, 900 + i, N=20 + i, K=4) for i in range(5)]
+    insts = other[:2] + req + other[2:]
+    pl = B.plan(insts, block=block, pack=pack, lanes=True)
+    assert pl["block"] == block and pl["spanning"] == 1
+    _check_plan(insts, pl)
+    lanes = pl["lanes"]
+    off = sum(d["N"] + 1 for d in other[:2])
+    span_nodes = set(range(off, off + 16 * (N + 1)))
+    for w in range(pl["n_wg"]):
+        row = set(lanes[w][lanes[w] >= 0].tolist())
+        assert row <= span_nodes or not (row & span_nodes)        # spanning workgroups hold nothing else
+
+
+def test_spanning_limits(B):
+    too_many = scpgen.with_scenarios(scpgen.quad_instance(4, 1, N=10, K=2), 65, np.random.default_rng(0), group=3)
+    assert B.plan(too_many)["block"] == 0          # more than 64 members: persistent form unavailable
+    assert B.plan(too_many[:64])["spanning"] in (0, 1)
