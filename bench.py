@@ -51,6 +51,11 @@ def workload(name: str):
     if name == "mars4096":
         return dict(name=name, insts=scpgen.config2(4096), scp=15, admm=200, rho=1.0, prec="f32",
                     desc="3-DOF powered-descent Monte Carlo: 4096 instances, N=60, 15 SCP x 200 ADMM, rho=1, FP32")
+    if name == "serve":
+        return dict(name=name, scp=10, admm=100, rho=1.0, prec="f32", serve=True,
+                    desc="scenario-robust MPC serving: Poisson 2000 requests/s, 256 sessions, each request a "
+                         "quadrotor with N ~ U{30..80} and 16 scenarios sharing the first control, 10 SCP x 100 "
+                         "ADMM, rho=1, FP32, warm start from the device-resident previous solution")
     if name == "mix2048":
         return dict(name=name, insts=scpgen.config3(2048), scp=15, admm=200, rho=1.0, prec="f32", eps=1e-4,
                     cadences=(1, 5, 10, 25),
@@ -99,6 +104,30 @@ def _oracle_worker(args):
     return oracle.defect(inst, t.xbar, t.ubar)
 
 
+def _oracle_request_worker(args):
+    req, scp_iters, admm_iters, rho = args
+    import oracle
+    p = oracle.default_params(scp_iters=scp_iters, admm_iters=admm_iters, rho_eq=rho, rho_dyn=rho, rho_geo=rho)
+    trajs = [oracle.init_traj(d) for d in req]
+    oracle.scp.scp_group(trajs, p)
+    return max(oracle.defect(t.inst, t.xbar, t.ubar) for t in trajs)
+
+
+def cpu_baseline_requests(reqs, scp_iters, admm_iters, rho, cores) -> dict:
+    """The FP64 oracle on whole robust-MPC requests (16 coupled scenarios each), one process per
+    core, forked before the GPU is touched."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        defects = pool.map(_oracle_request_worker, [(r, scp_iters, admm_iters, rho) for r in reqs], chunksize=1)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(reqs) / dt, 3), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(reqs)} requests (sessions 0..{len(reqs) - 1}, 16 scenarios each), cold start, "
+                      f"{scp_iters}x{admm_iters} budget, FP64 NumPy, {cores} single-threaded worker processes, "
+                      f"{dt:.1f} s wall", "defect_p50": float(np.median(defects))}
+
+
 def cpu_baseline(wl, sample: int, cores: int) -> dict:
     """The FP64 oracle (as it stands) on a sample of the workload, one process per core.
     Runs before the GPU is touched (worker processes are forked from a GPU-free parent).  With a
@@ -134,6 +163,79 @@ def load_pmc(wl_name: str, khash: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def serve_main(a, wl, cpu):
+    """Served (continuous batching, persistent kernel) vs static batching with the plain form on
+    the same Poisson arrival trace; then the served capacity (every request queued at once)."""
+    import torch
+    from paper_2603_10711_amd import binding as B
+    from paper_2603_10711_amd import serve_load as SL
+
+    torch.cuda.init()
+    n_sess = 256
+    reqs = SL.session_requests(n_sess, S=16)
+    prm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"])
+    budget = int(a.budget_mb * 2**20) if a.budget_mb else 64 * 2**30
+    max_nodes = sum(16 * (r[0]["N"] + 1) for r in reqs) + 64 * 16 * 81
+    srv = B.Server(prm, precision=wl["prec"], block=256, max_nodes=max_nodes, max_traj=16 * (n_sess + 64),
+                   max_wg=8 * (n_sess + 64), max_span=n_sess + 64, max_requests=n_sess + 64,
+                   budget_bytes=budget, scp_per_step=1, max_inflight=2, device="cuda:0")
+    prepared = [srv.prepare(r) for r in reqs]
+    # warm-up: a few requests through the whole path (kernels loaded, staging touched)
+    ids = [srv.submit(prepared[s], session=s) for s in range(4)]
+    srv.drain(ids)
+    times, sess = SL.arrivals(a.rate, a.duration, n_sess)
+    served = SL.run_served(srv, prepared, times, sess)
+    print(f"[serve] served {served}", file=sys.stderr, flush=True)
+    # capacity: the same kind of requests all queued at once (sessions round robin)
+    n_cap = a.capacity_requests
+    t0 = time.perf_counter()
+    ids = [srv.submit(prepared[k % n_sess], session=k % n_sess) for k in range(n_cap)]
+    res = srv.drain(ids, timeout_s=600)
+    cap_wall = time.perf_counter() - t0
+    capacity = {"requests": n_cap, "wall_s": round(cap_wall, 3), "solves_per_s": round(n_cap / cap_wall, 1)}
+    st = srv.stats()
+    srv.close()
+    print(f"[serve] capacity {capacity}", file=sys.stderr, flush=True)
+    plain = None
+    if a.plain_steps > 0:
+        parts = [B.request_arrays(r) for r in reqs]
+        pprm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], form="plain")
+        plain = SL.run_static_plain(B, parts, times, sess, pprm, precision=wl["prec"], stream=torch.cuda.Stream(),
+                                    max_wall=a.duration * 3)
+        print(f"[serve] static plain {plain}", file=sys.stderr, flush=True)
+    nodes_per_req = float(np.mean([16 * (reqs[s][0]["N"] + 1) for s in sess])) if len(sess) else 0.0
+    fl = float(np.mean([sum((d["N"] + 1) * flops_per_node_iter(d["model"], d["obstacles"].shape[0]) for d in reqs[s])
+                        for s in sess])) * wl["scp"] * wl["admm"]
+    achieved = capacity["solves_per_s"] * fl / 1e12
+    out = {
+        "metric": METRIC,
+        "value": served["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": int(st["steps"]),
+        "warmup": 4,
+        "ms_per_step": round(served["wall_s"] * 1e3 / max(1, served.get("steps", 1)), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded sessions and Poisson arrival trace)",
+        "config": {"workload": wl["desc"], "form": "served (persistent kernel, continuous batching)",
+                   "offered_rate": a.rate, "duration_s": a.duration, "sessions": n_sess,
+                   "budget_bytes": budget, "arena_bytes": int(srv.nbytes), "nodes_per_request": round(nodes_per_req, 1)},
+        "served": served,
+        "latency_ms_p50": served["latency_ms"]["p50"],
+        "latency_ms_p99": served["latency_ms"]["p99"],
+        "capacity": capacity,
+        "plain": plain,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": "k_persistent",
+                     "basis": "served capacity run (all requests queued), algorithmic flops over wall time"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +246,10 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered requests/s")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
+    ap.add_argument("--budget-mb", type=float, default=0.0, help="serve: HBM admission budget (0 = 64 GB)")
+    ap.add_argument("--capacity-requests", type=int, default=2000)
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (instances shard across GPUs "
@@ -151,6 +257,12 @@ def main(argv=None):
         sys.exit(2)
     wl = workload(a.workload)
     cores = min(os.cpu_count() or 1, 16)
+    if wl.get("serve"):
+        cpu = None
+        if not a.no_cpu_baseline:
+            reqs = [scpgen.config4_request(s, S=16) for s in range(cores)]
+            cpu = cpu_baseline_requests(reqs, wl["scp"], wl["admm"], wl["rho"], cores)
+        return serve_main(a, wl, cpu)
     cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_sample, cores)
 
     import torch

@@ -36,6 +36,10 @@ FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9
 SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_destroy", "scp_linearize", "admm_solve",
            "scp_solve", "scp_reset", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
            "scp_traj_node_offset", "scp_plan", "scp_autotune_device_bytes", "scp_autotune", "scp_last_error"]
+SERVE_SYMBOLS = ["scp_server_device_bytes", "scp_server_create", "scp_server_destroy", "scp_server_request_bytes",
+                 "scp_server_submit", "scp_server_step", "scp_server_collect", "scp_server_get_stats",
+                 "scp_server_last_error"]
+REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2, 3
 
 
 class ProblemDesc(ctypes.Structure):
@@ -62,6 +66,22 @@ class TuneEntry(ctypes.Structure):
     def as_dict(self) -> dict:
         return dict(block=self.block, pack="dense" if self.pack == PACK_DENSE else "aligned",
                     check_every=self.check_every, valid=bool(self.valid), ms=self.ms)
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("prec", c_int32), ("block", c_int32), ("pack", c_int32), ("max_nodes", c_int64),
+                ("max_traj", c_int32), ("max_wg", c_int32), ("max_span", c_int32), ("max_requests", c_int32),
+                ("budget_bytes", c_size_t), ("solve", ScpParams), ("scp_per_step", c_int32),
+                ("max_inflight", c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("rejected", c_int64), ("queued", c_int32),
+                ("running", c_int32), ("resident", c_int32), ("steps", c_int64), ("evictions", c_int64),
+                ("warm_starts", c_int64), ("resident_bytes", c_size_t), ("peak_resident_bytes", c_size_t)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _LIB = None
@@ -109,6 +129,25 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scp_autotune.restype = c_int32
     lib.scp_last_error.argtypes = [c_void_p]
     lib.scp_last_error.restype = ctypes.c_char_p
+    lib.scp_server_device_bytes.argtypes = [POINTER(ServerConfig)]
+    lib.scp_server_device_bytes.restype = c_size_t
+    lib.scp_server_create.argtypes = [POINTER(ServerConfig), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
+    lib.scp_server_create.restype = c_int32
+    lib.scp_server_destroy.argtypes = [c_void_p]
+    lib.scp_server_destroy.restype = None
+    lib.scp_server_request_bytes.argtypes = [c_void_p, POINTER(ProblemDesc)]
+    lib.scp_server_request_bytes.restype = c_size_t
+    lib.scp_server_submit.argtypes = [c_void_p, POINTER(ProblemDesc), c_int32, POINTER(c_int64)]
+    lib.scp_server_submit.restype = c_int32
+    lib.scp_server_step.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
+    lib.scp_server_step.restype = c_int32
+    lib.scp_server_collect.argtypes = [c_void_p, c_int64, c_int32, POINTER(c_int32), POINTER(c_double),
+                                       POINTER(c_double), POINTER(c_double), POINTER(c_double)]
+    lib.scp_server_collect.restype = c_int32
+    lib.scp_server_get_stats.argtypes = [c_void_p, POINTER(ServerStats)]
+    lib.scp_server_get_stats.restype = c_int32
+    lib.scp_server_last_error.argtypes = [c_void_p]
+    lib.scp_server_last_error.restype = ctypes.c_char_p
     _LIB = lib
     return lib
 
@@ -181,6 +220,33 @@ def make_desc(insts: list[dict], prec: int = F32, block: int = 0, pack: int = PA
     return desc, keep
 
 
+def request_arrays(insts: list[dict]) -> dict:
+    """The C-record arrays of one request, for fast concatenation into batches (concat_desc)."""
+    return dict(model=np.array([d["model"] for d in insts], dtype=np.int32),
+                horizon=np.array([d["N"] for d in insts], dtype=np.int32),
+                grouped=np.array([d.get("group", -1) >= 0 for d in insts]),
+                params=np.concatenate([param_record(d) for d in insts]),
+                xg=np.concatenate([_pad(d["x_guess"], MAX_NX) for d in insts]),
+                ug=np.concatenate([_pad(d["u_guess"], MAX_NU) for d in insts]),
+                shape=[(d["N"], d["nx"], d["nu"]) for d in insts])
+
+
+def concat_desc(parts: list[dict], prec: int = F32, block: int = 0, pack: int = PACK_ALIGNED):
+    """One C description of several requests (request k's grouped trajectories form group k)."""
+    model = np.concatenate([p["model"] for p in parts])
+    horizon = np.concatenate([p["horizon"] for p in parts])
+    group = np.concatenate([np.where(p["grouped"], k, -1) for k, p in enumerate(parts)]).astype(np.int32)
+    params = np.concatenate([p["params"] for p in parts])
+    xg = np.concatenate([p["xg"] for p in parts])
+    ug = np.concatenate([p["ug"] for p in parts])
+    keep = (model, horizon, group, params, xg, ug)
+    desc = ProblemDesc(len(model), prec, model.ctypes.data_as(POINTER(c_int32)),
+                       horizon.ctypes.data_as(POINTER(c_int32)), group.ctypes.data_as(POINTER(c_int32)),
+                       params.ctypes.data_as(POINTER(c_double)), xg.ctypes.data_as(POINTER(c_double)),
+                       ug.ctypes.data_as(POINTER(c_double)), block, pack)
+    return desc, keep
+
+
 def plan(insts: list[dict], precision: str = "f32", block: int = 0, pack: int = PACK_ALIGNED,
          lanes: bool = False) -> dict:
     """Host-side persistent-kernel plan of a batch (no GPU needed)."""
@@ -231,16 +297,21 @@ class ScpError(RuntimeError):
 class Problem:
     """A batch of trajectories resident on the GPU (one arena tensor), driven through the C ABI."""
 
-    def __init__(self, insts: list[dict], precision: str = "f32", block: int = 0, device: str = "cuda",
-                 stream=None, pack: int = PACK_ALIGNED):
+    def __init__(self, insts: list[dict] | None, precision: str = "f32", block: int = 0, device: str = "cuda",
+                 stream=None, pack: int = PACK_ALIGNED, parts: list[dict] | None = None):
+        """insts: problem dictionaries; or parts: request_arrays() of several requests."""
         import torch
         self.torch = torch
         self.lib = load()
-        self.insts = insts
-        self.n_traj = len(insts)
         self.prec = F32 if precision == "f32" else F64
         self.dtype = torch.float32 if self.prec == F32 else torch.float64
-        desc, self._keep = make_desc(insts, self.prec, block, pack)
+        if parts is not None:
+            desc, self._keep = concat_desc(parts, self.prec, block, pack)
+            self.insts = [dict(N=N, nx=nx, nu=nu) for p in parts for N, nx, nu in p["shape"]]
+        else:
+            desc, self._keep = make_desc(insts, self.prec, block, pack)
+            self.insts = insts
+        self.n_traj = len(self.insts)
         nbytes = self.lib.scp_problem_device_bytes(byref(desc))
         if nbytes == 0:
             h = c_void_p()
@@ -319,6 +390,154 @@ class Problem:
     def close(self):
         if getattr(self, "h", None):
             self.lib.scp_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The library's continuous-batching request server on one device pool (a torch uint8 arena).
+
+    Marshalling only: requests (lists of problem dictionaries) are packed into C descriptions,
+    scheduling, admission, warm starts and every computation run in the library."""
+
+    def __init__(self, prm: ScpParams, precision: str = "f32", block: int = 256, pack: int = PACK_ALIGNED,
+                 max_nodes: int = 1 << 16, max_traj: int = 1024, max_wg: int = 1024, max_span: int = 256,
+                 max_requests: int = 256, budget_bytes: int | None = None, scp_per_step: int = 1,
+                 max_inflight: int = 2, device: str = "cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.prec = F32 if precision == "f32" else F64
+        cfg = ServerConfig(self.prec, block, pack, max_nodes, max_traj, max_wg, max_span, max_requests, 0, prm,
+                           scp_per_step, max_inflight)
+        nbytes = self.lib.scp_server_device_bytes(byref(cfg))
+        if nbytes == 0:
+            h = c_void_p()
+            self.lib.scp_server_create(byref(cfg), None, 0, None, byref(h))
+            raise ScpError(f"invalid server configuration: {self.lib.scp_server_last_error(None).decode()}")
+        cfg.budget_bytes = nbytes if budget_bytes is None else int(budget_bytes)
+        self.cfg = cfg
+        self.nbytes = nbytes
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.arena.device)
+        self.arena.record_stream(self.stream)
+        torch.cuda.synchronize(self.arena.device)
+        h = c_void_p()
+        st = self.lib.scp_server_create(byref(cfg), c_void_p(self.arena.data_ptr()), nbytes,
+                                        c_void_p(self.stream.cuda_stream), byref(h))
+        if st != SCP_OK:
+            raise ScpError(f"scp_server_create failed ({st}): {self.lib.scp_server_last_error(None).decode()}")
+        self.h = h
+        self.shapes = {}
+
+    def _check(self, st, what):
+        if st != SCP_OK:
+            raise ScpError(f"{what} failed ({st}): {self.lib.scp_server_last_error(self.h).decode()}")
+
+    def request_bytes(self, insts: list[dict]) -> int:
+        desc, keep = make_desc(insts, self.prec)
+        return int(self.lib.scp_server_request_bytes(self.h, byref(desc)))
+
+    def prepare(self, insts: list[dict]):
+        """A reusable C description of a request (submit it any number of times)."""
+        desc, keep = make_desc(insts, self.prec)
+        return (desc, keep, [(d["N"], d["nx"], d["nu"]) for d in insts])
+
+    def submit(self, insts, session: int = -1) -> int:
+        """Queue a request (a list of problem dictionaries, or a prepared description)."""
+        desc, keep, shape = insts if isinstance(insts, tuple) else self.prepare(insts)
+        rid = c_int64(0)
+        self._check(self.lib.scp_server_submit(self.h, byref(desc), session, byref(rid)), "scp_server_submit")
+        self.shapes[rid.value] = shape
+        return rid.value
+
+    def poll(self, rid: int, release: bool = True):
+        """None while queued or running, else (latency_ms, info array (n_traj, 12))."""
+        shape = self.shapes[rid]
+        state = c_int32(0)
+        lat = c_double(0.0)
+        info = np.zeros((len(shape), INFO_FIELDS))
+        self._check(self.lib.scp_server_collect(self.h, rid, 1 if release else 0, byref(state), byref(lat),
+                                                info.ctypes.data_as(POINTER(c_double)), None, None),
+                    "scp_server_collect")
+        if state.value != REQ_DONE:
+            if state.value == REQ_UNKNOWN:
+                raise ScpError(f"request {rid} unknown or already collected")
+            return None
+        if release:
+            self.shapes.pop(rid, None)
+        return lat.value, info
+
+    def step(self, wait: bool = False) -> int:
+        pending = c_int32(0)
+        self._check(self.lib.scp_server_step(self.h, 1 if wait else 0, byref(pending)), "scp_server_step")
+        return pending.value
+
+    def collect(self, rid: int, release: bool = True):
+        """None while the request is queued or running; else dict(latency_ms, info, x, u) with
+        per-trajectory arrays (x: (N+1, nx), u: (N, nu)) and info dictionaries."""
+        shape = self.shapes.get(rid)
+        if shape is None:
+            raise ScpError(f"unknown request {rid}")
+        nt = len(shape)
+        nxr = sum(N + 1 for N, _, _ in shape)
+        nur = sum(N for N, _, _ in shape)
+        state = c_int32(0)
+        lat = c_double(0.0)
+        info = np.zeros((nt, INFO_FIELDS))
+        x = np.zeros((nxr, MAX_NX))
+        u = np.zeros((max(nur, 1), MAX_NU))
+        dp = lambda a: a.ctypes.data_as(POINTER(c_double))
+        self._check(self.lib.scp_server_collect(self.h, rid, 1 if release else 0, byref(state), byref(lat), dp(info),
+                                                dp(x), dp(u)), "scp_server_collect")
+        if state.value != REQ_DONE:
+            if state.value == REQ_UNKNOWN:
+                raise ScpError(f"request {rid} unknown or already collected")
+            return None
+        if release:
+            self.shapes.pop(rid, None)
+        xs, us, xo, uo = [], [], 0, 0
+        for N, nx, nu in shape:
+            xs.append(x[xo:xo + N + 1, :nx].copy())
+            us.append(u[uo:uo + N, :nu].copy())
+            xo += N + 1
+            uo += N
+        infos = [{k: float(info[t, v]) for k, v in INFO.items()} for t in range(nt)]
+        return dict(latency_ms=lat.value, info=infos, x=xs, u=us)
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        self._check(self.lib.scp_server_get_stats(self.h, byref(out)), "scp_server_get_stats")
+        return out.as_dict()
+
+    def drain(self, ids, timeout_s: float = 60.0) -> dict:
+        """Step until every request in ids is done; returns {id: result}."""
+        import time
+        out = {}
+        t0 = time.perf_counter()
+        todo = list(ids)
+        while todo:
+            self.step(wait=True)
+            rest = []
+            for rid in todo:
+                r = self.collect(rid)
+                if r is None:
+                    rest.append(rid)
+                else:
+                    out[rid] = r
+            todo = rest
+            if time.perf_counter() - t0 > timeout_s:
+                raise ScpError(f"requests not done after {timeout_s} s: {todo[:8]}")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.scp_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

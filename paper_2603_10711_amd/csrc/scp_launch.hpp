@@ -23,4 +23,11 @@ template <class T>
 hipError_t launch_persistent(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int block, int models, int kmax,
                              hipStream_t s);
 
+// Server: scatter n staged admissions (records at blob + rec_off) into the pool, with cold
+// initialization or in-place warm start; gather n finished requests into the output staging.
+template <class T>
+hipError_t launch_admit(const Dev<T>& dv, int block, const unsigned char* blob, int rec_off, int n, hipStream_t s);
+template <class T>
+hipError_t launch_collect(const Dev<T>& dv, const CollectRec* recs, int n, unsigned char* out, hipStream_t s);
+
 }  // namespace scp

@@ -63,6 +63,23 @@ constexpr int GX_MAX_WG = 64;
 // per-workgroup record: model id | straddling flag << 8 | spanning-group flag << 9
 enum : int { WG_CROSS = 1 << 8, WG_SPAN = 1 << 9 };
 
+// Server admission record (device staging): where a request goes in the pool and where its
+// data sits in the staged blob (byte offsets).  Its trajectory records already hold pool node
+// offsets and trajectory slots, its lane table pool node indices.
+struct AdmitRec {
+    int traj_first, n_traj, node_off, n_nodes, wg_first, n_wg;
+    int warm;     // 1: shift the resident solution in place (MPC warm start)
+    int x1_node;  // warm: pool node of scenario 0, node 1, of the previous solution
+    int o_traj, o_params, o_node_traj, o_lane, o_wginfo, o_wggroup, o_xg, o_ug;
+};
+
+// Server result record: a finished request's info, nominal states and controls go to the
+// output staging at o_out (info doubles, then N+1 rows of 7 and of 4 values per trajectory).
+struct CollectRec {
+    int traj_first, n_traj, node_off, n_nodes;
+    long long o_out;
+};
+
 template <class T>
 struct Dev {
     const int* traj;       // [n_traj * TR_FIELDS]

@@ -38,6 +38,8 @@ struct Shared {
     int flag[BLOCK];               // per-trajectory flags at the group leader lane
     int st[BLOCK];                 // per-trajectory status bits at the first lane
     int sync_fail;                 // a spanning-group barrier timed out
+    T gxw[GX_WIDTH][BLOCK];        // spanning groups: member rows staged for publication
+    int gxm[BLOCK];                // member index of the row staged at a lane, -1 none
 };
 
 // Spanning consensus group of a workgroup (on = false for every other workgroup).
@@ -47,9 +49,10 @@ struct Span {
     int nwg;   // workgroups of the group
 };
 
-// Polls of a group barrier before it is declared failed (about a second); the barrier then
-// stops waiting, so every workgroup still reaches the end of the kernel.
-constexpr int kSpinLimit = 1 << 20;
+// Longest wait at a group barrier, in ticks of the device wall clock (100 MHz: 20 ms), before
+// the barrier is declared failed; it then stops waiting, so every workgroup still reaches the
+// end of the kernel quickly.
+constexpr unsigned long long kSpinTicks = 2000000ull;
 
 template <class T>
 __device__ __forceinline__ T* gx_row(const Dev<T>& dv, const Span& sp, unsigned nbar, int member) {
@@ -61,14 +64,33 @@ __device__ __forceinline__ T gx_read(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Barrier over the workgroups of a spanning group.  Each thread makes its exchange-record stores
-// visible at agent scope, the workgroup arrives once (release), thread 0 waits until all
-// workgroups of the group have arrived as often as this one (acquire), then the workgroup
-// proceeds.  nbar counts the group barriers this workgroup has passed in this launch.
+// Barrier over the workgroups of a spanning group, with the exchange of member rows.  Writer
+// lanes stage their rows in LDS (gxw, gxm); wave 0 publishes them with agent-scope atomic
+// stores; after a workgroup barrier, thread 0 arrives once with an agent-scope release (one L2
+// write-back), polls the arrival counter with relaxed agent-scope loads (no cache maintenance
+// per poll) and takes one agent-scope acquire fence (one L2 invalidation).  Readers then load
+// the rows with agent-scope atomic loads.  Both fences are required on gfx950: without them
+// arrivals and rows written on other XCDs can stay invisible.  A wait longer than
+// kSpinTicks of the device wall clock marks the workgroup's results invalid (SCP_ST_SYNC)
+// and stops waiting, so a group whose workgroups are not all resident cannot hold the queue.
+// nbar counts the group barriers this workgroup has passed in this launch; rows of barrier b
+// live in buffer b & 1.
 template <class T, int BLOCK>
 __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK>& sh, const Span& sp, unsigned& nbar,
                                            const int t) {
-    __threadfence();
+    __syncthreads();
+    if (t < 64) {
+        for (int j = t; j < BLOCK; j += 64) {
+            const int m = sh.gxm[j];
+            if (m >= 0) {
+                T* row = gx_row(dv, sp, nbar, m);
+#pragma unroll
+                for (int k = 0; k < GX_WIDTH; ++k)
+                    __hip_atomic_store(row + k, sh.gxw[k][j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sh.gxm[j] = -1;
+            }
+        }
+    }
     __syncthreads();
     nbar += 1u;
     if (t == 0) {
@@ -76,15 +98,16 @@ __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK>& s
         __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (!sh.sync_fail) {
             const unsigned target = nbar * (unsigned)sp.nwg;
-            int spins = 0;
-            while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit) {
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - t0 > kSpinTicks) {
                     sh.sync_fail = 1;
                     break;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -158,6 +181,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         sh.st[t] = 0;
     }
     if (t == 0) sh.sync_fail = 0;
+    if (t < BLOCK) sh.gxm[t] = -1;
 
     for (int k = 0; k < kp.n_scp; ++k) {
         // ---------------- a2: linearization at the nominal ----------------
@@ -214,9 +238,9 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             const bool g0 = valid && id.first();
             const unsigned b = nbar;
             if (g0) {
-                T* row = gx_row(dv, span, b, mem);
 #pragma unroll
-                for (int r = 0; r < NU; ++r) row[r] = ubar[r];
+                for (int r = 0; r < NU; ++r) sh.gxw[r][t] = ubar[r];
+                sh.gxm[t] = mem;
             }
             group_sync(dv, sh, span, nbar, t);
             if (g0) {
@@ -318,10 +342,10 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 const bool g0 = !done && id.first();
                 const unsigned b = nbar;
                 if (g0) {
-                    T* row = gx_row(dv, span, b, mem);
 #pragma unroll
                     for (int q = 0; q < C; ++q)
-                        if (slot_is_u<M>(q)) row[slot_comp_u<M>(q)] = s.cp[q];
+                        if (slot_is_u<M>(q)) sh.gxw[slot_comp_u<M>(q)][t] = s.cp[q];
+                    sh.gxm[t] = mem;
                 }
                 group_sync(dv, sh, span, nbar, t);
                 if (g0) {
@@ -415,9 +439,9 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                     // member maxima to HBM; the group maximum is the same in every workgroup
                     const unsigned b = nbar;
                     if (!done && leader) {
-                        T* row = gx_row(dv, span, b, mem);
-                        row[0] = T(bits_res(sh.mx[0][tb]));
-                        row[1] = T(bits_res(sh.mx[1][tb]));
+                        sh.gxw[0][t] = T(bits_res(sh.mx[0][tb]));
+                        sh.gxw[1][t] = T(bits_res(sh.mx[1][tb]));
+                        sh.gxm[t] = mem;
                         sh.mx[0][tb] = 0ull;
                         sh.mx[1][tb] = 0ull;
                     }
@@ -499,10 +523,10 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 }
                 const T vnom = J0 + kp.merit_w * p0, vnew = J1 + kp.merit_w * p1, vmod = J1 + kp.merit_w * pm;
                 if (span.on) {
-                    T* row = gx_row(dv, span, nbar, mem);
-                    row[0] = vnom;
-                    row[1] = vnew;
-                    row[2] = vmod;
+                    sh.gxw[0][t] = vnom;
+                    sh.gxw[1][t] = vnew;
+                    sh.gxw[2][t] = vmod;
+                    sh.gxm[t] = mem;
                 } else {
                     mnom = mnom + vnom;
                     mnew = mnew + vnew;

@@ -1,0 +1,164 @@
+"""The continuous-batching request server on the GPU.
+
+* a cold request served in a mix equals the oracle (FP64 mode, 1e-9) and the same request solved
+  through the problem API;
+* MPC sessions: every warm-started request equals the oracle's session solver (shifted warm
+  start, FP64, 1e-9);
+* alone vs in the mix: every request of a session gives bit-identical results when its session
+  runs alone on a fresh server and when it is interleaved with other sessions, request types and
+  horizons (FP32);
+* backpressure: under a small HBM budget every request still completes, the resident footprint
+  never exceeds the budget, and idle warm states are evicted.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scpgen
+from _parity import oracle_scp, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B(lib):
+    from paper_2603_10711_amd import binding
+    return binding
+
+
+def _server(B, prec="f32", scp=2, admm=30, block=None, **kw):
+    prm = B.scp_params(scp, admm)
+    return B.Server(prm, precision=prec, block=block or (256 if prec == "f32" else 128), max_nodes=1 << 15,
+                    max_traj=512, max_wg=512, max_span=64, max_requests=64, **kw)
+
+
+def test_cold_request_fp64_matches_oracle_and_problem_api(B):
+    req = scpgen.config4_request(11, S=16, N=30)
+    other = [scpgen.quad_instance(4, 700 + i, N=25 + 7 * i, K=4) for i in range(3)]
+    srv = _server(B, "f64")
+    ids = [srv.submit([d]) for d in other[:2]]
+    rid = srv.submit(req, session=-1)
+    ids.append(srv.submit([other[2]]))
+    res = srv.drain(ids + [rid])
+    got = res[rid]
+    trajs, oinfo = oracle_scp(req, 2, 30)
+    worst = max(max(rel_err(x, t.xbar), rel_err(u, t.ubar)) for x, u, t in zip(got["x"], got["u"], trajs))
+    _say("served vs oracle", worst, srv.stats())
+    assert worst < TOL64
+    prob = B.Problem(req, precision="f64", block=128)
+    prob.solve(B.scp_params(2, 30))
+    x, u, info = (a.cpu().numpy() for a in prob.result())
+    for m in range(16):
+        np.testing.assert_array_equal(prob.split(x, m, 6), got["x"][m])
+        np.testing.assert_array_equal(prob.split(u, m, 3, True), got["u"][m])
+    for i, o in zip(got["info"], oinfo):
+        assert i["admm_iters"] == o["admm_iters"] and i["n_accept"] == o["n_accept"]
+    prob.close()
+    srv.close()
+
+
+def _session_reqs(session, n, S=3, N=12):
+    return [scpgen.config4_request(session, S=S, N=N) for _ in range(n)]
+
+
+def test_session_warm_starts_fp64_match_oracle(B):
+    reqs = _session_reqs(21, 3)
+    prm = oracle.default_params(scp_iters=2, admm_iters=30)
+    ref = oracle.mpc_session(reqs, prm)
+    srv = _server(B, "f64")
+    got = []
+    for r in reqs:                      # the MPC loop: the next request follows the previous result
+        rid = srv.submit(r, session=21)
+        got.append(srv.drain([rid])[rid])
+    assert srv.stats()["warm_starts"] == 2
+    for k, ((trajs, _), g) in enumerate(zip(ref, got)):
+        worst = max(max(rel_err(x, t.xbar), rel_err(u, t.ubar)) for x, u, t in zip(g["x"], g["u"], trajs))
+        _say("session request", k, worst)
+        assert worst < TOL64
+    srv.close()
+
+
+def _mixed_stream(seed=0):
+    """Interleaved submissions: three MPC sessions (16 and 4 scenarios, different horizons),
+    single quadrotors and powered-descent instances."""
+    rng = np.random.default_rng(seed)
+    events = []
+    for k in range(3):
+        events.append(("s", 31, scpgen.config4_request(31, S=16, N=40)))
+        events.append(("s", 32, scpgen.config4_request(32, S=4, N=70)))
+        events.append(("s", 33, scpgen.config4_request(33, S=16, N=80)))
+        events.append(("q", -1, [scpgen.quad_instance(3, 40 + k, N=int(rng.integers(20, 121)), K=8, T=5.0)]))
+        events.append(("m", -1, [scpgen.mars_instance(3, 50 + k, N=int(rng.integers(20, 121)), tf=50.0)]))
+    return events
+
+
+def _run_stream(B, srv, events, steps_between=1):
+    ids = []
+    for kind, sess, req in events:
+        ids.append((kind, sess, srv.submit(req, session=sess)))
+        for _ in range(steps_between):
+            srv.step()
+    res = srv.drain([i for _, _, i in ids])
+    return [(kind, sess, res[i]) for kind, sess, i in ids]
+
+
+def test_alone_equals_in_mix_fp32(B):
+    events = _mixed_stream()
+    srv = _server(B, "f32", scp=3, admm=40)
+    mixed = _run_stream(B, srv, events)
+    st = srv.stats()
+    _say("mix stats", st)
+    assert st["warm_starts"] == 6 and st["completed"] == len(events)
+    srv.close()
+    for sess in (31, 32, 33):
+        alone_srv = _server(B, "f32", scp=3, admm=40)
+        alone = _run_stream(B, alone_srv, [e for e in events if e[1] == sess])
+        alone_srv.close()
+        mine = [r for k, s, r in mixed if s == sess]
+        assert len(alone) == len(mine) == 3
+        for (_, _, a), m in zip(alone, mine):
+            for xa, xm in zip(a["x"], m["x"]):
+                np.testing.assert_array_equal(xa, xm)
+            for ua, um in zip(a["u"], m["u"]):
+                np.testing.assert_array_equal(ua, um)
+            assert [i["admm_iters"] for i in a["info"]] == [i["admm_iters"] for i in m["info"]]
+    # the independent requests: alone through the problem API
+    for kind, sess, r in mixed:
+        if sess >= 0:
+            continue
+    singles = [e for e in events if e[1] < 0]
+    for (kind, _, req), (_, _, m) in zip(singles, [x for x in mixed if x[1] < 0]):
+        prob = B.Problem(req, precision="f32", block=256)
+        prob.solve(B.scp_params(3, 40))
+        x, u, info = (a.cpu().numpy() for a in prob.result())
+        nx, nu = req[0]["nx"], req[0]["nu"]
+        np.testing.assert_array_equal(prob.split(x, 0, nx), m["x"][0])
+        np.testing.assert_array_equal(prob.split(u, 0, nu, True), m["u"][0])
+        prob.close()
+
+
+def test_backpressure_small_budget(B):
+    reqs = [scpgen.config4_request(60 + k, S=16, N=30) for k in range(8)]
+    probe = _server(B, "f32")
+    one = probe.request_bytes(reqs[0])
+    probe.close()
+    srv = _server(B, "f32", budget_bytes=int(2.5 * one))
+    ids = [srv.submit(r, session=60 + k) for k, r in enumerate(reqs)]
+    res = srv.drain(ids)
+    st = srv.stats()
+    _say("backpressure", one, st)
+    assert len(res) == 8 and st["completed"] == 8
+    assert st["peak_resident_bytes"] <= 2.5 * one
+    assert st["evictions"] >= 6
+    # a request larger than the whole budget is refused at submission
+    tiny = _server(B, "f32", budget_bytes=one // 2)
+    with pytest.raises(B.ScpError):
+        tiny.submit(reqs[0])
+    tiny.close()
+    srv.close()

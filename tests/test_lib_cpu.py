@@ -20,8 +20,8 @@ def B():
     return binding
 
 
-def _header_functions():
-    txt = open(os.path.join(ROOT, "include", "scp.h")).read()
+def _header_functions(name="scp.h"):
+    txt = open(os.path.join(ROOT, "include", name)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b([a-z_]+)\s*\([^;{]*\)\s*;", txt)) - {"sizeof"})
 
@@ -33,6 +33,28 @@ def test_library_exports_every_declared_symbol(B):
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(B.SYMBOLS) == names
+    serve = _header_functions("scp_serve.h")
+    for n in serve:
+        assert hasattr(lib, n), n
+    assert sorted(B.SERVE_SYMBOLS) == serve
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert headers == ["scp.h", "scp_serve.h"]
+
+
+def test_server_config_validation(B):
+    lib = B.load()
+    prm = B.scp_params(10, 100)
+    good = B.ServerConfig(0, 256, 0, 1 << 14, 256, 256, 32, 32, 0, prm, 1, 2)
+    assert lib.scp_server_device_bytes(byref(good)) > (1 << 14) * 350 * 4
+    bad = [dict(block=96), dict(prec=1, block=256), dict(scp_per_step=3), dict(max_nodes=0), dict(max_inflight=0)]
+    for kw in bad:
+        c = B.ServerConfig(0, 256, 0, 1 << 14, 256, 256, 32, 32, 0, prm, 1, 2)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        assert lib.scp_server_device_bytes(byref(c)) == 0, kw
+        h = c_void_p()
+        assert lib.scp_server_create(byref(c), None, 0, None, byref(h)) == 1 and not h.value
+        assert len(lib.scp_server_last_error(None)) > 0
 
 
 def _desc(B, insts, prec=0, block=0, group=None, pack=0):
