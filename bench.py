@@ -186,10 +186,11 @@ def serve_main(a, wl, cpu):
     times, sess = SL.arrivals(a.rate, a.duration, n_sess)
     served = SL.run_served(srv, prepared, times, sess)
     print(f"[serve] served {served}", file=sys.stderr, flush=True)
-    # capacity: the same kind of requests all queued at once (sessions round robin)
+    # capacity: requests of the same shapes all queued at once, without sessions (a session's
+    # requests run one after the other, so queued session requests would measure that order)
     n_cap = a.capacity_requests
     t0 = time.perf_counter()
-    ids = [srv.submit(prepared[k % n_sess], session=k % n_sess) for k in range(n_cap)]
+    ids = [srv.submit(prepared[k % n_sess], session=-1) for k in range(n_cap)]
     res = srv.drain(ids, timeout_s=600)
     cap_wall = time.perf_counter() - t0
     capacity = {"requests": n_cap, "wall_s": round(cap_wall, 3), "solves_per_s": round(n_cap / cap_wall, 1)}
