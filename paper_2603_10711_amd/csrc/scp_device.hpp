@@ -88,8 +88,8 @@ __device__ __forceinline__ double trsqrt(double a) { return 1.0 / sqrt(a); }
 // t+1 (lane_next) or t-1 (lane_prev); the lane without a neighbour receives 0.  Called with
 // the whole wavefront active.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
 __device__ __forceinline__ float lane_next(float v) { return __builtin_bit_cast(float, dpp_next_i(__builtin_bit_cast(int, v))); }
 __device__ __forceinline__ float lane_prev(float v) { return __builtin_bit_cast(float, dpp_prev_i(__builtin_bit_cast(int, v))); }
 __device__ __forceinline__ double lane_next(double v) {
@@ -586,20 +586,19 @@ template <class M, class T>
 __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
                                       NodeState<M, T>& s, const T* znext, const T* munext) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN;
+    // No node masks are needed here: z_0 = lambda_0 = mu_0 = 0 always (node 0 has no dynamic
+    // coupling), the caller passes the next node's z and mu, which at node N are those of a
+    // node 0, of an idle lane or zeros, and d_N = 0; so w_N = 0 and A'w = B'w = 0 at node N,
+    // and the terms below add exact zeros where the paper's sums have no term.
     T w[NX], g[NN], tx[NX], tu[NU];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) w[r] = id.last() ? T(0) : munext[r] + rho.dyn * (znext[r] - nc.d[r]);
+    for (int r = 0; r < NX; ++r) w[r] = munext[r] + rho.dyn * (znext[r] - nc.d[r]);
     at_mul<M, T>(nc.Ar, w, tx);
     bt_mul<M, T>(nc.B, w, tu);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-        T v = nc.g0[r];
-        if (!id.first()) v = v + (rho.eq * s.z[r] - s.lam[r]);
-        if (!id.last()) v = v + tx[r];
-        g[r] = v;
-    }
+    for (int r = 0; r < NX; ++r) g[r] = (nc.g0[r] + (rho.eq * s.z[r] - s.lam[r])) + tx[r];
 #pragma unroll
-    for (int r = 0; r < NU; ++r) g[NX + r] = id.last() ? T(0) : tu[r];
+    for (int r = 0; r < NU; ++r) g[NX + r] = tu[r];
     // mirror terms, group order
 #pragma unroll
     for (int r = 0; r < NX; ++r) g[r] = g[r] + (rho.geo * s.cp[M::C_XBOX + r] - s.du[M::C_XBOX + r]);
@@ -631,7 +630,7 @@ __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const
         T bu = T(0);
 #pragma unroll
         for (int c = 0; c < NU; ++c) bu = bu + nc.B[r * NU + c] * s.u[c];
-        s.dd[r] = id.last() ? T(0) : (ax[r] + bu) + nc.d[r];
+        s.dd[r] = (ax[r] + bu) + nc.d[r];  // meaningless at node N (no interval); never read there
     }
 }
 
@@ -658,15 +657,10 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
     for (int r = 0; r < NX; ++r)
         s.cp[M::C_XBOX + r] = clampv(s.x[r] + s.du[M::C_XBOX + r] * rho.inv_geo, nc.lo[r], nc.hi[r]);
-    // u box
-    {
-        const bool act = !id.last();
+    // u box (at node N: u = 0, dual 0 and box [0, 0], so the copy is 0 without a mask)
 #pragma unroll
-        for (int r = 0; r < NU; ++r) {
-            const T v = clampv(s.u[r] + s.du[M::C_UBOX + r] * rho.inv_geo, nc.lo[NX + r], nc.hi[NX + r]);
-            s.cp[M::C_UBOX + r] = act ? v : T(0);
-        }
-    }
+    for (int r = 0; r < NU; ++r)
+        s.cp[M::C_UBOX + r] = clampv(s.u[r] + s.du[M::C_UBOX + r] * rho.inv_geo, nc.lo[NX + r], nc.hi[NX + r]);
     if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
         {
             T v[3];
@@ -701,10 +695,9 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
             T v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = s.u[r] + s.du[M::C_SOC + r] * rho.inv_geo;
-            proj_cone<4>(T(1), T(0.5), v);
-            const bool act = !id.last();
+            proj_cone<4>(T(1), T(0.5), v);  // at node N the input is 0 and so is the copy
 #pragma unroll
-            for (int r = 0; r < 4; ++r) s.cp[M::C_SOC + r] = act ? v[r] : T(0);
+            for (int r = 0; r < 4; ++r) s.cp[M::C_SOC + r] = v[r];
         }
     }
 }
@@ -716,6 +709,16 @@ __device__ __forceinline__ constexpr int slot_group(int k) {
         return k < M::C_UBOX ? 0 : k < M::C_BALL ? 1 : k < M::C_HS ? 2 : 3 + (k - M::C_HS) / 3;
     } else {
         return k < M::C_UBOX ? 0 : k < M::C_CONE ? 1 : k < M::C_SOC ? 2 : 3;
+    }
+}
+// Slots whose group is absent only at node N, where variable, dual and copy are all 0, so their
+// dual update needs no mask: the x box (always present), the u box and the SOC.
+template <class M>
+__device__ __forceinline__ constexpr bool slot_self_zero(int k) {
+    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        return k < M::C_BALL;
+    } else {
+        return k < M::C_CONE || k >= M::C_SOC;
     }
 }
 template <class M>
@@ -754,9 +757,9 @@ __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeS
     }
 #pragma unroll
     for (int k = 0; k < M::C; ++k) {
-        const bool act = group_active<M>(id, slot_group<M>(k));
         const T v = s.du[k] + rho.geo * (slot_var<M, T>(s, k) - s.cp[k]);
-        s.du[k] = act ? v : T(0);
+        // groups absent only at node N with a zero copy there (u box, SOC) update to 0 by themselves
+        s.du[k] = (slot_self_zero<M>(k) || group_active<M>(id, slot_group<M>(k))) ? v : T(0);
     }
 }
 

@@ -27,8 +27,9 @@ namespace scp {
 
 template <class T, int BLOCK>
 struct Shared {
-    T ex[2 * SCP_MAX_NX][BLOCK];   // z, mu of every node (backward exchange); x / xbar at accept
-    T fw[SCP_MAX_NX][BLOCK];       // d_dyn of every node (forward exchange)
+    T ex[2 * SCP_MAX_NX][BLOCK + 1];  // z, mu of every node (backward exchange); x / xbar at accept;
+                                      // column BLOCK stays 0 (the neighbour of the last lane)
+    T fw[SCP_MAX_NX][BLOCK + 1];      // d_dyn of lane t in column t + 1 (forward exchange)
     T dz[SCP_MAX_NX][BLOCK];       // z - z_old (dual-residual neighbour term)
     T zo[SCP_MAX_NX][BLOCK];       // own z before Steps 2-3 on residual iterations
     T cpo[36][BLOCK];              // own copies before Step 3 on residual iterations
@@ -181,6 +182,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         sh.st[t] = 0;
     }
     if (t == 0) sh.sync_fail = 0;
+    if (t < 2 * SCP_MAX_NX) sh.ex[t][BLOCK] = T(0);
+    if (t < SCP_MAX_NX) sh.fw[t][0] = T(0);
     if (t < BLOCK) sh.gxm[t] = -1;
 
     for (int k = 0; k < kp.n_scp; ++k) {
@@ -290,6 +293,9 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         // ---------------- a5-a9: ADMM iterations ----------------
         for (int j = 1; j <= kp.max_iters; ++j) {
             const bool check = (kp.check_every > 0 && j % kp.check_every == 0) || j == kp.max_iters;
+            // The next lane of a node N is a node 0, an idle lane or past the workgroup edge: its
+            // z and mu are exactly 0, which is what Step 1 needs there.  d_dyn of the previous
+            // lane is read at every node but used only at nodes i >= 1.
             T zn[NX], mn[NX];
             if constexpr (WAVE1) {
 #pragma unroll
@@ -299,33 +305,27 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 }
             }
             if (!done) {
+                if constexpr (!WAVE1) {
 #pragma unroll
-                for (int r = 0; r < NX; ++r) {
-                    if constexpr (!WAVE1) {
-                        zn[r] = id.last() ? T(0) : sh.ex[r][t + 1];
-                        mn[r] = id.last() ? T(0) : sh.ex[NX + r][t + 1];
-                    } else {
-                        zn[r] = id.last() ? T(0) : zn[r];
-                        mn[r] = id.last() ? T(0) : mn[r];
+                    for (int r = 0; r < NX; ++r) {
+                        zn[r] = sh.ex[r][t + 1];
+                        mn[r] = sh.ex[NX + r][t + 1];
                     }
                 }
                 step1<M, T>(id, rho, nc, s, zn, mn);
                 if constexpr (!WAVE1) {
 #pragma unroll
-                    for (int r = 0; r < NX; ++r) sh.fw[r][t] = s.dd[r];
+                    for (int r = 0; r < NX; ++r) sh.fw[r][t + 1] = s.dd[r];
                 }
             }
             T dp[NX];
             if constexpr (WAVE1) {
 #pragma unroll
-                for (int r = 0; r < NX; ++r) {
-                    const T v = lane_prev(s.dd[r]);
-                    dp[r] = (!done && !id.first()) ? v : T(0);
-                }
+                for (int r = 0; r < NX; ++r) dp[r] = lane_prev(s.dd[r]);
             } else {
                 __syncthreads();
 #pragma unroll
-                for (int r = 0; r < NX; ++r) dp[r] = (!done && !id.first()) ? sh.fw[r][t - 1] : T(0);
+                for (int r = 0; r < NX; ++r) dp[r] = sh.fw[r][t];
             }
             if (!done) {
                 if (check) {
@@ -610,7 +610,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             dv.planes[(size_t)(PL_Z + r) * P + gn] = s.z[r];
             dv.planes[(size_t)(PL_LAM + r) * P + gn] = s.lam[r];
             dv.planes[(size_t)(PL_MU + r) * P + gn] = s.mu[r];
-            dv.planes[(size_t)(PL_DD + r) * P + gn] = s.dd[r];
+            dv.planes[(size_t)(PL_DD + r) * P + gn] = id.last() ? T(0) : s.dd[r];
         }
 #pragma unroll
         for (int r = 0; r < NU; ++r) {

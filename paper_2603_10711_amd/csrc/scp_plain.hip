@@ -176,6 +176,10 @@ __global__ __launch_bounds__(256) void k_step1(Dev<T> dv, KParams<T> kp) {
         for (int r = 0; r < NX; ++r) zn[r] = mn[r] = T(0);
     }
     step1<M, T>(id, rho, nc, s, zn, mn);
+    if (id.last()) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) s.dd[r] = T(0);   // no interval after node N
+    }
     stp<NX>(PL(dv, PL_X), P, g, s.x);
     stp<NU>(PL(dv, PL_U), P, g, s.u);
     stp<NX>(PL(dv, PL_DD), P, g, s.dd);
