@@ -372,6 +372,14 @@ __device__ __forceinline__ bool group_active(const NodeId& id, int g) {
     }
 }
 
+// Penalty of group g at this node: rho_geo where the group exists, 0 where it does not.  With it
+// a group absent at a node keeps a zero dual and adds nothing to Step 1 without per-component
+// masks; its copy there is a finite dummy that is reported (and stored) as 0.
+template <class M, class T>
+__device__ __forceinline__ T group_rho(const NodeId& id, T rho_geo, int g) {
+    return group_active<M>(id, g) ? rho_geo : T(0);
+}
+
 // ------------------------------------------------------------------------------------------
 // a3: convexified sets
 // ------------------------------------------------------------------------------------------
@@ -605,16 +613,20 @@ __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
     for (int r = 0; r < NU; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_UBOX + r] - s.du[M::C_UBOX + r]);
     if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        const T rb = group_rho<M>(id, rho.geo, 2);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_BALL + r] - s.du[M::C_BALL + r]);
+        for (int r = 0; r < 3; ++r) g[NX + r] = g[NX + r] + (rb * s.cp[M::C_BALL + r] - s.du[M::C_BALL + r]);
 #pragma unroll
-        for (int j = 0; j < M::KM; ++j)
+        for (int j = 0; j < M::KM; ++j) {
+            const T rj = group_rho<M>(id, rho.geo, 3 + j);
 #pragma unroll
             for (int r = 0; r < 3; ++r)
-                g[r] = g[r] + (rho.geo * s.cp[M::C_HS + 3 * j + r] - s.du[M::C_HS + 3 * j + r]);
+                g[r] = g[r] + (rj * s.cp[M::C_HS + 3 * j + r] - s.du[M::C_HS + 3 * j + r]);
+        }
     } else {
+        const T rc = group_rho<M>(id, rho.geo, 2);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) g[r] = g[r] + (rho.geo * s.cp[M::C_CONE + r] - s.du[M::C_CONE + r]);
+        for (int r = 0; r < 3; ++r) g[r] = g[r] + (rc * s.cp[M::C_CONE + r] - s.du[M::C_CONE + r]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_SOC + r] - s.du[M::C_SOC + r]);
     }
@@ -648,7 +660,8 @@ __device__ __forceinline__ void step2(const NodeId& id, const Rho<T>& rho, NodeS
 // ------------------------------------------------------------------------------------------
 // a7: Step 3 (geometric layer): copy^g = projection of (var^g + nu^g / rho_geo)
 // ------------------------------------------------------------------------------------------
-// The u copies at node 0 of a consensus group are averaged afterwards by the caller.
+// The u copies at node 0 of a consensus group are averaged afterwards by the caller.  Copies of
+// groups absent at this node are finite dummies (see group_rho).
 template <class M, class T>
 __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
                                       NodeState<M, T>& s, T ball_r, T kappa, T inv1k2) {
@@ -667,9 +680,8 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
             for (int r = 0; r < 3; ++r) v[r] = s.u[r] + s.du[M::C_BALL + r] * rho.inv_geo;
             proj_ball3(ball_r, v);
-            const bool act = !id.last() && id.ball;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) s.cp[M::C_BALL + r] = act ? v[r] : T(0);
+            for (int r = 0; r < 3; ++r) s.cp[M::C_BALL + r] = v[r];
         }
 #pragma unroll
         for (int j = 0; j < M::KM; ++j) {
@@ -677,9 +689,8 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
             for (int r = 0; r < 3; ++r) v[r] = s.x[r] + s.du[M::C_HS + 3 * j + r] * rho.inv_geo;
             proj_halfspace(&nc.hs[4 * j], nc.hs[4 * j + 3], v);
-            const bool act = !id.first() && j < id.K;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) s.cp[M::C_HS + 3 * j + r] = act ? v[r] : T(0);
+            for (int r = 0; r < 3; ++r) s.cp[M::C_HS + 3 * j + r] = v[r];
         }
     } else {
         {
@@ -687,9 +698,8 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
             for (int r = 0; r < 3; ++r) v[r] = s.x[r] + s.du[M::C_CONE + r] * rho.inv_geo;
             proj_cone<3>(kappa, inv1k2, v);
-            const bool act = !id.first();
 #pragma unroll
-            for (int r = 0; r < 3; ++r) s.cp[M::C_CONE + r] = act ? v[r] : T(0);
+            for (int r = 0; r < 3; ++r) s.cp[M::C_CONE + r] = v[r];
         }
         {
             T v[4];
@@ -757,9 +767,10 @@ __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeS
     }
 #pragma unroll
     for (int k = 0; k < M::C; ++k) {
-        const T v = s.du[k] + rho.geo * (slot_var<M, T>(s, k) - s.cp[k]);
-        // groups absent only at node N with a zero copy there (u box, SOC) update to 0 by themselves
-        s.du[k] = (slot_self_zero<M>(k) || group_active<M>(id, slot_group<M>(k))) ? v : T(0);
+        // groups absent only at node N with a zero copy there (u box, SOC) update to 0 by
+        // themselves; the others use their group penalty, 0 where they are absent
+        const T rg = slot_self_zero<M>(k) ? rho.geo : group_rho<M>(id, rho.geo, slot_group<M>(k));
+        s.du[k] = s.du[k] + rg * (slot_var<M, T>(s, k) - s.cp[k]);
     }
 }
 

@@ -619,7 +619,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         }
 #pragma unroll
         for (int q = 0; q < C; ++q) {
-            dv.planes[(size_t)(PL_CP + q) * P + gn] = s.cp[q];
+            dv.planes[(size_t)(PL_CP + q) * P + gn] = group_active<M>(id, slot_group<M>(q)) ? s.cp[q] : T(0);
             dv.planes[(size_t)(PL_DU + q) * P + gn] = s.du[q];
         }
     }

@@ -248,6 +248,9 @@ __global__ __launch_bounds__(256) void k_step234(Dev<T> dv, KParams<T> kp, int c
         const T v = s.du[k] + rho.geo * (slot_var<M, T>(s, k) - s.cp[k]);
         s.du[k] = act ? v : T(0);
     }
+#pragma unroll
+    for (int k = 0; k < M::C; ++k)   // copies of groups absent at this node are stored as 0
+        if (!group_active<M>(id, slot_group<M>(k))) s.cp[k] = T(0);
     stp<NX>(PL(dv, PL_Z), P, g, s.z);
     stp<NX>(PL(dv, PL_LAM), P, g, s.lam);
     stp<NX>(PL(dv, PL_MU), P, g, s.mu);
