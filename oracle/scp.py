@@ -26,13 +26,33 @@ from .dynamics import rk4, rk4_jac, QUAD, MARS
 
 def default_params(**kw) -> dict:
     """Solver parameters; the defaults are the fixed-budget settings of the workloads
-    (rho = 1 for all three penalties, always-accept steps, fixed trust radius)."""
-    p = dict(scp_iters=10, admm_iters=100, rho_eq=1.0, rho_dyn=1.0, rho_geo=1.0,
+    (rho = 1 for all three penalties, always-accept steps, fixed trust radius).  rho_final > 0
+    turns on the penalty schedule of penalty_factors."""
+    p = dict(scp_iters=10, admm_iters=100, rho_eq=1.0, rho_dyn=1.0, rho_geo=1.0, rho_final=0.0,
              check_every=0, eps_p=0.0, eps_d=0.0,
              eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
              merit_w=1.0e3)
     p.update(kw)
     return p
+
+
+def penalty_factors(params: dict) -> list[float]:
+    """Factor applied to all three penalties at each SCP iteration (Sec. IV-A.2, parameter
+    study: the penalties are scaled geometrically over the SCP iterations up to a final value).
+
+    Reading: with K SCP iterations, rho_eq grows from its given value to rho_final by a constant
+    ratio q = (rho_final / rho_eq)^(1 / (K - 1)), evaluated once in double precision; the factor
+    of iteration k is q^k formed by repeated multiplication (1, q, q*q, ...); rho_dyn and rho_geo
+    keep their ratios to rho_eq.  rho_final <= 0, or K = 1, means no schedule.  The duals are
+    carried across SCP iterations unscaled (they are the multipliers themselves)."""
+    K = params["scp_iters"]
+    rf = params.get("rho_final", 0.0) or 0.0
+    q = (rf / params["rho_eq"]) ** (1.0 / (K - 1)) if rf > 0.0 and K > 1 else 1.0
+    out, s = [], 1.0
+    for _ in range(K):
+        out.append(s)
+        s = s * q
+    return out
 
 
 # ------------------------------------------------------------------------------------------
@@ -260,7 +280,7 @@ def scp_group(trajs: list[Traj], params: dict, delta: float | None = None) -> di
 
     Returns the group's info; the trajectories' nominals hold the solution.
     """
-    rho = (params["rho_eq"], params["rho_dyn"], params["rho_geo"])
+    factors = penalty_factors(params)
     delta = trajs[0].inst["delta"] if delta is None else delta
     coupled = len(trajs) > 1
     iters_total = 0
@@ -268,6 +288,7 @@ def scp_group(trajs: list[Traj], params: dict, delta: float | None = None) -> di
     rp = rd = float("nan")
     status = 0
     for k in range(params["scp_iters"]):
+        rho = (params["rho_eq"] * factors[k], params["rho_dyn"] * factors[k], params["rho_geo"] * factors[k])
         packs = _prepare(trajs, delta, rho)
         it, rp, rd = admm_run(packs, rho, params["admm_iters"], params["check_every"],
                               params["eps_p"], params["eps_d"], couple_u0=coupled)
