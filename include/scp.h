@@ -170,6 +170,13 @@ typedef struct {
     scp_form form;                    /* plain (HBM state) or persistent kernel             */
     int32_t scp_per_launch;           /* persistent form: SCP iterations per kernel launch
                                          (0 = all in one launch)                            */
+    double rho_final;                 /* > 0: penalty schedule (Sec. IV-A.2 parameter study):
+                                         rho_eq grows geometrically from admm.rho_eq at the first
+                                         SCP iteration to rho_final at the last (ratio
+                                         (rho_final/rho_eq)^(1/(scp_iters-1)) in double, factors
+                                         by repeated multiplication), rho_dyn and rho_geo keep
+                                         their ratios to rho_eq, duals carry over unscaled.
+                                         0: fixed penalties.                                  */
     int32_t graph;                    /* 1: the first call with these parameters captures its
                                          whole launch sequence into a hipGraph kept by the
                                          handle, later calls with equal parameters replay it.

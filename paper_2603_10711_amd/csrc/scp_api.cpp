@@ -319,6 +319,12 @@ struct scp_problem {
 
 namespace {
 
+// Ratio of the geometric penalty schedule (1: none).
+double sched_ratio(const scp_params& s) {
+    if (!(s.rho_final > 0.0) || s.scp_iters < 2) return 1.0;
+    return std::pow(s.rho_final / s.admm.rho_eq, 1.0 / (double)(s.scp_iters - 1));
+}
+
 template <class T>
 KParams<T> kparams(const admm_params* a, const scp_params* s) {
     KParams<T> k{};
@@ -329,6 +335,11 @@ KParams<T> kparams(const admm_params* a, const scp_params* s) {
     k.eps_d = T(a->eps_dual);
     k.max_iters = a->max_iters;
     k.check_every = a->check_every;
+    k.rho_base[0] = a->rho_eq;
+    k.rho_base[1] = a->rho_dyn;
+    k.rho_base[2] = a->rho_geo;
+    k.sched_s0 = 1.0;
+    k.sched_q = 1.0;
     if (s) {
         k.eta0 = T(s->eta0);
         k.eta1 = T(s->eta1);
@@ -337,9 +348,18 @@ KParams<T> kparams(const admm_params* a, const scp_params* s) {
         k.grow = T(s->grow);
         k.delta_max = T(s->delta_max);
         k.merit_w = T(s->merit_w);
+        k.sched_q = sched_ratio(*s);
     }
     k.n_scp = 1;
     return k;
+}
+
+// penalties of one SCP iteration: base * factor
+template <class T>
+void scale_rho(KParams<T>& k, double f) {
+    k.rho_eq = T(k.rho_base[0] * f);
+    k.rho_dyn = T(k.rho_base[1] * f);
+    k.rho_geo = T(k.rho_base[2] * f);
 }
 
 scp_status fail(scp_problem* p, scp_status st, const std::string& msg) {
@@ -366,7 +386,7 @@ bool same_params(const scp_params& a, const scp_params& b) {
            a.admm.eps_dual == b.admm.eps_dual && std::memcmp(&a.eta0, &b.eta0, sizeof(double)) == 0 &&
            a.eta1 == b.eta1 && a.eta2 == b.eta2 && a.shrink == b.shrink && a.grow == b.grow &&
            std::memcmp(&a.delta_max, &b.delta_max, sizeof(double)) == 0 && a.merit_w == b.merit_w &&
-           a.form == b.form && a.scp_per_launch == b.scp_per_launch;
+           a.form == b.form && a.scp_per_launch == b.scp_per_launch && a.rho_final == b.rho_final;
 }
 
 template <class T>
@@ -407,7 +427,9 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
     hipError_t e = launch_plain<T>(PlainOp::Reset, dv, kp, L.models, L.kmax, 1, 0, p->stream);
     if (e != hipSuccess) return hip_check(p, e, "reset launch");
     if (s->form == SCP_FORM_PLAIN) {
-        for (int k = 0; k < s->scp_iters; ++k) {
+        double f = 1.0;
+        for (int k = 0; k < s->scp_iters; ++k, f *= kp.sched_q) {
+            scale_rho(kp, f);
             e = launch_plain<T>(PlainOp::Lin, dv, kp, L.models, L.kmax, 0, 0, p->stream);
             if (e != hipSuccess) return hip_check(p, e, "linearize launch");
             scp_status st = run_plain_admm<T>(p, dv, kp);
@@ -430,9 +452,12 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
         e = launch_persistent<T>(dv, kp, L.n_wg, L.block, L.models, L.kmax, p->stream);
         return hip_check(p, e, "persistent launch");
     }
+    double f = 1.0;
     while (done < s->scp_iters) {
         const int n = std::min(per, s->scp_iters - done);
         kp.n_scp = n;
+        kp.sched_s0 = f;
+        for (int k = 0; k < n; ++k) f *= kp.sched_q;
         kp.reset_info = done == 0 ? 1 : 0;
         kp.final_metrics = (done + n == s->scp_iters) ? 1 : 0;
         e = launch_persistent<T>(dv, kp, L.n_wg, L.block, L.models, L.kmax, p->stream);
@@ -478,10 +503,10 @@ std::string tune_key(const scp_problem_desc* d, const scp_params* q, const std::
              std::to_string(same) + ";";
     }
     char buf[512];
-    std::snprintf(buf, sizeof buf, "|%d|%.17g,%.17g,%.17g,%d,%.17g,%.17g|%.17g,%.17g,%.17g,%.17g,%.17g,%.17g,%.17g|%d|",
+    std::snprintf(buf, sizeof buf, "|%d|%.17g,%.17g,%.17g,%d,%.17g,%.17g|%.17g,%.17g,%.17g,%.17g,%.17g,%.17g,%.17g|%d|%.17g|",
                   q->scp_iters, q->admm.rho_eq, q->admm.rho_dyn, q->admm.rho_geo, q->admm.max_iters,
                   q->admm.eps_prim, q->admm.eps_dual, q->eta0, q->eta1, q->eta2, q->shrink, q->grow, q->delta_max,
-                  q->merit_w, q->scp_per_launch);
+                  q->merit_w, q->scp_per_launch, q->rho_final);
     k += buf;
     for (int c : cads) k += std::to_string(c) + ",";
     return k;
@@ -589,6 +614,7 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
     if (prm->scp_iters < 0) return fail(p, SCP_ERR_ARG, "scp_iters must be >= 0");
     if (prm->form != SCP_FORM_PLAIN && prm->form != SCP_FORM_PERSISTENT) return fail(p, SCP_ERR_ARG, "invalid form");
     if (prm->graph != 0 && prm->graph != 1) return fail(p, SCP_ERR_ARG, "graph must be 0 or 1");
+    if (!(prm->rho_final >= 0.0)) return fail(p, SCP_ERR_ARG, "rho_final must be >= 0");
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok)
         return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory exceeds 256 nodes or a consensus group more than 64 members; "
                                             "use the plain form");

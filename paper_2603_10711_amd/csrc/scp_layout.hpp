@@ -116,6 +116,10 @@ struct KParams {
     int reset_info;
     int has_groups;
     int iter_base;    // plain form: index of the first ADMM iteration of this launch batch
+    // penalty schedule: the penalties of SCP iteration k of a launch are rho_base * s_k with
+    // s_0 = sched_s0 and s_{k+1} = s_k * sched_q, in double (rho_base in double too)
+    double rho_base[3];
+    double sched_s0, sched_q;
 };
 
 }  // namespace scp

@@ -144,7 +144,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
     const bool first_lane = valid && id.first();
     const bool leader = first_lane && lb == tb;
-    const Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    Rho<T> rho;
+    double sfac = kp.sched_s0;  // penalty-schedule factor of the current SCP iteration
     const T ball_r = valid ? prm[SCP_P_UBALL] : T(0);
     const T kappa = valid ? prm[SCP_P_GLIDE] : T(1);
     const T inv1k2 = T(1) / (T(1) + kappa * kappa);
@@ -186,7 +187,11 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     if (t < SCP_MAX_NX) sh.fw[t][0] = T(0);
     if (t < BLOCK) sh.gxm[t] = -1;
 
-    for (int k = 0; k < kp.n_scp; ++k) {
+    for (int k = 0; k < kp.n_scp; ++k, sfac *= kp.sched_q) {
+        {
+            const T re = T(kp.rho_base[0] * sfac), rd = T(kp.rho_base[1] * sfac), rg = T(kp.rho_base[2] * sfac);
+            rho = Rho<T>{re, rd, rg, T(1) / rg, T(1) / (re + rd)};
+        }
         // ---------------- a2: linearization at the nominal ----------------
         T F[NX];
         if (valid && !id.last()) {

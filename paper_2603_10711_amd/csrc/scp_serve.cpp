@@ -111,6 +111,7 @@ bool valid_config(const scp_server_config* c, std::string& err) {
         return false;
     }
     if (c->scp_per_step < 1 || q.scp_iters % c->scp_per_step != 0) { err = "scp_per_step must divide scp_iters"; return false; }
+    if (q.rho_final != 0.0) { err = "the server runs fixed penalties (rho_final = 0)"; return false; }
     if (c->max_inflight < 1 || c->max_inflight > 8) { err = "max_inflight must be in 1..8"; return false; }
     return true;
 }
@@ -639,6 +640,11 @@ scp_status do_step(scp_server* s, int wait, int32_t* pending) {
     kp.grow = T(q.grow);
     kp.delta_max = T(q.delta_max);
     kp.merit_w = T(q.merit_w);
+    kp.rho_base[0] = q.admm.rho_eq;
+    kp.rho_base[1] = q.admm.rho_dyn;
+    kp.rho_base[2] = q.admm.rho_geo;
+    kp.sched_s0 = 1.0;
+    kp.sched_q = 1.0;
     kp.n_scp = s->cfg.scp_per_step;
     kp.final_metrics = 1;
     kp.reset_info = 0;

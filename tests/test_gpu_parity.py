@@ -252,3 +252,20 @@ def test_reset_then_solve_equals_fresh_solve(B):
         np.testing.assert_array_equal(u3, u1)
         np.testing.assert_array_equal(i3, i1)
         fresh.close()
+
+
+@pytest.mark.parametrize("form,per_launch", [("plain", 0), ("persistent", 0), ("persistent", 1)])
+def test_penalty_schedule_fp64(B, form, per_launch):
+    """The paper's geometric penalty schedule (1e2 -> 1e3 over the SCP iterations), duals carried
+    unscaled, the persistent form also split into one launch per SCP iteration."""
+    insts = _ragged_quads(5, 60) + [scpgen.mars_instance(2, 30, N=14)]
+    kw = dict(rho_eq=100.0, rho_dyn=100.0, rho_geo=100.0, rho_final=1e3)
+    trajs, oinfo = oracle_scp(insts, 4, 40, **kw)
+    _say("schedule", form, per_launch)
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(4, 40, rho=100.0, rho_final=1e3, form=form, scp_per_launch=per_launch))
+    f = gpu_fields(prob)
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < TOL64
+    prob.close()
