@@ -29,6 +29,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Fuse a multiply and an add only where one source expression holds both.  HIP's default
+    # ("fast") lets the backend fuse across statements, and which product it picks then depends
+    # on the code around it, so kernel instantiations that differ only in unrelated code (the
+    # obstacle count, the model mix of a launch) would round the same node differently.
+    "-ffp-contract=on",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I" + os.path.join(ROOT, "include"),
 ]

@@ -79,6 +79,10 @@ __device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf
 __device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
 __device__ __forceinline__ float tmaxv(float a, float b) { return __builtin_fmaxf(a, b); }
 __device__ __forceinline__ double tmaxv(double a, double b) { return __builtin_fmax(a, b); }
+// fused multiply-add written out, where the rounding of a sum must not depend on which product
+// the compiler chooses to contract (it can differ between kernel instantiations)
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // 1/sqrt(a): one hardware reciprocal square root in FP32 (about 1 ulp), exact division in FP64
 __device__ __forceinline__ float trsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
 __device__ __forceinline__ double trsqrt(double a) { return 1.0 / sqrt(a); }
@@ -590,9 +594,12 @@ __device__ __forceinline__ void chol_solve(const T* L, T* g) {
 // g_u =         1{i<N} B_i' w_i + sum_g (rho_geo uhat^g - nu_u^g),  w_i = mu_{i+1} + rho_dyn (z_{i+1} - d_i)
 // then x, u from the cached factor and d_dyn,i = A_i x_i + B_i u_i + d_i.
 // Absent groups hold exactly zero copies and duals, so summing over all slots is exact.
-template <class M, class T>
+// HSS: the half-space groups are carried in scalar form (hs_* below); their Step-1 term comes
+// in hs_x (added to the position rows) instead of from s.cp / s.du.
+template <class M, class T, bool HSS = false>
 __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
-                                      NodeState<M, T>& s, const T* znext, const T* munext) {
+                                      NodeState<M, T>& s, const T* znext, const T* munext,
+                                      const T* hs_x = nullptr) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN;
     // No node masks are needed here: z_0 = lambda_0 = mu_0 = 0 always (node 0 has no dynamic
     // coupling), the caller passes the next node's z and mu, which at node N are those of a
@@ -616,12 +623,17 @@ __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const
         const T rb = group_rho<M>(id, rho.geo, 2);
 #pragma unroll
         for (int r = 0; r < 3; ++r) g[NX + r] = g[NX + r] + (rb * s.cp[M::C_BALL + r] - s.du[M::C_BALL + r]);
+        if constexpr (HSS) {
 #pragma unroll
-        for (int j = 0; j < M::KM; ++j) {
-            const T rj = group_rho<M>(id, rho.geo, 3 + j);
+            for (int r = 0; r < 3; ++r) g[r] = g[r] + hs_x[r];
+        } else {
 #pragma unroll
-            for (int r = 0; r < 3; ++r)
-                g[r] = g[r] + (rj * s.cp[M::C_HS + 3 * j + r] - s.du[M::C_HS + 3 * j + r]);
+            for (int j = 0; j < M::KM; ++j) {
+                const T rj = group_rho<M>(id, rho.geo, 3 + j);
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    g[r] = g[r] + (rj * s.cp[M::C_HS + 3 * j + r] - s.du[M::C_HS + 3 * j + r]);
+            }
         }
     } else {
         const T rc = group_rho<M>(id, rho.geo, 2);
@@ -662,7 +674,7 @@ __device__ __forceinline__ void step2(const NodeId& id, const Rho<T>& rho, NodeS
 // ------------------------------------------------------------------------------------------
 // The u copies at node 0 of a consensus group are averaged afterwards by the caller.  Copies of
 // groups absent at this node are finite dummies (see group_rho).
-template <class M, class T>
+template <class M, class T, bool HSS = false>
 __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
                                       NodeState<M, T>& s, T ball_r, T kappa, T inv1k2) {
     constexpr int NX = M::NX, NU = M::NU;
@@ -684,7 +696,7 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
             for (int r = 0; r < 3; ++r) s.cp[M::C_BALL + r] = v[r];
         }
 #pragma unroll
-        for (int j = 0; j < M::KM; ++j) {
+        for (int j = 0; j < (HSS ? 0 : M::KM); ++j) {
             T v[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) v[r] = s.x[r] + s.du[M::C_HS + 3 * j + r] * rho.inv_geo;
@@ -756,7 +768,7 @@ __device__ __forceinline__ T slot_var(const NodeState<M, T>& s, int k) {
 // ------------------------------------------------------------------------------------------
 // a8: Step 4 (dual ascent)
 // ------------------------------------------------------------------------------------------
-template <class M, class T>
+template <class M, class T, bool HSS = false>
 __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeState<M, T>& s, const T* ddprev) {
     if (!id.first()) {
 #pragma unroll
@@ -767,11 +779,111 @@ __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeS
     }
 #pragma unroll
     for (int k = 0; k < M::C; ++k) {
+        if constexpr (HSS && M::ID == SCP_MODEL_QUAD_PM) {
+            if (k >= M::C_HS) continue;
+        }
         // groups absent only at node N with a zero copy there (u box, SOC) update to 0 by
         // themselves; the others use their group penalty, 0 where they are absent
         const T rg = slot_self_zero<M>(k) ? rho.geo : group_rho<M>(id, rho.geo, slot_group<M>(k));
         s.du[k] = s.du[k] + rg * (slot_var<M, T>(s, k) - s.cp[k]);
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Half-space groups in scalar form (persistent kernel)
+// ------------------------------------------------------------------------------------------
+// With a unit normal a, the projection onto {a'y >= b} moves its input along a only, so after
+// one ADMM iteration the group's dual is nu = -sigma a with sigma = rho t, t = max(0, b - a'v),
+// and its copy is x + ((kappa - sigma) / rho) a with kappa = 2 sigma - sigma_prev.  Steps 1, 3
+// and 4 then need per group two scalars instead of two 3-vectors:
+//   Step 1 term  rho cp - nu = rho x_prev + kappa a (+ e, below)
+//   Step 3 + 4   t = max(0, b - (a'x - sigma / rho)),  sigma' = rho t,  kappa' = 2 sigma' - sigma
+// The dual carried into an SCP iteration, nu_c, is generally not along the new normal: with
+// sigma_0 = -a'nu_c and the orthogonal part p = nu_c + sigma_0 a (kappa_0 = sigma_0), the Step-1
+// term carries e = -p in the first ADMM iteration and e = +p in the second, and the copy of the
+// first iteration has the extra p / rho.  All of this is exact in real arithmetic (a'a = 1).
+// Absent groups have a = 0, b = 0 and therefore t = 0: no masks.  Every multiply-add below is an
+// explicit FMA, so each kernel instantiation rounds the same way.
+
+// Enter an SCP iteration: scalars from the carried duals s.du (vector form) and the new normals.
+// perp receives p (3 per group), psum the sum over groups.
+template <class M, class T>
+__device__ __forceinline__ void hs_enter(const NodeConst<M, T>& nc, const NodeState<M, T>& s, T* sig, T* kap, T* perp,
+                                         T* psum) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) psum[r] = T(0);
+#pragma unroll
+    for (int j = 0; j < M::KM; ++j) {
+        const T* a = &nc.hs[4 * j];
+        const T* du = &s.du[M::C_HS + 3 * j];
+        const T s0 = -tfma(a[2], du[2], tfma(a[1], du[1], a[0] * du[0]));
+        sig[j] = s0;
+        kap[j] = s0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            perp[3 * j + r] = tfma(s0, a[r], du[r]);
+            psum[r] = psum[r] + perp[3 * j + r];
+        }
+    }
+}
+
+// Step-1 term of all half-space groups at ADMM iteration `it` (1-based) of the SCP iteration:
+// nr x_prev + sum_j kappa_j a_j (+ e), nr = rho_geo times the number of groups at this node.
+template <class M, class T>
+__device__ __forceinline__ void hs_step1_term(const NodeConst<M, T>& nc, const T* xprev, T nr, const T* kap, int it,
+                                              const T* psum, T* hx) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) hx[r] = nr * xprev[r];
+#pragma unroll
+    for (int j = 0; j < M::KM; ++j)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) hx[r] = tfma(kap[j], nc.hs[4 * j + r], hx[r]);
+    if (it <= 2) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) hx[r] = it == 1 ? hx[r] - psum[r] : hx[r] + psum[r];
+    }
+}
+
+// Steps 3 and 4 of all half-space groups.
+template <class M, class T>
+__device__ __forceinline__ void hs_step34(const NodeConst<M, T>& nc, const Rho<T>& rho, const T* x, T* sig, T* kap) {
+#pragma unroll
+    for (int j = 0; j < M::KM; ++j) {
+        const T* a = &nc.hs[4 * j];
+        const T av = tfma(-sig[j], rho.inv_geo, tfma(a[2], x[2], tfma(a[1], x[1], a[0] * x[0])));
+        const T t = tmaxv(T(0), a[3] - av);
+        const T sn = rho.geo * t;
+        kap[j] = tfma(T(2), sn, -sig[j]);  // 2 sn is exact: one rounding, as (sn + sn) - sig
+        sig[j] = sn;
+    }
+}
+
+// Vector form of the half-space copies after ADMM iteration `it` (0: the re-initialized copies)
+// and of their duals, into s.cp / s.du.  perp is read only for it <= 1.
+template <class M, class T>
+__device__ __forceinline__ void hs_copies(const NodeConst<M, T>& nc, const Rho<T>& rho, NodeState<M, T>& s,
+                                          const T* sig, const T* kap, int it, const T* perp) {
+#pragma unroll
+    for (int j = 0; j < M::KM; ++j) {
+        const T c = (kap[j] - sig[j]) * rho.inv_geo;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            T v = tfma(c, nc.hs[4 * j + r], s.x[r]);
+            if (it == 1) v = tfma(perp[3 * j + r], rho.inv_geo, v);
+            s.cp[M::C_HS + 3 * j + r] = v;
+        }
+    }
+}
+template <class M, class T>
+__device__ __forceinline__ void hs_duals(const NodeConst<M, T>& nc, NodeState<M, T>& s, const T* sig, int it,
+                                         const T* perp) {
+#pragma unroll
+    for (int j = 0; j < M::KM; ++j)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const T v = it == 0 ? tfma(-sig[j], nc.hs[4 * j + r], perp[3 * j + r]) : -sig[j] * nc.hs[4 * j + r];
+            s.du[M::C_HS + 3 * j + r] = v;
+        }
 }
 
 // ------------------------------------------------------------------------------------------

@@ -25,7 +25,9 @@
 
 namespace scp {
 
-template <class T, int BLOCK>
+// HSR: rows of half-space state (3 per half-space group and 3 for their sum; 1 where the
+// kernel holds no half-space groups).
+template <class T, int BLOCK, int HSR>
 struct Shared {
     T ex[2 * SCP_MAX_NX][BLOCK + 1];  // z, mu of every node (backward exchange); x / xbar at accept;
                                       // column BLOCK stays 0 (the neighbour of the last lane)
@@ -39,6 +41,8 @@ struct Shared {
     int flag[BLOCK];               // per-trajectory flags at the group leader lane
     int st[BLOCK];                 // per-trajectory status bits at the first lane
     int sync_fail;                 // a spanning-group barrier timed out
+    T hsp[HSR][BLOCK];             // half-space groups: carried-dual parts orthogonal to the new
+                                   // normals (3 per group), then their sum
     T gxw[GX_WIDTH][BLOCK];        // spanning groups: member rows staged for publication
     int gxm[BLOCK];                // member index of the row staged at a lane, -1 none
 };
@@ -76,8 +80,8 @@ __device__ __forceinline__ T gx_read(const T* p) {
 // and stops waiting, so a group whose workgroups are not all resident cannot hold the queue.
 // nbar counts the group barriers this workgroup has passed in this launch; rows of barrier b
 // live in buffer b & 1.
-template <class T, int BLOCK>
-__device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK>& sh, const Span& sp, unsigned& nbar,
+template <class T, int BLOCK, int HSR>
+__device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR>& sh, const Span& sp, unsigned& nbar,
                                            const int t) {
     __syncthreads();
     if (t < 64) {
@@ -116,8 +120,8 @@ __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK>& s
 // WAVE1: no trajectory of this workgroup straddles a wavefront boundary, so neighbour values
 // move with DPP wavefront shifts instead of LDS and the two exchange barriers of every ADMM
 // iteration disappear.  The per-trajectory reductions still go through LDS.
-template <class M, class T, int BLOCK, bool WAVE1, bool SPAN>
-__device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK>& sh,
+template <class M, class T, int BLOCK, bool WAVE1, bool SPAN, int HSR>
+__device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR>& sh,
                                                 const int t, const int gn, const Span span_in) {
     // SPAN: this kernel variant may hold spanning groups (compiled out of the other variant)
     const Span span{SPAN && span_in.on, span_in.slot, span_in.nwg};
@@ -144,7 +148,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
     const bool first_lane = valid && id.first();
     const bool leader = first_lane && lb == tb;
-    Rho<T> rho;
+    Rho<T> rho{};
     double sfac = kp.sched_s0;  // penalty-schedule factor of the current SCP iteration
     const T ball_r = valid ? prm[SCP_P_UBALL] : T(0);
     const T kappa = valid ? prm[SCP_P_GLIDE] : T(1);
@@ -175,6 +179,19 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
     int status = 0;
     int n_acc = 0, iters_sum = 0;
+    // half-space groups in scalar form (quadrotor): dual -sig a, Step-1 coefficient kap
+    constexpr bool HSQ = (M::ID == SCP_MODEL_QUAD_PM) && (M::KM > 0);
+    constexpr int HSN = HSQ ? M::KM : 1;
+    static_assert(!HSQ || HSR == 3 * HSN + 3, "half-space rows of the workgroup state");
+    T sig[HSN], kap[HSN];
+#pragma unroll
+    for (int q = 0; q < HSN; ++q) sig[q] = kap[q] = T(0);
+    if constexpr (HSQ) {
+#pragma unroll
+        for (int q = 0; q < M::NHS; ++q) nc.hs[q] = T(0);  // idle lanes: no half-spaces
+    }
+    T nr = T(0);          // rho_geo times the number of half-space groups at this node
+    int last_iters = 0;   // ADMM iterations this lane ran in the last SCP iteration
     T rp_last = T(0), rd_last = T(0), ratio_last = T(0), merit_last = T(0);
     bool conv_last = false;
     if (t < BLOCK) {
@@ -290,6 +307,18 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 sh.ex[NX + r][t] = s.mu[r];
             }
         }
+        // The scalar half-space state is entered, left and materialized in every lane (idle
+        // lanes hold zeros): a lane-conditional update would keep the vector copies and duals
+        // of the half-space groups alive through the ADMM loop.
+        if constexpr (HSQ) {
+            T perp[3 * HSN], psum[3];
+            hs_enter<M, T>(nc, s, sig, kap, perp, psum);
+#pragma unroll
+            for (int q = 0; q < 3 * HSN; ++q) sh.hsp[q][t] = perp[q];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) sh.hsp[3 * HSN + r][t] = psum[r];
+            nr = rho.geo * T(id.first() ? 0 : min(id.K, (int)M::KM));
+        }
         bool done = !valid;
         int iters_here = kp.max_iters;
         bool conv_here = false;
@@ -317,7 +346,28 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                         mn[r] = sh.ex[NX + r][t + 1];
                     }
                 }
-                step1<M, T>(id, rho, nc, s, zn, mn);
+                if (check) {
+                    // z and copies before this iteration, for the dual residual
+                    if constexpr (HSQ) {
+                        T perp[3 * HSN];
+#pragma unroll
+                        for (int q = 0; q < 3 * HSN; ++q) perp[q] = j == 2 ? sh.hsp[q][t] : T(0);
+                        hs_copies<M, T>(nc, rho, s, sig, kap, j - 1, perp);
+                    }
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) sh.zo[r][t] = s.z[r];
+#pragma unroll
+                    for (int q = 0; q < C; ++q) sh.cpo[q][t] = s.cp[q];
+                }
+                if constexpr (HSQ) {
+                    T psum[3], hx[3];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) psum[r] = j <= 2 ? sh.hsp[3 * HSN + r][t] : T(0);
+                    hs_step1_term<M, T>(nc, s.x, nr, kap, j, psum, hx);
+                    step1<M, T, true>(id, rho, nc, s, zn, mn, hx);
+                } else {
+                    step1<M, T>(id, rho, nc, s, zn, mn);
+                }
                 if constexpr (!WAVE1) {
 #pragma unroll
                     for (int r = 0; r < NX; ++r) sh.fw[r][t + 1] = s.dd[r];
@@ -333,14 +383,9 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 for (int r = 0; r < NX; ++r) dp[r] = sh.fw[r][t];
             }
             if (!done) {
-                if (check) {
-#pragma unroll
-                    for (int r = 0; r < NX; ++r) sh.zo[r][t] = s.z[r];
-#pragma unroll
-                    for (int q = 0; q < C; ++q) sh.cpo[q][t] = s.cp[q];
-                }
                 step2<M, T>(id, rho, s, dp);
-                step3<M, T>(id, rho, nc, s, ball_r, kappa, inv1k2);
+                step3<M, T, HSQ>(id, rho, nc, s, ball_r, kappa, inv1k2);
+                if constexpr (HSQ) hs_step34<M, T>(nc, rho, s.x, sig, kap);
             }
             if (span.on) {
                 // scenario consensus across workgroups
@@ -382,7 +427,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 }
             }
             if (!done) {
-                step4<M, T>(id, rho, s, dp);
+                step4<M, T, HSQ>(id, rho, s, dp);
                 if constexpr (!WAVE1) {
 #pragma unroll
                     for (int r = 0; r < NX; ++r) {
@@ -401,6 +446,12 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                     for (int r = 0; r < NX; ++r) {
                         dz[r] = s.z[r] - sh.zo[r][t];
                         if constexpr (!WAVE1) sh.dz[r][t] = dz[r];
+                    }
+                    if constexpr (HSQ) {
+                        T perp[3 * HSN];
+#pragma unroll
+                        for (int q = 0; q < 3 * HSN; ++q) perp[q] = j == 1 ? sh.hsp[q][t] : T(0);
+                        hs_copies<M, T>(nc, rho, s, sig, kap, j, perp);
                     }
 #pragma unroll
                     for (int q = 0; q < C; ++q) dcp[q] = s.cp[q] - sh.cpo[q][t];
@@ -477,6 +528,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             }
             if constexpr (!WAVE1) __syncthreads();
         }
+        // half-space duals back to vector form: carried into the next SCP iteration / written back
+        if constexpr (HSQ) {
+            T perp[3 * HSN];
+#pragma unroll
+            for (int q = 0; q < 3 * HSN; ++q) perp[q] = iters_here == 0 ? sh.hsp[q][t] : T(0);
+            hs_duals<M, T>(nc, s, sig, iters_here, perp);
+        }
+        last_iters = iters_here;
 
         // ---------------- a10: merit ratio test and nominal update ----------------
         T xn1[NX];
@@ -607,6 +666,13 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     __syncthreads();
 
     // ---------------- write-back ----------------
+    if constexpr (HSQ) {
+        // with no SCP iteration: x = 0, sig = kap = 0 and a = 0, so the copies are 0
+        T perp[3 * HSN];
+#pragma unroll
+        for (int q = 0; q < 3 * HSN; ++q) perp[q] = (kp.n_scp > 0 && last_iters == 1) ? sh.hsp[q][t] : T(0);
+        hs_copies<M, T>(nc, rho, s, sig, kap, last_iters, perp);
+    }
     if (valid) {
 #pragma unroll
         for (int r = 0; r < NX; ++r) {
@@ -660,8 +726,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
 }
 
-template <class M, class T, int BLOCK, bool SPAN>
-__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK>& sh, const int t,
+template <class M, class T, int BLOCK, bool SPAN, int HSR>
+__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR>& sh, const int t,
                                          const int gn, const bool cross, const Span& sp) {
     if constexpr (BLOCK == 64) {
         persistent_body<M, T, BLOCK, true, SPAN>(dv, kp, sh, t, gn, sp);
@@ -675,7 +741,7 @@ __device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp,
 // SPAN: the launch has consensus groups spanning several workgroups.
 template <class T, int BLOCK, int MODELS, int KM, bool SPAN>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) {
-    __shared__ Shared<T, BLOCK> sh;
+    __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM + 3 : 1> sh;
     const int t = threadIdx.x;
     const int w = dv.wg_list ? dv.wg_list[blockIdx.x] : (int)blockIdx.x;
     const int gn = dv.lane_node[(size_t)w * BLOCK + t];

@@ -7,6 +7,8 @@
 * alone vs in the mix: every request of a session gives bit-identical results when its session
   runs alone on a fresh server and when it is interleaved with other sessions, request types and
   horizons (FP32);
+* the same holds when the only difference is the kernel instantiation of the launches (a
+  companion with more obstacles, or of the other model, shares every launch);
 * backpressure: under a small HBM budget every request still completes, the resident footprint
   never exceeds the budget, and idle warm states are evicted.
 """
@@ -141,6 +143,36 @@ def test_alone_equals_in_mix_fp32(B):
         np.testing.assert_array_equal(prob.split(x, 0, nx), m["x"][0])
         np.testing.assert_array_equal(prob.split(u, 0, nu, True), m["u"][0])
         prob.close()
+
+
+def _session_with_companions(B, sess, S, N, companions):
+    """Three requests of one MPC session; with companions, every request shares its launches with
+    an 8-obstacle quadrotor and a powered-descent instance (another kernel instantiation)."""
+    srv = _server(B, "f32", scp=3, admm=40)
+    req = scpgen.config4_request(sess, S=S, N=N)
+    outs = []
+    for k in range(3):
+        ids = [srv.submit(req, session=sess)]
+        if companions:
+            ids.append(srv.submit([scpgen.quad_instance(3, 40 + k, N=90, K=8, T=5.0)]))
+            ids.append(srv.submit([scpgen.mars_instance(3, 50 + k, N=60, tf=50.0)]))
+        outs.append(srv.drain(ids)[ids[0]])
+    srv.close()
+    return outs
+
+
+@pytest.mark.parametrize("sess,S,N", [(34, 4, 50), (35, 8, 60), (37, 4, 30)])
+def test_result_independent_of_kernel_instantiation_fp32(B, sess, S, N):
+    """The kernel instantiation a launch uses (obstacle capacity, model mix) must not change any
+    bit of a request's result."""
+    alone = _session_with_companions(B, sess, S, N, False)
+    mixed = _session_with_companions(B, sess, S, N, True)
+    for k, (a, m) in enumerate(zip(alone, mixed)):
+        _say("request", k, [int((xa != xm).sum()) for xa, xm in zip(a["x"], m["x"])])
+        for xa, xm in zip(a["x"], m["x"]):
+            np.testing.assert_array_equal(xa, xm)
+        for ua, um in zip(a["u"], m["u"]):
+            np.testing.assert_array_equal(ua, um)
 
 
 def test_backpressure_small_budget(B):
