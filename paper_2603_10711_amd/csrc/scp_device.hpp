@@ -802,6 +802,8 @@ __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeS
 // sigma_0 = -a'nu_c and the orthogonal part p = nu_c + sigma_0 a (kappa_0 = sigma_0), the Step-1
 // term carries e = -p in the first ADMM iteration and e = +p in the second, and the copy of the
 // first iteration has the extra p / rho.  All of this is exact in real arithmetic (a'a = 1).
+// The caller keeps e (the sum of p over the groups, with its sign for the coming iteration) in
+// registers and p itself in LDS, read only on the iterations that need it.
 // Absent groups have a = 0, b = 0 and therefore t = 0: no masks.  Every multiply-add below is an
 // explicit FMA, so each kernel instantiation rounds the same way.
 
@@ -827,21 +829,18 @@ __device__ __forceinline__ void hs_enter(const NodeConst<M, T>& nc, const NodeSt
     }
 }
 
-// Step-1 term of all half-space groups at ADMM iteration `it` (1-based) of the SCP iteration:
-// nr x_prev + sum_j kappa_j a_j (+ e), nr = rho_geo times the number of groups at this node.
+// Step-1 term of all half-space groups: nr x_prev + e + sum_j kappa_j a_j, with nr = rho_geo
+// times the number of groups at this node and e = -sum p (first ADMM iteration of the SCP
+// iteration), +sum p (second) or 0 (later).
 template <class M, class T>
-__device__ __forceinline__ void hs_step1_term(const NodeConst<M, T>& nc, const T* xprev, T nr, const T* kap, int it,
-                                              const T* psum, T* hx) {
+__device__ __forceinline__ void hs_step1_term(const NodeConst<M, T>& nc, const T* xprev, T nr, const T* kap,
+                                              const T* e, T* hx) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) hx[r] = nr * xprev[r];
+    for (int r = 0; r < 3; ++r) hx[r] = tfma(nr, xprev[r], e[r]);
 #pragma unroll
     for (int j = 0; j < M::KM; ++j)
 #pragma unroll
         for (int r = 0; r < 3; ++r) hx[r] = tfma(kap[j], nc.hs[4 * j + r], hx[r]);
-    if (it <= 2) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) hx[r] = it == 1 ? hx[r] - psum[r] : hx[r] + psum[r];
-    }
 }
 
 // Steps 3 and 4 of all half-space groups.
@@ -858,32 +857,33 @@ __device__ __forceinline__ void hs_step34(const NodeConst<M, T>& nc, const Rho<T
     }
 }
 
-// Vector form of the half-space copies after ADMM iteration `it` (0: the re-initialized copies)
-// and of their duals, into s.cp / s.du.  perp is read only for it <= 1.
+// Vector form of the half-space copies into s.cp.  perp: p of every group after exactly one
+// ADMM iteration of the SCP iteration, else nullptr.
 template <class M, class T>
 __device__ __forceinline__ void hs_copies(const NodeConst<M, T>& nc, const Rho<T>& rho, NodeState<M, T>& s,
-                                          const T* sig, const T* kap, int it, const T* perp) {
+                                          const T* sig, const T* kap, const T* perp) {
 #pragma unroll
     for (int j = 0; j < M::KM; ++j) {
         const T c = (kap[j] - sig[j]) * rho.inv_geo;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             T v = tfma(c, nc.hs[4 * j + r], s.x[r]);
-            if (it == 1) v = tfma(perp[3 * j + r], rho.inv_geo, v);
+            if (perp) v = tfma(perp[3 * j + r], rho.inv_geo, v);
             s.cp[M::C_HS + 3 * j + r] = v;
         }
     }
 }
+// Vector form of the half-space duals into s.du.  perp: p of every group when no ADMM iteration
+// has run in the SCP iteration, else nullptr.
 template <class M, class T>
-__device__ __forceinline__ void hs_duals(const NodeConst<M, T>& nc, NodeState<M, T>& s, const T* sig, int it,
+__device__ __forceinline__ void hs_duals(const NodeConst<M, T>& nc, NodeState<M, T>& s, const T* sig,
                                          const T* perp) {
 #pragma unroll
     for (int j = 0; j < M::KM; ++j)
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const T v = it == 0 ? tfma(-sig[j], nc.hs[4 * j + r], perp[3 * j + r]) : -sig[j] * nc.hs[4 * j + r];
-            s.du[M::C_HS + 3 * j + r] = v;
-        }
+        for (int r = 0; r < 3; ++r)
+            s.du[M::C_HS + 3 * j + r] = perp ? tfma(-sig[j], nc.hs[4 * j + r], perp[3 * j + r])
+                                             : -sig[j] * nc.hs[4 * j + r];
 }
 
 // ------------------------------------------------------------------------------------------

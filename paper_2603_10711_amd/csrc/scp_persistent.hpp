@@ -25,8 +25,8 @@
 
 namespace scp {
 
-// HSR: rows of half-space state (3 per half-space group and 3 for their sum; 1 where the
-// kernel holds no half-space groups).
+// HSR: rows of half-space state (3 per half-space group; 1 where the kernel holds no half-space
+// groups).
 template <class T, int BLOCK, int HSR>
 struct Shared {
     T ex[2 * SCP_MAX_NX][BLOCK + 1];  // z, mu of every node (backward exchange); x / xbar at accept;
@@ -42,7 +42,7 @@ struct Shared {
     int st[BLOCK];                 // per-trajectory status bits at the first lane
     int sync_fail;                 // a spanning-group barrier timed out
     T hsp[HSR][BLOCK];             // half-space groups: carried-dual parts orthogonal to the new
-                                   // normals (3 per group), then their sum
+                                   // normals (3 per group)
     T gxw[GX_WIDTH][BLOCK];        // spanning groups: member rows staged for publication
     int gxm[BLOCK];                // member index of the row staged at a lane, -1 none
 };
@@ -182,7 +182,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     // half-space groups in scalar form (quadrotor): dual -sig a, Step-1 coefficient kap
     constexpr bool HSQ = (M::ID == SCP_MODEL_QUAD_PM) && (M::KM > 0);
     constexpr int HSN = HSQ ? M::KM : 1;
-    static_assert(!HSQ || HSR == 3 * HSN + 3, "half-space rows of the workgroup state");
+    static_assert(!HSQ || HSR == 3 * HSN, "half-space rows of the workgroup state");
     T sig[HSN], kap[HSN];
 #pragma unroll
     for (int q = 0; q < HSN; ++q) sig[q] = kap[q] = T(0);
@@ -191,6 +191,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         for (int q = 0; q < M::NHS; ++q) nc.hs[q] = T(0);  // idle lanes: no half-spaces
     }
     T nr = T(0);          // rho_geo times the number of half-space groups at this node
+    T ehs[3] = {T(0), T(0), T(0)};  // orthogonal remainders' Step-1 term for the coming iteration
     int last_iters = 0;   // ADMM iterations this lane ran in the last SCP iteration
     T rp_last = T(0), rd_last = T(0), ratio_last = T(0), merit_last = T(0);
     bool conv_last = false;
@@ -316,7 +317,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
 #pragma unroll
             for (int q = 0; q < 3 * HSN; ++q) sh.hsp[q][t] = perp[q];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) sh.hsp[3 * HSN + r][t] = psum[r];
+            for (int r = 0; r < 3; ++r) ehs[r] = -psum[r];
             nr = rho.geo * T(id.first() ? 0 : min(id.K, (int)M::KM));
         }
         bool done = !valid;
@@ -325,8 +326,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         __syncthreads();
 
         // ---------------- a5-a9: ADMM iterations ----------------
+        int until_test = kp.check_every;  // iterations to the next residual test (0: never)
         for (int j = 1; j <= kp.max_iters; ++j) {
-            const bool check = (kp.check_every > 0 && j % kp.check_every == 0) || j == kp.max_iters;
+            bool test = false;
+            if (until_test > 0 && --until_test == 0) {
+                test = true;
+                until_test = kp.check_every;
+            }
+            const bool check = test || j == kp.max_iters;
             // The next lane of a node N is a node 0, an idle lane or past the workgroup edge: its
             // z and mu are exactly 0, which is what Step 1 needs there.  d_dyn of the previous
             // lane is read at every node but used only at nodes i >= 1.
@@ -349,10 +356,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 if (check) {
                     // z and copies before this iteration, for the dual residual
                     if constexpr (HSQ) {
-                        T perp[3 * HSN];
+                        if (j == 2) {
+                            T perp[3 * HSN];
 #pragma unroll
-                        for (int q = 0; q < 3 * HSN; ++q) perp[q] = j == 2 ? sh.hsp[q][t] : T(0);
-                        hs_copies<M, T>(nc, rho, s, sig, kap, j - 1, perp);
+                            for (int q = 0; q < 3 * HSN; ++q) perp[q] = sh.hsp[q][t];
+                            hs_copies<M, T>(nc, rho, s, sig, kap, perp);
+                        } else {
+                            hs_copies<M, T>(nc, rho, s, sig, kap, nullptr);
+                        }
                     }
 #pragma unroll
                     for (int r = 0; r < NX; ++r) sh.zo[r][t] = s.z[r];
@@ -360,10 +371,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                     for (int q = 0; q < C; ++q) sh.cpo[q][t] = s.cp[q];
                 }
                 if constexpr (HSQ) {
-                    T psum[3], hx[3];
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) psum[r] = j <= 2 ? sh.hsp[3 * HSN + r][t] : T(0);
-                    hs_step1_term<M, T>(nc, s.x, nr, kap, j, psum, hx);
+                    T hx[3];
+                    hs_step1_term<M, T>(nc, s.x, nr, kap, ehs, hx);
                     step1<M, T, true>(id, rho, nc, s, zn, mn, hx);
                 } else {
                     step1<M, T>(id, rho, nc, s, zn, mn);
@@ -371,6 +380,16 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 if constexpr (!WAVE1) {
 #pragma unroll
                     for (int r = 0; r < NX; ++r) sh.fw[r][t + 1] = s.dd[r];
+                }
+            }
+            if constexpr (HSQ) {
+                // the remainders enter with -sum p, then +sum p, then leave (every lane alike)
+                if (j == 1) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) ehs[r] = -ehs[r];
+                } else if (j == 2) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) ehs[r] = T(0);
                 }
             }
             T dp[NX];
@@ -448,10 +467,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                         if constexpr (!WAVE1) sh.dz[r][t] = dz[r];
                     }
                     if constexpr (HSQ) {
-                        T perp[3 * HSN];
+                        if (j == 1) {
+                            T perp[3 * HSN];
 #pragma unroll
-                        for (int q = 0; q < 3 * HSN; ++q) perp[q] = j == 1 ? sh.hsp[q][t] : T(0);
-                        hs_copies<M, T>(nc, rho, s, sig, kap, j, perp);
+                            for (int q = 0; q < 3 * HSN; ++q) perp[q] = sh.hsp[q][t];
+                            hs_copies<M, T>(nc, rho, s, sig, kap, perp);
+                        } else {
+                            hs_copies<M, T>(nc, rho, s, sig, kap, nullptr);
+                        }
                     }
 #pragma unroll
                     for (int q = 0; q < C; ++q) dcp[q] = s.cp[q] - sh.cpo[q][t];
@@ -475,7 +498,6 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                     atomicMax(&sh.mx[1][tb], res_bits(rd));
                 }
                 __syncthreads();
-                const bool test = kp.check_every > 0 && j % kp.check_every == 0;
                 if (!span.on) {
                     if (!done && leader) {
                         unsigned long long bp = 0ull, bd = 0ull;
@@ -530,10 +552,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         }
         // half-space duals back to vector form: carried into the next SCP iteration / written back
         if constexpr (HSQ) {
-            T perp[3 * HSN];
+            if (kp.max_iters == 0) {
+                T perp[3 * HSN];
 #pragma unroll
-            for (int q = 0; q < 3 * HSN; ++q) perp[q] = iters_here == 0 ? sh.hsp[q][t] : T(0);
-            hs_duals<M, T>(nc, s, sig, iters_here, perp);
+                for (int q = 0; q < 3 * HSN; ++q) perp[q] = sh.hsp[q][t];
+                hs_duals<M, T>(nc, s, sig, perp);
+            } else {
+                hs_duals<M, T>(nc, s, sig, nullptr);
+            }
         }
         last_iters = iters_here;
 
@@ -668,10 +694,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     // ---------------- write-back ----------------
     if constexpr (HSQ) {
         // with no SCP iteration: x = 0, sig = kap = 0 and a = 0, so the copies are 0
-        T perp[3 * HSN];
+        if (kp.n_scp > 0 && last_iters == 1) {
+            T perp[3 * HSN];
 #pragma unroll
-        for (int q = 0; q < 3 * HSN; ++q) perp[q] = (kp.n_scp > 0 && last_iters == 1) ? sh.hsp[q][t] : T(0);
-        hs_copies<M, T>(nc, rho, s, sig, kap, last_iters, perp);
+            for (int q = 0; q < 3 * HSN; ++q) perp[q] = sh.hsp[q][t];
+            hs_copies<M, T>(nc, rho, s, sig, kap, perp);
+        } else {
+            hs_copies<M, T>(nc, rho, s, sig, kap, nullptr);
+        }
     }
     if (valid) {
 #pragma unroll
@@ -741,7 +771,7 @@ __device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp,
 // SPAN: the launch has consensus groups spanning several workgroups.
 template <class T, int BLOCK, int MODELS, int KM, bool SPAN>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) {
-    __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM + 3 : 1> sh;
+    __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM : 1> sh;
     const int t = threadIdx.x;
     const int w = dv.wg_list ? dv.wg_list[blockIdx.x] : (int)blockIdx.x;
     const int gn = dv.lane_node[(size_t)w * BLOCK + t];
