@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/scp.h"
 
 namespace scp {
@@ -567,9 +569,10 @@ __device__ __forceinline__ int assemble_factor(const T* __restrict__ prm, const 
     return st;
 }
 
-// Solve L L' xi = g in place (forward then backward substitution).
-template <class M, class T>
-__device__ __forceinline__ void chol_solve(const T* L, T* g) {
+// Solve L L' xi = g in place (forward then backward substitution).  L: the packed factor, or an
+// accessor with operator[] over it (the persistent kernel may keep it in LDS).
+template <class M, class T, class LA>
+__device__ __forceinline__ void chol_solve(const LA& L, T* g) {
     constexpr int NN = M::NN;
 #pragma unroll
     for (int r = 0; r < NN; ++r) {
@@ -596,11 +599,19 @@ __device__ __forceinline__ void chol_solve(const T* L, T* g) {
 // Absent groups hold exactly zero copies and duals, so summing over all slots is exact.
 // HSS: the half-space groups are carried in scalar form (hs_* below); their Step-1 term comes
 // in hs_x (added to the position rows) instead of from s.cp / s.du.
-template <class M, class T, bool HSS = false>
+template <class M, class T, bool HSS = false, class LA = const T*>
 __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
                                       NodeState<M, T>& s, const T* znext, const T* munext,
-                                      const T* hs_x = nullptr) {
+                                      const T* hs_x = nullptr, const LA* Lacc = nullptr) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN;
+    // A factor held outside the registers is fetched first; the scheduling barrier keeps the
+    // loads ahead of the right-hand side, whose arithmetic then covers their latency.
+    T Lr[Dims<M>::NL];
+    if constexpr (!std::is_same<LA, const T*>::value) {
+#pragma unroll
+        for (int q = 0; q < Dims<M>::NL; ++q) Lr[q] = (*Lacc)[q];
+        __builtin_amdgcn_sched_barrier(0);
+    }
     // No node masks are needed here: z_0 = lambda_0 = mu_0 = 0 always (node 0 has no dynamic
     // coupling), the caller passes the next node's z and mu, which at node N are those of a
     // node 0, of an idle lane or zeros, and d_N = 0; so w_N = 0 and A'w = B'w = 0 at node N,
@@ -642,7 +653,8 @@ __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
         for (int r = 0; r < 4; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_SOC + r] - s.du[M::C_SOC + r]);
     }
-    chol_solve<M, T>(nc.L, g);
+    if constexpr (std::is_same<LA, const T*>::value) chol_solve<M, T>(nc.L, g);
+    else chol_solve<M, T>(Lr, g);
 #pragma unroll
     for (int r = 0; r < NX; ++r) s.x[r] = g[r];
 #pragma unroll

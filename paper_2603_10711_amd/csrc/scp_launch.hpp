@@ -23,6 +23,10 @@ template <class T>
 hipError_t launch_persistent(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int block, int models, int kmax,
                              hipStream_t s);
 
+// Static LDS of one persistent workgroup of `block` lanes (element size esz) for quadrotor
+// launches with up to 8 obstacles, the largest workgroup state; 0 for an unsupported size.
+size_t persistent_shared_bytes(int esz, int block);
+
 // Server: scatter n staged admissions (records at blob + rec_off) into the pool, with cold
 // initialization or in-place warm start; gather n finished requests into the output staging.
 template <class T>

@@ -50,6 +50,21 @@ hipError_t launch_persistent(const Dev<T>& dv, const KParams<T>& kp, int n_wg, i
     }
 }
 
+template <class T>
+static size_t shared_bytes(int block) {
+    constexpr int HSR = 3 * 8;  // quadrotor kernels with 8 obstacles: the largest state
+    switch (block) {
+        case 64: return sizeof(Shared<T, 64, HSR, persistent_lds_factor_rows(64, 3)>);
+        case 128: return sizeof(Shared<T, 128, HSR, persistent_lds_factor_rows(128, 3)>);
+        case 256: return sizeof(Shared<T, 256, HSR, persistent_lds_factor_rows(256, 3)>);
+        default: return 0;
+    }
+}
+
+size_t persistent_shared_bytes(int esz, int block) {
+    return esz == 4 ? shared_bytes<float>(block) : shared_bytes<double>(block);
+}
+
 template hipError_t launch_persistent<float>(const Dev<float>&, const KParams<float>&, int, int, int, int, hipStream_t);
 template hipError_t launch_persistent<double>(const Dev<double>&, const KParams<double>&, int, int, int, int, hipStream_t);
 

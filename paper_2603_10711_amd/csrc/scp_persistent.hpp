@@ -27,12 +27,23 @@ namespace scp {
 
 // HSR: rows of half-space state (3 per half-space group; 1 where the kernel holds no half-space
 // groups).
-template <class T, int BLOCK, int HSR>
+// A lane's column of a row-major LDS array [k][STRIDE], read as a packed vector.
+template <class T, int STRIDE>
+struct StridedLds {
+    const T* p;
+    __device__ __forceinline__ T operator[](int k) const { return p[k * STRIDE]; }
+};
+
+// One-wavefront workgroups exchange neighbours with DPP, so their exchange arrays shrink to one
+// row; the LDS this frees holds the Cholesky factors instead (LR rows, 1 where unused): with the
+// factor out of the registers, the ADMM state stays in VGPRs instead of spilling to AGPRs.
+template <class T, int BLOCK, int HSR, int LR>
 struct Shared {
-    T ex[2 * SCP_MAX_NX][BLOCK + 1];  // z, mu of every node (backward exchange); x / xbar at accept;
-                                      // column BLOCK stays 0 (the neighbour of the last lane)
-    T fw[SCP_MAX_NX][BLOCK + 1];      // d_dyn of lane t in column t + 1 (forward exchange)
-    T dz[SCP_MAX_NX][BLOCK];       // z - z_old (dual-residual neighbour term)
+    static constexpr int XR = BLOCK == 64 ? 1 : SCP_MAX_NX;
+    T ex[2 * XR][BLOCK + 1];       // z, mu of every node (backward exchange); x / xbar at accept;
+                                   // column BLOCK stays 0 (the neighbour of the last lane)
+    T fw[XR][BLOCK + 1];           // d_dyn of lane t in column t + 1 (forward exchange)
+    T dz[XR][BLOCK];               // z - z_old (dual-residual neighbour term)
     T zo[SCP_MAX_NX][BLOCK];       // own z before Steps 2-3 on residual iterations
     T cpo[36][BLOCK];              // own copies before Step 3 on residual iterations
     T red[8][BLOCK];               // per-node terms for fixed-order trajectory sums
@@ -41,6 +52,7 @@ struct Shared {
     int flag[BLOCK];               // per-trajectory flags at the group leader lane
     int st[BLOCK];                 // per-trajectory status bits at the first lane
     int sync_fail;                 // a spanning-group barrier timed out
+    T Lf[LR][BLOCK];               // packed Cholesky factor of every node (LDS-resident form)
     T hsp[HSR][BLOCK];             // half-space groups: carried-dual parts orthogonal to the new
                                    // normals (3 per group)
     T gxw[GX_WIDTH][BLOCK];        // spanning groups: member rows staged for publication
@@ -80,8 +92,8 @@ __device__ __forceinline__ T gx_read(const T* p) {
 // and stops waiting, so a group whose workgroups are not all resident cannot hold the queue.
 // nbar counts the group barriers this workgroup has passed in this launch; rows of barrier b
 // live in buffer b & 1.
-template <class T, int BLOCK, int HSR>
-__device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR>& sh, const Span& sp, unsigned& nbar,
+template <class T, int BLOCK, int HSR, int LR>
+__device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR, LR>& sh, const Span& sp, unsigned& nbar,
                                            const int t) {
     __syncthreads();
     if (t < 64) {
@@ -120,8 +132,8 @@ __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HS
 // WAVE1: no trajectory of this workgroup straddles a wavefront boundary, so neighbour values
 // move with DPP wavefront shifts instead of LDS and the two exchange barriers of every ADMM
 // iteration disappear.  The per-trajectory reductions still go through LDS.
-template <class M, class T, int BLOCK, bool WAVE1, bool SPAN, int HSR>
-__device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR>& sh,
+template <class M, class T, int BLOCK, bool WAVE1, bool SPAN, int HSR, int LR>
+__device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR, LR>& sh,
                                                 const int t, const int gn, const Span span_in) {
     // SPAN: this kernel variant may hold spanning groups (compiled out of the other variant)
     const Span span{SPAN && span_in.on, span_in.slot, span_in.nwg};
@@ -183,6 +195,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     constexpr bool HSQ = (M::ID == SCP_MODEL_QUAD_PM) && (M::KM > 0);
     constexpr int HSN = HSQ ? M::KM : 1;
     static_assert(!HSQ || HSR == 3 * HSN, "half-space rows of the workgroup state");
+    constexpr bool LDSL = LR >= Dims<M>::NL;  // the factor lives in LDS
+    static_assert(WAVE1 || Shared<T, BLOCK, HSR, LR>::XR == SCP_MAX_NX, "LDS exchange needs full rows");
     T sig[HSN], kap[HSN];
 #pragma unroll
     for (int q = 0; q < HSN; ++q) sig[q] = kap[q] = T(0);
@@ -201,8 +215,10 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         sh.st[t] = 0;
     }
     if (t == 0) sh.sync_fail = 0;
-    if (t < 2 * SCP_MAX_NX) sh.ex[t][BLOCK] = T(0);
-    if (t < SCP_MAX_NX) sh.fw[t][0] = T(0);
+    if constexpr (!WAVE1) {
+        if (t < 2 * SCP_MAX_NX) sh.ex[t][BLOCK] = T(0);
+        if (t < SCP_MAX_NX) sh.fw[t][0] = T(0);
+    }
     if (t < BLOCK) sh.gxm[t] = -1;
 
     for (int k = 0; k < kp.n_scp; ++k, sfac *= kp.sched_q) {
@@ -290,6 +306,10 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             status |= convexify<M, T>(prm, id, xbar, uc, delta, nc);
             status |= assemble_factor<M, T>(prm, id, rho, nc);
         }
+        if constexpr (LDSL) {
+#pragma unroll
+            for (int q = 0; q < Dims<M>::NL; ++q) sh.Lf[q][t] = nc.L[q];
+        }
         // primal re-initialization from the nominal; duals carried
 #pragma unroll
         for (int r = 0; r < NX; ++r) {
@@ -373,7 +393,15 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 if constexpr (HSQ) {
                     T hx[3];
                     hs_step1_term<M, T>(nc, s.x, nr, kap, ehs, hx);
-                    step1<M, T, true>(id, rho, nc, s, zn, mn, hx);
+                    if constexpr (LDSL) {
+                        const StridedLds<T, BLOCK> la{&sh.Lf[0][t]};
+                        step1<M, T, true, StridedLds<T, BLOCK>>(id, rho, nc, s, zn, mn, hx, &la);
+                    } else {
+                        step1<M, T, true>(id, rho, nc, s, zn, mn, hx);
+                    }
+                } else if constexpr (LDSL) {
+                    const StridedLds<T, BLOCK> la{&sh.Lf[0][t]};
+                    step1<M, T, false, StridedLds<T, BLOCK>>(id, rho, nc, s, zn, mn, nullptr, &la);
                 } else {
                     step1<M, T>(id, rho, nc, s, zn, mn);
                 }
@@ -667,15 +695,23 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     // ---------------- metrics of the final nominal ----------------
     T m_cost = T(0), m_def = T(0), m_viol = T(0), m_bnd = T(0);
     if (kp.final_metrics) {
+        T xnf[NX];
+        if constexpr (WAVE1) {
 #pragma unroll
-        for (int r = 0; r < NX; ++r) sh.ex[r][t] = xbar[r];
-        __syncthreads();
+            for (int r = 0; r < NX; ++r) xnf[r] = lane_next(xbar[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) sh.ex[r][t] = xbar[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NX; ++r) xnf[r] = sh.ex[r][t + 1];
+        }
         if (valid) {
             if (!id.last()) {
                 T Fx[NX];
                 rk4<M, T>(prm, xbar, ubar, Fx);
 #pragma unroll
-                for (int r = 0; r < NX; ++r) m_def = nmax(m_def, tabs(sh.ex[r][t + 1] - Fx[r]));
+                for (int r = 0; r < NX; ++r) m_def = nmax(m_def, tabs(xnf[r] - Fx[r]));
             }
             m_cost = node_cost<M, T>(prm, id, xbar, ubar);
             m_viol = node_violation<M, T>(prm, id, xbar, ubar);
@@ -756,8 +792,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
 }
 
-template <class M, class T, int BLOCK, bool SPAN, int HSR>
-__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR>& sh, const int t,
+template <class M, class T, int BLOCK, bool SPAN, int HSR, int LR>
+__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR, LR>& sh, const int t,
                                          const int gn, const bool cross, const Span& sp) {
     if constexpr (BLOCK == 64) {
         persistent_body<M, T, BLOCK, true, SPAN>(dv, kp, sh, t, gn, sp);
@@ -767,11 +803,18 @@ __device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp,
     }
 }
 
+// LDS rows of the factors: one-wavefront workgroups keep the quadrotor's factor in LDS (and the
+// powered descent's when it is the only model); the LDS of a mixed kernel stays within four
+// workgroups per CU with the quadrotor's factor alone.
+constexpr int persistent_lds_factor_rows(int block, int models) {
+    return block != 64 ? 1 : models == 2 ? Dims<Mars>::NL : Dims<Quad<8>>::NL;
+}
+
 // MODELS: 1 quadrotor only, 2 powered descent only, 3 both (each workgroup holds one model).
 // SPAN: the launch has consensus groups spanning several workgroups.
 template <class T, int BLOCK, int MODELS, int KM, bool SPAN>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) {
-    __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM : 1> sh;
+    __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM : 1, persistent_lds_factor_rows(BLOCK, MODELS)> sh;
     const int t = threadIdx.x;
     const int w = dv.wg_list ? dv.wg_list[blockIdx.x] : (int)blockIdx.x;
     const int gn = dv.lane_node[(size_t)w * BLOCK + t];

@@ -718,9 +718,8 @@ scp_status scp_server_create(const scp_server_config* cfg, void* arena_dev, size
     s->trajs.reset(cfg->max_traj);
     s->wgs.reset(cfg->max_wg);
     for (int g = cfg->max_span - 1; g >= 0; --g) s->span_free.push_back(g);
-    // one wave per SIMD (4 per CU) and the LDS of the persistent kernel's workgroup state (with
-    // the half-space rows of up to 8 obstacles)
-    const size_t lds = (size_t)cfg->block * (119 * s->esz + 28) + 16;
+    // one wave per SIMD (4 per CU) and the LDS of the persistent kernel's workgroup state
+    const size_t lds = std::max<size_t>(1, persistent_shared_bytes(s->esz, cfg->block));
     const int per_cu = std::max(1, std::min(4 / (cfg->block / 64), (int)(163840 / lds)));
     s->wg_cap_running = 256 * per_cu;
     const int slots = cfg->max_inflight + 1;
