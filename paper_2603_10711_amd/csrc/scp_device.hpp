@@ -807,9 +807,10 @@ __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeS
 // With a unit normal a, the projection onto {a'y >= b} moves its input along a only, so after
 // one ADMM iteration the group's dual is nu = -sigma a with sigma = rho t, t = max(0, b - a'v),
 // and its copy is x + ((kappa - sigma) / rho) a with kappa = 2 sigma - sigma_prev.  Steps 1, 3
-// and 4 then need per group two scalars instead of two 3-vectors:
-//   Step 1 term  rho cp - nu = rho x_prev + kappa a (+ e, below)
-//   Step 3 + 4   t = max(0, b - (a'x - sigma / rho)),  sigma' = rho t,  kappa' = 2 sigma' - sigma
+// and 4 then need per group two scalars instead of two 3-vectors.  They are kept divided by
+// rho (s = sigma / rho, k = kappa / rho), which removes two multiplications per group:
+//   Step 1 term  rho cp - nu = rho x_prev + rho sum_j k_j a_j (+ e, below)
+//   Step 3 + 4   t = max(0, b - (a'x - s)),  s' = t,  k' = 2 s' - s
 // The dual carried into an SCP iteration, nu_c, is generally not along the new normal: with
 // sigma_0 = -a'nu_c and the orthogonal part p = nu_c + sigma_0 a (kappa_0 = sigma_0), the Step-1
 // term carries e = -p in the first ADMM iteration and e = +p in the second, and the copy of the
@@ -822,8 +823,8 @@ __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeS
 // Enter an SCP iteration: scalars from the carried duals s.du (vector form) and the new normals.
 // perp receives p (3 per group), psum the sum over groups.
 template <class M, class T>
-__device__ __forceinline__ void hs_enter(const NodeConst<M, T>& nc, const NodeState<M, T>& s, T* sig, T* kap, T* perp,
-                                         T* psum) {
+__device__ __forceinline__ void hs_enter(const NodeConst<M, T>& nc, const Rho<T>& rho, const NodeState<M, T>& s,
+                                         T* sc, T* kc, T* perp, T* psum) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) psum[r] = T(0);
 #pragma unroll
@@ -831,8 +832,7 @@ __device__ __forceinline__ void hs_enter(const NodeConst<M, T>& nc, const NodeSt
         const T* a = &nc.hs[4 * j];
         const T* du = &s.du[M::C_HS + 3 * j];
         const T s0 = -tfma(a[2], du[2], tfma(a[1], du[1], a[0] * du[0]));
-        sig[j] = s0;
-        kap[j] = s0;
+        sc[j] = kc[j] = s0 * rho.inv_geo;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             perp[3 * j + r] = tfma(s0, a[r], du[r]);
@@ -841,31 +841,33 @@ __device__ __forceinline__ void hs_enter(const NodeConst<M, T>& nc, const NodeSt
     }
 }
 
-// Step-1 term of all half-space groups: nr x_prev + e + sum_j kappa_j a_j, with nr = rho_geo
+// Step-1 term of all half-space groups: nr x_prev + e + rho sum_j k_j a_j, with nr = rho_geo
 // times the number of groups at this node and e = -sum p (first ADMM iteration of the SCP
 // iteration), +sum p (second) or 0 (later).
 template <class M, class T>
-__device__ __forceinline__ void hs_step1_term(const NodeConst<M, T>& nc, const T* xprev, T nr, const T* kap,
-                                              const T* e, T* hx) {
+__device__ __forceinline__ void hs_step1_term(const NodeConst<M, T>& nc, const Rho<T>& rho, const T* xprev, T nr,
+                                              const T* kc, const T* e, T* hx) {
+    T acc[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) hx[r] = tfma(nr, xprev[r], e[r]);
+    for (int r = 0; r < 3; ++r) acc[r] = kc[0] * nc.hs[r];
 #pragma unroll
-    for (int j = 0; j < M::KM; ++j)
+    for (int j = 1; j < M::KM; ++j)
 #pragma unroll
-        for (int r = 0; r < 3; ++r) hx[r] = tfma(kap[j], nc.hs[4 * j + r], hx[r]);
+        for (int r = 0; r < 3; ++r) acc[r] = tfma(kc[j], nc.hs[4 * j + r], acc[r]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) hx[r] = tfma(rho.geo, acc[r], tfma(nr, xprev[r], e[r]));
 }
 
 // Steps 3 and 4 of all half-space groups.
 template <class M, class T>
-__device__ __forceinline__ void hs_step34(const NodeConst<M, T>& nc, const Rho<T>& rho, const T* x, T* sig, T* kap) {
+__device__ __forceinline__ void hs_step34(const NodeConst<M, T>& nc, const T* x, T* sc, T* kc) {
 #pragma unroll
     for (int j = 0; j < M::KM; ++j) {
         const T* a = &nc.hs[4 * j];
-        const T av = tfma(-sig[j], rho.inv_geo, tfma(a[2], x[2], tfma(a[1], x[1], a[0] * x[0])));
+        const T av = tfma(a[2], x[2], tfma(a[1], x[1], tfma(a[0], x[0], -sc[j])));
         const T t = tmaxv(T(0), a[3] - av);
-        const T sn = rho.geo * t;
-        kap[j] = tfma(T(2), sn, -sig[j]);  // 2 sn is exact: one rounding, as (sn + sn) - sig
-        sig[j] = sn;
+        kc[j] = tfma(T(2), t, -sc[j]);  // 2 t is exact: one rounding, as (t + t) - s
+        sc[j] = t;
     }
 }
 
@@ -873,10 +875,10 @@ __device__ __forceinline__ void hs_step34(const NodeConst<M, T>& nc, const Rho<T
 // ADMM iteration of the SCP iteration, else nullptr.
 template <class M, class T>
 __device__ __forceinline__ void hs_copies(const NodeConst<M, T>& nc, const Rho<T>& rho, NodeState<M, T>& s,
-                                          const T* sig, const T* kap, const T* perp) {
+                                          const T* sc, const T* kc, const T* perp) {
 #pragma unroll
     for (int j = 0; j < M::KM; ++j) {
-        const T c = (kap[j] - sig[j]) * rho.inv_geo;
+        const T c = kc[j] - sc[j];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             T v = tfma(c, nc.hs[4 * j + r], s.x[r]);
@@ -888,14 +890,16 @@ __device__ __forceinline__ void hs_copies(const NodeConst<M, T>& nc, const Rho<T
 // Vector form of the half-space duals into s.du.  perp: p of every group when no ADMM iteration
 // has run in the SCP iteration, else nullptr.
 template <class M, class T>
-__device__ __forceinline__ void hs_duals(const NodeConst<M, T>& nc, NodeState<M, T>& s, const T* sig,
-                                         const T* perp) {
+__device__ __forceinline__ void hs_duals(const NodeConst<M, T>& nc, const Rho<T>& rho, NodeState<M, T>& s,
+                                         const T* sc, const T* perp) {
 #pragma unroll
-    for (int j = 0; j < M::KM; ++j)
+    for (int j = 0; j < M::KM; ++j) {
+        const T sig = rho.geo * sc[j];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            s.du[M::C_HS + 3 * j + r] = perp ? tfma(-sig[j], nc.hs[4 * j + r], perp[3 * j + r])
-                                             : -sig[j] * nc.hs[4 * j + r];
+            s.du[M::C_HS + 3 * j + r] = perp ? tfma(-sig, nc.hs[4 * j + r], perp[3 * j + r])
+                                             : -sig * nc.hs[4 * j + r];
+    }
 }
 
 // ------------------------------------------------------------------------------------------

@@ -191,7 +191,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
     int status = 0;
     int n_acc = 0, iters_sum = 0;
-    // half-space groups in scalar form (quadrotor): dual -sig a, Step-1 coefficient kap
+    // half-space groups in scalar form (quadrotor): dual -rho sig a, Step-1 coefficient rho kap
     constexpr bool HSQ = (M::ID == SCP_MODEL_QUAD_PM) && (M::KM > 0);
     constexpr int HSN = HSQ ? M::KM : 1;
     static_assert(!HSQ || HSR == 3 * HSN, "half-space rows of the workgroup state");
@@ -333,7 +333,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         // of the half-space groups alive through the ADMM loop.
         if constexpr (HSQ) {
             T perp[3 * HSN], psum[3];
-            hs_enter<M, T>(nc, s, sig, kap, perp, psum);
+            hs_enter<M, T>(nc, rho, s, sig, kap, perp, psum);
 #pragma unroll
             for (int q = 0; q < 3 * HSN; ++q) sh.hsp[q][t] = perp[q];
 #pragma unroll
@@ -392,7 +392,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 }
                 if constexpr (HSQ) {
                     T hx[3];
-                    hs_step1_term<M, T>(nc, s.x, nr, kap, ehs, hx);
+                    hs_step1_term<M, T>(nc, rho, s.x, nr, kap, ehs, hx);
                     if constexpr (LDSL) {
                         const StridedLds<T, BLOCK> la{&sh.Lf[0][t]};
                         step1<M, T, true, StridedLds<T, BLOCK>>(id, rho, nc, s, zn, mn, hx, &la);
@@ -412,10 +412,10 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             }
             if constexpr (HSQ) {
                 // the remainders enter with -sum p, then +sum p, then leave (every lane alike)
-                if (j == 1) {
+                if (__builtin_expect(j == 1, 0)) {
 #pragma unroll
                     for (int r = 0; r < 3; ++r) ehs[r] = -ehs[r];
-                } else if (j == 2) {
+                } else if (__builtin_expect(j == 2, 0)) {
 #pragma unroll
                     for (int r = 0; r < 3; ++r) ehs[r] = T(0);
                 }
@@ -432,7 +432,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             if (!done) {
                 step2<M, T>(id, rho, s, dp);
                 step3<M, T, HSQ>(id, rho, nc, s, ball_r, kappa, inv1k2);
-                if constexpr (HSQ) hs_step34<M, T>(nc, rho, s.x, sig, kap);
+                if constexpr (HSQ) hs_step34<M, T>(nc, s.x, sig, kap);
             }
             if (span.on) {
                 // scenario consensus across workgroups
@@ -584,9 +584,9 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 T perp[3 * HSN];
 #pragma unroll
                 for (int q = 0; q < 3 * HSN; ++q) perp[q] = sh.hsp[q][t];
-                hs_duals<M, T>(nc, s, sig, perp);
+                hs_duals<M, T>(nc, rho, s, sig, perp);
             } else {
-                hs_duals<M, T>(nc, s, sig, nullptr);
+                hs_duals<M, T>(nc, rho, s, sig, nullptr);
             }
         }
         last_iters = iters_here;
