@@ -346,14 +346,10 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         __syncthreads();
 
         // ---------------- a5-a9: ADMM iterations ----------------
-        int until_test = kp.check_every;  // iterations to the next residual test (0: never)
-        for (int j = 1; j <= kp.max_iters; ++j) {
-            bool test = false;
-            if (until_test > 0 && --until_test == 0) {
-                test = true;
-                until_test = kp.check_every;
-            }
-            const bool check = test || j == kp.max_iters;
+        // The iterations between two residual tests run a copy of the body without the test's
+        // code (CHK false): no per-iteration test bookkeeping in the common path.
+        auto admm_iter = [&](const int j, auto chk, const bool test) __attribute__((always_inline)) -> bool {
+            constexpr bool check = decltype(chk)::value;
             // The next lane of a node N is a node 0, an idle lane or past the workgroup edge: its
             // z and mu are exactly 0, which is what Step 1 needs there.  d_dyn of the previous
             // lane is read at every node but used only at nodes i >= 1.
@@ -373,7 +369,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                         mn[r] = sh.ex[NX + r][t + 1];
                     }
                 }
-                if (check) {
+                if constexpr (check) {
                     // z and copies before this iteration, for the dual residual
                     if constexpr (HSQ) {
                         if (j == 2) {
@@ -483,7 +479,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                     }
                 }
             }
-            if (check) {
+            if constexpr (check) {
                 T rp = T(0), sp[NN], dz[NX];
 #pragma unroll
                 for (int r = 0; r < NX; ++r) dz[r] = T(0);
@@ -574,9 +570,20 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                         iters_here = j;
                     }
                 }
-                if (!__syncthreads_or(done ? 0 : 1)) break;
+                if (!__syncthreads_or(done ? 0 : 1)) return true;
             }
             if constexpr (!WAVE1) __syncthreads();
+            return false;
+        };
+        {
+            const int K = kp.max_iters, c = kp.check_every;
+            int j = 1;
+            while (j <= K) {
+                const int jc = c > 0 ? min((j + c - 1) / c * c, K) : K;  // next iteration with a check
+                for (; j < jc; ++j) admm_iter(j, std::false_type{}, false);
+                if (admm_iter(j, std::true_type{}, c > 0 && j % c == 0)) break;
+                ++j;
+            }
         }
         // half-space duals back to vector form: carried into the next SCP iteration / written back
         if constexpr (HSQ) {
