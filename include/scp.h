@@ -92,9 +92,13 @@ enum {
     SCP_P_ALPHA = 75,         /* powered descent mass-flow coefficient alpha                */
     SCP_P_GVEC = 76,          /* [3] powered descent gravity vector                         */
     SCP_P_GLIDE = 79,         /* tan of the glide-slope half angle (powered descent)        */
-    SCP_P_NOBS = 80,          /* number of spherical obstacles K <= SCP_MAX_OBS (quadrotor) */
+    SCP_P_NOBS = 80,          /* number of obstacles K <= SCP_MAX_OBS (quadrotor)           */
     SCP_P_OBS = 81,           /* [8 x 4] obstacle centre (3) and radius (1)                 */
-    SCP_PARAM_STRIDE = 113
+    SCP_P_DIST = 113,         /* [3] constant disturbance acceleration added to v' (quad)   */
+    SCP_P_CYL = 116,          /* bit j set: obstacle j is a vertical cylinder (axis along z
+                                 through its centre; the centre's z is ignored), else a
+                                 sphere                                                     */
+    SCP_PARAM_STRIDE = 117
 };
 
 /*

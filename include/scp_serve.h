@@ -89,6 +89,20 @@ size_t scp_server_request_bytes(const scp_server* s, const scp_problem_desc* req
  * starts, -1 none.  Errors: SCP_ERR_ARG (invalid, or larger than the pool or the budget). */
 scp_status scp_server_submit(scp_server* s, const scp_problem_desc* req, int32_t session, int64_t* id);
 
+/* Submission flags. */
+enum {
+    /* Closed-loop MPC (Sec. IV-A.4, the controller applies the shared first control to the
+     * plant): a warm start keeps the request's own x_init (the measured state) instead of the
+     * previous scenario-0 state at node 1; the shifted trajectory and duals still seed the solve.
+     * No effect on a cold start. */
+    SCP_SUBMIT_MEASURED = 1
+};
+
+/* scp_server_submit with flags (SCP_SUBMIT_*); scp_server_submit is flags = 0.  Unknown flag
+ * bits: SCP_ERR_ARG. */
+scp_status scp_server_submit_ex(scp_server* s, const scp_problem_desc* req, int32_t session, uint32_t flags,
+                                int64_t* id);
+
 /* One scheduling step: collect finished device work, admit what fits, and launch one step of
  * the running requests if fewer than max_inflight steps are pending.  Blocks only when
  * max_inflight steps are pending and `wait` is nonzero.  *pending (optional) = requests

@@ -16,7 +16,8 @@ QUAD, MARS = 1, 2
 def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
     """Continuous-time dynamics x' = f(x, u).
 
-    Quadrotor point mass: p' = v, v' = u/m_s - g e3 - c ||v|| v  (drag isotropic and quadratic).
+    Quadrotor point mass: p' = v, v' = u/m_s - g e3 - c ||v|| v + d  (drag isotropic and
+    quadratic; d the instance's constant disturbance acceleration, 0 unless given).
     Powered descent (scaled units): r' = v, v' = T/m + g_vec, m' = -alpha Gamma.
     The norm is written sqrt(v.v) so the function stays analytic for complex-step tests.
     """
@@ -24,6 +25,8 @@ def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
         p, v = x[:3], x[3:6]
         nv = np.sqrt(v @ v)
         acc = u / inst["mscale"] - np.array([0.0, 0.0, inst["grav"]]) - inst["drag"] * nv * v
+        if "dist" in inst:
+            acc = acc + np.asarray(inst["dist"], dtype=float)
         return np.concatenate([v, acc])
     r, v, m = x[:3], x[3:6], x[6]
     T, G = u[:3], u[3]

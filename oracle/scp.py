@@ -100,6 +100,15 @@ def _trust_box(center, delta, lo_h, hi_h):
     return lo, hi
 
 
+def _cyl_flags(inst: dict) -> np.ndarray:
+    """Per obstacle: True for a vertical cylinder (axis along z), False for a sphere."""
+    K = inst["obstacles"].shape[0]
+    flags = np.zeros(K, dtype=bool)
+    given = np.asarray(inst.get("cyl", ()), dtype=bool)
+    flags[:min(K, given.size)] = given[:K]
+    return flags
+
+
 def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_center=None):
     """Constraint groups of the convex subproblem, in a fixed order.
 
@@ -110,6 +119,7 @@ def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_c
       first-control set).
     Quadrotor: control ball ||u|| <= u_ball (nodes 0..N-1), then one half-space per obstacle
       at nodes 1..N: n'(p - c) >= r with n = (pbar - c)/||pbar - c|| (+e3 if ||pbar - c|| < 1e-9).
+      A vertical cylinder uses the horizontal part of pbar - c (fallback +e1).
     Powered descent: glide-slope cone ||(r_x, r_y)|| <= tan(86 deg) r_z at nodes 1..N, then
       the SOC ||T|| <= Gamma at nodes 0..N-1.
     """
@@ -139,14 +149,18 @@ def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_c
     if inst["model"] == QUAD:
         if math.isfinite(inst["u_ball"]):
             groups.append(Group("u", (0, 1, 2), "ball", uact.copy(), radius=float(inst["u_ball"])))
+        cyl = _cyl_flags(inst)
         for j in range(inst["obstacles"].shape[0]):
             c, r = inst["obstacles"][j, :3], inst["obstacles"][j, 3]
             a = np.zeros((N + 1, 3))
             b = np.zeros(N + 1)
+            fallback = np.array([1.0, 0.0, 0.0]) if cyl[j] else np.array([0.0, 0.0, 1.0])
             for i in range(1, N + 1):
                 dvec = xbar[i, :3] - c
+                if cyl[j]:
+                    dvec[2] = 0.0
                 nd = np.sqrt(dvec @ dvec)
-                nvec = dvec / nd if nd >= 1e-9 else np.array([0.0, 0.0, 1.0])
+                nvec = dvec / nd if nd >= 1e-9 else fallback
                 a[i] = nvec
                 b[i] = r + nvec @ c
             groups.append(Group("x", (0, 1, 2), "halfspace", inner.copy(), a=a, b=b))
@@ -181,7 +195,8 @@ def defect(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
 
 def violation(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
     """Max violation of the hard (unconvexified) constraints: state/control bounds, control
-    ball, obstacle spheres (penetration depth, nodes 1..N), SOC ||T|| <= Gamma, glide slope."""
+    ball, obstacles (penetration depth, nodes 1..N; horizontal distance for a cylinder),
+    SOC ||T|| <= Gamma, glide slope."""
     N = inst["N"]
     v = 0.0
     v = max(v, float(np.max(np.maximum(0.0, inst["x_lo"] - x))), float(np.max(np.maximum(0.0, x - inst["x_hi"]))))
@@ -190,9 +205,11 @@ def violation(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
     if inst["model"] == QUAD:
         if N > 0 and math.isfinite(inst["u_ball"]):
             v = max(v, float(np.max(np.sqrt(np.sum(u[:, :3] ** 2, axis=1)) - inst["u_ball"])))
+        cyl = _cyl_flags(inst)
         for j in range(inst["obstacles"].shape[0]):
             c, r = inst["obstacles"][j, :3], inst["obstacles"][j, 3]
-            dist = np.sqrt(np.sum((x[1:, :3] - c) ** 2, axis=1))
+            dims = 2 if cyl[j] else 3
+            dist = np.sqrt(np.sum((x[1:, :dims] - c[:dims]) ** 2, axis=1))
             if dist.size:
                 v = max(v, float(np.max(r - dist)))
     else:
@@ -346,7 +363,7 @@ def scp_solve(insts: list[dict], params: dict | None = None):
     return sols, infos
 
 
-def shift_warm_start(trajs: list[Traj], next_insts: list[dict] | None = None) -> list[Traj]:
+def shift_warm_start(trajs: list[Traj], next_insts: list[dict] | None = None, measured: bool = False) -> list[Traj]:
     """MPC warm start of the next request of a session (Sec. IV-A.4, receding horizon).
 
     Reading (the paper gives no formula): the next request starts one node later along the
@@ -357,7 +374,8 @@ def shift_warm_start(trajs: list[Traj], next_insts: list[dict] | None = None) ->
         i+1 for i < N-1, row N-1 is repeated;
       * lambda_0 = mu_0 = 0 (node 0 has no dynamic coupling), and every dual at a node where its
         group does not exist is 0;
-      * the new initial state, for every scenario, is the previous scenario-0 nominal at node 1.
+      * the new initial state, for every scenario, is the previous scenario-0 nominal at node 1;
+        with ``measured`` (closed-loop MPC) it is next_insts' own x_init, the measured state.
     The trust radius and the iteration records start afresh (the caller's scp_group does so).
     Returns new Traj objects; their instances are next_insts (the next request's data, same
     shapes) or copies of the previous ones, with the new x_init.  The inputs are unchanged.
@@ -377,7 +395,8 @@ def shift_warm_start(trajs: list[Traj], next_insts: list[dict] | None = None) ->
     out = []
     for k, t in enumerate(trajs):
         inst = dict(t.inst if next_insts is None else next_insts[k])
-        inst["x_init"] = x_init.copy()
+        if not (measured and next_insts is not None):
+            inst["x_init"] = x_init.copy()
         N = inst["N"]
         nt = Traj(inst, sh_x(t.xbar), sh_u(t.ubar, N))
         st = t.state

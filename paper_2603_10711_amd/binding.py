@@ -25,8 +25,10 @@ FORM_PLAIN, FORM_PERSISTENT = 0, 1
 PACK_ALIGNED, PACK_DENSE = 0, 1
 MAX_NX, MAX_NU, MAX_OBS = 7, 4, 8
 P = dict(H=0, XINIT=1, XTGT=8, TMASK=15, QR=22, QN=29, QNV=36, CN=43, R=44, XLO=48, XHI=55, ULO=62, UHI=66,
-         UBALL=70, DELTA=71, DRAG=72, MSCALE=73, GRAV=74, ALPHA=75, GVEC=76, GLIDE=79, NOBS=80, OBS=81)
-PARAM_STRIDE = 113
+         UBALL=70, DELTA=71, DRAG=72, MSCALE=73, GRAV=74, ALPHA=75, GVEC=76, GLIDE=79, NOBS=80, OBS=81,
+         DIST=113, CYL=116)
+PARAM_STRIDE = 117
+SUBMIT_MEASURED = 1
 INFO = dict(admm_iters=0, r_p=1, r_d=2, n_accept=3, delta=4, status=5, defect=6, cost=7, viol=8, bnd_err=9,
             merit=10, ratio=11)
 INFO_FIELDS = 12
@@ -37,7 +39,7 @@ SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_destro
            "scp_solve", "scp_reset", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
            "scp_traj_node_offset", "scp_plan", "scp_autotune_device_bytes", "scp_autotune", "scp_last_error"]
 SERVE_SYMBOLS = ["scp_server_device_bytes", "scp_server_create", "scp_server_destroy", "scp_server_request_bytes",
-                 "scp_server_submit", "scp_server_step", "scp_server_collect", "scp_server_get_stats",
+                 "scp_server_submit", "scp_server_submit_ex", "scp_server_step", "scp_server_collect", "scp_server_get_stats",
                  "scp_server_last_error"]
 REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2, 3
 
@@ -140,6 +142,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scp_server_request_bytes.restype = c_size_t
     lib.scp_server_submit.argtypes = [c_void_p, POINTER(ProblemDesc), c_int32, POINTER(c_int64)]
     lib.scp_server_submit.restype = c_int32
+    lib.scp_server_submit_ex.argtypes = [c_void_p, POINTER(ProblemDesc), c_int32, ctypes.c_uint32, POINTER(c_int64)]
+    lib.scp_server_submit_ex.restype = c_int32
     lib.scp_server_step.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
     lib.scp_server_step.restype = c_int32
     lib.scp_server_collect.argtypes = [c_void_p, c_int64, c_int32, POINTER(c_int32), POINTER(c_double),
@@ -182,6 +186,8 @@ def param_record(inst: dict) -> np.ndarray:
     r[P["NOBS"]] = obs.shape[0]          # the library rejects counts above MAX_OBS
     keep = obs[:MAX_OBS].ravel()
     r[P["OBS"]:P["OBS"] + keep.size] = keep
+    r[P["DIST"]:P["DIST"] + 3] = inst.get("dist", (0.0, 0.0, 0.0))
+    r[P["CYL"]] = float(sum(1 << j for j, c in enumerate(inst.get("cyl", ())) if c))
     return r
 
 
@@ -449,11 +455,14 @@ class Server:
         desc, keep = make_desc(insts, self.prec)
         return (desc, keep, [(d["N"], d["nx"], d["nu"]) for d in insts])
 
-    def submit(self, insts, session: int = -1) -> int:
-        """Queue a request (a list of problem dictionaries, or a prepared description)."""
+    def submit(self, insts, session: int = -1, measured: bool = False) -> int:
+        """Queue a request (a list of problem dictionaries, or a prepared description).
+        measured: a warm start keeps the request's x_init (closed-loop MPC, SUBMIT_MEASURED)."""
         desc, keep, shape = insts if isinstance(insts, tuple) else self.prepare(insts)
         rid = c_int64(0)
-        self._check(self.lib.scp_server_submit(self.h, byref(desc), session, byref(rid)), "scp_server_submit")
+        flags = SUBMIT_MEASURED if measured else 0
+        self._check(self.lib.scp_server_submit_ex(self.h, byref(desc), session, flags, byref(rid)),
+                    "scp_server_submit_ex")
         self.shapes[rid.value] = shape
         return rid.value
 

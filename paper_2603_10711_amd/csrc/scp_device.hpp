@@ -117,13 +117,14 @@ __device__ __forceinline__ double lane_prev(double v) {
 template <class M, class T>
 __device__ __forceinline__ void f_cont(const T* __restrict__ prm, const T* x, const T* u, T* f) {
     if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
-        // p' = v, v' = u/m_s - g e3 - c ||v|| v
+        // p' = v, v' = u/m_s - g e3 - c ||v|| v + d  (d: constant disturbance acceleration)
         const T c = prm[SCP_P_DRAG], ms = prm[SCP_P_MSCALE], g = prm[SCP_P_GRAV];
+        const T* dist = prm + SCP_P_DIST;
         const T nv = tsqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
         f[0] = x[3]; f[1] = x[4]; f[2] = x[5];
-        f[3] = u[0] / ms - c * nv * x[3];
-        f[4] = u[1] / ms - c * nv * x[4];
-        f[5] = (u[2] / ms - g) - c * nv * x[5];
+        f[3] = (u[0] / ms - c * nv * x[3]) + dist[0];
+        f[4] = (u[1] / ms - c * nv * x[4]) + dist[1];
+        f[5] = ((u[2] / ms - g) - c * nv * x[5]) + dist[2];
     } else {
         // r' = v, v' = T/m + g_vec, m' = -alpha Gamma
         const T m = x[6];
@@ -436,15 +437,20 @@ __device__ __forceinline__ int convexify(const T* __restrict__ prm, const NodeId
         nc.hi[NX + r] = id.last() ? T(0) : hi;
     }
     if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+        const int cyl = (int)prm[SCP_P_CYL];
 #pragma unroll
         for (int j = 0; j < M::KM; ++j) {
             T a0 = T(0), a1 = T(0), a2 = T(0), b = T(0);
             if (j < id.K && !id.first()) {
+                // sphere: normal along xbar - c; vertical cylinder: its horizontal part
+                const bool cj = (cyl >> j) & 1;
                 const T* o = prm + SCP_P_OBS + 4 * j;
-                const T d0 = xbar[0] - o[0], d1 = xbar[1] - o[1], d2 = xbar[2] - o[2];
+                const T d0 = xbar[0] - o[0], d1 = xbar[1] - o[1], d2 = cj ? T(0) : xbar[2] - o[2];
                 const T nd = tsqrt((d0 * d0 + d1 * d1) + d2 * d2);
                 if (nd >= T(1e-9)) {
                     a0 = d0 / nd; a1 = d1 / nd; a2 = d2 / nd;
+                } else if (cj) {
+                    a0 = T(1);
                 } else {
                     a2 = T(1);
                 }
@@ -1113,9 +1119,10 @@ __device__ __forceinline__ T node_violation(const T* __restrict__ prm, const Nod
             v = nmax(v, nu - prm[SCP_P_UBALL]);
         }
         if (!id.first()) {
+            const int cyl = (int)prm[SCP_P_CYL];
             for (int j = 0; j < id.K; ++j) {
                 const T* o = prm + SCP_P_OBS + 4 * j;
-                const T d0 = x[0] - o[0], d1 = x[1] - o[1], d2 = x[2] - o[2];
+                const T d0 = x[0] - o[0], d1 = x[1] - o[1], d2 = ((cyl >> j) & 1) ? T(0) : x[2] - o[2];
                 v = nmax(v, o[3] - tsqrt((d0 * d0 + d1 * d1) + d2 * d2));
             }
         }

@@ -70,6 +70,7 @@ struct AdmitRec {
     int traj_first, n_traj, node_off, n_nodes, wg_first, n_wg;
     int warm;     // 1: shift the resident solution in place (MPC warm start)
     int x1_node;  // warm: pool node of scenario 0, node 1, of the previous solution
+    int keep_xinit;  // warm: keep the request's x_init (measured state) instead of that node
     int o_traj, o_params, o_node_traj, o_lane, o_wginfo, o_wggroup, o_xg, o_ug;
 };
 

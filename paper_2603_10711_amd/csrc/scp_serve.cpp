@@ -165,6 +165,7 @@ struct Request {
     std::vector<int> gslots;
     // progress
     RState state = RState::Queued;
+    uint32_t flags = 0;  // SCP_SUBMIT_*
     int scp_enq = 0;
     bool warm = false;
     double t_submit = 0, t_done = 0;
@@ -393,6 +394,7 @@ bool stage_admit(scp_server* s, Request& r, unsigned char* blob, size_t& used, s
     a.n_wg = L.n_wg;
     a.warm = x1_node >= 0 ? 1 : 0;
     a.x1_node = (int)std::max(0LL, x1_node);
+    a.keep_xinit = (r.flags & SCP_SUBMIT_MEASURED) ? 1 : 0;
     a.o_traj = put(trec.data(), trec.size() * 4);
     a.o_params = put(prm.data(), prm.size() * sizeof(T));
     a.o_node_traj = put(nt.data(), nt.size() * 4);
@@ -758,8 +760,14 @@ size_t scp_server_request_bytes(const scp_server* s, const scp_problem_desc* req
 }
 
 scp_status scp_server_submit(scp_server* s, const scp_problem_desc* d, int32_t session, int64_t* id) {
+    return scp_server_submit_ex(s, d, session, 0u, id);
+}
+
+scp_status scp_server_submit_ex(scp_server* s, const scp_problem_desc* d, int32_t session, uint32_t flags,
+                                int64_t* id) {
     if (!s) return SCP_ERR_ARG;
     if (!d || !id) return fail(s, SCP_ERR_ARG, "NULL argument");
+    if (flags & ~(uint32_t)SCP_SUBMIT_MEASURED) return fail(s, SCP_ERR_ARG, "unknown submission flags");
     Request r;
     std::string err;
     if (!plan_request(s, d, r.L, err)) {
@@ -786,6 +794,7 @@ scp_status scp_server_submit(scp_server* s, const scp_problem_desc* d, int32_t s
     r.ug.assign(d->u_guess, d->u_guess + urows * SCP_MAX_NU);
     r.id = s->next_id++;
     r.session = session;
+    r.flags = flags;
     r.t_submit = now_ms();
     r.last_use = r.t_submit;
     *id = r.id;

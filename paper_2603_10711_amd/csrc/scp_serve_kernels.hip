@@ -84,12 +84,16 @@ __global__ void k_admit(Dev<T> dv, int block, const unsigned char* __restrict__ 
         }
         return;
     }
-    // warm start: every scenario starts at the previous scenario-0 state at node 1
-    __shared__ T x1[SCP_MAX_NX];
-    if (tid < SCP_MAX_NX) x1[tid] = pl[(size_t)(PL_XBAR + tid) * P + r.x1_node];
-    __syncthreads();
-    for (int k = tid; k < r.n_traj * SCP_MAX_NX; k += nt)
-        prm[(size_t)(r.traj_first + k / SCP_MAX_NX) * SCP_PARAM_STRIDE + SCP_P_XINIT + k % SCP_MAX_NX] = x1[k % SCP_MAX_NX];
+    // warm start: every scenario starts at the previous scenario-0 state at node 1, unless the
+    // request brings its own (measured) initial state
+    if (!r.keep_xinit) {
+        __shared__ T x1[SCP_MAX_NX];
+        if (tid < SCP_MAX_NX) x1[tid] = pl[(size_t)(PL_XBAR + tid) * P + r.x1_node];
+        __syncthreads();
+        for (int k = tid; k < r.n_traj * SCP_MAX_NX; k += nt)
+            prm[(size_t)(r.traj_first + k / SCP_MAX_NX) * SCP_PARAM_STRIDE + SCP_P_XINIT + k % SCP_MAX_NX] =
+                x1[k % SCP_MAX_NX];
+    }
     for (int t = tid; t < r.n_traj; t += nt) {
         const int* rec = s_traj + t * TR_FIELDS;
         if (rec[TR_MODEL] == SCP_MODEL_QUAD_PM)

@@ -19,7 +19,10 @@ Every instance is a ``dict`` with the physical problem in solver units:
 ``u_ball``      radius of the control ball ||u|| <= u_ball (quadrotor; inf = none)
 ``delta``       trust-region radius (l-inf box around the nominal)
 ``drag``, ``mscale``, ``grav``  quadrotor drag coefficient, mass scale, gravity
-``obstacles``   (K, 4) sphere centres and radii (quadrotor)
+``obstacles``   (K, 4) obstacle centres and radii (quadrotor)
+``cyl``         (K,) bool, optional: obstacle j is a vertical cylinder (axis along z through
+                its centre) instead of a sphere
+``dist``        (3,), optional: constant disturbance acceleration in the quadrotor model
 ``alpha``, ``gvec``, ``glide_tan``  powered-descent mass-flow coefficient, gravity vector,
                 tangent of the glide-slope half angle
 ``x_guess``, ``u_guess``  initial nominal trajectory, shapes (N+1, nx) and (N, nu)
