@@ -1,7 +1,10 @@
 """Benchmark of the SCP + consensus-ADMM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096|mix2048|serve|mpc]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--plain-steps P] [--sched-steps S]
+
+``--plain-steps 0`` and ``--sched-steps 0`` leave out the plain-form and penalty-schedule legs
+(profiled runs do, so that every persistent-kernel dispatch in them is the configured one).
 
 One step = one full batched solve of the workload from its initial guess (reset of the resident
 state, then linearization, convexification, factorization, ADMM iterations, acceptance and metrics
