@@ -46,8 +46,16 @@ typedef enum {
 typedef enum {
     SCP_MODEL_QUAD_PM = 1,    /* quadrotor point mass, nx=6 (p, v), nu=3 (u):
                                  p' = v, v' = u/m_s - g e3 - c |v| v                        */
-    SCP_MODEL_MARS3DOF = 2    /* 3-DOF powered descent in scaled units, nx=7 (r, v, m),
+    SCP_MODEL_MARS3DOF = 2,   /* 3-DOF powered descent in scaled units, nx=7 (r, v, m),
                                  nu=4 (T, Gamma): r' = v, v' = T/m + g_vec, m' = -alpha Gamma */
+    SCP_MODEL_QUAD_6DOF = 3   /* 6-DOF rigid-body quadrotor (Sec. IV-A.1), nx=13 (p, v,
+                                 unit quaternion q = (w, x, y, z), body rates w_b), nu=4
+                                 (total thrust f, body torques tau):
+                                 p' = v, v' = (f/m) R(q) e3 - g e3 + d,
+                                 q' = q (x) (0, w_b) / 2, w_b' = J^-1 (tau - w_b x J w_b),
+                                 m = SCP_P_MSCALE, g = SCP_P_GRAV, J = diag(SCP_P_INERTIA);
+                                 R(q) e3 is the third column of the rotation matrix of
+                                 q / |q| (a unit thrust direction off the unit sphere too) */
 } scp_model;
 
 typedef enum { SCP_F32 = 0, SCP_F64 = 1 } scp_precision;
@@ -60,7 +68,7 @@ typedef enum {
 
 typedef enum { SCP_PACK_ALIGNED = 0, SCP_PACK_DENSE = 1 } scp_pack;
 
-#define SCP_MAX_NX 7
+#define SCP_MAX_NX 13
 #define SCP_MAX_NU 4
 #define SCP_MAX_OBS 8
 #define SCP_MAX_N 1023        /* largest horizon N (intervals) of one trajectory */
@@ -72,33 +80,36 @@ typedef enum { SCP_PACK_ALIGNED = 0, SCP_PACK_DENSE = 1 } scp_pack;
  */
 enum {
     SCP_P_H = 0,              /* step size T/N                                              */
-    SCP_P_XINIT = 1,          /* [7] initial state, x_0 = x_init (eq. ocp)                  */
-    SCP_P_XTGT = 8,           /* [7] terminal target                                        */
-    SCP_P_TMASK = 15,         /* [7] 1.0 where x_N is fixed to the target (selection S)     */
-    SCP_P_QR = 22,            /* [7] diagonal of the running state Hessian Q_i, i < N       */
-    SCP_P_QN = 29,            /* [7] diagonal of the terminal Hessian Q_N                   */
-    SCP_P_QNV = 36,           /* [7] terminal gradient q_N                                  */
-    SCP_P_CN = 43,            /* constant of the terminal cost (reported cost only)         */
-    SCP_P_R = 44,             /* [4] diagonal of the control Hessian R_i                    */
-    SCP_P_XLO = 48,           /* [7] hard state lower bounds                                */
-    SCP_P_XHI = 55,           /* [7] hard state upper bounds                                */
-    SCP_P_ULO = 62,           /* [4] hard control lower bounds                              */
-    SCP_P_UHI = 66,           /* [4] hard control upper bounds                              */
-    SCP_P_UBALL = 70,         /* control ball radius ||u|| <= r (quadrotor; HUGE_VAL = none)*/
-    SCP_P_DELTA = 71,         /* initial trust-region radius (l-inf box around the nominal) */
-    SCP_P_DRAG = 72,          /* quadrotor drag coefficient c                               */
-    SCP_P_MSCALE = 73,        /* quadrotor mass scale m_s                                   */
-    SCP_P_GRAV = 74,          /* quadrotor gravity g                                        */
-    SCP_P_ALPHA = 75,         /* powered descent mass-flow coefficient alpha                */
-    SCP_P_GVEC = 76,          /* [3] powered descent gravity vector                         */
-    SCP_P_GLIDE = 79,         /* tan of the glide-slope half angle (powered descent)        */
-    SCP_P_NOBS = 80,          /* number of obstacles K <= SCP_MAX_OBS (quadrotor)           */
-    SCP_P_OBS = 81,           /* [8 x 4] obstacle centre (3) and radius (1)                 */
-    SCP_P_DIST = 113,         /* [3] constant disturbance acceleration added to v' (quad)   */
-    SCP_P_CYL = 116,          /* bit j set: obstacle j is a vertical cylinder (axis along z
+    SCP_P_XINIT = 1,          /* [13] initial state, x_0 = x_init (eq. ocp)                 */
+    SCP_P_XTGT = 14,          /* [13] terminal target                                       */
+    SCP_P_TMASK = 27,         /* [13] 1.0 where x_N is fixed to the target (selection S)    */
+    SCP_P_QR = 40,            /* [13] diagonal of the running state Hessian Q_i, i < N      */
+    SCP_P_QN = 53,            /* [13] diagonal of the terminal Hessian Q_N                  */
+    SCP_P_QNV = 66,           /* [13] terminal gradient q_N                                 */
+    SCP_P_CN = 79,            /* constant of the terminal cost (reported cost only)         */
+    SCP_P_R = 80,             /* [4] diagonal of the control Hessian R_i                    */
+    SCP_P_XLO = 84,           /* [13] hard state lower bounds                               */
+    SCP_P_XHI = 97,           /* [13] hard state upper bounds                               */
+    SCP_P_ULO = 110,          /* [4] hard control lower bounds                              */
+    SCP_P_UHI = 114,          /* [4] hard control upper bounds                              */
+    SCP_P_UBALL = 118,        /* control ball radius ||u|| <= r (point-mass quadrotor;
+                                 HUGE_VAL = none; ignored by the 6-DOF model)               */
+    SCP_P_DELTA = 119,        /* initial trust-region radius (l-inf box around the nominal) */
+    SCP_P_DRAG = 120,         /* point-mass quadrotor drag coefficient c                    */
+    SCP_P_MSCALE = 121,       /* quadrotor mass scale m_s (6-DOF: the mass m)               */
+    SCP_P_GRAV = 122,         /* quadrotor gravity g                                        */
+    SCP_P_ALPHA = 123,        /* powered descent mass-flow coefficient alpha                */
+    SCP_P_GVEC = 124,         /* [3] powered descent gravity vector                         */
+    SCP_P_GLIDE = 127,        /* tan of the glide-slope half angle (powered descent)        */
+    SCP_P_NOBS = 128,         /* number of obstacles K <= SCP_MAX_OBS (quadrotors)          */
+    SCP_P_OBS = 129,          /* [8 x 4] obstacle centre (3) and radius (1)                 */
+    SCP_P_DIST = 161,         /* [3] constant disturbance acceleration added to v'
+                                 (quadrotors)                                               */
+    SCP_P_CYL = 164,          /* bit j set: obstacle j is a vertical cylinder (axis along z
                                  through its centre; the centre's z is ignored), else a
                                  sphere                                                     */
-    SCP_PARAM_STRIDE = 117
+    SCP_P_INERTIA = 165,      /* [3] principal moments of inertia J_xx, J_yy, J_zz (6-DOF)  */
+    SCP_PARAM_STRIDE = 168
 };
 
 /*
@@ -245,14 +256,16 @@ typedef enum {
     SCP_FIELD_COUNT = 16
 } scp_field;
 
-/* Width (values per node) of a field: XBAR/X/Z/LAM/MU/DDYN/D 7, UBAR/U 4, COPY/DUAL 36,
- * A 49 (row-major 7x7), B 28 (row-major 7x4), BOXLO/BOXHI 11 (x then u), HS 32
- * (a_x, a_y, a_z, b per obstacle).  0 for an invalid id. */
+/* Width (values per node) of a field: XBAR/X/Z/LAM/MU/DDYN/D 13, UBAR/U 4, COPY/DUAL 44,
+ * A 169 (row-major 13x13), B 52 (row-major 13x4), BOXLO/BOXHI 17 (x then u), HS 32
+ * (a_x, a_y, a_z, b per obstacle).  A model's values fill the leading slots (its nx, nu
+ * rows and columns); the rest are 0.  0 for an invalid id. */
 int32_t scp_field_width(int32_t field);
 
 /* Copy one field of every node (trajectories concatenated, N+1 rows each, scp_field_width
  * values per row, problem precision) to dst_dev.  Mirror copies and duals are packed per
- * model in a fixed group order: quadrotor [x box 6][u box 3][ball 3][half-space k: 3 each],
+ * model in a fixed group order: point-mass quadrotor [x box 6][u box 3][ball 3][half-space k:
+ * 3 each], 6-DOF quadrotor [x box 13][u box 4][ball 3, unused][half-space k: 3 each],
  * powered descent [x box 7][u box 4][glide cone 3][SOC 4].  Async. */
 scp_status scp_get_field(const scp_problem* p, int32_t field, void* dst_dev);
 

@@ -86,7 +86,8 @@ void scp_server_destroy(scp_server* s);
 size_t scp_server_request_bytes(const scp_server* s, const scp_problem_desc* req);
 
 /* Queue a request (its description is copied).  session >= 0 names an MPC session for warm
- * starts, -1 none.  Errors: SCP_ERR_ARG (invalid, or larger than the pool or the budget). */
+ * starts, -1 none.  Errors: SCP_ERR_ARG (invalid, or larger than the pool or the budget, or
+ * a trajectory of the 6-DOF quadrotor model, which the persistent kernel does not run). */
 scp_status scp_server_submit(scp_server* s, const scp_problem_desc* req, int32_t session, int64_t* id);
 
 /* Submission flags. */

@@ -1,4 +1,4 @@
-"""Dynamics of the two models, their RK4 discretization and its exact Jacobians.
+"""Dynamics of the three models, their RK4 discretization and its exact Jacobians.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-QUAD, MARS = 1, 2
+QUAD, MARS, QUAD6 = 1, 2, 3
 
 
 def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
@@ -19,8 +19,25 @@ def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
     Quadrotor point mass: p' = v, v' = u/m_s - g e3 - c ||v|| v + d  (drag isotropic and
     quadratic; d the instance's constant disturbance acceleration, 0 unless given).
     Powered descent (scaled units): r' = v, v' = T/m + g_vec, m' = -alpha Gamma.
+    6-DOF quadrotor (Sec. IV-A.1, Newton-Euler rigid body): x = (p, v, q, w) with the unit
+    quaternion q = (q_w, q_x, q_y, q_z) rotating body to world and w the body angular rate;
+    u = (f, tau) total thrust along the body z axis and body torques:
+        p' = v,  v' = (f/m) R(q) e3 - g e3 + d,  q' = (1/2) q (x) (0, w),  J w' = tau - w x (J w),
+    with J = diag(inertia).  R(q) e3 is the third column of the rotation matrix of q / ||q||:
+    (2(q_x q_z + q_w q_y), 2(q_y q_z - q_w q_x), q_w^2 - q_x^2 - q_y^2 + q_z^2) / ||q||^2, so the
+    thrust direction stays a unit vector when the iterates leave the unit sphere.
     The norm is written sqrt(v.v) so the function stays analytic for complex-step tests.
     """
+    if inst["model"] == QUAD6:
+        v, q, w = x[3:6], x[6:10], x[10:13]
+        f, tau = u[0], u[1:4]
+        J = np.asarray(inst["inertia"], dtype=float)
+        acc = (f / inst["mscale"]) * _rot_e3(q) - np.array([0.0, 0.0, inst["grav"]])
+        if "dist" in inst:
+            acc = acc + np.asarray(inst["dist"], dtype=float)
+        qdot = 0.5 * _quat_mul(q, np.concatenate([[0.0], w]))
+        wdot = (tau - np.cross(w, J * w)) / J
+        return np.concatenate([v, acc, qdot, wdot])
     if inst["model"] == QUAD:
         p, v = x[:3], x[3:6]
         nv = np.sqrt(v @ v)
@@ -33,14 +50,68 @@ def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
     return np.concatenate([v, T / m + inst["gvec"], [-inst["alpha"] * G]])
 
 
+def _quat_mul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Hamilton product a (x) b of quaternions stored scalar first."""
+    aw, av = a[0], a[1:]
+    bw, bv = b[0], b[1:]
+    return np.concatenate([[aw * bw - av @ bv], aw * bv + bw * av + np.cross(av, bv)])
+
+
+def _rot_e3(q: np.ndarray) -> np.ndarray:
+    """Third column of the rotation matrix of q / ||q||."""
+    qw, qx, qy, qz = q
+    n2 = qw * qw + qx * qx + qy * qy + qz * qz
+    return np.array([2.0 * (qx * qz + qw * qy), 2.0 * (qy * qz - qw * qx), qw * qw - qx * qx - qy * qy + qz * qz]) / n2
+
+
+def _skew(a: np.ndarray) -> np.ndarray:
+    """Matrix of the cross product a x (.)."""
+    return np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+
+
 def jac_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     """Jacobians (df/dx, df/du) of ``f_cont``.
 
     Drag term: d(c||v||v)/dv = c (||v|| I + v v^T / ||v||), taken as 0 at v = 0.
+    6-DOF quadrotor: d(R(q) e3)/dq by the quotient rule on the normalized form; q (x) (0, w) is
+    bilinear, so its
+    derivative in q is the right-multiplication matrix of (0, w) and in w the left-multiplication
+    matrix of q restricted to the vector part; d(w x Jw)/dw = [w]x J - [Jw]x.
     """
     nx, nu = x.shape[0], u.shape[0]
     Jx = np.zeros((nx, nx))
     Ju = np.zeros((nx, nu))
+    if inst["model"] == QUAD6:
+        q, w = x[6:10], x[10:13]
+        qw, qx, qy, qz = q
+        f = u[0]
+        m = inst["mscale"]
+        J = np.asarray(inst["inertia"], dtype=float)
+        Jx[0:3, 3:6] = np.eye(3)
+        n2 = q @ q
+        dc = 2.0 * np.array([[qy, qz, qw, qx],
+                             [-qx, -qw, qz, qy],
+                             [qw, -qx, -qy, qz]])
+        dR = dc / n2 - np.outer(_rot_e3(q), 2.0 * q) / n2
+        Jx[3:6, 6:10] = (f / m) * dR
+        Ju[3:6, 0] = _rot_e3(q) / m
+        # q' = (1/2) q (x) p with p = (0, w): right multiplication by p, and left multiplication by q
+        pw, pv = 0.0, w
+        Rp = np.zeros((4, 4))
+        Rp[0, 0] = pw
+        Rp[0, 1:] = -pv
+        Rp[1:, 0] = pv
+        Rp[1:, 1:] = pw * np.eye(3) - _skew(pv)
+        Lq = np.zeros((4, 4))
+        Lq[0, 0] = qw
+        Lq[0, 1:] = -q[1:]
+        Lq[1:, 0] = q[1:]
+        Lq[1:, 1:] = qw * np.eye(3) + _skew(q[1:])
+        Jx[6:10, 6:10] = 0.5 * Rp
+        Jx[6:10, 10:13] = 0.5 * Lq[:, 1:]
+        Jx[10:13, 10:13] = -(_skew(w) @ np.diag(J) - _skew(J * w)) / J[:, None]
+        Ju[10:13, 1:4] = np.diag(1.0 / J)
+        return Jx, Ju
     if inst["model"] == QUAD:
         v = x[3:6]
         nv = np.sqrt(v @ v)

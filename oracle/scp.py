@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .admm import Group, QP, AdmmState, build_H, admm_run
-from .dynamics import rk4, rk4_jac, QUAD, MARS
+from .dynamics import rk4, rk4_jac, QUAD, MARS, QUAD6
 
 
 def default_params(**kw) -> dict:
@@ -117,9 +117,10 @@ def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_c
     u box (nodes 0..N-1): trust box around ubar intersected with the hard control bounds;
       at node 0 the box is centred at ``u0_center`` when given (scenario groups share one
       first-control set).
-    Quadrotor: control ball ||u|| <= u_ball (nodes 0..N-1), then one half-space per obstacle
-      at nodes 1..N: n'(p - c) >= r with n = (pbar - c)/||pbar - c|| (+e3 if ||pbar - c|| < 1e-9).
-      A vertical cylinder uses the horizontal part of pbar - c (fallback +e1).
+    Quadrotors: control ball ||u|| <= u_ball (point mass only, nodes 0..N-1), then one
+      half-space per obstacle at nodes 1..N: n'(p - c) >= r with n = (pbar - c)/||pbar - c||
+      (+e3 if ||pbar - c|| < 1e-9).  A vertical cylinder uses the horizontal part of pbar - c
+      (fallback +e1).  The 6-DOF model's position is its first three states as well.
     Powered descent: glide-slope cone ||(r_x, r_y)|| <= tan(86 deg) r_z at nodes 1..N, then
       the SOC ||T|| <= Gamma at nodes 0..N-1.
     """
@@ -146,8 +147,8 @@ def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_c
 
     inner = np.ones(N + 1, dtype=bool)
     inner[0] = False
-    if inst["model"] == QUAD:
-        if math.isfinite(inst["u_ball"]):
+    if inst["model"] in (QUAD, QUAD6):
+        if inst["model"] == QUAD and math.isfinite(inst["u_ball"]):
             groups.append(Group("u", (0, 1, 2), "ball", uact.copy(), radius=float(inst["u_ball"])))
         cyl = _cyl_flags(inst)
         for j in range(inst["obstacles"].shape[0]):
@@ -202,8 +203,8 @@ def violation(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
     v = max(v, float(np.max(np.maximum(0.0, inst["x_lo"] - x))), float(np.max(np.maximum(0.0, x - inst["x_hi"]))))
     if N > 0:
         v = max(v, float(np.max(np.maximum(0.0, inst["u_lo"] - u))), float(np.max(np.maximum(0.0, u - inst["u_hi"]))))
-    if inst["model"] == QUAD:
-        if N > 0 and math.isfinite(inst["u_ball"]):
+    if inst["model"] in (QUAD, QUAD6):
+        if inst["model"] == QUAD and N > 0 and math.isfinite(inst["u_ball"]):
             v = max(v, float(np.max(np.sqrt(np.sum(u[:, :3] ** 2, axis=1)) - inst["u_ball"])))
         cyl = _cyl_flags(inst)
         for j in range(inst["obstacles"].shape[0]):

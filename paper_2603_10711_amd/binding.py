@@ -19,15 +19,15 @@ LIB_PATH = os.path.join(HERE, "libscp.so")
 
 # --- constants mirrored from include/scp.h ------------------------------------------------
 SCP_OK = 0
-QUAD, MARS = 1, 2
+QUAD, MARS, QUAD6 = 1, 2, 3
 F32, F64 = 0, 1
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 PACK_ALIGNED, PACK_DENSE = 0, 1
-MAX_NX, MAX_NU, MAX_OBS = 7, 4, 8
-P = dict(H=0, XINIT=1, XTGT=8, TMASK=15, QR=22, QN=29, QNV=36, CN=43, R=44, XLO=48, XHI=55, ULO=62, UHI=66,
-         UBALL=70, DELTA=71, DRAG=72, MSCALE=73, GRAV=74, ALPHA=75, GVEC=76, GLIDE=79, NOBS=80, OBS=81,
-         DIST=113, CYL=116)
-PARAM_STRIDE = 117
+MAX_NX, MAX_NU, MAX_OBS = 13, 4, 8
+P = dict(H=0, XINIT=1, XTGT=14, TMASK=27, QR=40, QN=53, QNV=66, CN=79, R=80, XLO=84, XHI=97, ULO=110, UHI=114,
+         UBALL=118, DELTA=119, DRAG=120, MSCALE=121, GRAV=122, ALPHA=123, GVEC=124, GLIDE=127, NOBS=128, OBS=129,
+         DIST=161, CYL=164, INERTIA=165)
+PARAM_STRIDE = 168
 SUBMIT_MEASURED = 1
 INFO = dict(admm_iters=0, r_p=1, r_d=2, n_accept=3, delta=4, status=5, defect=6, cost=7, viol=8, bnd_err=9,
             merit=10, ratio=11)
@@ -188,6 +188,7 @@ def param_record(inst: dict) -> np.ndarray:
     r[P["OBS"]:P["OBS"] + keep.size] = keep
     r[P["DIST"]:P["DIST"] + 3] = inst.get("dist", (0.0, 0.0, 0.0))
     r[P["CYL"]] = float(sum(1 << j for j, c in enumerate(inst.get("cyl", ())) if c))
+    r[P["INERTIA"]:P["INERTIA"] + 3] = inst.get("inertia", (0.0, 0.0, 0.0))
     return r
 
 
@@ -374,7 +375,7 @@ class Problem:
             cur.wait_stream(self.stream)
 
     def result(self):
-        """(x, u, info) as device tensors: x (nodes, 7), u (nodes, 4), info (n_traj, 12) float64."""
+        """(x, u, info) as device tensors: x (nodes, MAX_NX), u (nodes, MAX_NU), info (n_traj, 12) float64."""
         t = self.torch
         x = t.empty((self.n_nodes, MAX_NX), dtype=self.dtype, device=self.arena.device)
         u = t.empty((self.n_nodes, MAX_NU), dtype=self.dtype, device=self.arena.device)

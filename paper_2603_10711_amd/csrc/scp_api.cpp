@@ -24,9 +24,13 @@ namespace {
 
 thread_local std::string g_create_error;
 
-bool valid_model(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_MARS3DOF; }
-int model_nx(int m) { return m == SCP_MODEL_QUAD_PM ? 6 : 7; }
-int model_nu(int m) { return m == SCP_MODEL_QUAD_PM ? 3 : 4; }
+bool valid_model(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_MARS3DOF || m == SCP_MODEL_QUAD_6DOF; }
+bool quad_like(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_QUAD_6DOF; }
+// model bit of Layout::models
+int model_bit(int m) { return m == SCP_MODEL_QUAD_PM ? 1 : m == SCP_MODEL_MARS3DOF ? 2 : 4; }
+const char* const kNoPersistent =
+    "the persistent form needs trajectories of at most 256 nodes, consensus groups of at most 64 members and the "
+    "point-mass quadrotor or powered-descent model; use the plain form";
 
 // Pack units (single trajectories or whole consensus groups) of one model into workgroups of
 // `block` lanes, first-fit decreasing by size.  Returns false if a unit does not fit.
@@ -159,7 +163,7 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
         if (N < 1 || N > SCP_MAX_N) { err = "horizon out of range at trajectory " + std::to_string(t); return false; }
         const double* prm = d->params + (size_t)t * SCP_PARAM_STRIDE;
         const double K = prm[SCP_P_NOBS];
-        if (m == SCP_MODEL_QUAD_PM && !(K >= 0 && K <= SCP_MAX_OBS && K == std::floor(K))) {
+        if (quad_like(m) && !(K >= 0 && K <= SCP_MAX_OBS && K == std::floor(K))) {
             err = "obstacle count out of range at trajectory " + std::to_string(t);
             return false;
         }
@@ -169,7 +173,7 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
         r[TR_MODEL] = m;
         r[TR_N] = N;
         r[TR_OFF] = (int)off;
-        r[TR_K] = m == SCP_MODEL_QUAD_PM ? (int)K : 0;
+        r[TR_K] = quad_like(m) ? (int)K : 0;
         r[TR_BALL] = (m == SCP_MODEL_QUAD_PM && std::isfinite(prm[SCP_P_UBALL])) ? 1 : 0;
         r[TR_GFIRST] = t;
         r[TR_GSIZE] = 1;
@@ -177,7 +181,7 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
         traj_off[t] = (int)off;
         horizon[t] = N;
         off += N + 1;
-        L.models |= (m == SCP_MODEL_QUAD_PM) ? 1 : 2;
+        L.models |= model_bit(m);
         L.kmax = std::max(L.kmax, r[TR_K]);
         if (off > (1LL << 30)) { err = "too many nodes"; return false; }
     }
@@ -225,6 +229,7 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     if (d->prec == SCP_F64) cands.erase(std::remove(cands.begin(), cands.end(), 256), cands.end());
     long best_idle = -1;
     double best_score = 0.0;
+    if (L.models & 4) cands.clear();  // the 6-DOF model runs in the plain form only
     for (int b : cands) {
         Packed pk;
         if (!pack(units, traj_off, horizon, b, d->pack == SCP_PACK_ALIGNED, pk)) continue;
@@ -441,8 +446,7 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
         return hip_check(p, e, "metrics launch");
     }
     if (!L.persistent_ok)
-        return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory exceeds 256 nodes or a consensus group more than 64 members; "
-                                            "use the plain form");
+        return fail(p, SCP_ERR_UNSUPPORTED, kNoPersistent);
     const int per = s->scp_per_launch > 0 ? s->scp_per_launch : std::max(1, s->scp_iters);
     int done = 0;
     if (s->scp_iters == 0) {
@@ -473,7 +477,7 @@ void stage_problem(const scp_problem_desc* d, const Layout& L, std::vector<char>
     img_params.assign((size_t)L.n_traj * SCP_PARAM_STRIDE * sizeof(T), 0);
     T* prm = reinterpret_cast<T*>(img_params.data());
     for (size_t k = 0; k < (size_t)L.n_traj * SCP_PARAM_STRIDE; ++k) prm[k] = T(d->params[k]);
-    // nominal planes XBAR (7) and UBAR (4): contiguous block of 11 planes
+    // nominal planes XBAR (SCP_MAX_NX) and UBAR (SCP_MAX_NU): one contiguous block
     img_nom.assign((size_t)(SCP_MAX_NX + SCP_MAX_NU) * L.P * sizeof(T), 0);
     T* nom = reinterpret_cast<T*>(img_nom.data());
     long long xrow = 0, urow = 0;
@@ -616,8 +620,7 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
     if (prm->graph != 0 && prm->graph != 1) return fail(p, SCP_ERR_ARG, "graph must be 0 or 1");
     if (!(prm->rho_final >= 0.0)) return fail(p, SCP_ERR_ARG, "rho_final must be >= 0");
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok)
-        return fail(p, SCP_ERR_UNSUPPORTED, "a trajectory exceeds 256 nodes or a consensus group more than 64 members; "
-                                            "use the plain form");
+        return fail(p, SCP_ERR_UNSUPPORTED, kNoPersistent);
     scp_status st = SCP_OK;
     if (!prm->graph) {
         st = p->prec == SCP_F32 ? do_solve<float>(p, prm) : do_solve<double>(p, prm);
@@ -671,12 +674,12 @@ scp_status scp_reset(scp_problem* p) {
 int32_t scp_field_width(int32_t field) {
     switch (field) {
         case SCP_FIELD_XBAR: case SCP_FIELD_X: case SCP_FIELD_Z: case SCP_FIELD_LAM: case SCP_FIELD_MU:
-        case SCP_FIELD_DDYN: case SCP_FIELD_D: return 7;
-        case SCP_FIELD_UBAR: case SCP_FIELD_U: return 4;
-        case SCP_FIELD_COPY: case SCP_FIELD_DUAL: return 36;
-        case SCP_FIELD_A: return 49;
-        case SCP_FIELD_B: return 28;
-        case SCP_FIELD_BOXLO: case SCP_FIELD_BOXHI: return 11;
+        case SCP_FIELD_DDYN: case SCP_FIELD_D: return SCP_MAX_NX;
+        case SCP_FIELD_UBAR: case SCP_FIELD_U: return SCP_MAX_NU;
+        case SCP_FIELD_COPY: case SCP_FIELD_DUAL: return MAX_C;
+        case SCP_FIELD_A: return SCP_MAX_NX * SCP_MAX_NX;
+        case SCP_FIELD_B: return SCP_MAX_NX * SCP_MAX_NU;
+        case SCP_FIELD_BOXLO: case SCP_FIELD_BOXHI: return SCP_MAX_NX + SCP_MAX_NU;
         case SCP_FIELD_HS: return 32;
         default: return 0;
     }

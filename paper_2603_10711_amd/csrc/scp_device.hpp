@@ -28,28 +28,50 @@ namespace scp {
 // model traits
 // ------------------------------------------------------------------------------------------
 // Mirror-copy layout (one copy with its own dual per constraint group):
-//   quadrotor       [x box: NX][u box: NU][ball: 3][half-space k: 3 each, k < KM]
+//   quadrotors      [x box: NX][u box: NU][ball: 3][half-space k: 3 each, k < KM]
 //   powered descent [x box: NX][u box: NU][glide cone on r: 3][SOC on (T, Gamma): 4]
-// The first three state components (position) never enter the dynamics of either model, so
-// the first three columns of A are the unit vectors e_0..e_2 exactly; only the other
-// NXR = NX - 3 columns are stored ("Ar").
+// Both quadrotor models share the first layout (QL: "quadrotor layout"); the 6-DOF model never
+// has the ball group (its slots stay inactive).  The first three state components (position)
+// never enter the dynamics of any model, so the first three columns of A are the unit vectors
+// e_0..e_2 exactly; only the other NXR = NX - 3 columns are stored ("Ar").
 
 template <int KM_>
 struct Quad {
     static constexpr int ID = SCP_MODEL_QUAD_PM;
+    static constexpr bool QL = true;
     static constexpr int NX = 6, NU = 3, NN = 9, NXR = 3, KM = KM_;
     static constexpr int C_XBOX = 0, C_UBOX = 6, C_BALL = 9, C_HS = 12;
     static constexpr int C = 12 + 3 * KM_;
     static constexpr int NHS = KM_ > 0 ? 4 * KM_ : 1;
 };
 
+// 6-DOF quadrotor: x = (p, v, q, w_b), u = (f, tau)
+template <int KM_>
+struct Quad6 {
+    static constexpr int ID = SCP_MODEL_QUAD_6DOF;
+    static constexpr bool QL = true;
+    static constexpr int NX = 13, NU = 4, NN = 17, NXR = 10, KM = KM_;
+    static constexpr int C_XBOX = 0, C_UBOX = 13, C_BALL = 17, C_HS = 20;
+    static constexpr int C = 20 + 3 * KM_;
+    static constexpr int NHS = KM_ > 0 ? 4 * KM_ : 1;
+};
+
 struct Mars {
     static constexpr int ID = SCP_MODEL_MARS3DOF;
+    static constexpr bool QL = false;
     static constexpr int NX = 7, NU = 4, NN = 11, NXR = 4, KM = 0;
     static constexpr int C_XBOX = 0, C_UBOX = 7, C_CONE = 11, C_SOC = 14;
     static constexpr int C = 18;
     static constexpr int NHS = 1;
 };
+
+// run-time dimensions of a model id: state, control, and the mirror slots of its largest
+// instantiation (the prefix of each plane block a trajectory of that model uses)
+__host__ __device__ constexpr int model_nx(int m) { return m == SCP_MODEL_QUAD_PM ? 6 : m == SCP_MODEL_MARS3DOF ? 7 : 13; }
+__host__ __device__ constexpr int model_nu(int m) { return m == SCP_MODEL_QUAD_PM ? 3 : 4; }
+__host__ __device__ constexpr int model_slots(int m) {
+    return m == SCP_MODEL_QUAD_PM ? Quad<SCP_MAX_OBS>::C : m == SCP_MODEL_MARS3DOF ? Mars::C : Quad6<SCP_MAX_OBS>::C;
+}
 
 template <class M>
 __host__ __device__ constexpr int NU_OF() { return M::NU; }
@@ -125,6 +147,30 @@ __device__ __forceinline__ void f_cont(const T* __restrict__ prm, const T* x, co
         f[3] = (u[0] / ms - c * nv * x[3]) + dist[0];
         f[4] = (u[1] / ms - c * nv * x[4]) + dist[1];
         f[5] = ((u[2] / ms - g) - c * nv * x[5]) + dist[2];
+    } else if constexpr (M::ID == SCP_MODEL_QUAD_6DOF) {
+        // p' = v, v' = (f/m) R(q/|q|) e3 - g e3 + d, q' = q (x) (0, w) / 2, J w' = tau - w x (J w)
+        const T m = prm[SCP_P_MSCALE], g = prm[SCP_P_GRAV];
+        const T* J = prm + SCP_P_INERTIA;
+        const T* dist = prm + SCP_P_DIST;
+        const T qw = x[6], qx = x[7], qy = x[8], qz = x[9];
+        const T wx = x[10], wy = x[11], wz = x[12];
+        const T a = u[0] / m;
+        // third column of the rotation matrix of q / |q|
+        const T in2 = T(1) / ((qw * qw + qx * qx) + (qy * qy + qz * qz));
+        const T c0 = T(2) * (qx * qz + qw * qy) * in2;
+        const T c1 = T(2) * (qy * qz - qw * qx) * in2;
+        const T c2 = ((qw * qw - qx * qx) + (qz * qz - qy * qy)) * in2;
+        f[0] = x[3]; f[1] = x[4]; f[2] = x[5];
+        f[3] = a * c0 + dist[0];
+        f[4] = a * c1 + dist[1];
+        f[5] = (a * c2 - g) + dist[2];
+        f[6] = T(-0.5) * ((qx * wx + qy * wy) + qz * wz);
+        f[7] = T(0.5) * ((qw * wx + qy * wz) - qz * wy);
+        f[8] = T(0.5) * ((qw * wy + qz * wx) - qx * wz);
+        f[9] = T(0.5) * ((qw * wz + qx * wy) - qy * wx);
+        f[10] = (u[1] - (J[2] - J[1]) * (wy * wz)) / J[0];
+        f[11] = (u[2] - (J[0] - J[2]) * (wz * wx)) / J[1];
+        f[12] = (u[3] - (J[1] - J[0]) * (wx * wy)) / J[2];
     } else {
         // r' = v, v' = T/m + g_vec, m' = -alpha Gamma
         const T m = x[6];
@@ -149,6 +195,35 @@ __device__ __forceinline__ void f_jvp(const T* __restrict__ prm, const T* x, con
         df[0] = dx[3]; df[1] = dx[4]; df[2] = dx[5];
 #pragma unroll
         for (int k = 0; k < 3; ++k) df[3 + k] = du[k] / ms - c * (nv * dx[3 + k] + x[3 + k] * q);
+    } else if constexpr (M::ID == SCP_MODEL_QUAD_6DOF) {
+        // product rule through every bilinear term of f_cont
+        const T m = prm[SCP_P_MSCALE];
+        const T* J = prm + SCP_P_INERTIA;
+        const T qw = x[6], qx = x[7], qy = x[8], qz = x[9];
+        const T wx = x[10], wy = x[11], wz = x[12];
+        const T dqw = dx[6], dqx = dx[7], dqy = dx[8], dqz = dx[9];
+        const T dwx = dx[10], dwy = dx[11], dwz = dx[12];
+        const T a = u[0] / m, da = du[0] / m;
+        // c = n(q) / |q|^2 with the quadratic numerator n: dc = (dn - c d|q|^2) / |q|^2
+        const T in2 = T(1) / ((qw * qw + qx * qx) + (qy * qy + qz * qz));
+        const T dn2 = T(2) * ((qw * dqw + qx * dqx) + (qy * dqy + qz * dqz));
+        const T c0 = T(2) * (qx * qz + qw * qy) * in2;
+        const T c1 = T(2) * (qy * qz - qw * qx) * in2;
+        const T c2 = ((qw * qw - qx * qx) + (qz * qz - qy * qy)) * in2;
+        const T dc0 = (T(2) * ((dqx * qz + qx * dqz) + (dqw * qy + qw * dqy)) - c0 * dn2) * in2;
+        const T dc1 = (T(2) * ((dqy * qz + qy * dqz) - (dqw * qx + qw * dqx)) - c1 * dn2) * in2;
+        const T dc2 = (T(2) * ((qw * dqw - qx * dqx) + (qz * dqz - qy * dqy)) - c2 * dn2) * in2;
+        df[0] = dx[3]; df[1] = dx[4]; df[2] = dx[5];
+        df[3] = da * c0 + a * dc0;
+        df[4] = da * c1 + a * dc1;
+        df[5] = da * c2 + a * dc2;
+        df[6] = T(-0.5) * (((dqx * wx + dqy * wy) + dqz * wz) + ((qx * dwx + qy * dwy) + qz * dwz));
+        df[7] = T(0.5) * (((dqw * wx + dqy * wz) - dqz * wy) + ((qw * dwx + qy * dwz) - qz * dwy));
+        df[8] = T(0.5) * (((dqw * wy + dqz * wx) - dqx * wz) + ((qw * dwy + qz * dwx) - qx * dwz));
+        df[9] = T(0.5) * (((dqw * wz + dqx * wy) - dqy * wx) + ((qw * dwz + qx * dwy) - qy * dwx));
+        df[10] = (du[1] - (J[2] - J[1]) * (dwy * wz + wy * dwz)) / J[0];
+        df[11] = (du[2] - (J[0] - J[2]) * (dwz * wx + wz * dwx)) / J[1];
+        df[12] = (du[3] - (J[1] - J[0]) * (dwx * wy + wx * dwy)) / J[2];
     } else {
         const T m = x[6];
         const T dm = dx[6];
@@ -366,7 +441,7 @@ struct NodeId {
 // cone at i >= 1.
 template <class M>
 __device__ __forceinline__ bool group_active(const NodeId& id, int g) {
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         if (g == 0) return true;                         // x box
         if (g == 1) return !id.last();                   // u box
         if (g == 2) return !id.last() && id.ball;        // ball
@@ -436,7 +511,7 @@ __device__ __forceinline__ int convexify(const T* __restrict__ prm, const NodeId
         nc.lo[NX + r] = id.last() ? T(0) : lo;
         nc.hi[NX + r] = id.last() ? T(0) : hi;
     }
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         const int cyl = (int)prm[SCP_P_CYL];
 #pragma unroll
         for (int j = 0; j < M::KM; ++j) {
@@ -473,7 +548,7 @@ __device__ __forceinline__ void group_counts(const NodeId& id, T* Dx, T* Du) {
     for (int r = 0; r < NX; ++r) Dx[r] = T(1);
 #pragma unroll
     for (int r = 0; r < NU; ++r) Du[r] = T(1);
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         if (!id.first()) {
 #pragma unroll
             for (int r = 0; r < 3; ++r) Dx[r] = Dx[r] + T(id.K);
@@ -639,7 +714,7 @@ __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const
     for (int r = 0; r < NX; ++r) g[r] = g[r] + (rho.geo * s.cp[M::C_XBOX + r] - s.du[M::C_XBOX + r]);
 #pragma unroll
     for (int r = 0; r < NU; ++r) g[NX + r] = g[NX + r] + (rho.geo * s.cp[M::C_UBOX + r] - s.du[M::C_UBOX + r]);
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         const T rb = group_rho<M>(id, rho.geo, 2);
 #pragma unroll
         for (int r = 0; r < 3; ++r) g[NX + r] = g[NX + r] + (rb * s.cp[M::C_BALL + r] - s.du[M::C_BALL + r]);
@@ -707,7 +782,7 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
     for (int r = 0; r < NU; ++r)
         s.cp[M::C_UBOX + r] = clampv(s.u[r] + s.du[M::C_UBOX + r] * rho.inv_geo, nc.lo[NX + r], nc.hi[NX + r]);
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         {
             T v[3];
 #pragma unroll
@@ -748,7 +823,7 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
 // variable component feeding mirror slot k (x or u), and the group of slot k
 template <class M>
 __device__ __forceinline__ constexpr int slot_group(int k) {
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         return k < M::C_UBOX ? 0 : k < M::C_BALL ? 1 : k < M::C_HS ? 2 : 3 + (k - M::C_HS) / 3;
     } else {
         return k < M::C_UBOX ? 0 : k < M::C_CONE ? 1 : k < M::C_SOC ? 2 : 3;
@@ -758,7 +833,7 @@ __device__ __forceinline__ constexpr int slot_group(int k) {
 // dual update needs no mask: the x box (always present), the u box and the SOC.
 template <class M>
 __device__ __forceinline__ constexpr bool slot_self_zero(int k) {
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         return k < M::C_BALL;
     } else {
         return k < M::C_CONE || k >= M::C_SOC;
@@ -766,7 +841,7 @@ __device__ __forceinline__ constexpr bool slot_self_zero(int k) {
 }
 template <class M>
 __device__ __forceinline__ constexpr bool slot_is_u(int k) {
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         return k >= M::C_UBOX && k < M::C_HS;
     } else {
         return (k >= M::C_UBOX && k < M::C_CONE) || k >= M::C_SOC;
@@ -774,7 +849,7 @@ __device__ __forceinline__ constexpr bool slot_is_u(int k) {
 }
 template <class M>
 __device__ __forceinline__ constexpr int slot_comp(int k) {
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         return k < M::C_UBOX ? k : k < M::C_BALL ? k - M::C_UBOX : k < M::C_HS ? k - M::C_BALL : (k - M::C_HS) % 3;
     } else {
         return k < M::C_UBOX ? k : k < M::C_CONE ? k - M::C_UBOX : k < M::C_SOC ? k - M::C_CONE : k - M::C_SOC;
@@ -800,7 +875,7 @@ __device__ __forceinline__ void step4(const NodeId& id, const Rho<T>& rho, NodeS
     }
 #pragma unroll
     for (int k = 0; k < M::C; ++k) {
-        if constexpr (HSS && M::ID == SCP_MODEL_QUAD_PM) {
+        if constexpr (HSS && M::QL) {
             if (k >= M::C_HS) continue;
         }
         // groups absent only at node N with a zero copy there (u box, SOC) update to 0 by
@@ -974,8 +1049,8 @@ __device__ __forceinline__ T dual_res(const NodeId& id, const Rho<T>& rho, const
 // index of slot k among the u slots (scratch addressing)
 template <class M>
 __device__ __forceinline__ constexpr int slot_comp_u(int k) {
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
-        return k - M::C_UBOX;   // ubox 0..2, ball 3..5
+    if constexpr (M::QL) {
+        return k - M::C_UBOX;   // u box 0..NU-1, ball NU..NU+2
     } else {
         return k < M::C_CONE ? k - M::C_UBOX : NU_OF<M>() + (k - M::C_SOC);
     }
@@ -1113,7 +1188,7 @@ __device__ __forceinline__ T node_violation(const T* __restrict__ prm, const Nod
             v = nmax(v, u[r] - prm[SCP_P_UHI + r]);
         }
     }
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) {
+    if constexpr (M::QL) {
         if (!id.last() && id.ball) {
             const T nu = tsqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
             v = nmax(v, nu - prm[SCP_P_UBALL]);

@@ -3,7 +3,8 @@
 // Node data is stored component-plane major ("SoA"): value k of node g lives at
 // planes[k * P + g], P = node count padded to a multiple of 256, so consecutive lanes of a
 // wavefront touch consecutive addresses.  Plane blocks are sized for the largest model
-// (nx = 7, nu = 4, 36 mirror slots); smaller models use a prefix of each block.
+// (nx = 13, nu = 4, 44 mirror slots); smaller models use a prefix of each block.  The
+// nominal, physical and guess blocks keep x and u adjacent (x block, then u block).
 #pragma once
 
 #include <stdint.h>
@@ -11,32 +12,40 @@
 namespace scp {
 
 enum Plane : int {
-    PL_XBAR = 0,     // 7  nominal state
-    PL_UBAR = 7,     // 4  nominal control (row N zero)
-    PL_X = 11,       // 7  physical state
-    PL_U = 18,       // 4  physical control
-    PL_Z = 22,       // 7  dynamic auxiliary z
-    PL_LAM = 29,     // 7  lambda
-    PL_MU = 36,      // 7  mu
-    PL_DD = 43,      // 7  d_dyn = A x + B u + d
-    PL_CP = 50,      // 36 mirror copies
-    PL_DU = 86,      // 36 mirror duals
-    PL_AR = 122,     // 28 non-unit columns of A (row-major NX x NXR)
-    PL_B = 150,      // 28 B (row-major NX x NU)
-    PL_D = 178,      // 7  d
-    PL_L = 185,      // 66 packed Cholesky factor (diagonal slots hold reciprocals)
-    PL_LO = 251,     // 11 box lower bounds (x then u)
-    PL_HI = 262,     // 11 box upper bounds
-    PL_HS = 273,     // 32 half-spaces (a_x, a_y, a_z, b) per obstacle
-    PL_G0 = 305,     // 7  constant Step-1 right-hand side (x part)
-    PL_DZ = 312,     // 7  z - z_old (residual iterations)
-    PL_SP = 319,     // 11 node-local part of the dual residual vector
-    PL_RP = 330,     // 1  node primal residual
-    PL_MER = 331,    // 8  merit / metric terms of one node
-    PL_XG = 339,     // 7  initial guess of the states (restored by scp_reset)
-    PL_UG = 346,     // 4  initial guess of the controls
-    NPLANES = 350
+    PL_XBAR = 0,    // 13  nominal state
+    PL_UBAR = 13,   // 4   nominal control (row N zero)
+    PL_X = 17,      // 13  physical state
+    PL_U = 30,      // 4   physical control
+    PL_Z = 34,      // 13  dynamic auxiliary z
+    PL_LAM = 47,    // 13  lambda
+    PL_MU = 60,     // 13  mu
+    PL_DD = 73,     // 13  d_dyn = A x + B u + d
+    PL_CP = 86,     // 44  mirror copies
+    PL_DU = 130,    // 44  mirror duals
+    PL_AR = 174,    // 130 non-unit columns of A (row-major NX x NXR)
+    PL_B = 304,     // 52  B (row-major NX x NU)
+    PL_D = 356,     // 13  d
+    PL_L = 369,     // 153 packed Cholesky factor (diagonal slots hold reciprocals)
+    PL_LO = 522,    // 17  box lower bounds (x then u)
+    PL_HI = 539,    // 17  box upper bounds
+    PL_HS = 556,    // 32  half-spaces (a_x, a_y, a_z, b) per obstacle
+    PL_G0 = 588,    // 13  constant Step-1 right-hand side (x part)
+    PL_DZ = 601,    // 13  z - z_old (residual iterations)
+    PL_SP = 614,    // 17  node-local part of the dual residual vector
+    PL_RP = 631,    // 1   node primal residual
+    PL_MER = 632,   // 8   merit / metric terms of one node
+    PL_XG = 640,    // 13  initial guess of the states (restored by scp_reset)
+    PL_UG = 653,    // 4   initial guess of the controls
+    NPLANES = 657
 };
+
+// mirror slots of the largest model (the PL_CP / PL_DU block width)
+constexpr int MAX_C = 44;
+// Largest state dimension and mirror-slot count among the models the persistent kernel and the
+// request server run (point-mass quadrotor, powered descent); their workgroup exchange arrays
+// are sized by these.
+constexpr int PERSIST_MAX_NX = 7;
+constexpr int PERSIST_MAX_C = 36;
 
 // merit / metric term slots inside PL_MER
 enum : int { MER_COST_NOM = 0, MER_PEN_NOM = 1, MER_COST_NEW = 2, MER_PEN_NEW = 3, MER_PEN_MOD = 4,
@@ -75,7 +84,8 @@ struct AdmitRec {
 };
 
 // Server result record: a finished request's info, nominal states and controls go to the
-// output staging at o_out (info doubles, then N+1 rows of 7 and of 4 values per trajectory).
+// output staging at o_out (info doubles, then N+1 rows of SCP_MAX_NX and of SCP_MAX_NU values
+// per trajectory).
 struct CollectRec {
     int traj_first, n_traj, node_off, n_nodes;
     long long o_out;

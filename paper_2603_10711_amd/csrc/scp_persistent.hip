@@ -33,6 +33,7 @@ template <class T>
 hipError_t launch_persistent(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int block, int models, int kmax,
                              hipStream_t s) {
     if (n_wg <= 0) return hipSuccess;
+    if (models & ~3) return hipErrorInvalidValue;  // point-mass quadrotor and powered descent only
     if (dv.n_gslots > 0) {
         const int n = dv.n_gslots * GX_SYNC_STRIDE;
         hipLaunchKernelGGL(k_zero_sync, dim3((n + 255) / 256), dim3(256), 0, s, dv.gsync, n);

@@ -39,13 +39,13 @@ struct StridedLds {
 // factor out of the registers, the ADMM state stays in VGPRs instead of spilling to AGPRs.
 template <class T, int BLOCK, int HSR, int LR>
 struct Shared {
-    static constexpr int XR = BLOCK == 64 ? 1 : SCP_MAX_NX;
+    static constexpr int XR = BLOCK == 64 ? 1 : PERSIST_MAX_NX;
     T ex[2 * XR][BLOCK + 1];       // z, mu of every node (backward exchange); x / xbar at accept;
                                    // column BLOCK stays 0 (the neighbour of the last lane)
     T fw[XR][BLOCK + 1];           // d_dyn of lane t in column t + 1 (forward exchange)
     T dz[XR][BLOCK];               // z - z_old (dual-residual neighbour term)
-    T zo[SCP_MAX_NX][BLOCK];       // own z before Steps 2-3 on residual iterations
-    T cpo[36][BLOCK];              // own copies before Step 3 on residual iterations
+    T zo[PERSIST_MAX_NX][BLOCK];   // own z before Steps 2-3 on residual iterations
+    T cpo[PERSIST_MAX_C][BLOCK];   // own copies before Step 3 on residual iterations
     T red[8][BLOCK];               // per-node terms for fixed-order trajectory sums
     T ucp[8][BLOCK];               // node-0 u copies of consensus groups
     unsigned long long mx[2][BLOCK];  // per-trajectory residual maxima, slot = first lane
@@ -196,7 +196,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     constexpr int HSN = HSQ ? M::KM : 1;
     static_assert(!HSQ || HSR == 3 * HSN, "half-space rows of the workgroup state");
     constexpr bool LDSL = LR >= Dims<M>::NL;  // the factor lives in LDS
-    static_assert(WAVE1 || Shared<T, BLOCK, HSR, LR>::XR == SCP_MAX_NX, "LDS exchange needs full rows");
+    static_assert(WAVE1 || Shared<T, BLOCK, HSR, LR>::XR == PERSIST_MAX_NX, "LDS exchange needs full rows");
+    static_assert(M::NX <= PERSIST_MAX_NX && M::C <= PERSIST_MAX_C, "model too large for the workgroup state");
     T sig[HSN], kap[HSN];
 #pragma unroll
     for (int q = 0; q < HSN; ++q) sig[q] = kap[q] = T(0);
@@ -216,8 +217,8 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
     if (t == 0) sh.sync_fail = 0;
     if constexpr (!WAVE1) {
-        if (t < 2 * SCP_MAX_NX) sh.ex[t][BLOCK] = T(0);
-        if (t < SCP_MAX_NX) sh.fw[t][0] = T(0);
+        if (t < 2 * PERSIST_MAX_NX) sh.ex[t][BLOCK] = T(0);
+        if (t < PERSIST_MAX_NX) sh.fw[t][0] = T(0);
     }
     if (t < BLOCK) sh.gxm[t] = -1;
 

@@ -7,6 +7,22 @@
 
 namespace scp {
 
+// every plane block holds the largest model (6-DOF quadrotor with SCP_MAX_OBS obstacles)
+using QMax = Quad6<SCP_MAX_OBS>;
+static_assert(PL_UBAR - PL_XBAR >= QMax::NX && PL_X - PL_UBAR >= QMax::NU, "nominal blocks");
+static_assert(PL_U - PL_X >= QMax::NX && PL_Z - PL_U >= QMax::NU && PL_LAM - PL_Z >= QMax::NX, "iterate blocks");
+static_assert(PL_MU - PL_LAM >= QMax::NX && PL_DD - PL_MU >= QMax::NX && PL_CP - PL_DD >= QMax::NX, "iterate blocks");
+static_assert(PL_DU - PL_CP >= MAX_C && PL_AR - PL_DU >= MAX_C && QMax::C <= MAX_C && Quad<SCP_MAX_OBS>::C <= MAX_C,
+              "mirror blocks");
+static_assert(PL_B - PL_AR >= QMax::NX * QMax::NXR && PL_D - PL_B >= QMax::NX * QMax::NU && PL_L - PL_D >= QMax::NX,
+              "linearization blocks");
+static_assert(PL_LO - PL_L >= Dims<QMax>::NL && PL_HI - PL_LO >= QMax::NN && PL_HS - PL_HI >= QMax::NN, "factor, box");
+static_assert(PL_G0 - PL_HS >= QMax::NHS && PL_DZ - PL_G0 >= QMax::NX && PL_SP - PL_DZ >= QMax::NX, "half-spaces");
+static_assert(PL_RP - PL_SP >= QMax::NN && PL_XG - PL_MER >= 8 && NPLANES - PL_UG >= QMax::NU &&
+              PL_UG - PL_XG >= QMax::NX, "residual, merit, guess blocks");
+// node 0 of a consensus group parks its u-slot copies in the merit block
+static_assert(QMax::NU + 3 <= 8 && Mars::NU + 4 <= 8, "u-slot stash");
+
 template <int NV, class T>
 __device__ __forceinline__ void ldp(const T* __restrict__ pl, int P, int g, T* v) {
 #pragma unroll
@@ -47,7 +63,7 @@ __device__ __forceinline__ void load_const(const Dev<T>& dv, int g, NodeConst<M,
     ldp<NX>(PL(dv, PL_D), P, g, nc.d);
     ldp<NN>(PL(dv, PL_LO), P, g, nc.lo);
     ldp<NN>(PL(dv, PL_HI), P, g, nc.hi);
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    if constexpr (M::QL) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
     ldp<NX>(PL(dv, PL_G0), P, g, nc.g0);
 }
 
@@ -132,7 +148,7 @@ __global__ __launch_bounds__(256) void k_lin(Dev<T> dv, KParams<T> kp) {
     stp<NX>(PL(dv, PL_D), P, g, nc.d);
     stp<M::NN>(PL(dv, PL_LO), P, g, nc.lo);
     stp<M::NN>(PL(dv, PL_HI), P, g, nc.hi);
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) stp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    if constexpr (M::QL) stp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
     stp<NX>(PL(dv, PL_G0), P, g, nc.g0);
     stp<NX>(PL(dv, PL_X), P, g, s.x);
     stp<NU>(PL(dv, PL_U), P, g, s.u);
@@ -202,7 +218,7 @@ __global__ __launch_bounds__(256) void k_step234(Dev<T> dv, KParams<T> kp, int c
     NodeConst<M, T> nc;
     ldp<NN>(PL(dv, PL_LO), P, g, nc.lo);
     ldp<NN>(PL(dv, PL_HI), P, g, nc.hi);
-    if constexpr (M::ID == SCP_MODEL_QUAD_PM) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    if constexpr (M::QL) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
     NodeState<M, T> s;
     ldp<NX>(PL(dv, PL_X), P, g, s.x);
     ldp<NU>(PL(dv, PL_U), P, g, s.u);
@@ -550,7 +566,21 @@ __global__ __launch_bounds__(256) void k_reset_state(Dev<T> dv) {
     for (int r = 0; r < SCP_MAX_NX; ++r) PL(dv, PL_XBAR)[(size_t)r * P + g] = PL(dv, PL_XG)[(size_t)r * P + g];
 #pragma unroll
     for (int r = 0; r < SCP_MAX_NU; ++r) PL(dv, PL_UBAR)[(size_t)r * P + g] = PL(dv, PL_UG)[(size_t)r * P + g];
-    for (int k = PL_X; k < PL_AR; ++k) dv.planes[(size_t)k * P + g] = T(0);   // x, u, z, lambda, mu, d_dyn, copies, duals
+    // x, u, z, lambda, mu, d_dyn, copies, duals: the slots of this node's model
+    const int model = dv.traj[dv.node_traj[g] * TR_FIELDS + TR_MODEL];
+    const int nx = model_nx(model), nu = model_nu(model), nc = model_slots(model);
+    for (int k = 0; k < nx; ++k) {
+        PL(dv, PL_X)[(size_t)k * P + g] = T(0);
+        PL(dv, PL_Z)[(size_t)k * P + g] = T(0);
+        PL(dv, PL_LAM)[(size_t)k * P + g] = T(0);
+        PL(dv, PL_MU)[(size_t)k * P + g] = T(0);
+        PL(dv, PL_DD)[(size_t)k * P + g] = T(0);
+    }
+    for (int k = 0; k < nu; ++k) PL(dv, PL_U)[(size_t)k * P + g] = T(0);
+    for (int k = 0; k < nc; ++k) {
+        PL(dv, PL_CP)[(size_t)k * P + g] = T(0);
+        PL(dv, PL_DU)[(size_t)k * P + g] = T(0);
+    }
 }
 
 // gather one field of every node into a dense [node][width] array
@@ -562,31 +592,30 @@ __global__ __launch_bounds__(256) void k_gather(Dev<T> dv, int plane, int width,
     const int model = dv.traj[tr * TR_FIELDS + TR_MODEL];
     const int P = dv.P;
     T* o = out + (size_t)g * width;
+    const int nx = model_nx(model), nu = model_nu(model), nxr = nx - 3;
     if (mode == 1) {
-        // dense A from the stored non-unit columns
-        const int nx = model == SCP_MODEL_QUAD_PM ? 6 : 7, nxr = nx - 3;
+        // dense A (SCP_MAX_NX x SCP_MAX_NX, the model's nx x nx block leading) from the stored
+        // non-unit columns
         const int N = dv.traj[tr * TR_FIELDS + TR_N], i = g - dv.traj[tr * TR_FIELDS + TR_OFF];
-        for (int r = 0; r < 7; ++r)
-            for (int c = 0; c < 7; ++c) {
+        for (int r = 0; r < SCP_MAX_NX; ++r)
+            for (int c = 0; c < SCP_MAX_NX; ++c) {
                 T v = T(0);
                 if (r < nx && c < nx) {
                     if (c < 3) v = (i < N && r == c) ? T(1) : T(0);
                     else v = PL(dv, PL_AR)[(size_t)(r * nxr + (c - 3)) * P + g];
                 }
-                o[r * 7 + c] = v;
+                o[r * SCP_MAX_NX + c] = v;
             }
     } else if (mode == 2) {
-        const int nx = model == SCP_MODEL_QUAD_PM ? 6 : 7, nu = nx == 6 ? 3 : 4;
-        for (int r = 0; r < 7; ++r)
-            for (int c = 0; c < 4; ++c)
-                o[r * 4 + c] = (r < nx && c < nu) ? PL(dv, PL_B)[(size_t)(r * nu + c) * P + g] : T(0);
+        for (int r = 0; r < SCP_MAX_NX; ++r)
+            for (int c = 0; c < SCP_MAX_NU; ++c)
+                o[r * SCP_MAX_NU + c] = (r < nx && c < nu) ? PL(dv, PL_B)[(size_t)(r * nu + c) * P + g] : T(0);
     } else if (mode == 3) {
-        // box bounds: x part then u part at fixed offsets 0..6 / 7..10
-        const int nx = model == SCP_MODEL_QUAD_PM ? 6 : 7, nu = nx == 6 ? 3 : 4;
-        for (int k = 0; k < 11; ++k) {
+        // box bounds: x part then u part at fixed offsets 0..SCP_MAX_NX-1 / SCP_MAX_NX..
+        for (int k = 0; k < SCP_MAX_NX + SCP_MAX_NU; ++k) {
             T v = T(0);
-            if (k < 7 && k < nx) v = PL(dv, plane)[(size_t)k * P + g];
-            if (k >= 7 && k - 7 < nu) v = PL(dv, plane)[(size_t)(nx + k - 7) * P + g];
+            if (k < SCP_MAX_NX && k < nx) v = PL(dv, plane)[(size_t)k * P + g];
+            if (k >= SCP_MAX_NX && k - SCP_MAX_NX < nu) v = PL(dv, plane)[(size_t)(nx + k - SCP_MAX_NX) * P + g];
             o[k] = v;
         }
     } else {
@@ -610,6 +639,10 @@ hipError_t launch_plain(PlainOp op, const Dev<T>& dv, const KParams<T>& kp, int 
             else launch_model(Quad<8>{});
         }
         if (models & 2) launch_model(Mars{});
+        if (models & 4) {
+            if (kmax <= 4) launch_model(Quad6<4>{});
+            else launch_model(Quad6<8>{});
+        }
     };
     switch (op) {
         case PlainOp::Lin:

@@ -15,18 +15,18 @@ template <class M, class T>
 __device__ void shift_traj(T* __restrict__ pl, const int P, const int off, const int N, const int K, const bool ball) {
     auto at = [&](int plane, int i) -> T& { return pl[(size_t)plane * P + off + i]; };
     for (int i = 0; i < N; ++i) {
-        for (int r = 0; r < SCP_MAX_NX; ++r) {
+        for (int r = 0; r < M::NX; ++r) {
             at(PL_XBAR + r, i) = at(PL_XBAR + r, i + 1);
             at(PL_LAM + r, i) = at(PL_LAM + r, i + 1);
             at(PL_MU + r, i) = at(PL_MU + r, i + 1);
         }
         const bool urow = i + 1 < N;  // control rows 0..N-1: row i takes row i+1 for i < N-1
         if (urow)
-            for (int r = 0; r < SCP_MAX_NU; ++r) at(PL_UBAR + r, i) = at(PL_UBAR + r, i + 1);
+            for (int r = 0; r < M::NU; ++r) at(PL_UBAR + r, i) = at(PL_UBAR + r, i + 1);
         for (int q = 0; q < M::C; ++q)
             if (!slot_is_u<M>(q) || urow) at(PL_DU + q, i) = at(PL_DU + q, i + 1);
     }
-    for (int r = 0; r < SCP_MAX_NX; ++r) {
+    for (int r = 0; r < M::NX; ++r) {
         at(PL_LAM + r, 0) = T(0);
         at(PL_MU + r, 0) = T(0);
     }
@@ -80,7 +80,7 @@ __global__ void k_admit(Dev<T> dv, int block, const unsigned char* __restrict__ 
                 pl[(size_t)(PL_MU + c) * P + g] = T(0);
             }
             for (int c = 0; c < SCP_MAX_NU; ++c) pl[(size_t)(PL_UBAR + c) * P + g] = ug[(size_t)k * SCP_MAX_NU + c];
-            for (int c = 0; c < 36; ++c) pl[(size_t)(PL_DU + c) * P + g] = T(0);
+            for (int c = 0; c < MAX_C; ++c) pl[(size_t)(PL_DU + c) * P + g] = T(0);
         }
         return;
     }

@@ -8,7 +8,8 @@ other code with the other.
 
 Every instance is a ``dict`` with the physical problem in solver units:
 
-``model``       1 = quadrotor point mass (nx=6, nu=3), 2 = 3-DOF powered descent (nx=7, nu=4)
+``model``       1 = quadrotor point mass (nx=6, nu=3), 2 = 3-DOF powered descent (nx=7, nu=4),
+                3 = 6-DOF quadrotor (nx=13: p, v, quaternion, body rates; nu=4: thrust, torques)
 ``N``           number of intervals (N+1 state nodes, N control nodes)
 ``h``           step size T/N
 ``x_init``      initial state (boundary condition x_0 = x_init, eq. (ocp))
@@ -18,7 +19,8 @@ Every instance is a ``dict`` with the physical problem in solver units:
 ``x_lo``/``x_hi``/``u_lo``/``u_hi``  hard bounds (+-inf where absent)
 ``u_ball``      radius of the control ball ||u|| <= u_ball (quadrotor; inf = none)
 ``delta``       trust-region radius (l-inf box around the nominal)
-``drag``, ``mscale``, ``grav``  quadrotor drag coefficient, mass scale, gravity
+``drag``, ``mscale``, ``grav``  quadrotor drag coefficient, mass scale (6-DOF: the mass), gravity
+``inertia``     (3,), 6-DOF quadrotor principal moments of inertia
 ``obstacles``   (K, 4) obstacle centres and radii (quadrotor)
 ``cyl``         (K,) bool, optional: obstacle j is a vertical cylinder (axis along z through
                 its centre) instead of a sphere
@@ -40,8 +42,9 @@ import numpy as np
 
 QUAD = 1
 MARS = 2
-NX = {QUAD: 6, MARS: 7}
-NU = {QUAD: 3, MARS: 4}
+QUAD6 = 3
+NX = {QUAD: 6, MARS: 7, QUAD6: 13}
+NU = {QUAD: 3, MARS: 4, QUAD6: 4}
 KMAX = 8  # most obstacles one quadrotor instance may carry
 
 G_EARTH = 9.81
@@ -140,6 +143,93 @@ def mars_instance(config: int, instance: int, N: int = 60, tf: float = 50.0,
         gvec=np.array([0.0, 0.0, -gz]), glide_tan=math.tan(math.radians(86.0)),
         x_guess=x_guess, u_guess=u_guess, group=-1,
     )
+
+
+# 6-DOF quadrotor (Sec. IV-A.1): mass 1 kg, g = 9.81 m/s^2, thrust in [0, 20] N, body torques in
+# [-5, 5] N m.  The paper takes the rest of the vehicle from a simulator it cites; the principal
+# moments of inertia here are a stated choice for a 1 kg quadrotor.
+Q6_MASS = 1.0
+Q6_INERTIA = np.array([0.02, 0.02, 0.04])
+Q6_START = np.array([-5.0, -5.0, 2.0])
+Q6_GOAL = np.array([5.0, 5.0, 2.0])
+# the parameter-study scene: three spheres (radii 1.2..1.5 m) across the direct path
+Q6_SCENE_OBSTACLES = np.array([[-2.0, -1.6, 2.0, 1.2],
+                               [0.3, 0.0, 2.2, 1.5],
+                               [2.4, 2.0, 1.8, 1.3]])
+
+
+def quad6_instance(obstacles: np.ndarray, N: int = 50, T: float = 6.0, delta: float = 1.0,
+                   start: np.ndarray = Q6_START, goal: np.ndarray = Q6_GOAL,
+                   guess_noise: float = 0.0, rng: np.random.Generator | None = None) -> dict:
+    """6-DOF quadrotor from hover at ``start`` to ``goal`` with zero velocity there (both fixed:
+    S selects position and velocity), spherical obstacles, cost sum ||u||^2 (R = 2 I).
+
+    Initial guess: straight-line positions, constant velocity (goal - start)/T, level attitude
+    q = (1, 0, 0, 0), zero rates, hover thrust m g; with ``guess_noise`` > 0 the interior
+    positions and velocities get seeded Gaussian noise of that standard deviation
+    ("noise-initialized" trajectories).
+    """
+    nx, nu = 13, 4
+    x0 = np.zeros(nx)
+    x0[:3] = start
+    x0[6] = 1.0
+    xg = np.zeros(nx)
+    xg[:3] = goal
+    xg[6] = 1.0
+    s = np.linspace(0.0, 1.0, N + 1)[:, None]
+    x_guess = np.zeros((N + 1, nx))
+    x_guess[:, :3] = start + s * (goal - start)
+    x_guess[:, 3:6] = (goal - start) / T
+    x_guess[:, 6] = 1.0
+    x_guess[0] = x0
+    if guess_noise > 0.0:
+        g = rng if rng is not None else np.random.default_rng(0)
+        x_guess[1:N, :6] += guess_noise * g.standard_normal((N - 1, 6))
+    u_guess = np.tile(np.array([Q6_MASS * G_EARTH, 0.0, 0.0, 0.0]), (N, 1))
+    inf = math.inf
+    t_mask = np.array([True] * 6 + [False] * 7)
+    return dict(
+        model=QUAD6, N=N, h=T / N, nx=nx, nu=nu,
+        x_init=x0, x_target=xg, t_mask=t_mask,
+        Qr=np.zeros(nx), R=np.full(nu, 2.0),
+        Qn=np.zeros(nx), qn=np.zeros(nx), cN=0.0,
+        x_lo=np.full(nx, -inf), x_hi=np.full(nx, inf),
+        u_lo=np.array([0.0, -5.0, -5.0, -5.0]), u_hi=np.array([20.0, 5.0, 5.0, 5.0]), u_ball=inf,
+        delta=delta, drag=0.0, mscale=Q6_MASS, grav=G_EARTH, inertia=Q6_INERTIA.copy(),
+        obstacles=np.asarray(obstacles, dtype=float).reshape(-1, 4).copy(),
+        alpha=0.0, gvec=np.array([0.0, 0.0, -G_EARTH]), glide_tan=inf,
+        x_guess=x_guess, u_guess=u_guess, group=-1,
+    )
+
+
+def quad6_scene(N: int = 50, T: float = 6.0) -> dict:
+    """The parameter-study scene of Sec. IV-A.2 (N = 50, 6 s, three obstacles)."""
+    return quad6_instance(Q6_SCENE_OBSTACLES, N=N, T=T)
+
+
+def quad6_benchmark_instance(instance: int, N: int = 40, T: float = 6.0, K: int = 3) -> dict:
+    """One trajectory of the scalability benchmark of Sec. IV-A.3: K random spheres (radii
+    U[1, 2] m) with centres drawn around the straight path (a point U[0.2, 0.8] of the way plus
+    U[-1.5, 1.5]^3), redrawn while start or goal lies within r + 0.25; noise-initialized guess
+    (standard deviation 0.1).  Draw order: per obstacle s, offset (3), radius; then the guess
+    noise."""
+    g = _rng(5, instance)
+    obs = np.zeros((K, 4))
+    for j in range(K):
+        while True:
+            sj = g.uniform(0.2, 0.8)
+            c = Q6_START + sj * (Q6_GOAL - Q6_START) + g.uniform(-1.5, 1.5, 3)
+            r = g.uniform(1.0, 2.0)
+            if (np.linalg.norm(Q6_START - c) >= r + 0.25) and (np.linalg.norm(Q6_GOAL - c) >= r + 0.25):
+                break
+        obs[j, :3] = c
+        obs[j, 3] = r
+    return quad6_instance(obs, N=N, T=T, guess_noise=0.1, rng=g)
+
+
+def config5(n_inst: int = 1000, first: int = 0) -> list[dict]:
+    """6-DOF quadrotor batch of the scalability benchmark: N = 40, three random obstacles."""
+    return [quad6_benchmark_instance(i) for i in range(first, first + n_inst)]
 
 
 def with_scenarios(base: dict, S: int, rng: np.random.Generator, group: int) -> list[dict]:

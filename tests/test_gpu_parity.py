@@ -43,6 +43,8 @@ def _ragged_quads(n, seed_base=0, K=None):
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 2e-6)])
 def test_linearize_and_convexify(B, prec, tol):
     insts = _ragged_quads(6) + [scpgen.mars_instance(2, i, N=9 + i) for i in range(3)]
+    insts += [scpgen.quad6_benchmark_instance(i, N=7 + 3 * i) for i in range(3)]
+    insts[-1]["x_guess"][:, 6:10] *= 1.3      # off the unit sphere: the normalized thrust direction
     _say("linearize", prec, len(insts))
     prob = B.Problem(insts, precision=prec)
     prob.linearize(B.admm_params(1.0))
@@ -52,14 +54,17 @@ def test_linearize_and_convexify(B, prec, tol):
         nx, nu, N = inst["nx"], inst["nu"], inst["N"]
         Ao, Bo, do = oracle.linearize(inst, inst["x_guess"], inst["u_guess"])
         o = prob.offsets[t]
-        assert rel_err(A[o:o + N].reshape(N, 7, 7)[:, :nx, :nx], Ao) < tol
-        assert rel_err(Bm[o:o + N].reshape(N, 7, 4)[:, :nx, :nu], Bo) < tol
+        assert rel_err(A[o:o + N].reshape(N, B.MAX_NX, B.MAX_NX)[:, :nx, :nx], Ao) < tol
+        assert rel_err(Bm[o:o + N].reshape(N, B.MAX_NX, B.MAX_NU)[:, :nx, :nu], Bo) < tol
         assert rel_err(d[o:o + N, :nx], do) < tol
         g = oracle.convexify(inst, inst["x_guess"], inst["u_guess"], inst["delta"])
         assert rel_err(lo[o:o + N + 1, :nx], g[0].lo) < tol and rel_err(hi[o:o + N + 1, :nx], g[0].hi) < tol
-        assert rel_err(lo[o:o + N, 7:7 + nu], g[1].lo[:N]) < tol and rel_err(hi[o:o + N, 7:7 + nu], g[1].hi[:N]) < tol
-        if inst["model"] == 1:
-            for j, grp in enumerate(g[3:]):
+        ub = slice(B.MAX_NX, B.MAX_NX + nu)
+        assert rel_err(lo[o:o + N, ub], g[1].lo[:N]) < tol and rel_err(hi[o:o + N, ub], g[1].hi[:N]) < tol
+        if inst["model"] in (1, 3):
+            hsg = [grp for grp in g if grp.kind == "halfspace"]
+            assert len(hsg) == inst["obstacles"].shape[0]
+            for j, grp in enumerate(hsg):
                 assert rel_err(hs[o + 1:o + N + 1, 4 * j:4 * j + 3], grp.a[1:]) < tol
                 assert rel_err(hs[o + 1:o + N + 1, 4 * j + 3], grp.b[1:]) < tol
     prob.close()

@@ -1,0 +1,165 @@
+"""GPU parity of the 6-DOF quadrotor model (Sec. IV-A.1; plain form), through the C ABI, against
+the FP64 oracle.
+
+* ADMM at fixed iteration counts on ragged horizons (several 256-node blocks and a ragged tail,
+  obstacle counts 0..8): every block of iterates in FP64 to 1e-9 and in FP32 to 1e-4.
+* The parameter-study scene (Sec. IV-A.2: N = 50, 20 SCP x 200 ADMM, rho geometric from 1e2 to
+  1e3) in FP64: every block and the info record (cost, defect, violation, boundary error) to 1e-9.
+* The scalability-benchmark batch at its full size (Sec. IV-A.3: 1000 trajectories, N = 40,
+  three random obstacles) solved once in FP64 at the bench budget: sampled trajectories against
+  the oracle to 1e-9; and in FP32 the first SCP iteration of sampled trajectories to 1e-4 (at
+  the full budget the SCP map amplifies FP32 rounding far beyond it, as for the other models)
+  and every FP32 trajectory bit-identical alone and in the batch.
+* The persistent form and the request server refuse this model with an error, not a fallback.
+
+The mirror copies of this model sit in the quadrotor layout [x box 13][u box 4][ball 3][half-
+space k: 3 each]; the ball slots never hold a group and must read 0.  They are dropped before the
+comparison with the oracle, which has no ball group for this model.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scpgen
+from _parity import compare, gpu_fields, oracle_linearize_admm, oracle_scp, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+TOL32 = 1e-4
+BALL = [17, 18, 19]
+SCHED = dict(rho=100.0, rho_final=1e3)
+OSCHED = dict(rho_eq=100.0, rho_dyn=100.0, rho_geo=100.0, rho_final=1e3)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B(lib):
+    from paper_2603_10711_amd import binding
+    return binding
+
+
+def _fields(prob):
+    f = gpu_fields(prob)
+    for k in ("copy", "dual"):
+        assert np.all(f[k][:, BALL] == 0.0), k
+        f[k] = np.delete(f[k], BALL, axis=1)
+    return f
+
+
+def _ragged(n, base=0):
+    out = []
+    for i in range(n):
+        N = 4 + (11 * i) % 37
+        d = scpgen.quad6_benchmark_instance(base + i, N=N, K=3)
+        K = i % 9
+        obs = np.tile(d["obstacles"], (3, 1))[:K]
+        d["obstacles"] = obs
+        out.append(d)
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_admm_fixed_iterations(B, prec, tol):
+    insts = _ragged(12)
+    _say("quad6 admm", prec, [d["N"] for d in insts], sum(d["N"] + 1 for d in insts))
+    prob = B.Problem(insts, precision=prec)
+    prob.linearize(B.admm_params(1.0))
+    prob.admm(B.admm_params(1.0, 17))
+    prob.admm(B.admm_params(1.0, 12))
+    f = _fields(prob)
+    trajs = [oracle_linearize_admm(d, 29) for d in insts]
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < tol
+    prob.close()
+
+
+def test_parameter_study_scene_fp64(B):
+    insts = [scpgen.quad6_scene()]
+    _say("quad6 scene fp64 20x200")
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(20, 200, form="plain", **SCHED))
+    f = _fields(prob)
+    _, _, info = prob.result()
+    trajs, oinfo = oracle_scp(insts, 20, 200, **OSCHED)
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < TOL64
+    inf = prob.info_dicts(info.cpu().numpy())[0]
+    d, t = insts[0], trajs[0]
+    _say("defect", inf["defect"], "cost", inf["cost"], "viol", inf["viol"], "bnd", inf["bnd_err"])
+    assert abs(inf["cost"] - oracle.cost(d, t.xbar, t.ubar)) <= TOL64 * abs(inf["cost"])
+    assert abs(inf["defect"] - oracle.defect(d, t.xbar, t.ubar)) <= TOL64
+    assert abs(inf["viol"] - oracle.violation(d, t.xbar, t.ubar)) <= TOL64
+    assert abs(inf["bnd_err"] - oracle.boundary_error(d, t.xbar)) <= TOL64
+    assert inf["admm_iters"] == oinfo[0]["admm_iters"]
+    assert inf["defect"] < 0.02     # the schedule converges this scene
+    prob.close()
+
+
+SAMPLE = [0, 137, 999]
+
+
+def test_benchmark_batch_fullsize_fp64_samples(B):
+    insts = scpgen.config5(1000)
+    _say("quad6 1000 x 41 fp64 20x200")
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(20, 200, form="plain", **SCHED))
+    x, u, info = (a.cpu().numpy() for a in prob.result())
+    for i in SAMPLE:
+        (t,), _ = oracle_scp([insts[i]], 20, 200, **OSCHED)
+        ex = rel_err(prob.split(x, i, 13), t.xbar)
+        eu = rel_err(prob.split(u, i, 4, True), t.ubar)
+        _say(i, ex, eu)
+        assert max(ex, eu) < TOL64
+        assert abs(info[i, 6] - oracle.defect(insts[i], t.xbar, t.ubar)) <= TOL64
+    prob.close()
+
+
+def test_benchmark_batch_fullsize_fp32(B):
+    insts = scpgen.config5(1000)
+    _say("quad6 1000 x 41 fp32 first SCP iteration")
+    prob = B.Problem(insts, precision="f32")
+    prob.solve(B.scp_params(1, 200, form="plain", **SCHED))
+    f = _fields(prob)
+    for i in SAMPLE:
+        (t,), _ = oracle_scp([insts[i]], 1, 200, **OSCHED)
+        worst = compare(prob, f, [insts[i]], [t], idx=[i])
+        _say(i, worst)
+        assert max(worst.values()) < TOL32
+    # full budget: every trajectory alone equals its row in the batch, bit for bit
+    prob.reset()
+    prm = B.scp_params(20, 200, form="plain", **SCHED)
+    prob.solve(prm)
+    x, u, info = (a.cpu().numpy() for a in prob.result())
+    for i in SAMPLE:
+        one = B.Problem([insts[i]], precision="f32")
+        one.solve(prm)
+        x1, u1, info1 = (a.cpu().numpy() for a in one.result())
+        np.testing.assert_array_equal(x1, prob.split(x, i))
+        np.testing.assert_array_equal(u1[:insts[i]["N"]], prob.split(u, i, controls=True))
+        np.testing.assert_array_equal(info1[0], info[i])
+        one.close()
+    defect = info[:, 6]
+    _say("fp32 defect p50", float(np.median(defect)), "p90", float(np.percentile(defect, 90)))
+    assert np.all(np.isfinite(defect)) and float(np.median(defect)) < 0.05
+    prob.close()
+
+
+def test_persistent_form_and_server_refuse_the_model(B):
+    insts = scpgen.config5(2)
+    prob = B.Problem(insts, precision="f32")
+    with pytest.raises(RuntimeError, match="plain form"):
+        prob.solve(B.scp_params(2, 10, form="persistent"))
+    prob.close()
+    srv = B.Server(B.scp_params(2, 10), precision="f32", block=256, max_nodes=1 << 12, max_traj=16, max_wg=16,
+                   max_span=4, max_requests=4)
+    try:
+        with pytest.raises(RuntimeError):
+            srv.submit(insts, session=-1)
+    finally:
+        srv.close()
