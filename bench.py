@@ -1,10 +1,12 @@
 """Benchmark of the SCP + consensus-ADMM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096|mix2048|serve|mpc]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096|mix2048|quad6_1000|serve|mpc]
                     [--no-cpu-baseline] [--plain-steps P] [--sched-steps S]
 
 ``--plain-steps 0`` and ``--sched-steps 0`` leave out the plain-form and penalty-schedule legs
 (profiled runs do, so that every persistent-kernel dispatch in them is the configured one).
+``--scp-iters`` / ``--admm-iters`` override the budget for counter runs of the plain form, whose
+per-dispatch counters do not depend on it (the JSON line then names the overridden budget).
 
 One step = one full batched solve of the workload from its initial guess (reset of the resident
 state, then linearization, convexification, factorization, ADMM iterations, acceptance and metrics
@@ -66,6 +68,12 @@ def workload(name: str):
                          "buffered cylinder through a stochastic crosswind corridor, 15 scenarios x N=30, "
                          "10 SCP x 100 ADMM per MPC step, FP32, linear disturbance observer, warm start with the "
                          "measured state")
+    if name == "quad6_1000":
+        return dict(name=name, insts=scpgen.config5(1000), scp=20, admm=200, rho=100.0, rho_final=1e3, prec="f32",
+                    plain_only=True,
+                    desc="6-DOF quadrotor batch (13 states, quaternion attitude, thrust and body torques): 1000 "
+                         "instances, N=40, T=6 s, 3 random obstacles, noise-initialized, 20 SCP x 200 ADMM, rho "
+                         "1e2 -> 1e3 geometric, trust region 1, FP32, plain form")
     if name == "mix2048":
         return dict(name=name, insts=scpgen.config3(2048), scp=15, admm=200, rho=1.0, prec="f32", eps=1e-4,
                     cadences=(1, 5, 10, 25),
@@ -86,6 +94,10 @@ def flops_per_node_iter(model: int, K: int) -> int:
         nx, nxr, nu = 6, 3, 3
         C = 12 + 3 * K
         s3 = 4 * (nx + nu) + 17 + 20 * K
+    elif model == scpgen.QUAD6:
+        nx, nxr, nu = 13, 10, 4
+        C = 17 + 3 * K
+        s3 = 4 * (nx + nu) + 20 * K
     else:
         nx, nxr, nu = 7, 4, 4
         C = 18
@@ -93,6 +105,23 @@ def flops_per_node_iter(model: int, K: int) -> int:
     n = nx + nu
     s1 = 3 * nx + 2 * nx * nxr + 2 * nx * nu + 4 * nx + 3 * C + 2 * n * n + 2 * nx * nxr + 2 * nx * nu + 2 * nx
     return s1 + 6 * nx + s3 + 6 * nx + 3 * C
+
+
+def bytes_per_node_iter(model: int, K: int, w: int = 4) -> int:
+    """Algorithmic HBM bytes of one plain-form ADMM iteration at one node (state streamed from
+    HBM, neighbour reads served by cache): w (const + 2 mut) with
+    const = n(n+1)/2 [factor] + nx n [A, B] + nx [d] + n [g0] + 2 n [box] + 4 K [half-spaces],
+    mut = 3 nx [z, lambda, mu] + 2 C [mirror copies and duals, present groups]."""
+    nx, nu = scpgen.NX[model], scpgen.NU[model]
+    n = nx + nu
+    if model == scpgen.MARS:
+        C, hs = 18, 0
+    else:
+        C = nx + nu + (3 if model == scpgen.QUAD else 0) + 3 * K
+        hs = 4 * K
+    const = n * (n + 1) // 2 + nx * n + nx + n + 2 * n + hs
+    mut = 3 * nx + 2 * C
+    return w * (const + 2 * mut)
 
 
 def kernel_source_hash() -> str:
@@ -105,10 +134,10 @@ def kernel_source_hash() -> str:
 
 
 def _oracle_worker(args):
-    inst, scp_iters, admm_iters, rho, check_every, eps = args
+    inst, scp_iters, admm_iters, rho, check_every, eps, rho_final = args
     import oracle
     p = oracle.default_params(scp_iters=scp_iters, admm_iters=admm_iters, rho_eq=rho, rho_dyn=rho, rho_geo=rho,
-                              check_every=check_every, eps_p=eps, eps_d=eps)
+                              check_every=check_every, eps_p=eps, eps_d=eps, rho_final=rho_final)
     t = oracle.init_traj(inst)
     oracle.scp.scp_group([t], p)
     return oracle.defect(inst, t.xbar, t.ubar)
@@ -145,13 +174,15 @@ def cpu_baseline(wl, sample: int, cores: int) -> dict:
     import multiprocessing as mp
     insts = wl["insts"][:sample]
     eps = wl.get("eps", 0.0)
-    args = [(d, wl["scp"], wl["admm"], wl["rho"], 10 if eps > 0 else 0, eps) for d in insts]
+    args = [(d, wl["scp"], wl["admm"], wl["rho"], 10 if eps > 0 else 0, eps, wl.get("rho_final", 0.0)) for d in insts]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         defects = pool.map(_oracle_worker, args, chunksize=1)
     dt = time.perf_counter() - t0
     stop = f", residual stop {eps:g} tested every 10 iterations" if eps > 0 else ""
+    if wl.get("rho_final", 0.0) > 0:
+        stop += f", rho {wl['rho']:g} -> {wl['rho_final']:g}"
     return {"value": round(sample / dt, 3), "unit": "solves/s", "cores": cores, "kind": "oracle",
             "sample": f"first {sample} instances of the workload, {wl['scp']}x{wl['admm']} budget{stop}, FP64 NumPy, "
                       f"{cores} single-threaded worker processes, {dt:.1f} s wall",
@@ -171,6 +202,93 @@ def load_pmc(wl_name: str, khash: str):
     if d.get("kernel_hash") != khash:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def plain_main(a, wl, cpu):
+    """A workload that only the plain form runs (the 6-DOF quadrotor): every step is a fresh
+    solve (scp_reset, then scp_solve replayed as one hipGraph on its own stream), timed with HIP
+    events on that stream.  Roofline: the plain ADMM kernels stream the node state from HBM, so
+    the bound is HBM bandwidth; the unit is one solve (one graph launch) and the algorithmic bytes
+    are node-iterations x bytes_per_node_iter."""
+    import torch
+    from paper_2603_10711_amd import binding as B
+
+    torch.cuda.init()
+    insts = wl["insts"]
+    stream = torch.cuda.Stream()
+    prob = B.Problem(insts, precision=wl["prec"], device="cuda:0", stream=stream)
+    prm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], rho_final=wl.get("rho_final", 0.0), form="plain",
+                       graph=True)
+    for _ in range(max(1, a.warmup)):
+        prob.reset()
+        prob.solve(prm)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        starts[k].record(stream)
+        prob.reset()
+        prob.solve(prm)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([st.elapsed_time(e) for st, e in zip(starts, ends)])
+    _, _, info = prob.result()
+    info = info.cpu().numpy()
+    prob.close()
+    n = len(insts)
+    defect, viol, bnd = info[:, 6], info[:, 8], info[:, 9]
+    good = int(np.sum(defect <= 1e-5))
+    success = int(np.sum((defect < 1e-2) & (viol < 1e-3) & (bnd < 0.1)))
+    iters = info[:, 0]
+    node_iters = float(sum((d["N"] + 1) * it for d, it in zip(insts, iters)))
+    nbytes = float(sum((d["N"] + 1) * it * bytes_per_node_iter(d["model"], d["obstacles"].shape[0])
+                       for d, it in zip(insts, iters)))
+    flops = float(sum((d["N"] + 1) * it * flops_per_node_iter(d["model"], d["obstacles"].shape[0])
+                      for d, it in zip(insts, iters)))
+    kernel_ms = float(np.mean(step_ms))
+    achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+    traffic = load_pmc_plain(wl["name"], kernel_source_hash())
+    out = {
+        "metric": METRIC, "value": round(n * a.steps / wall, 1), "unit": "solves/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(wall / a.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if wl["prec"] == "f32" else "f64",
+        "data": "synthetic (seeded generator of the workload's shapes and distributions)",
+        "config": {"workload": wl["desc"], "form": "plain (hipGraph per solve)", "instances": n,
+                   "nodes": int(sum(d["N"] + 1 for d in insts))},
+        "goodput_solves_per_s": round(good * a.steps / wall, 1),
+        "defect_le_1e-5": f"{good}/{n}",
+        "success": f"{success}/{n}",
+        "success_rule": "max defect < 1e-2, obstacle penetration < 1e-3 m, boundary error < 0.1",
+        "defect_p50": float(np.median(defect)), "defect_p90": float(np.percentile(defect, 90)),
+        "latency_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "node_admm_iters_per_s": round(node_iters * a.steps / wall, 1),
+        "achieved_tflops": round(flops / (kernel_ms * 1e-3) / 1e12, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "one plain solve (hipGraph of k_lin, k_step1, k_step234, k_resid, k_acc_*)",
+                     "bytes_per_launch": nbytes, "kernel_ms": round(kernel_ms, 4)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def load_pmc_plain(wl_name: str, khash: str):
+    """HBM bytes of one plain solve from the committed rocprofv3 counter summary, if the kernel
+    sources are unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_plain_{wl_name}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != khash:
+        return None
+    return d.get("hbm_bytes_per_solve")
 
 
 def serve_main(a, wl, cpu):
@@ -331,12 +449,18 @@ def main(argv=None):
     ap.add_argument("--budget-mb", type=float, default=0.0, help="serve: HBM admission budget (0 = 64 GB)")
     ap.add_argument("--capacity-requests", type=int, default=2000)
     ap.add_argument("--sched-steps", type=int, default=5, help="steps with the paper's penalty schedule")
+    ap.add_argument("--scp-iters", type=int, default=0, help="override the workload's SCP budget (profiling runs)")
+    ap.add_argument("--admm-iters", type=int, default=0, help="override the workload's ADMM budget (profiling runs)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (instances shard across GPUs "
               "with no communication; see the design notes).", file=sys.stderr)
         sys.exit(2)
     wl = workload(a.workload)
+    if a.scp_iters > 0 or a.admm_iters > 0:
+        wl["scp"] = a.scp_iters or wl.get("scp")
+        wl["admm"] = a.admm_iters or wl.get("admm")
+        wl["desc"] += f" [budget overridden to {wl['scp']} SCP x {wl['admm']} ADMM]"
     cores = min(os.cpu_count() or 1, 16)
     if wl.get("mpc"):
         cpu = None if a.no_cpu_baseline else cpu_baseline_mpc(wl, 3)
@@ -348,6 +472,8 @@ def main(argv=None):
             cpu = cpu_baseline_requests(reqs, wl["scp"], wl["admm"], wl["rho"], cores)
         return serve_main(a, wl, cpu)
     cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_sample, cores)
+    if wl.get("plain_only"):
+        return plain_main(a, wl, cpu)
 
     import torch
     from paper_2603_10711_amd import binding as B

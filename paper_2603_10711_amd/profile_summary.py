@@ -3,6 +3,8 @@
     python -m paper_2603_10711_amd.profile_summary stats <kernel_stats.csv> <out.md> --cmd "<command>"
     python -m paper_2603_10711_amd.profile_summary pmc <fetch dir> <write dir> <copy fetch dir> <copy write dir> \
         <workload> <out.json> --cmd "<command>"
+    python -m paper_2603_10711_amd.profile_summary pmcplain <fetch dir> <write dir> <copy fetch dir> <copy write dir> \
+        <workload> <scp iters> <admm iters> <out.json> --cmd "<command>"
     python -m paper_2603_10711_amd.profile_summary sq <counter dir> <title> <admm iterations per solve> <out.md> \
         --cmd "<command>"
 
@@ -75,6 +77,47 @@ def pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, out, cmd
     json.dump(d, open(out, "w"), indent=1)
 
 
+def pmc_plain(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, scp_iters, admm_iters, out, cmd) -> None:
+    """HBM bytes of one plain-form solve: per-dispatch FETCH_SIZE / WRITE_SIZE of every kernel
+    (scaled by the copy calibration) times its dispatches in a solve of the full budget: the ADMM
+    kernels run scp_iters x admm_iters times, the residual kernel once per SCP iteration, the
+    per-SCP-iteration kernels scp_iters times, the reset and metric kernels once."""
+    copy_bytes = 1 << 30
+    cf, _ = _counter(copy_fetch_dir, "__amd_rocclr_copyBuffer")
+    cw, _ = _counter(copy_write_dir, "__amd_rocclr_copyBuffer")
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+
+    def per_kernel(dirpath):
+        path = glob.glob(os.path.join(dirpath, "*counter_collection.csv"))[0]
+        vals = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Kernel_Name"].startswith("void scp::"):
+                vals[r["Kernel_Name"].split("<")[0].replace("void scp::", "")].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items()}
+
+    kf, kw = per_kernel(fetch_dir), per_kernel(write_dir)
+    admm = scp_iters * admm_iters
+    count = {"k_step1": admm, "k_step234": admm, "k_resid": scp_iters, "k_lin": scp_iters,
+             "k_acc_nodes": scp_iters, "k_acc_traj": scp_iters, "k_acc_apply": scp_iters, "k_check": scp_iters,
+             "k_reset": 2, "k_reset_state": 1, "k_met_nodes": 1, "k_met_traj": 1}
+    kernels = {}
+    total_r = total_w = 0.0
+    for k in sorted(set(kf) | set(kw)):
+        r = kf.get(k, 0.0) * 1024.0 * f_scale
+        w = kw.get(k, 0.0) * 1024.0 * w_scale
+        kernels[k] = {"read_bytes_per_dispatch": r, "write_bytes_per_dispatch": w, "dispatches_per_solve": count.get(k, 0)}
+        total_r += r * count.get(k, 0)
+        total_w += w * count.get(k, 0)
+    d = {"workload": workload, "kernel_hash": kernel_source_hash(), "command": cmd,
+         "budget": f"{scp_iters} SCP x {admm_iters} ADMM", "kernels": kernels,
+         "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
+                              "fetch_scale": f_scale, "write_scale": w_scale},
+         "hbm_read_bytes_per_solve": total_r, "hbm_write_bytes_per_solve": total_w,
+         "hbm_bytes_per_solve": total_r + total_w}
+    json.dump(d, open(out, "w"), indent=1)
+
+
 def sq(dirpath: str, title: str, iters: int, out: str, cmd: str) -> None:
     """SQ counters of k_persistent per dispatch and per wave, and the VALU issue share."""
     path = glob.glob(os.path.join(dirpath, "*counter_collection.csv"))[0]
@@ -109,6 +152,13 @@ def main(argv=None):
     for k in ("fetch", "write", "copy_fetch", "copy_write", "workload", "out"):
         p.add_argument(k)
     p.add_argument("--cmd", required=True)
+    pp = sub.add_parser("pmcplain")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "workload"):
+        pp.add_argument(k)
+    pp.add_argument("scp_iters", type=int)
+    pp.add_argument("admm_iters", type=int)
+    pp.add_argument("out")
+    pp.add_argument("--cmd", required=True)
     q = sub.add_parser("sq")
     for k in ("dir", "title", "iters", "out"):
         q.add_argument(k)
@@ -116,6 +166,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.csv, a.out, a.cmd)
+    elif a.mode == "pmcplain":
+        pmc_plain(a.fetch, a.write, a.copy_fetch, a.copy_write, a.workload, a.scp_iters, a.admm_iters, a.out, a.cmd)
     elif a.mode == "sq":
         sq(a.dir, a.title, int(a.iters), a.out, a.cmd)
     else:
