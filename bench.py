@@ -1,6 +1,6 @@
 """Benchmark of the SCP + consensus-ADMM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096|mix2048|quad6_1000|serve|mpc]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad1024|mars4096|mix2048|quad6_1000|lander6_1000|serve|mpc]
                     [--no-cpu-baseline] [--plain-steps P] [--sched-steps S]
 
 ``--plain-steps 0`` and ``--sched-steps 0`` leave out the plain-form and penalty-schedule legs
@@ -74,6 +74,13 @@ def workload(name: str):
                     desc="6-DOF quadrotor batch (13 states, quaternion attitude, thrust and body torques): 1000 "
                          "instances, N=40, T=6 s, 3 random obstacles, noise-initialized, 20 SCP x 200 ADMM, rho "
                          "1e2 -> 1e3 geometric, trust region 1, FP32, plain form")
+    if name == "lander6_1000":
+        return dict(name=name, insts=scpgen.config6(1000), scp=20, admm=200, rho=100.0, rho_final=1e3, prec="f32",
+                    plain_only=True,
+                    desc="6-DOF powered-descent Monte Carlo (14 states, body-frame thrust, gimbal, tilt, rate and "
+                         "glide-slope limits, linearized lower thrust bound): 1000 descents with 5% initial "
+                         "dispersion, N=30, horizon 5, 20 SCP x 200 ADMM, rho 1e2 -> 1e3 geometric, trust region "
+                         "1, FP32, plain form")
     if name == "mix2048":
         return dict(name=name, insts=scpgen.config3(2048), scp=15, admm=200, rho=1.0, prec="f32", eps=1e-4,
                     cadences=(1, 5, 10, 25),
@@ -98,6 +105,11 @@ def flops_per_node_iter(model: int, K: int) -> int:
         nx, nxr, nu = 13, 10, 4
         C = 17 + 3 * K
         s3 = 4 * (nx + nu) + 20 * K
+    elif model == scpgen.LANDER6:
+        nx, nxr, nu = 14, 11, 3
+        C = 34
+        # glide cone 21, tilt ball 12, rate ball 17, thrust ball 17, lower bound 20, gimbal cone 21
+        s3 = 4 * (nx + nu) + 21 + 12 + 17 + 17 + 20 + 21
     else:
         nx, nxr, nu = 7, 4, 4
         C = 18
@@ -116,6 +128,8 @@ def bytes_per_node_iter(model: int, K: int, w: int = 4) -> int:
     n = nx + nu
     if model == scpgen.MARS:
         C, hs = 18, 0
+    elif model == scpgen.LANDER6:
+        C, hs = 34, 4
     else:
         C = nx + nu + (3 if model == scpgen.QUAD else 0) + 3 * K
         hs = 4 * K

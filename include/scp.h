@@ -55,7 +55,14 @@ typedef enum {
                                  q' = q (x) (0, w_b) / 2, w_b' = J^-1 (tau - w_b x J w_b),
                                  m = SCP_P_MSCALE, g = SCP_P_GRAV, J = diag(SCP_P_INERTIA);
                                  R(q) e3 is the third column of the rotation matrix of
-                                 q / |q| (a unit thrust direction off the unit sphere too) */
+                                 q / |q| (a unit thrust direction off the unit sphere too) */,
+    SCP_MODEL_LANDER6 = 4     /* 6-DOF powered descent (Sec. IV-B.1), unified units, nx=14
+                                 (r, v Up-East-North, unit quaternion q, body rates w_b, mass
+                                 m), nu=3 (body-frame thrust T): r' = v,
+                                 v' = R(q/|q|) T / m + g (g = SCP_P_GVEC),
+                                 q' = q (x) (0, w_b) / 2,
+                                 J w_b' = r_T x T - w_b x J w_b (r_T = SCP_P_ARM),
+                                 m' = -alpha |T| (alpha = SCP_P_ALPHA)                    */
 } scp_model;
 
 typedef enum { SCP_F32 = 0, SCP_F64 = 1 } scp_precision;
@@ -68,7 +75,7 @@ typedef enum {
 
 typedef enum { SCP_PACK_ALIGNED = 0, SCP_PACK_DENSE = 1 } scp_pack;
 
-#define SCP_MAX_NX 13
+#define SCP_MAX_NX 14
 #define SCP_MAX_NU 4
 #define SCP_MAX_OBS 8
 #define SCP_MAX_N 1023        /* largest horizon N (intervals) of one trajectory */
@@ -80,36 +87,46 @@ typedef enum { SCP_PACK_ALIGNED = 0, SCP_PACK_DENSE = 1 } scp_pack;
  */
 enum {
     SCP_P_H = 0,              /* step size T/N                                              */
-    SCP_P_XINIT = 1,          /* [13] initial state, x_0 = x_init (eq. ocp)                 */
-    SCP_P_XTGT = 14,          /* [13] terminal target                                       */
-    SCP_P_TMASK = 27,         /* [13] 1.0 where x_N is fixed to the target (selection S)    */
-    SCP_P_QR = 40,            /* [13] diagonal of the running state Hessian Q_i, i < N      */
-    SCP_P_QN = 53,            /* [13] diagonal of the terminal Hessian Q_N                  */
-    SCP_P_QNV = 66,           /* [13] terminal gradient q_N                                 */
-    SCP_P_CN = 79,            /* constant of the terminal cost (reported cost only)         */
-    SCP_P_R = 80,             /* [4] diagonal of the control Hessian R_i                    */
-    SCP_P_XLO = 84,           /* [13] hard state lower bounds                               */
-    SCP_P_XHI = 97,           /* [13] hard state upper bounds                               */
-    SCP_P_ULO = 110,          /* [4] hard control lower bounds                              */
-    SCP_P_UHI = 114,          /* [4] hard control upper bounds                              */
-    SCP_P_UBALL = 118,        /* control ball radius ||u|| <= r (point-mass quadrotor;
-                                 HUGE_VAL = none; ignored by the 6-DOF model)               */
-    SCP_P_DELTA = 119,        /* initial trust-region radius (l-inf box around the nominal) */
-    SCP_P_DRAG = 120,         /* point-mass quadrotor drag coefficient c                    */
-    SCP_P_MSCALE = 121,       /* quadrotor mass scale m_s (6-DOF: the mass m)               */
-    SCP_P_GRAV = 122,         /* quadrotor gravity g                                        */
-    SCP_P_ALPHA = 123,        /* powered descent mass-flow coefficient alpha                */
-    SCP_P_GVEC = 124,         /* [3] powered descent gravity vector                         */
-    SCP_P_GLIDE = 127,        /* tan of the glide-slope half angle (powered descent)        */
-    SCP_P_NOBS = 128,         /* number of obstacles K <= SCP_MAX_OBS (quadrotors)          */
-    SCP_P_OBS = 129,          /* [8 x 4] obstacle centre (3) and radius (1)                 */
-    SCP_P_DIST = 161,         /* [3] constant disturbance acceleration added to v'
+    SCP_P_XINIT = 1,          /* [14] initial state, x_0 = x_init (eq. ocp)                 */
+    SCP_P_XTGT = 15,          /* [14] terminal target                                       */
+    SCP_P_TMASK = 29,         /* [14] 1.0 where x_N is fixed to the target (selection S)    */
+    SCP_P_QR = 43,            /* [14] diagonal of the running state Hessian Q_i, i < N      */
+    SCP_P_QN = 57,            /* [14] diagonal of the terminal Hessian Q_N                  */
+    SCP_P_QNV = 71,           /* [14] terminal gradient q_N                                 */
+    SCP_P_CN = 85,            /* constant of the terminal cost (reported cost only)         */
+    SCP_P_R = 86,             /* [4] diagonal of the control Hessian R_i                    */
+    SCP_P_XLO = 90,           /* [14] hard state lower bounds                               */
+    SCP_P_XHI = 104,          /* [14] hard state upper bounds                               */
+    SCP_P_ULO = 118,          /* [4] hard control lower bounds                              */
+    SCP_P_UHI = 122,          /* [4] hard control upper bounds                              */
+    SCP_P_UBALL = 126,        /* control ball radius ||u|| <= r (point-mass quadrotor;
+                                 HUGE_VAL = none; ignored by the other models)              */
+    SCP_P_DELTA = 127,        /* initial trust-region radius (l-inf box around the nominal) */
+    SCP_P_DRAG = 128,         /* point-mass quadrotor drag coefficient c                    */
+    SCP_P_MSCALE = 129,       /* quadrotor mass scale m_s (6-DOF quadrotor: the mass m)     */
+    SCP_P_GRAV = 130,         /* quadrotor gravity g                                        */
+    SCP_P_ALPHA = 131,        /* powered descent mass-flow coefficient alpha                */
+    SCP_P_GVEC = 132,         /* [3] powered descent gravity vector                         */
+    SCP_P_GLIDE = 135,        /* glide slope (powered descent, 6-DOF lander): the tangent
+                                 of the cone's half angle about the vertical axis           */
+    SCP_P_NOBS = 136,         /* number of obstacles K <= SCP_MAX_OBS (quadrotors)          */
+    SCP_P_OBS = 137,          /* [8 x 4] obstacle centre (3) and radius (1)                 */
+    SCP_P_DIST = 169,         /* [3] constant disturbance acceleration added to v'
                                  (quadrotors)                                               */
-    SCP_P_CYL = 164,          /* bit j set: obstacle j is a vertical cylinder (axis along z
+    SCP_P_CYL = 172,          /* bit j set: obstacle j is a vertical cylinder (axis along z
                                  through its centre; the centre's z is ignored), else a
                                  sphere                                                     */
-    SCP_P_INERTIA = 165,      /* [3] principal moments of inertia J_xx, J_yy, J_zz (6-DOF)  */
-    SCP_PARAM_STRIDE = 168
+    SCP_P_INERTIA = 173,      /* [3] principal moments of inertia J_xx, J_yy, J_zz (6-DOF)  */
+    SCP_P_ARM = 176,          /* [3] 6-DOF lander: thrust point in the body frame           */
+    SCP_P_TMIN = 179,         /* 6-DOF lander: thrust magnitude lower bound (non-convex;
+                                 linearized at the nominal thrust each SCP iteration)       */
+    SCP_P_TMAX = 180,         /* 6-DOF lander: thrust magnitude upper bound                 */
+    SCP_P_GIMBAL = 181,       /* 6-DOF lander: tangent of the gimbal cone's half angle
+                                 about the body x axis                                      */
+    SCP_P_TILT = 182,         /* 6-DOF lander: tilt bound as |(q_y, q_z)| <= this value
+                                 (the sine of half the largest tilt angle)                  */
+    SCP_P_WMAX = 183,         /* 6-DOF lander: body-rate bound |w_b| <= this value          */
+    SCP_PARAM_STRIDE = 184
 };
 
 /*
@@ -152,7 +169,8 @@ typedef struct {
                                  MPC, Sec. IV-A.4).  NULL = every trajectory alone.  In the
                                  persistent form a group larger than one workgroup spans
                                  several (at most 64 members, each member whole in one
-                                 workgroup), coupled by a barrier in device memory.         */
+                                 workgroup), coupled by a barrier in device memory.  Groups
+                                 of the 6-DOF lander are refused (SCP_ERR_ARG).             */
     const double* params;     /* [n_traj * SCP_PARAM_STRIDE] records, see SCP_P_*           */
     const double* x_guess;    /* initial nominal states, rows of SCP_MAX_NX doubles, (N+1)
                                  rows per trajectory, trajectories concatenated             */
@@ -256,8 +274,8 @@ typedef enum {
     SCP_FIELD_COUNT = 16
 } scp_field;
 
-/* Width (values per node) of a field: XBAR/X/Z/LAM/MU/DDYN/D 13, UBAR/U 4, COPY/DUAL 44,
- * A 169 (row-major 13x13), B 52 (row-major 13x4), BOXLO/BOXHI 17 (x then u), HS 32
+/* Width (values per node) of a field: XBAR/X/Z/LAM/MU/DDYN/D 14, UBAR/U 4, COPY/DUAL 44,
+ * A 196 (row-major 14x14), B 56 (row-major 14x4), BOXLO/BOXHI 18 (x then u), HS 32
  * (a_x, a_y, a_z, b per obstacle).  A model's values fill the leading slots (its nx, nu
  * rows and columns); the rest are 0.  0 for an invalid id. */
 int32_t scp_field_width(int32_t field);
@@ -266,7 +284,9 @@ int32_t scp_field_width(int32_t field);
  * values per row, problem precision) to dst_dev.  Mirror copies and duals are packed per
  * model in a fixed group order: point-mass quadrotor [x box 6][u box 3][ball 3][half-space k:
  * 3 each], 6-DOF quadrotor [x box 13][u box 4][ball 3, unused][half-space k: 3 each],
- * powered descent [x box 7][u box 4][glide cone 3][SOC 4].  Async. */
+ * powered descent [x box 7][u box 4][glide cone 3][SOC 4], 6-DOF lander [x box 14][u box 3]
+ * [glide cone on (r_E, r_N, r_U) 3][tilt on (q_y, q_z) 2][rate ball 3][thrust ball 3]
+ * [thrust lower-bound half-space 3][gimbal cone on (T_y, T_z, T_x) 3].  Async. */
 scp_status scp_get_field(const scp_problem* p, int32_t field, void* dst_dev);
 
 /* Total nodes (sum of N+1) and the node offset of trajectory t (for slicing results). */

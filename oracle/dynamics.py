@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-QUAD, MARS, QUAD6 = 1, 2, 3
+QUAD, MARS, QUAD6, LANDER6 = 1, 2, 3, 4
 
 
 def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
@@ -26,8 +26,23 @@ def f_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> np.ndarray:
     with J = diag(inertia).  R(q) e3 is the third column of the rotation matrix of q / ||q||:
     (2(q_x q_z + q_w q_y), 2(q_y q_z - q_w q_x), q_w^2 - q_x^2 - q_y^2 + q_z^2) / ||q||^2, so the
     thrust direction stays a unit vector when the iterates leave the unit sphere.
+    6-DOF lander (Sec. IV-B.1, unified non-dimensional units): x = (r, v, q, w, m) with position
+    and velocity in the Up-East-North frame, q rotating body to inertial, w the body rate and m the
+    mass; u = T_B, the thrust vector in the body frame:
+        r' = v,  v' = R(q/||q||) T_B / m + g,  q' = (1/2) q (x) (0, w),
+        J w' = r_T x T_B - w x (J w),  m' = -alpha ||T_B||,
+    with r_T the thrust point in the body frame ("arm") and J = diag(inertia).
     The norm is written sqrt(v.v) so the function stays analytic for complex-step tests.
     """
+    if inst["model"] == LANDER6:
+        v, q, w, m = x[3:6], x[6:10], x[10:13], x[13]
+        T = u[0:3]
+        J = np.asarray(inst["inertia"], dtype=float)
+        acc = _rot(q) @ T / m + np.asarray(inst["gvec"], dtype=float)
+        qdot = 0.5 * _quat_mul(q, np.concatenate([[0.0], w]))
+        wdot = (np.cross(np.asarray(inst["arm"], dtype=float), T) - np.cross(w, J * w)) / J
+        mdot = -inst["alpha"] * np.sqrt(T @ T)
+        return np.concatenate([v, acc, qdot, wdot, [mdot]])
     if inst["model"] == QUAD6:
         v, q, w = x[3:6], x[6:10], x[10:13]
         f, tau = u[0], u[1:4]
@@ -64,6 +79,19 @@ def _rot_e3(q: np.ndarray) -> np.ndarray:
     return np.array([2.0 * (qx * qz + qw * qy), 2.0 * (qy * qz - qw * qx), qw * qw - qx * qx - qy * qy + qz * qz]) / n2
 
 
+def _rot_hom(q: np.ndarray) -> np.ndarray:
+    """Rotation matrix of a unit quaternion written as the homogeneous quadratic in q."""
+    qw, qx, qy, qz = q
+    return np.array([[qw * qw + qx * qx - qy * qy - qz * qz, 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy)],
+                     [2.0 * (qx * qy + qw * qz), qw * qw - qx * qx + qy * qy - qz * qz, 2.0 * (qy * qz - qw * qx)],
+                     [2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), qw * qw - qx * qx - qy * qy + qz * qz]])
+
+
+def _rot(q: np.ndarray) -> np.ndarray:
+    """Rotation matrix of q / ||q||."""
+    return _rot_hom(q) / (q @ q)
+
+
 def _skew(a: np.ndarray) -> np.ndarray:
     """Matrix of the cross product a x (.)."""
     return np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
@@ -81,6 +109,42 @@ def jac_cont(inst: dict, x: np.ndarray, u: np.ndarray) -> tuple[np.ndarray, np.n
     nx, nu = x.shape[0], u.shape[0]
     Jx = np.zeros((nx, nx))
     Ju = np.zeros((nx, nu))
+    if inst["model"] == LANDER6:
+        q, w, m = x[6:10], x[10:13], x[13]
+        qw, qx, qy, qz = q
+        T = u[0:3]
+        T0, T1, T2 = T
+        J = np.asarray(inst["inertia"], dtype=float)
+        n2 = q @ q
+        p = _rot_hom(q) @ T
+        # d(R_hom(q) T)/dq, one column per quaternion component (w, x, y, z)
+        dp = 2.0 * np.array([[qw * T0 - qz * T1 + qy * T2, qx * T0 + qy * T1 + qz * T2,
+                              -qy * T0 + qx * T1 + qw * T2, -qz * T0 - qw * T1 + qx * T2],
+                             [qz * T0 + qw * T1 - qx * T2, qy * T0 - qx * T1 - qw * T2,
+                              qx * T0 + qy * T1 + qz * T2, qw * T0 - qz * T1 + qy * T2],
+                             [-qy * T0 + qx * T1 + qw * T2, qz * T0 + qw * T1 - qx * T2,
+                              -qw * T0 + qz * T1 - qy * T2, qx * T0 + qy * T1 + qz * T2]])
+        Jx[0:3, 3:6] = np.eye(3)
+        Jx[3:6, 6:10] = (dp / n2 - np.outer(p, 2.0 * q) / (n2 * n2)) / m
+        Jx[3:6, 13] = -p / n2 / (m * m)
+        Ju[3:6, 0:3] = _rot(q) / m
+        Lq = np.zeros((4, 4))
+        Lq[0, 0] = qw
+        Lq[0, 1:] = -q[1:]
+        Lq[1:, 0] = q[1:]
+        Lq[1:, 1:] = qw * np.eye(3) + _skew(q[1:])
+        Rp = np.zeros((4, 4))
+        Rp[0, 1:] = -w
+        Rp[1:, 0] = w
+        Rp[1:, 1:] = -_skew(w)
+        Jx[6:10, 6:10] = 0.5 * Rp
+        Jx[6:10, 10:13] = 0.5 * Lq[:, 1:]
+        Jx[10:13, 10:13] = -(_skew(w) @ np.diag(J) - _skew(J * w)) / J[:, None]
+        Ju[10:13, 0:3] = _skew(np.asarray(inst["arm"], dtype=float)) / J[:, None]
+        nT = np.sqrt(T @ T)
+        if nT > 0.0:
+            Ju[13, 0:3] = -inst["alpha"] * T / nT
+        return Jx, Ju
     if inst["model"] == QUAD6:
         q, w = x[6:10], x[10:13]
         qw, qx, qy, qz = q

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .admm import Group, QP, AdmmState, build_H, admm_run
-from .dynamics import rk4, rk4_jac, QUAD, MARS, QUAD6
+from .dynamics import rk4, rk4_jac, QUAD, MARS, QUAD6, LANDER6
 
 
 def default_params(**kw) -> dict:
@@ -123,6 +123,12 @@ def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_c
       (fallback +e1).  The 6-DOF model's position is its first three states as well.
     Powered descent: glide-slope cone ||(r_x, r_y)|| <= tan(86 deg) r_z at nodes 1..N, then
       the SOC ||T|| <= Gamma at nodes 0..N-1.
+    6-DOF lander (position Up-East-North): at nodes 1..N the glide-slope cone
+      ||(r_E, r_N)|| <= glide_tan r_U (components (1, 2, 0): the axis last), the tilt limit
+      ||(q_y, q_z)|| <= tilt_r and the rate ball ||w|| <= w_max; at nodes 0..N-1 the thrust ball
+      ||T|| <= T_max, the lower thrust bound ||T|| >= T_min linearized at the nominal thrust as
+      the half-space n'T >= T_min with n = Tbar/||Tbar|| (+e1 if ||Tbar|| < 1e-9), and the
+      gimbal cone ||(T_y, T_z)|| <= gimbal_tan T_x (components (1, 2, 0)).
     """
     N, nx, nu = inst["N"], inst["nx"], inst["nu"]
     allx = np.ones(N + 1, dtype=bool)
@@ -165,6 +171,20 @@ def convexify(inst: dict, xbar: np.ndarray, ubar: np.ndarray, delta: float, u0_c
                 a[i] = nvec
                 b[i] = r + nvec @ c
             groups.append(Group("x", (0, 1, 2), "halfspace", inner.copy(), a=a, b=b))
+    elif inst["model"] == LANDER6:
+        groups.append(Group("x", (1, 2, 0), "cone", inner.copy(), kappa=float(inst["glide_tan"])))
+        groups.append(Group("x", (8, 9), "ball", inner.copy(), radius=float(inst["tilt_r"])))
+        groups.append(Group("x", (10, 11, 12), "ball", inner.copy(), radius=float(inst["w_max"])))
+        groups.append(Group("u", (0, 1, 2), "ball", uact.copy(), radius=float(inst["T_max"])))
+        a = np.zeros((N + 1, 3))
+        b = np.zeros(N + 1)
+        for i in range(N):
+            t = ubar[i]
+            nt = np.sqrt(t @ t)
+            a[i] = t / nt if nt >= 1e-9 else np.array([1.0, 0.0, 0.0])
+            b[i] = float(inst["T_min"])
+        groups.append(Group("u", (0, 1, 2), "halfspace", uact.copy(), a=a, b=b))
+        groups.append(Group("u", (1, 2, 0), "cone", uact.copy(), kappa=float(inst["gimbal_tan"])))
     else:
         groups.append(Group("x", (0, 1, 2), "cone", inner.copy(), kappa=float(inst["glide_tan"])))
         groups.append(Group("u", (0, 1, 2, 3), "soc", uact.copy()))
@@ -197,7 +217,8 @@ def defect(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
 def violation(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
     """Max violation of the hard (unconvexified) constraints: state/control bounds, control
     ball, obstacles (penetration depth, nodes 1..N; horizontal distance for a cylinder),
-    SOC ||T|| <= Gamma, glide slope."""
+    SOC ||T|| <= Gamma, glide slope; for the 6-DOF lander the thrust magnitude bounds (the lower
+    one unconvexified), gimbal, glide slope, tilt and rate limits."""
     N = inst["N"]
     v = 0.0
     v = max(v, float(np.max(np.maximum(0.0, inst["x_lo"] - x))), float(np.max(np.maximum(0.0, x - inst["x_hi"]))))
@@ -213,6 +234,15 @@ def violation(inst: dict, x: np.ndarray, u: np.ndarray) -> float:
             dist = np.sqrt(np.sum((x[1:, :dims] - c[:dims]) ** 2, axis=1))
             if dist.size:
                 v = max(v, float(np.max(r - dist)))
+    elif inst["model"] == LANDER6:
+        if N > 0:
+            nt = np.sqrt(np.sum(u[:N, :3] ** 2, axis=1))
+            v = max(v, float(np.max(nt - inst["T_max"])), float(np.max(inst["T_min"] - nt)))
+            v = max(v, float(np.max(np.sqrt(u[:N, 1] ** 2 + u[:N, 2] ** 2) - inst["gimbal_tan"] * u[:N, 0])))
+            xs = x[1:]
+            v = max(v, float(np.max(np.sqrt(xs[:, 1] ** 2 + xs[:, 2] ** 2) - inst["glide_tan"] * xs[:, 0])))
+            v = max(v, float(np.max(np.sqrt(xs[:, 8] ** 2 + xs[:, 9] ** 2) - inst["tilt_r"])))
+            v = max(v, float(np.max(np.sqrt(np.sum(xs[:, 10:13] ** 2, axis=1)) - inst["w_max"])))
     else:
         if N > 0:
             v = max(v, float(np.max(np.sqrt(np.sum(u[:, :3] ** 2, axis=1)) - u[:, 3])))

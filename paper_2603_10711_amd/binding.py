@@ -19,15 +19,15 @@ LIB_PATH = os.path.join(HERE, "libscp.so")
 
 # --- constants mirrored from include/scp.h ------------------------------------------------
 SCP_OK = 0
-QUAD, MARS, QUAD6 = 1, 2, 3
+QUAD, MARS, QUAD6, LANDER6 = 1, 2, 3, 4
 F32, F64 = 0, 1
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 PACK_ALIGNED, PACK_DENSE = 0, 1
-MAX_NX, MAX_NU, MAX_OBS = 13, 4, 8
-P = dict(H=0, XINIT=1, XTGT=14, TMASK=27, QR=40, QN=53, QNV=66, CN=79, R=80, XLO=84, XHI=97, ULO=110, UHI=114,
-         UBALL=118, DELTA=119, DRAG=120, MSCALE=121, GRAV=122, ALPHA=123, GVEC=124, GLIDE=127, NOBS=128, OBS=129,
-         DIST=161, CYL=164, INERTIA=165)
-PARAM_STRIDE = 168
+MAX_NX, MAX_NU, MAX_OBS = 14, 4, 8
+P = dict(H=0, XINIT=1, XTGT=15, TMASK=29, QR=43, QN=57, QNV=71, CN=85, R=86, XLO=90, XHI=104, ULO=118, UHI=122,
+         UBALL=126, DELTA=127, DRAG=128, MSCALE=129, GRAV=130, ALPHA=131, GVEC=132, GLIDE=135, NOBS=136, OBS=137,
+         DIST=169, CYL=172, INERTIA=173, ARM=176, TMIN=179, TMAX=180, GIMBAL=181, TILT=182, WMAX=183)
+PARAM_STRIDE = 184
 SUBMIT_MEASURED = 1
 INFO = dict(admm_iters=0, r_p=1, r_d=2, n_accept=3, delta=4, status=5, defect=6, cost=7, viol=8, bnd_err=9,
             merit=10, ratio=11)
@@ -189,6 +189,12 @@ def param_record(inst: dict) -> np.ndarray:
     r[P["DIST"]:P["DIST"] + 3] = inst.get("dist", (0.0, 0.0, 0.0))
     r[P["CYL"]] = float(sum(1 << j for j, c in enumerate(inst.get("cyl", ())) if c))
     r[P["INERTIA"]:P["INERTIA"] + 3] = inst.get("inertia", (0.0, 0.0, 0.0))
+    r[P["ARM"]:P["ARM"] + 3] = inst.get("arm", (0.0, 0.0, 0.0))
+    r[P["TMIN"]] = inst.get("T_min", 0.0)
+    r[P["TMAX"]] = inst.get("T_max", 0.0)
+    r[P["GIMBAL"]] = inst.get("gimbal_tan", 0.0)
+    r[P["TILT"]] = inst.get("tilt_r", 0.0)
+    r[P["WMAX"]] = inst.get("w_max", 0.0)
     return r
 
 

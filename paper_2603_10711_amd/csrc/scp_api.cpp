@@ -24,13 +24,17 @@ namespace {
 
 thread_local std::string g_create_error;
 
-bool valid_model(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_MARS3DOF || m == SCP_MODEL_QUAD_6DOF; }
+bool valid_model(int m) {
+    return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_MARS3DOF || m == SCP_MODEL_QUAD_6DOF || m == SCP_MODEL_LANDER6;
+}
 bool quad_like(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_QUAD_6DOF; }
 // model bit of Layout::models
-int model_bit(int m) { return m == SCP_MODEL_QUAD_PM ? 1 : m == SCP_MODEL_MARS3DOF ? 2 : 4; }
+int model_bit(int m) {
+    return m == SCP_MODEL_QUAD_PM ? 1 : m == SCP_MODEL_MARS3DOF ? 2 : m == SCP_MODEL_QUAD_6DOF ? 4 : 8;
+}
 const char* const kNoPersistent =
     "the persistent form needs trajectories of at most 256 nodes, consensus groups of at most 64 members and the "
-    "point-mass quadrotor or powered-descent model; use the plain form";
+    "point-mass quadrotor or 3-DOF powered-descent model; use the plain form";
 
 // Pack units (single trajectories or whole consensus groups) of one model into workgroups of
 // `block` lanes, first-fit decreasing by size.  Returns false if a unit does not fit.
@@ -201,6 +205,10 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
                     return false;
                 }
             }
+            if (e - t > 1 && d->model[t] == SCP_MODEL_LANDER6) {
+                err = "consensus groups of the 6-DOF lander are not supported";
+                return false;
+            }
             for (int q = e; q < L.n_traj; ++q)
                 if (d->group[q] == gid) {
                     err = "members of a consensus group must be consecutive";
@@ -229,7 +237,7 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     if (d->prec == SCP_F64) cands.erase(std::remove(cands.begin(), cands.end(), 256), cands.end());
     long best_idle = -1;
     double best_score = 0.0;
-    if (L.models & 4) cands.clear();  // the 6-DOF model runs in the plain form only
+    if (L.models & (4 | 8)) cands.clear();  // the 6-DOF models run in the plain form only
     for (int b : cands) {
         Packed pk;
         if (!pack(units, traj_off, horizon, b, d->pack == SCP_PACK_ALIGNED, pk)) continue;

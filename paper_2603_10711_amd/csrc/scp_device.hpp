@@ -30,6 +30,9 @@ namespace scp {
 // Mirror-copy layout (one copy with its own dual per constraint group):
 //   quadrotors      [x box: NX][u box: NU][ball: 3][half-space k: 3 each, k < KM]
 //   powered descent [x box: NX][u box: NU][glide cone on r: 3][SOC on (T, Gamma): 4]
+//   6-DOF lander    [x box: 14][u box: 3][glide cone on (r_E, r_N, r_U): 3][tilt on (q_y, q_z): 2]
+//                   [rate ball on w: 3][thrust ball: 3][lower thrust half-space: 3]
+//                   [gimbal cone on (T_y, T_z, T_x): 3]
 // Both quadrotor models share the first layout (QL: "quadrotor layout"); the 6-DOF model never
 // has the ball group (its slots stay inactive).  The first three state components (position)
 // never enter the dynamics of any model, so the first three columns of A are the unit vectors
@@ -38,7 +41,7 @@ namespace scp {
 template <int KM_>
 struct Quad {
     static constexpr int ID = SCP_MODEL_QUAD_PM;
-    static constexpr bool QL = true;
+    static constexpr bool QL = true, HSD = true;
     static constexpr int NX = 6, NU = 3, NN = 9, NXR = 3, KM = KM_;
     static constexpr int C_XBOX = 0, C_UBOX = 6, C_BALL = 9, C_HS = 12;
     static constexpr int C = 12 + 3 * KM_;
@@ -49,7 +52,7 @@ struct Quad {
 template <int KM_>
 struct Quad6 {
     static constexpr int ID = SCP_MODEL_QUAD_6DOF;
-    static constexpr bool QL = true;
+    static constexpr bool QL = true, HSD = true;
     static constexpr int NX = 13, NU = 4, NN = 17, NXR = 10, KM = KM_;
     static constexpr int C_XBOX = 0, C_UBOX = 13, C_BALL = 17, C_HS = 20;
     static constexpr int C = 20 + 3 * KM_;
@@ -58,19 +61,34 @@ struct Quad6 {
 
 struct Mars {
     static constexpr int ID = SCP_MODEL_MARS3DOF;
-    static constexpr bool QL = false;
+    static constexpr bool QL = false, HSD = false;
     static constexpr int NX = 7, NU = 4, NN = 11, NXR = 4, KM = 0;
     static constexpr int C_XBOX = 0, C_UBOX = 7, C_CONE = 11, C_SOC = 14;
     static constexpr int C = 18;
     static constexpr int NHS = 1;
 };
 
+// 6-DOF lander: x = (r, v, q, w_b, m), u = T (body frame).  HSD: the node carries half-space
+// data (here the linearized lower thrust bound: normal and offset).
+struct Lander6 {
+    static constexpr int ID = SCP_MODEL_LANDER6;
+    static constexpr bool QL = false, HSD = true;
+    static constexpr int NX = 14, NU = 3, NN = 17, NXR = 11, KM = 0;
+    static constexpr int C_XBOX = 0, C_UBOX = 14, C_GLIDE = 17, C_TILT = 20, C_RATE = 22, C_TBALL = 25,
+                         C_THS = 28, C_GIMB = 31;
+    static constexpr int C = 34;
+    static constexpr int NHS = 4;
+};
+
 // run-time dimensions of a model id: state, control, and the mirror slots of its largest
 // instantiation (the prefix of each plane block a trajectory of that model uses)
-__host__ __device__ constexpr int model_nx(int m) { return m == SCP_MODEL_QUAD_PM ? 6 : m == SCP_MODEL_MARS3DOF ? 7 : 13; }
-__host__ __device__ constexpr int model_nu(int m) { return m == SCP_MODEL_QUAD_PM ? 3 : 4; }
+__host__ __device__ constexpr int model_nx(int m) {
+    return m == SCP_MODEL_QUAD_PM ? 6 : m == SCP_MODEL_MARS3DOF ? 7 : m == SCP_MODEL_QUAD_6DOF ? 13 : 14;
+}
+__host__ __device__ constexpr int model_nu(int m) { return m == SCP_MODEL_QUAD_PM || m == SCP_MODEL_LANDER6 ? 3 : 4; }
 __host__ __device__ constexpr int model_slots(int m) {
-    return m == SCP_MODEL_QUAD_PM ? Quad<SCP_MAX_OBS>::C : m == SCP_MODEL_MARS3DOF ? Mars::C : Quad6<SCP_MAX_OBS>::C;
+    return m == SCP_MODEL_QUAD_PM ? Quad<SCP_MAX_OBS>::C : m == SCP_MODEL_MARS3DOF ? Mars::C
+         : m == SCP_MODEL_QUAD_6DOF ? Quad6<SCP_MAX_OBS>::C : Lander6::C;
 }
 
 template <class M>
@@ -131,6 +149,36 @@ __device__ __forceinline__ double lane_prev(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Lane permutations inside each aligned group of four lanes (DPP quad_perm; SEL packs the source
+// lane of lanes 0..3 in two bits each).  Every lane of a group must be active.
+template <int SEL>
+__device__ __forceinline__ int quad_perm_i(int v) { return __builtin_amdgcn_mov_dpp(v, SEL, 0xF, 0xF, false); }
+template <int SEL>
+__device__ __forceinline__ float quad_perm(float v) { return __builtin_bit_cast(float, quad_perm_i<SEL>(__builtin_bit_cast(int, v))); }
+template <int SEL>
+__device__ __forceinline__ double quad_perm(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = quad_perm_i<SEL>((int)(b & 0xffffffffll)), hi = quad_perm_i<SEL>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// the value of lane k of this lane's group (k a constant after unrolling)
+template <class T>
+__device__ __forceinline__ T quad_bcast(T v, int k) {
+    switch (k & 3) {
+        case 0: return quad_perm<0x00>(v);
+        case 1: return quad_perm<0x55>(v);
+        case 2: return quad_perm<0xAA>(v);
+        default: return quad_perm<0xFF>(v);
+    }
+}
+// sum over the group as (v0 + v1) + (v2 + v3); addition commutes exactly, so every lane of the
+// group gets the same bits
+template <class T>
+__device__ __forceinline__ T quad_sum(T v) {
+    const T a = v + quad_perm<0xB1>(v);   // lanes (1, 0, 3, 2)
+    return a + quad_perm<0x4E>(a);         // lanes (2, 3, 0, 1)
+}
+
 // ------------------------------------------------------------------------------------------
 // continuous dynamics and their directional derivative (JVP)
 // ------------------------------------------------------------------------------------------
@@ -171,6 +219,33 @@ __device__ __forceinline__ void f_cont(const T* __restrict__ prm, const T* x, co
         f[10] = (u[1] - (J[2] - J[1]) * (wy * wz)) / J[0];
         f[11] = (u[2] - (J[0] - J[2]) * (wz * wx)) / J[1];
         f[12] = (u[3] - (J[1] - J[0]) * (wx * wy)) / J[2];
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        // r' = v, v' = R(q/|q|) T / m + g, q' = q (x) (0, w) / 2, J w' = r_T x T - w x (J w),
+        // m' = -alpha |T|
+        const T* J = prm + SCP_P_INERTIA;
+        const T* ra = prm + SCP_P_ARM;
+        const T* gv = prm + SCP_P_GVEC;
+        const T qw = x[6], qx = x[7], qy = x[8], qz = x[9];
+        const T wx = x[10], wy = x[11], wz = x[12], m = x[13];
+        const T T0 = u[0], T1 = u[1], T2 = u[2];
+        const T in2 = T(1) / ((qw * qw + qx * qx) + (qy * qy + qz * qz));
+        // R_hom(q) T, the rotation written as a homogeneous quadratic in q
+        const T p0 = ((qw * qw + qx * qx) - (qy * qy + qz * qz)) * T0 + T(2) * ((qx * qy - qw * qz) * T1 + (qx * qz + qw * qy) * T2);
+        const T p1 = ((qw * qw - qx * qx) + (qy * qy - qz * qz)) * T1 + T(2) * ((qx * qy + qw * qz) * T0 + (qy * qz - qw * qx) * T2);
+        const T p2 = ((qw * qw - qx * qx) - (qy * qy - qz * qz)) * T2 + T(2) * ((qx * qz - qw * qy) * T0 + (qy * qz + qw * qx) * T1);
+        const T sc = in2 / m;
+        f[0] = x[3]; f[1] = x[4]; f[2] = x[5];
+        f[3] = p0 * sc + gv[0];
+        f[4] = p1 * sc + gv[1];
+        f[5] = p2 * sc + gv[2];
+        f[6] = T(-0.5) * ((qx * wx + qy * wy) + qz * wz);
+        f[7] = T(0.5) * ((qw * wx + qy * wz) - qz * wy);
+        f[8] = T(0.5) * ((qw * wy + qz * wx) - qx * wz);
+        f[9] = T(0.5) * ((qw * wz + qx * wy) - qy * wx);
+        f[10] = ((ra[1] * T2 - ra[2] * T1) - (J[2] - J[1]) * (wy * wz)) / J[0];
+        f[11] = ((ra[2] * T0 - ra[0] * T2) - (J[0] - J[2]) * (wz * wx)) / J[1];
+        f[12] = ((ra[0] * T1 - ra[1] * T0) - (J[1] - J[0]) * (wx * wy)) / J[2];
+        f[13] = -prm[SCP_P_ALPHA] * tsqrt((T0 * T0 + T1 * T1) + T2 * T2);
     } else {
         // r' = v, v' = T/m + g_vec, m' = -alpha Gamma
         const T m = x[6];
@@ -224,6 +299,44 @@ __device__ __forceinline__ void f_jvp(const T* __restrict__ prm, const T* x, con
         df[10] = (du[1] - (J[2] - J[1]) * (dwy * wz + wy * dwz)) / J[0];
         df[11] = (du[2] - (J[0] - J[2]) * (dwz * wx + wz * dwx)) / J[1];
         df[12] = (du[3] - (J[1] - J[0]) * (dwx * wy + wx * dwy)) / J[2];
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        const T* J = prm + SCP_P_INERTIA;
+        const T* ra = prm + SCP_P_ARM;
+        const T qw = x[6], qx = x[7], qy = x[8], qz = x[9];
+        const T wx = x[10], wy = x[11], wz = x[12], m = x[13];
+        const T dqw = dx[6], dqx = dx[7], dqy = dx[8], dqz = dx[9];
+        const T dwx = dx[10], dwy = dx[11], dwz = dx[12], dm = dx[13];
+        const T T0 = u[0], T1 = u[1], T2 = u[2], dT0 = du[0], dT1 = du[1], dT2 = du[2];
+        const T in2 = T(1) / ((qw * qw + qx * qx) + (qy * qy + qz * qz));
+        const T p0 = ((qw * qw + qx * qx) - (qy * qy + qz * qz)) * T0 + T(2) * ((qx * qy - qw * qz) * T1 + (qx * qz + qw * qy) * T2);
+        const T p1 = ((qw * qw - qx * qx) + (qy * qy - qz * qz)) * T1 + T(2) * ((qx * qy + qw * qz) * T0 + (qy * qz - qw * qx) * T2);
+        const T p2 = ((qw * qw - qx * qx) - (qy * qy - qz * qz)) * T2 + T(2) * ((qx * qz - qw * qy) * T0 + (qy * qz + qw * qx) * T1);
+        // dp = R_hom(q) dT + (dR_hom/dq . dq) T
+        const T r0 = ((qw * qw + qx * qx) - (qy * qy + qz * qz)) * dT0 + T(2) * ((qx * qy - qw * qz) * dT1 + (qx * qz + qw * qy) * dT2);
+        const T r1 = ((qw * qw - qx * qx) + (qy * qy - qz * qz)) * dT1 + T(2) * ((qx * qy + qw * qz) * dT0 + (qy * qz - qw * qx) * dT2);
+        const T r2 = ((qw * qw - qx * qx) - (qy * qy - qz * qz)) * dT2 + T(2) * ((qx * qz - qw * qy) * dT0 + (qy * qz + qw * qx) * dT1);
+        const T e0 = T(2) * (((qw * T0 - qz * T1) + qy * T2) * dqw + ((qx * T0 + qy * T1) + qz * T2) * dqx +
+                             ((qx * T1 - qy * T0) + qw * T2) * dqy + ((qx * T2 - qz * T0) - qw * T1) * dqz);
+        const T e1 = T(2) * (((qz * T0 + qw * T1) - qx * T2) * dqw + ((qy * T0 - qx * T1) - qw * T2) * dqx +
+                             ((qx * T0 + qy * T1) + qz * T2) * dqy + ((qw * T0 - qz * T1) + qy * T2) * dqz);
+        const T e2 = T(2) * (((qx * T1 - qy * T0) + qw * T2) * dqw + ((qz * T0 + qw * T1) - qx * T2) * dqx +
+                             ((qz * T1 - qw * T0) - qy * T2) * dqy + ((qx * T0 + qy * T1) + qz * T2) * dqz);
+        // d(p / (|q|^2 m)) = (dp - p (d|q|^2 / |q|^2 + dm / m)) / (|q|^2 m)
+        const T k = T(2) * ((qw * dqw + qx * dqx) + (qy * dqy + qz * dqz)) * in2 + dm / m;
+        const T sc = in2 / m;
+        df[0] = dx[3]; df[1] = dx[4]; df[2] = dx[5];
+        df[3] = ((r0 + e0) - p0 * k) * sc;
+        df[4] = ((r1 + e1) - p1 * k) * sc;
+        df[5] = ((r2 + e2) - p2 * k) * sc;
+        df[6] = T(-0.5) * (((dqx * wx + dqy * wy) + dqz * wz) + ((qx * dwx + qy * dwy) + qz * dwz));
+        df[7] = T(0.5) * (((dqw * wx + dqy * wz) - dqz * wy) + ((qw * dwx + qy * dwz) - qz * dwy));
+        df[8] = T(0.5) * (((dqw * wy + dqz * wx) - dqx * wz) + ((qw * dwy + qz * dwx) - qx * dwz));
+        df[9] = T(0.5) * (((dqw * wz + dqx * wy) - dqy * wx) + ((qw * dwz + qx * dwy) - qy * dwx));
+        df[10] = ((ra[1] * dT2 - ra[2] * dT1) - (J[2] - J[1]) * (dwy * wz + wy * dwz)) / J[0];
+        df[11] = ((ra[2] * dT0 - ra[0] * dT2) - (J[0] - J[2]) * (dwz * wx + wz * dwx)) / J[1];
+        df[12] = ((ra[0] * dT1 - ra[1] * dT0) - (J[1] - J[0]) * (dwx * wy + wx * dwy)) / J[2];
+        const T nt = tsqrt((T0 * T0 + T1 * T1) + T2 * T2);
+        df[13] = nt > T(0) ? -prm[SCP_P_ALPHA] * ((T0 * dT0 + T1 * dT1) + T2 * dT2) / nt : T(0);
     } else {
         const T m = x[6];
         const T dm = dx[6];
@@ -385,6 +498,15 @@ __device__ __forceinline__ void proj_ball3(T r, T* v) {
     for (int k = 0; k < 3; ++k) v[k] = v[k] * s;
 }
 
+// {y : ||y|| <= r}, 2-vector
+template <class T>
+__device__ __forceinline__ void proj_ball2(T r, T* v) {
+    const T vv = v[0] * v[0] + v[1] * v[1];
+    const T s = vv > r * r ? r * trsqrt(vv) : T(1);
+    v[0] = v[0] * s;
+    v[1] = v[1] * s;
+}
+
 // {(y, s) : ||y|| <= kappa s}, y of length M-1; inv1k2 = 1/(1 + kappa^2)
 template <int M, class T>
 __device__ __forceinline__ void proj_cone(T kappa, T inv1k2, T* v) {
@@ -446,6 +568,11 @@ __device__ __forceinline__ bool group_active(const NodeId& id, int g) {
         if (g == 1) return !id.last();                   // u box
         if (g == 2) return !id.last() && id.ball;        // ball
         return !id.first() && (g - 3) < id.K;            // half-space g-3
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        if (g == 0) return true;                         // x box
+        if (g == 1) return !id.last();                   // u box
+        if (g <= 4) return !id.first();                  // glide cone, tilt, rate ball
+        return !id.last();                               // thrust ball, lower bound, gimbal
     } else {
         if (g == 0) return true;
         if (g == 1) return !id.last();
@@ -536,6 +663,16 @@ __device__ __forceinline__ int convexify(const T* __restrict__ prm, const NodeId
             nc.hs[4 * j + 2] = a2;
             nc.hs[4 * j + 3] = b;
         }
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        // lower thrust bound |T| >= T_min linearized at the nominal thrust: n'T >= T_min with
+        // n = Tbar / |Tbar| (+e1 if |Tbar| < 1e-9)
+        const T t0 = ucenter[0], t1 = ucenter[1], t2 = ucenter[2];
+        const T nt = tsqrt((t0 * t0 + t1 * t1) + t2 * t2);
+        const bool ok = nt >= T(1e-9);
+        nc.hs[0] = ok ? t0 / nt : T(1);
+        nc.hs[1] = ok ? t1 / nt : T(0);
+        nc.hs[2] = ok ? t2 / nt : T(0);
+        nc.hs[3] = prm[SCP_P_TMIN];
     }
     return st;
 }
@@ -557,6 +694,17 @@ __device__ __forceinline__ void group_counts(const NodeId& id, T* Dx, T* Du) {
 #pragma unroll
             for (int r = 0; r < 3; ++r) Du[r] = Du[r] + T(1);
         }
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        if (!id.first()) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Dx[r] = Dx[r] + T(1);       // glide cone
+            Dx[8] = Dx[8] + T(1);                                   // tilt
+            Dx[9] = Dx[9] + T(1);
+#pragma unroll
+            for (int r = 10; r < 13; ++r) Dx[r] = Dx[r] + T(1);     // rate ball
+        }
+#pragma unroll
+        for (int r = 0; r < NU; ++r) Du[r] = Du[r] + T(3);          // thrust ball, bound, gimbal
     } else {
         if (!id.first()) {
 #pragma unroll
@@ -730,6 +878,23 @@ __device__ __forceinline__ void step1(const NodeId& id, const Rho<T>& rho, const
                     g[r] = g[r] + (rj * s.cp[M::C_HS + 3 * j + r] - s.du[M::C_HS + 3 * j + r]);
             }
         }
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        const T rx = group_rho<M>(id, rho.geo, 2);   // glide, tilt and rate groups: nodes 1..N
+        g[1] = g[1] + (rx * s.cp[M::C_GLIDE + 0] - s.du[M::C_GLIDE + 0]);
+        g[2] = g[2] + (rx * s.cp[M::C_GLIDE + 1] - s.du[M::C_GLIDE + 1]);
+        g[0] = g[0] + (rx * s.cp[M::C_GLIDE + 2] - s.du[M::C_GLIDE + 2]);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) g[8 + r] = g[8 + r] + (rx * s.cp[M::C_TILT + r] - s.du[M::C_TILT + r]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) g[10 + r] = g[10 + r] + (rx * s.cp[M::C_RATE + r] - s.du[M::C_RATE + r]);
+        const T ru = group_rho<M>(id, rho.geo, 5);   // thrust groups: nodes 0..N-1
+#pragma unroll
+        for (int r = 0; r < 3; ++r) g[NX + r] = g[NX + r] + (ru * s.cp[M::C_TBALL + r] - s.du[M::C_TBALL + r]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) g[NX + r] = g[NX + r] + (ru * s.cp[M::C_THS + r] - s.du[M::C_THS + r]);
+        g[NX + 1] = g[NX + 1] + (ru * s.cp[M::C_GIMB + 0] - s.du[M::C_GIMB + 0]);
+        g[NX + 2] = g[NX + 2] + (ru * s.cp[M::C_GIMB + 1] - s.du[M::C_GIMB + 1]);
+        g[NX + 0] = g[NX + 0] + (ru * s.cp[M::C_GIMB + 2] - s.du[M::C_GIMB + 2]);
     } else {
         const T rc = group_rho<M>(id, rho.geo, 2);
 #pragma unroll
@@ -772,7 +937,8 @@ __device__ __forceinline__ void step2(const NodeId& id, const Rho<T>& rho, NodeS
 // groups absent at this node are finite dummies (see group_rho).
 template <class M, class T, bool HSS = false>
 __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const NodeConst<M, T>& nc,
-                                      NodeState<M, T>& s, T ball_r, T kappa, T inv1k2) {
+                                      NodeState<M, T>& s, T ball_r, T kappa, T inv1k2,
+                                      const T* __restrict__ prm = nullptr) {
     constexpr int NX = M::NX, NU = M::NU;
     // x box
 #pragma unroll
@@ -800,6 +966,54 @@ __device__ __forceinline__ void step3(const NodeId& id, const Rho<T>& rho, const
 #pragma unroll
             for (int r = 0; r < 3; ++r) s.cp[M::C_HS + 3 * j + r] = v[r];
         }
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        const T ig = rho.inv_geo;
+        {   // glide cone, components (r_E, r_N, r_U): the axis last
+            const T kg = prm[SCP_P_GLIDE];
+            T v[3] = {s.x[1] + s.du[M::C_GLIDE + 0] * ig, s.x[2] + s.du[M::C_GLIDE + 1] * ig,
+                      s.x[0] + s.du[M::C_GLIDE + 2] * ig};
+            proj_cone<3>(kg, T(1) / (T(1) + kg * kg), v);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_GLIDE + r] = v[r];
+        }
+        {   // tilt: |(q_y, q_z)| <= sin(tilt / 2)
+            T v[2] = {s.x[8] + s.du[M::C_TILT + 0] * ig, s.x[9] + s.du[M::C_TILT + 1] * ig};
+            proj_ball2(prm[SCP_P_TILT], v);
+            s.cp[M::C_TILT + 0] = v[0];
+            s.cp[M::C_TILT + 1] = v[1];
+        }
+        {   // body-rate ball
+            T v[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[r] = s.x[10 + r] + s.du[M::C_RATE + r] * ig;
+            proj_ball3(prm[SCP_P_WMAX], v);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_RATE + r] = v[r];
+        }
+        {   // thrust magnitude upper bound
+            T v[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[r] = s.u[r] + s.du[M::C_TBALL + r] * ig;
+            proj_ball3(prm[SCP_P_TMAX], v);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_TBALL + r] = v[r];
+        }
+        {   // linearized thrust lower bound (unit normal)
+            T v[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[r] = s.u[r] + s.du[M::C_THS + r] * ig;
+            proj_halfspace(&nc.hs[0], nc.hs[3], v);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_THS + r] = v[r];
+        }
+        {   // gimbal cone, components (T_y, T_z, T_x)
+            const T kq = prm[SCP_P_GIMBAL];
+            T v[3] = {s.u[1] + s.du[M::C_GIMB + 0] * ig, s.u[2] + s.du[M::C_GIMB + 1] * ig,
+                      s.u[0] + s.du[M::C_GIMB + 2] * ig};
+            proj_cone<3>(kq, T(1) / (T(1) + kq * kq), v);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) s.cp[M::C_GIMB + r] = v[r];
+        }
     } else {
         {
             T v[3];
@@ -825,6 +1039,9 @@ template <class M>
 __device__ __forceinline__ constexpr int slot_group(int k) {
     if constexpr (M::QL) {
         return k < M::C_UBOX ? 0 : k < M::C_BALL ? 1 : k < M::C_HS ? 2 : 3 + (k - M::C_HS) / 3;
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        return k < M::C_UBOX ? 0 : k < M::C_GLIDE ? 1 : k < M::C_TILT ? 2 : k < M::C_RATE ? 3 : k < M::C_TBALL ? 4
+             : k < M::C_THS ? 5 : k < M::C_GIMB ? 6 : 7;
     } else {
         return k < M::C_UBOX ? 0 : k < M::C_CONE ? 1 : k < M::C_SOC ? 2 : 3;
     }
@@ -835,6 +1052,9 @@ template <class M>
 __device__ __forceinline__ constexpr bool slot_self_zero(int k) {
     if constexpr (M::QL) {
         return k < M::C_BALL;
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        // x box, u box, thrust ball and gimbal cone (both project 0 to 0 at node N)
+        return k < M::C_GLIDE || (k >= M::C_TBALL && k < M::C_THS) || k >= M::C_GIMB;
     } else {
         return k < M::C_CONE || k >= M::C_SOC;
     }
@@ -843,6 +1063,8 @@ template <class M>
 __device__ __forceinline__ constexpr bool slot_is_u(int k) {
     if constexpr (M::QL) {
         return k >= M::C_UBOX && k < M::C_HS;
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        return (k >= M::C_UBOX && k < M::C_GLIDE) || k >= M::C_TBALL;
     } else {
         return (k >= M::C_UBOX && k < M::C_CONE) || k >= M::C_SOC;
     }
@@ -851,6 +1073,11 @@ template <class M>
 __device__ __forceinline__ constexpr int slot_comp(int k) {
     if constexpr (M::QL) {
         return k < M::C_UBOX ? k : k < M::C_BALL ? k - M::C_UBOX : k < M::C_HS ? k - M::C_BALL : (k - M::C_HS) % 3;
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        // the cones list their components axis last: (1, 2, 0)
+        return k < M::C_UBOX ? k : k < M::C_GLIDE ? k - M::C_UBOX : k < M::C_TILT ? (k - M::C_GLIDE + 1) % 3
+             : k < M::C_RATE ? 8 + (k - M::C_TILT) : k < M::C_TBALL ? 10 + (k - M::C_RATE)
+             : k < M::C_THS ? k - M::C_TBALL : k < M::C_GIMB ? k - M::C_THS : (k - M::C_GIMB + 1) % 3;
     } else {
         return k < M::C_UBOX ? k : k < M::C_CONE ? k - M::C_UBOX : k < M::C_SOC ? k - M::C_CONE : k - M::C_SOC;
     }
@@ -1051,6 +1278,8 @@ template <class M>
 __device__ __forceinline__ constexpr int slot_comp_u(int k) {
     if constexpr (M::QL) {
         return k - M::C_UBOX;   // u box 0..NU-1, ball NU..NU+2
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        return k < M::C_GLIDE ? k - M::C_UBOX : NU_OF<M>() + (k - M::C_TBALL);   // no consensus groups
     } else {
         return k < M::C_CONE ? k - M::C_UBOX : NU_OF<M>() + (k - M::C_SOC);
     }
@@ -1200,6 +1429,18 @@ __device__ __forceinline__ T node_violation(const T* __restrict__ prm, const Nod
                 const T d0 = x[0] - o[0], d1 = x[1] - o[1], d2 = ((cyl >> j) & 1) ? T(0) : x[2] - o[2];
                 v = nmax(v, o[3] - tsqrt((d0 * d0 + d1 * d1) + d2 * d2));
             }
+        }
+    } else if constexpr (M::ID == SCP_MODEL_LANDER6) {
+        if (!id.last()) {
+            const T nt = tsqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+            v = nmax(v, nt - prm[SCP_P_TMAX]);
+            v = nmax(v, prm[SCP_P_TMIN] - nt);
+            v = nmax(v, tsqrt(u[1] * u[1] + u[2] * u[2]) - prm[SCP_P_GIMBAL] * u[0]);
+        }
+        if (!id.first()) {
+            v = nmax(v, tsqrt(x[1] * x[1] + x[2] * x[2]) - prm[SCP_P_GLIDE] * x[0]);
+            v = nmax(v, tsqrt(x[8] * x[8] + x[9] * x[9]) - prm[SCP_P_TILT]);
+            v = nmax(v, tsqrt((x[10] * x[10] + x[11] * x[11]) + x[12] * x[12]) - prm[SCP_P_WMAX]);
         }
     } else {
         if (!id.last()) {

@@ -2,8 +2,8 @@
 //
 // Node data is stored component-plane major ("SoA"): value k of node g lives at
 // planes[k * P + g], P = node count padded to a multiple of 256, so consecutive lanes of a
-// wavefront touch consecutive addresses.  Plane blocks are sized for the largest model
-// (nx = 13, nu = 4, 44 mirror slots); smaller models use a prefix of each block.  The
+// wavefront touch consecutive addresses.  Plane blocks are sized for the largest model of each
+// (nx <= 14, nu <= 4, n <= 17, 44 mirror slots); smaller models use a prefix of each block.  The
 // nominal, physical and guess blocks keep x and u adjacent (x block, then u block).
 #pragma once
 
@@ -12,31 +12,31 @@
 namespace scp {
 
 enum Plane : int {
-    PL_XBAR = 0,    // 13  nominal state
-    PL_UBAR = 13,   // 4   nominal control (row N zero)
-    PL_X = 17,      // 13  physical state
-    PL_U = 30,      // 4   physical control
-    PL_Z = 34,      // 13  dynamic auxiliary z
-    PL_LAM = 47,    // 13  lambda
-    PL_MU = 60,     // 13  mu
-    PL_DD = 73,     // 13  d_dyn = A x + B u + d
-    PL_CP = 86,     // 44  mirror copies
-    PL_DU = 130,    // 44  mirror duals
-    PL_AR = 174,    // 130 non-unit columns of A (row-major NX x NXR)
-    PL_B = 304,     // 52  B (row-major NX x NU)
-    PL_D = 356,     // 13  d
-    PL_L = 369,     // 153 packed Cholesky factor (diagonal slots hold reciprocals)
-    PL_LO = 522,    // 17  box lower bounds (x then u)
-    PL_HI = 539,    // 17  box upper bounds
-    PL_HS = 556,    // 32  half-spaces (a_x, a_y, a_z, b) per obstacle
-    PL_G0 = 588,    // 13  constant Step-1 right-hand side (x part)
-    PL_DZ = 601,    // 13  z - z_old (residual iterations)
-    PL_SP = 614,    // 17  node-local part of the dual residual vector
-    PL_RP = 631,    // 1   node primal residual
-    PL_MER = 632,   // 8   merit / metric terms of one node
-    PL_XG = 640,    // 13  initial guess of the states (restored by scp_reset)
-    PL_UG = 653,    // 4   initial guess of the controls
-    NPLANES = 657
+    PL_XBAR = 0,    // 14  nominal state
+    PL_UBAR = 14,   // 4   nominal control (row N zero)
+    PL_X = 18,      // 14  physical state
+    PL_U = 32,      // 4   physical control
+    PL_Z = 36,      // 14  dynamic auxiliary z
+    PL_LAM = 50,    // 14  lambda
+    PL_MU = 64,     // 14  mu
+    PL_DD = 78,     // 14  d_dyn = A x + B u + d
+    PL_CP = 92,     // 44  mirror copies
+    PL_DU = 136,    // 44  mirror duals
+    PL_AR = 180,    // 154 non-unit columns of A (row-major NX x NXR)
+    PL_B = 334,     // 52  B (row-major NX x NU)
+    PL_D = 386,     // 14  d
+    PL_L = 400,     // 153 packed Cholesky factor (diagonal slots hold reciprocals)
+    PL_LO = 553,    // 17  box lower bounds (x then u)
+    PL_HI = 570,    // 17  box upper bounds
+    PL_HS = 587,    // 32  half-spaces (a_x, a_y, a_z, b) per obstacle / thrust bound
+    PL_G0 = 619,    // 14  constant Step-1 right-hand side (x part)
+    PL_DZ = 633,    // 14  z - z_old (residual iterations)
+    PL_SP = 647,    // 17  node-local part of the dual residual vector
+    PL_RP = 664,    // 1   node primal residual
+    PL_MER = 665,   // 8   merit / metric terms of one node
+    PL_XG = 673,    // 14  initial guess of the states (restored by scp_reset)
+    PL_UG = 687,    // 4   initial guess of the controls
+    NPLANES = 691
 };
 
 // mirror slots of the largest model (the PL_CP / PL_DU block width)

@@ -20,7 +20,16 @@ static_assert(PL_LO - PL_L >= Dims<QMax>::NL && PL_HI - PL_LO >= QMax::NN && PL_
 static_assert(PL_G0 - PL_HS >= QMax::NHS && PL_DZ - PL_G0 >= QMax::NX && PL_SP - PL_DZ >= QMax::NX, "half-spaces");
 static_assert(PL_RP - PL_SP >= QMax::NN && PL_XG - PL_MER >= 8 && NPLANES - PL_UG >= QMax::NU &&
               PL_UG - PL_XG >= QMax::NX, "residual, merit, guess blocks");
-// node 0 of a consensus group parks its u-slot copies in the merit block
+// the 6-DOF lander (14 states, 3 controls, 34 slots) fits the same blocks
+static_assert(PL_UBAR - PL_XBAR >= Lander6::NX && PL_LAM - PL_Z >= Lander6::NX && PL_CP - PL_DD >= Lander6::NX,
+              "lander state blocks");
+static_assert(PL_B - PL_AR >= Lander6::NX * Lander6::NXR && PL_D - PL_B >= Lander6::NX * Lander6::NU &&
+              PL_L - PL_D >= Lander6::NX && Lander6::C <= MAX_C && PL_LO - PL_L >= Dims<Lander6>::NL &&
+              PL_HI - PL_LO >= Lander6::NN && PL_RP - PL_SP >= Lander6::NN && PL_G0 - PL_HS >= Lander6::NHS &&
+              PL_UG - PL_XG >= Lander6::NX && PL_DZ - PL_G0 >= Lander6::NX && PL_SP - PL_DZ >= Lander6::NX,
+              "lander blocks");
+// node 0 of a consensus group parks its u-slot copies in the merit block (the lander takes no
+// consensus groups)
 static_assert(QMax::NU + 3 <= 8 && Mars::NU + 4 <= 8, "u-slot stash");
 
 template <int NV, class T>
@@ -63,7 +72,7 @@ __device__ __forceinline__ void load_const(const Dev<T>& dv, int g, NodeConst<M,
     ldp<NX>(PL(dv, PL_D), P, g, nc.d);
     ldp<NN>(PL(dv, PL_LO), P, g, nc.lo);
     ldp<NN>(PL(dv, PL_HI), P, g, nc.hi);
-    if constexpr (M::QL) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    if constexpr (M::HSD) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
     ldp<NX>(PL(dv, PL_G0), P, g, nc.g0);
 }
 
@@ -148,7 +157,7 @@ __global__ __launch_bounds__(256) void k_lin(Dev<T> dv, KParams<T> kp) {
     stp<NX>(PL(dv, PL_D), P, g, nc.d);
     stp<M::NN>(PL(dv, PL_LO), P, g, nc.lo);
     stp<M::NN>(PL(dv, PL_HI), P, g, nc.hi);
-    if constexpr (M::QL) stp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    if constexpr (M::HSD) stp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
     stp<NX>(PL(dv, PL_G0), P, g, nc.g0);
     stp<NX>(PL(dv, PL_X), P, g, s.x);
     stp<NU>(PL(dv, PL_U), P, g, s.u);
@@ -202,6 +211,186 @@ __global__ __launch_bounds__(256) void k_step1(Dev<T> dv, KParams<T> kp) {
 }
 
 // ------------------------------------------------------------------------------------------
+// a5: Step 1 of the 6-DOF models (n = 17), four lanes per node
+// ------------------------------------------------------------------------------------------
+// At n = 17 one lane per node underfills the chip (a 1000-trajectory batch of 41 nodes makes 641
+// wavefronts for 1024 SIMDs) and every lane works through a long chain of dependent loads.  Here
+// the four lanes of a DPP group share a node.  Lane l owns the components k = 4s + l (slot s):
+// their rows of w, their columns of A and B, and their rows of the factor, so each lane loads
+// about a third of the node's data.
+//  * w rows go to every lane of the group by broadcast;
+//  * the forward substitution is right-looking: y_k comes from its owner by broadcast and every
+//    lane updates its rows below k (the same subtraction sequence as the one-lane solve);
+//  * the backward substitution sums each lane's products over its rows below k across the group;
+//  * A x + B u is summed over the group the same way, and the owner of each row stores it.
+// Rows of the factor above the diagonal are held as zeros, so no step needs a lane mask.
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) {
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, KM = M::KM, NS = 5;
+    static_assert(NN <= 4 * NS && NX <= 16, "four lanes hold the node");
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = (int)(gid >> 2), l = (int)(gid & 3);
+    NodeId id;
+    const T* prm;
+    const int tr = node_of<M>(dv, g, id, prm);   // the lanes of a group share g and leave together
+    if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
+    const int P = dv.P;
+    const T rho_eq = kp.rho_eq, rho_dyn = kp.rho_dyn, rho_geo = kp.rho_geo;
+    const bool last = id.last();
+    auto at = [&](int plane, int node) -> T { return dv.planes[(size_t)plane * P + node]; };
+
+    // w = mu_{i+1} + rho_dyn (z_{i+1} - d_i) on the owned rows (z, mu of node N+1 read as 0)
+    T wl[4], dl[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int r = 4 * s + l;
+        T zn = T(0), mn = T(0), d = T(0);
+        if (r < NX) {
+            d = at(PL_D + r, g);
+            if (!last) {
+                zn = at(PL_Z + r, g + 1);
+                mn = at(PL_MU + r, g + 1);
+            }
+        }
+        dl[s] = d;
+        wl[s] = mn + rho_dyn * (zn - d);
+    }
+    T w[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) w[r] = quad_bcast(wl[r / 4], r % 4);
+
+    // owned columns of A (non-unit part) and of B
+    T Al[4][NX], Bl[NX];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + l;
+#pragma unroll
+        for (int r = 0; r < NX; ++r) Al[s][r] = (k >= 3 && k < NX) ? at(PL_AR + r * NXR + (k - 3), g) : T(0);
+    }
+    // the control component of this lane, if any: k = NX + cu with k = l (mod 4)
+    const int cu = (l - NX % 4 + 4) % 4;
+    const bool has_u = cu < NU;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) Bl[r] = has_u ? at(PL_B + r * NU + cu, g) : T(0);
+
+    // right-hand side of the owned components, summed as in the one-lane Step 1
+    T acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = 4 * s + l;
+        T v = T(0);
+        if (k < NX) {
+            T tx = wl[s];   // unit columns of A: (A'w)_k = w_k, the lane's own row k
+            if (k >= 3) {
+                tx = T(0);
+#pragma unroll
+                for (int r = 0; r < NX; ++r) tx = tx + Al[s][r] * w[r];
+            }
+            v = (at(PL_G0 + k, g) + (rho_eq * at(PL_Z + k, g) - at(PL_LAM + k, g))) + tx;
+            v = v + (rho_geo * at(PL_CP + M::C_XBOX + k, g) - at(PL_DU + M::C_XBOX + k, g));
+            if constexpr (M::QL) {
+                if (k < 3) {
+#pragma unroll
+                    for (int j = 0; j < KM; ++j) {
+                        const T rj = group_rho<M>(id, rho_geo, 3 + j);
+                        v = v + (rj * at(PL_CP + M::C_HS + 3 * j + k, g) - at(PL_DU + M::C_HS + 3 * j + k, g));
+                    }
+                }
+            } else {
+                // lander: at most one more group per state component (glide cone on r, listed
+                // (r_E, r_N, r_U); tilt on q_y, q_z; rate ball on w)
+                const int slot = k < 3 ? M::C_GLIDE + (k + 2) % 3 : (k == 8 || k == 9) ? M::C_TILT + (k - 8)
+                               : (k >= 10 && k < 13) ? M::C_RATE + (k - 10) : -1;
+                if (slot >= 0) {
+                    const T rx = group_rho<M>(id, rho_geo, 2);
+                    v = v + (rx * at(PL_CP + slot, g) - at(PL_DU + slot, g));
+                }
+            }
+        } else if (k < NN) {
+            T tu = T(0);
+#pragma unroll
+            for (int r = 0; r < NX; ++r) tu = tu + Bl[r] * w[r];
+            v = tu + (rho_geo * at(PL_CP + M::C_UBOX + cu, g) - at(PL_DU + M::C_UBOX + cu, g));
+            if constexpr (!M::QL) {
+                // lander: thrust ball, linearized lower bound, gimbal cone (listed (T_y, T_z, T_x))
+                const T ru = group_rho<M>(id, rho_geo, 5);
+                v = v + (ru * at(PL_CP + M::C_TBALL + cu, g) - at(PL_DU + M::C_TBALL + cu, g));
+                v = v + (ru * at(PL_CP + M::C_THS + cu, g) - at(PL_DU + M::C_THS + cu, g));
+                const int sg = M::C_GIMB + (cu + 2) % 3;
+                v = v + (ru * at(PL_CP + sg, g) - at(PL_DU + sg, g));
+            }
+        }
+        acc[s] = v;
+    }
+
+    // owned rows of the factor (diagonal slots hold 1/L_kk); entries above the diagonal are 0
+    T Lr[NS][NN];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int row = 4 * s + l;
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            if (j < 4 * s + 4) Lr[s][j] = (row < NN && j <= row) ? at(PL_L + tri(row, j), g) : T(0);
+            else Lr[s][j] = T(0);
+        }
+    }
+
+    // forward substitution L y = g
+    T yl[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) yl[s] = T(0);
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+        const T yk = quad_bcast(acc[k / 4] * Lr[k / 4][k], k % 4);
+        yl[k / 4] = (l == k % 4) ? yk : yl[k / 4];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (4 * s + 3 > k) acc[s] = acc[s] - Lr[s][k] * yk;
+    }
+    // backward substitution L' x = y
+    T xl[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xl[s] = T(0);
+#pragma unroll
+    for (int k = NN - 1; k >= 0; --k) {
+        T p = T(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (4 * s + 3 > k) p = p + Lr[s][k] * xl[s];   // rows not below k hold 0 here
+        const T xk = quad_bcast((yl[k / 4] - quad_sum(p)) * Lr[k / 4][k], k % 4);
+        xl[k / 4] = (l == k % 4) ? xk : xl[k / 4];
+    }
+
+    // x, u of the owned components (u = 0 at node N), then d_dyn = A x + B u + d
+    T q[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) q[r] = T(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = 4 * s + l;
+        if (k < NX) {
+            dv.planes[(size_t)(PL_X + k) * P + g] = xl[s];
+            if (s == 0) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) q[r] = q[r] + (k == r ? xl[s] : T(0));
+            }
+#pragma unroll
+            for (int r = 0; r < NX; ++r) q[r] = q[r] + Al[s < 4 ? s : 3][r] * xl[s];
+        } else if (k < NN) {
+            const T u = last ? T(0) : xl[s];
+            dv.planes[(size_t)(PL_U + cu) * P + g] = u;
+#pragma unroll
+            for (int r = 0; r < NX; ++r) q[r] = q[r] + Bl[r] * u;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+        const T dd = quad_sum(q[r]) + dl[r / 4];
+        if (l == r % 4) dv.planes[(size_t)(PL_DD + r) * P + g] = last ? T(0) : dd;   // no interval after node N
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // a6-a8: Steps 2-4 (+ node-local residual pieces on check iterations)
 // ------------------------------------------------------------------------------------------
 template <class M, class T>
@@ -218,7 +407,7 @@ __global__ __launch_bounds__(256) void k_step234(Dev<T> dv, KParams<T> kp, int c
     NodeConst<M, T> nc;
     ldp<NN>(PL(dv, PL_LO), P, g, nc.lo);
     ldp<NN>(PL(dv, PL_HI), P, g, nc.hi);
-    if constexpr (M::QL) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
+    if constexpr (M::HSD) ldp<M::NHS>(PL(dv, PL_HS), P, g, nc.hs);
     NodeState<M, T> s;
     ldp<NX>(PL(dv, PL_X), P, g, s.x);
     ldp<NU>(PL(dv, PL_U), P, g, s.u);
@@ -241,7 +430,7 @@ __global__ __launch_bounds__(256) void k_step234(Dev<T> dv, KParams<T> kp, int c
     const T ball_r = prm[SCP_P_UBALL], kappa = prm[SCP_P_GLIDE];
     const T inv1k2 = T(1) / (T(1) + kappa * kappa);
     step2<M, T>(id, rho, s, dp);
-    step3<M, T>(id, rho, nc, s, ball_r, kappa, inv1k2);
+    step3<M, T>(id, rho, nc, s, ball_r, kappa, inv1k2, prm);
     if (grouped0) {
         // node 0 of a consensus group: u copies are averaged by k_group, which also
         // finishes Step 4 and the residual pieces of those slots; keep the old copies.
@@ -643,13 +832,22 @@ hipError_t launch_plain(PlainOp op, const Dev<T>& dv, const KParams<T>& kp, int 
             if (kmax <= 4) launch_model(Quad6<4>{});
             else launch_model(Quad6<8>{});
         }
+        if (models & 8) launch_model(Lander6{});
     };
     switch (op) {
         case PlainOp::Lin:
             each([&](auto m) { hipLaunchKernelGGL((k_lin<decltype(m), T>), gn, b, 0, s, dv, kp); });
             break;
         case PlainOp::Step1:
-            each([&](auto m) { hipLaunchKernelGGL((k_step1<decltype(m), T>), gn, b, 0, s, dv, kp); });
+            each([&](auto m) {
+                using MM = decltype(m);
+                if constexpr (MM::NN == 17) {
+                    const dim3 g4((unsigned)(((size_t)dv.n_nodes * 4 + 255) / 256));
+                    hipLaunchKernelGGL((k_step1_lanes4<MM, T>), g4, b, 0, s, dv, kp);
+                } else {
+                    hipLaunchKernelGGL((k_step1<MM, T>), gn, b, 0, s, dv, kp);
+                }
+            });
             break;
         case PlainOp::Step234:
             each([&](auto m) { hipLaunchKernelGGL((k_step234<decltype(m), T>), gn, b, 0, s, dv, kp, check); });

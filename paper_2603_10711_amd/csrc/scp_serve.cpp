@@ -263,7 +263,7 @@ bool plan_request(const scp_server* s, const scp_problem_desc* d, Layout& L, std
     q.pack = s->cfg.pack;
     if (!build_layout(&q, L, err)) return false;
     if (!L.persistent_ok) {
-        err = (L.models & 4) ? "the server runs the point-mass quadrotor and powered-descent models only"
+        err = (L.models & (4 | 8)) ? "the server runs the point-mass quadrotor and 3-DOF powered-descent models only"
                              : "request does not fit the server's workgroups (longest trajectory, or a group over 64 members)";
         return false;
     }

@@ -9,7 +9,8 @@ other code with the other.
 Every instance is a ``dict`` with the physical problem in solver units:
 
 ``model``       1 = quadrotor point mass (nx=6, nu=3), 2 = 3-DOF powered descent (nx=7, nu=4),
-                3 = 6-DOF quadrotor (nx=13: p, v, quaternion, body rates; nu=4: thrust, torques)
+                3 = 6-DOF quadrotor (nx=13: p, v, quaternion, body rates; nu=4: thrust, torques),
+                4 = 6-DOF lander (nx=14: r, v, quaternion, body rates, mass; nu=3: body thrust)
 ``N``           number of intervals (N+1 state nodes, N control nodes)
 ``h``           step size T/N
 ``x_init``      initial state (boundary condition x_0 = x_init, eq. (ocp))
@@ -20,7 +21,10 @@ Every instance is a ``dict`` with the physical problem in solver units:
 ``u_ball``      radius of the control ball ||u|| <= u_ball (quadrotor; inf = none)
 ``delta``       trust-region radius (l-inf box around the nominal)
 ``drag``, ``mscale``, ``grav``  quadrotor drag coefficient, mass scale (6-DOF: the mass), gravity
-``inertia``     (3,), 6-DOF quadrotor principal moments of inertia
+``inertia``     (3,), 6-DOF principal moments of inertia
+``arm``         (3,), 6-DOF lander: thrust point in the body frame
+``T_min``, ``T_max``, ``gimbal_tan``, ``tilt_r``, ``w_max``  6-DOF lander: thrust magnitude bounds,
+                tangent of the gimbal angle, tilt bound as ||(q_y, q_z)|| <= sin(tilt/2), rate bound
 ``obstacles``   (K, 4) obstacle centres and radii (quadrotor)
 ``cyl``         (K,) bool, optional: obstacle j is a vertical cylinder (axis along z through
                 its centre) instead of a sphere
@@ -43,8 +47,9 @@ import numpy as np
 QUAD = 1
 MARS = 2
 QUAD6 = 3
-NX = {QUAD: 6, MARS: 7, QUAD6: 13}
-NU = {QUAD: 3, MARS: 4, QUAD6: 4}
+LANDER6 = 4
+NX = {QUAD: 6, MARS: 7, QUAD6: 13, LANDER6: 14}
+NU = {QUAD: 3, MARS: 4, QUAD6: 4, LANDER6: 3}
 KMAX = 8  # most obstacles one quadrotor instance may carry
 
 G_EARTH = 9.81
@@ -230,6 +235,88 @@ def quad6_benchmark_instance(instance: int, N: int = 40, T: float = 6.0, K: int 
 def config5(n_inst: int = 1000, first: int = 0) -> list[dict]:
     """6-DOF quadrotor batch of the scalability benchmark: N = 40, three random obstacles."""
     return [quad6_benchmark_instance(i) for i in range(first, first + n_inst)]
+
+
+# 6-DOF lander (Sec. IV-B.1, unified non-dimensional units, position Up-East-North, body x along
+# the thrust axis): the paper's alpha, horizon, mass, thrust, gimbal, glide-slope, tilt and rate
+# limits and boundary states; gravity, inertia and thrust point are stated choices.
+L6_ALPHA = 0.1
+L6_TF, L6_N = 5.0, 30
+L6_M_DRY, L6_M_WET = 0.75, 2.0
+L6_T_MIN, L6_T_MAX = 0.5, 3.0
+L6_GIMBAL_DEG, L6_GLIDE_DEG, L6_TILT_DEG, L6_WMAX_DEG = 10.0, 10.0, 20.0, 30.0
+L6_GRAVITY = np.array([-1.0, 0.0, 0.0])
+L6_INERTIA = np.array([0.02, 0.1, 0.1])
+L6_ARM = np.array([-0.25, 0.0, 0.0])
+L6_R0, L6_V0 = np.array([2.0, 1.0, 0.0]), np.array([-1.0, 0.2, 0.0])
+L6_VF = np.array([-0.1, 0.0, 0.0])
+
+
+def _l6_nominal_state() -> np.ndarray:
+    x = np.zeros(14)
+    x[0:3] = L6_R0
+    x[3:6] = L6_V0
+    x[6] = 1.0
+    x[13] = L6_M_WET
+    return x
+
+
+def lander6_instance(x_init: np.ndarray | None = None, N: int = L6_N, tf: float = L6_TF, delta: float = 1.0) -> dict:
+    """6-DOF powered descent to rest-like touchdown: r_N = 0, v_N = (-0.1, 0, 0), upright and
+    not rotating (S selects every state but the mass), cost -m_N (fuel), dry mass <= m <= wet
+    mass.  Initial guess: r and v linear to the target, upright, no rotation, full mass, thrust
+    m g along the body axis."""
+    nx, nu = 14, 3
+    x0 = _l6_nominal_state() if x_init is None else np.asarray(x_init, dtype=float)
+    xf = np.zeros(nx)
+    xf[3:6] = L6_VF
+    xf[6] = 1.0
+    xf[13] = L6_M_DRY
+    t_mask = np.array([True] * 13 + [False])
+    s = np.linspace(0.0, 1.0, N + 1)[:, None]
+    x_guess = np.zeros((N + 1, nx))
+    x_guess[:, 0:6] = (1.0 - s) * x0[0:6] + s * xf[0:6]
+    x_guess[:, 6] = 1.0
+    x_guess[:, 13] = x0[13]
+    x_guess[0] = x0
+    u_guess = np.tile(np.array([x0[13] * -L6_GRAVITY[0], 0.0, 0.0]), (N, 1))
+    inf = math.inf
+    x_lo = np.full(nx, -inf)
+    x_hi = np.full(nx, inf)
+    x_lo[13], x_hi[13] = L6_M_DRY, L6_M_WET
+    qn = np.zeros(nx)
+    qn[13] = -1.0
+    return dict(
+        model=LANDER6, N=N, h=tf / N, nx=nx, nu=nu,
+        x_init=x0.copy(), x_target=xf, t_mask=t_mask,
+        Qr=np.zeros(nx), R=np.zeros(nu), Qn=np.zeros(nx), qn=qn, cN=0.0,
+        x_lo=x_lo, x_hi=x_hi, u_lo=np.full(nu, -inf), u_hi=np.full(nu, inf), u_ball=inf,
+        delta=delta, drag=0.0, mscale=1.0, grav=0.0, alpha=L6_ALPHA, gvec=L6_GRAVITY.copy(),
+        inertia=L6_INERTIA.copy(), arm=L6_ARM.copy(),
+        glide_tan=math.tan(math.radians(90.0 - L6_GLIDE_DEG)),
+        tilt_r=math.sin(math.radians(L6_TILT_DEG / 2.0)), w_max=math.radians(L6_WMAX_DEG),
+        T_min=L6_T_MIN, T_max=L6_T_MAX, gimbal_tan=math.tan(math.radians(L6_GIMBAL_DEG)),
+        obstacles=np.zeros((0, 4)), x_guess=x_guess, u_guess=u_guess, group=-1,
+    )
+
+
+def lander6_perturbed(instance: int) -> dict:
+    """Monte-Carlo member of Sec. IV-B.2: every initial state component perturbed by 5 %: a
+    nonzero component k becomes x_k (1 + 0.05 e_k), a zero one 0.05 e_k, e_k ~ U[-1, 1]
+    (draw order: the 14 components); then the quaternion is renormalized and the mass capped
+    at the wet mass."""
+    g = _rng(6, instance)
+    x = _l6_nominal_state()
+    e = g.uniform(-1.0, 1.0, 14)
+    x = np.where(x != 0.0, x * (1.0 + 0.05 * e), 0.05 * e)
+    x[6:10] /= np.linalg.norm(x[6:10])
+    x[13] = min(x[13], L6_M_WET)
+    return lander6_instance(x)
+
+
+def config6(n_inst: int = 1000, first: int = 0) -> list[dict]:
+    """6-DOF lander Monte Carlo: N = 30, horizon 5, 5 % initial-state dispersion."""
+    return [lander6_perturbed(i) for i in range(first, first + n_inst)]
 
 
 def with_scenarios(base: dict, S: int, rng: np.random.Generator, group: int) -> list[dict]:

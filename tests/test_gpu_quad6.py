@@ -150,6 +150,31 @@ def test_benchmark_batch_fullsize_fp32(B):
     prob.close()
 
 
+def test_scenario_group_fp64(B):
+    """Scenarios sharing their first control by consensus (R8) on the 6-DOF model: node 0 of the
+    group takes the averaged copies; every block against the oracle, next to a lone trajectory."""
+    base = scpgen.quad6_benchmark_instance(7, N=18)
+    insts = []
+    for m, mass in enumerate((0.9, 1.0, 1.15)):
+        d = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+        d["mscale"] = mass
+        d["group"] = 3
+        insts.append(d)
+    insts.append(scpgen.quad6_benchmark_instance(8, N=11))
+    _say("quad6 scenario group fp64")
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(3, 30, form="plain", **SCHED))
+    f = _fields(prob)
+    trajs, _ = oracle_scp(insts, 3, 30, **OSCHED)
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < TOL64
+    cp = f["copy"]   # the node-0 control copies (u box) agree across the scenarios
+    for t in (1, 2):
+        np.testing.assert_allclose(cp[prob.offsets[t], 13:17], cp[prob.offsets[0], 13:17], rtol=0, atol=1e-12)
+    prob.close()
+
+
 def test_persistent_form_and_server_refuse_the_model(B):
     insts = scpgen.config5(2)
     prob = B.Problem(insts, precision="f32")

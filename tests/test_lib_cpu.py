@@ -70,7 +70,7 @@ def test_device_bytes_and_field_widths(B):
     d64, keep2 = _desc(B, scpgen.config1(8), prec=1)
     n64 = lib.scp_problem_device_bytes(byref(d64))
     assert n32 > 0 and n64 > 1.9 * n32 * 0.9
-    assert [lib.scp_field_width(i) for i in range(16)] == [13, 4, 13, 4, 13, 13, 13, 13, 44, 44, 169, 52, 13, 17, 17, 32]
+    assert [lib.scp_field_width(i) for i in range(16)] == [14, 4, 14, 4, 14, 14, 14, 14, 44, 44, 196, 56, 14, 18, 18, 32]
     assert lib.scp_field_width(99) == 0
 
 
