@@ -11,6 +11,7 @@ oracle.
   at the bench budget: sampled trajectories against the oracle to 1e-9; in FP32 the first SCP
   iteration of the samples to 1e-4 and, at the full budget, every sample bit-identical alone and
   in the batch.
+* Edge cases: horizons N = 1, 2 and 240 in one batch (FP64, 1e-9).
 * The persistent form, the request server and consensus groups refuse the model with an error.
 
 The lander's mirror copies [x box 14][u box 3][glide 3][tilt 2][rate 3][thrust ball 3][lower
@@ -161,6 +162,22 @@ def test_monte_carlo_fullsize_fp32(B):
     defect = info[:, 6]
     _say("fp32 defect p50", float(np.median(defect)), "p90", float(np.percentile(defect, 90)))
     assert np.all(np.isfinite(defect)) and float(np.median(defect)) < 0.05
+    prob.close()
+
+
+def test_edge_horizons_fp64(B):
+    """The shortest horizons (N = 1, 2) and a long one (N = 240) of the dispersed descent."""
+    x0s = [scpgen.lander6_perturbed(50 + i)["x_init"] for i in range(3)]
+    insts = [scpgen.lander6_instance(x0s[0], N=1, tf=5.0 / 30), scpgen.lander6_instance(x0s[1], N=2, tf=10.0 / 30),
+             scpgen.lander6_instance(x0s[2], N=240, tf=5.0)]
+    _say("lander edge horizons fp64", [d["N"] for d in insts])
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(3, 20, form="plain", **SCHED))
+    f = gpu_fields(prob)
+    trajs, _ = oracle_scp(insts, 3, 20, **OSCHED)
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < TOL64
     prob.close()
 
 

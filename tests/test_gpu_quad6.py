@@ -10,6 +10,10 @@ the FP64 oracle.
   the oracle to 1e-9; and in FP32 the first SCP iteration of sampled trajectories to 1e-4 (at
   the full budget the SCP map amplifies FP32 rounding far beyond it, as for the other models)
   and every FP32 trajectory bit-identical alone and in the batch.
+* Edge cases: horizons N = 1 and 2, no obstacles and N = 300 in one batch (FP64, 1e-9); a zero
+  quaternion in one nominal (the thrust direction is undefined there) sets SCP_ST_NONFINITE on
+  that trajectory only, the others equal their lone solves bit for bit.
+* A scenario group (consensus on the first control) in FP64 to 1e-9.
 * The persistent form and the request server refuse this model with an error, not a fallback.
 
 The mirror copies of this model sit in the quadrotor layout [x box 13][u box 4][ball 3][half-
@@ -172,6 +176,43 @@ def test_scenario_group_fp64(B):
     cp = f["copy"]   # the node-0 control copies (u box) agree across the scenarios
     for t in (1, 2):
         np.testing.assert_allclose(cp[prob.offsets[t], 13:17], cp[prob.offsets[0], 13:17], rtol=0, atol=1e-12)
+    prob.close()
+
+
+def test_edge_horizons_fp64(B):
+    """The shortest horizons (N = 1, 2), no obstacles, and a long horizon (N = 300) in one batch."""
+    insts = [scpgen.quad6_benchmark_instance(30, N=1), scpgen.quad6_benchmark_instance(31, N=2),
+             scpgen.quad6_benchmark_instance(32, N=5, K=0), scpgen.quad6_benchmark_instance(33, N=300)]
+    _say("quad6 edge horizons fp64", [d["N"] for d in insts])
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(3, 20, form="plain", **SCHED))
+    f = _fields(prob)
+    trajs, _ = oracle_scp(insts, 3, 20, **OSCHED)
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < TOL64
+    prob.close()
+
+
+def test_zero_quaternion_is_flagged_and_contained(B):
+    """A nominal with a zero quaternion leaves the thrust direction undefined: that trajectory
+    reports SCP_ST_NONFINITE and its neighbours in the batch are unaffected (bit for bit)."""
+    insts = [scpgen.quad6_benchmark_instance(40, N=12), scpgen.quad6_benchmark_instance(41, N=12),
+             scpgen.quad6_benchmark_instance(42, N=9)]
+    insts[1]["x_guess"][5, 6:10] = 0.0
+    prm = B.scp_params(2, 10, form="plain", **SCHED)
+    prob = B.Problem(insts, precision="f32")
+    prob.solve(prm)
+    x, u, info = (a.cpu().numpy() for a in prob.result())
+    assert int(info[1, 5]) & B.ST_NONFINITE
+    for i in (0, 2):
+        assert not int(info[i, 5]) & B.ST_NONFINITE
+        one = B.Problem([insts[i]], precision="f32")
+        one.solve(prm)
+        x1, u1, info1 = (a.cpu().numpy() for a in one.result())
+        np.testing.assert_array_equal(x1, prob.split(x, i))
+        np.testing.assert_array_equal(info1[0], info[i])
+        one.close()
     prob.close()
 
 
