@@ -34,7 +34,8 @@ int model_bit(int m) {
 }
 const char* const kNoPersistent =
     "the persistent form needs trajectories of at most 256 nodes, consensus groups of at most 64 members and the "
-    "point-mass quadrotor or 3-DOF powered-descent model; use the plain form";
+    "point-mass quadrotor or 3-DOF powered-descent model, or a batch of 6-DOF quadrotors alone with at most 64 "
+    "nodes per trajectory and no consensus groups (resident ADMM); use the plain form";
 
 // Pack units (single trajectories or whole consensus groups) of one model into workgroups of
 // `block` lanes, first-fit decreasing by size.  Returns false if a unit does not fit.
@@ -263,6 +264,12 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
         L.n_gslots = 0;
         L.lane.assign(1, -1);
     }
+    // a batch of 6-DOF quadrotors alone, without consensus groups: ADMM resident in one workgroup
+    // per trajectory, four lanes per node
+    int max_nodes = 0;
+    for (int q = 0; q < L.n_traj; ++q) max_nodes = std::max(max_nodes, horizon[q] + 1);
+    L.resident_ok = L.models == 4 && L.n_groups == 0 && max_nodes <= RESIDENT_MAX_NODES;
+    L.resident_block = L.resident_ok ? (4 * max_nodes + 63) / 64 * 64 : 0;
     // arena
     size_t o = 0;
     L.o_traj = o; o = align_up(o + L.traj.size() * 4);
@@ -416,6 +423,17 @@ scp_status run_plain_admm(scp_problem* p, const Dev<T>& dv, const KParams<T>& kp
     return SCP_OK;
 }
 
+// ADMM of a 6-DOF quadrotor batch resident in one workgroup per trajectory, then the residual
+// reduction of its last iteration (fixed budget)
+template <class T>
+scp_status run_resident_admm(scp_problem* p, const Dev<T>& dv, const KParams<T>& kp) {
+    const Layout& L = p->L;
+    if (kp.max_iters <= 0) return SCP_OK;
+    hipError_t e = launch_resident<T>(dv, kp, L.n_traj, L.resident_block, L.kmax, p->stream);
+    if (e == hipSuccess) e = launch_plain<T>(PlainOp::Resid, dv, kp, L.models, L.kmax, 0, kp.max_iters, p->stream);
+    return hip_check(p, e, "resident ADMM launch");
+}
+
 template <class T>
 scp_status do_linearize(scp_problem* p, const admm_params* a) {
     const Dev<T>& dv = *reinterpret_cast<const Dev<T>*>(p->prec == SCP_F32 ? (const void*)&p->df : (const void*)&p->dd);
@@ -439,13 +457,14 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
     kp.has_groups = L.n_groups > 0 ? 1 : 0;
     hipError_t e = launch_plain<T>(PlainOp::Reset, dv, kp, L.models, L.kmax, 1, 0, p->stream);
     if (e != hipSuccess) return hip_check(p, e, "reset launch");
-    if (s->form == SCP_FORM_PLAIN) {
+    const bool resident = s->form == SCP_FORM_PERSISTENT && !L.persistent_ok && L.resident_ok;
+    if (s->form == SCP_FORM_PLAIN || resident) {
         double f = 1.0;
         for (int k = 0; k < s->scp_iters; ++k, f *= kp.sched_q) {
             scale_rho(kp, f);
             e = launch_plain<T>(PlainOp::Lin, dv, kp, L.models, L.kmax, 0, 0, p->stream);
             if (e != hipSuccess) return hip_check(p, e, "linearize launch");
-            scp_status st = run_plain_admm<T>(p, dv, kp);
+            scp_status st = resident ? run_resident_admm<T>(p, dv, kp) : run_plain_admm<T>(p, dv, kp);
             if (st != SCP_OK) return st;
             e = launch_plain<T>(PlainOp::Accept, dv, kp, L.models, L.kmax, 0, 0, p->stream);
             if (e != hipSuccess) return hip_check(p, e, "accept launch");
@@ -627,8 +646,11 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
     if (prm->form != SCP_FORM_PLAIN && prm->form != SCP_FORM_PERSISTENT) return fail(p, SCP_ERR_ARG, "invalid form");
     if (prm->graph != 0 && prm->graph != 1) return fail(p, SCP_ERR_ARG, "graph must be 0 or 1");
     if (!(prm->rho_final >= 0.0)) return fail(p, SCP_ERR_ARG, "rho_final must be >= 0");
-    if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok)
+    if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && !p->L.resident_ok)
         return fail(p, SCP_ERR_UNSUPPORTED, kNoPersistent);
+    if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && prm->admm.check_every > 0)
+        return fail(p, SCP_ERR_UNSUPPORTED, "the resident ADMM of 6-DOF quadrotor batches runs fixed budgets "
+                                             "(check_every = 0)");
     scp_status st = SCP_OK;
     if (!prm->graph) {
         st = p->prec == SCP_F32 ? do_solve<float>(p, prm) : do_solve<double>(p, prm);

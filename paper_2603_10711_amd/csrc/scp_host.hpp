@@ -18,6 +18,10 @@ struct Layout {
     int models = 0, kmax = 0;
     int block = 0, n_wg = 0;
     bool persistent_ok = false;
+    // 6-DOF quadrotor batches: ADMM resident in one workgroup per trajectory of resident_block
+    // lanes (four per node)
+    bool resident_ok = false;
+    int resident_block = 0;
     int n_groups = 0;
     size_t esz = 4;
     // byte offsets inside the arena

@@ -45,6 +45,9 @@ constexpr int MAX_C = 44;
 // request server run (point-mass quadrotor, powered descent); their workgroup exchange arrays
 // are sized by these.
 constexpr int PERSIST_MAX_NX = 7;
+// Longest trajectory (nodes) whose ADMM iterations run resident in one workgroup (6-DOF quadrotor,
+// four lanes per node, at most 256 lanes)
+constexpr int RESIDENT_MAX_NODES = 64;
 constexpr int PERSIST_MAX_C = 36;
 
 // merit / metric term slots inside PL_MER

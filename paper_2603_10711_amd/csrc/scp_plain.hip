@@ -278,13 +278,14 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int k = 4 * s + l;
+        const int s4 = s < 4 ? s : 3;   // state components sit in slots 0..3
         T v = T(0);
         if (k < NX) {
-            T tx = wl[s];   // unit columns of A: (A'w)_k = w_k, the lane's own row k
+            T tx = wl[s4];   // unit columns of A: (A'w)_k = w_k, the lane's own row k
             if (k >= 3) {
                 tx = T(0);
 #pragma unroll
-                for (int r = 0; r < NX; ++r) tx = tx + Al[s][r] * w[r];
+                for (int r = 0; r < NX; ++r) tx = tx + Al[s4][r] * w[r];
             }
             v = (at(PL_G0 + k, g) + (rho_eq * at(PL_Z + k, g) - at(PL_LAM + k, g))) + tx;
             v = v + (rho_geo * at(PL_CP + M::C_XBOX + k, g) - at(PL_DU + M::C_XBOX + k, g));
@@ -387,6 +388,320 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
     for (int r = 0; r < NX; ++r) {
         const T dd = quad_sum(q[r]) + dl[r / 4];
         if (l == r % 4) dv.planes[(size_t)(PL_DD + r) * P + g] = last ? T(0) : dd;   // no interval after node N
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// a5-a8 of the 6-DOF quadrotor resident in one workgroup per trajectory
+// ------------------------------------------------------------------------------------------
+// The plain kernels stream every node from HBM twice per ADMM iteration.  Here one workgroup holds
+// a whole trajectory (N + 1 <= 64 nodes, four lanes per node with the components split as in
+// k_step1_lanes4) and runs all ADMM iterations of an SCP iteration with the node's factor rows,
+// A and B columns, box bounds and ADMM state in registers.  Nodes are coupled only through z and
+// mu of node i+1 (Step 1) and d_dyn of node i-1 (Step 2); those rows go through LDS, and two
+// workgroup barriers per iteration order the writes and reads.  Every lane of the workgroup
+// reaches every barrier: lanes past the trajectory's last node compute on zeros and store
+// nothing.  The arithmetic of every component is that of k_step1_lanes4 and k_step234.  The last
+// iteration also leaves the node-local residual pieces for k_resid, and the final iterate goes
+// back to the planes.  Fixed budgets only (no residual test inside).
+template <class T, int KM>
+__global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<T> kp) {
+    using M = Quad6<KM>;
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = 5, MAXN = RESIDENT_MAX_NODES;
+    __shared__ T sz[MAXN][16], smu[MAXN][16], sdd[MAXN][16];
+    const int tr = blockIdx.x;
+    if (tr >= dv.n_traj || dv.flags[tr * FL_FIELDS + FL_DONE]) return;   // uniform over the workgroup
+    const int* rec = dv.traj + tr * TR_FIELDS;
+    const int N = rec[TR_N], off = rec[TR_OFF];
+    const int t = threadIdx.x, i = t >> 2, l = t & 3;
+    const bool live = i <= N;
+    const int g = off + (live ? i : 0);
+    NodeId id;
+    id.i = live ? i : 0;
+    id.N = N;
+    id.K = rec[TR_K];
+    id.ball = false;
+    const bool first = id.first(), last = id.last();
+    const int P = dv.P;
+    const T rho_eq = kp.rho_eq, rho_dyn = kp.rho_dyn, rho_geo = kp.rho_geo;
+    const T inv_geo = T(1) / kp.rho_geo, inv_sum = T(1) / (kp.rho_eq + kp.rho_dyn);
+    auto at = [&](int plane) -> T { return live ? dv.planes[(size_t)plane * P + g] : T(0); };
+    auto put = [&](int plane, T v) {
+        if (live) dv.planes[(size_t)plane * P + g] = v;
+    };
+    const int cu = (l - NX % 4 + 4) % 4;   // control component of this lane (every lane has one)
+
+    // node data of the owned components
+    T dl[4], zl[4], laml[4], mul[4], g0l[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int r = 4 * s + l;
+        const bool ok = r < NX;
+        dl[s] = ok ? at(PL_D + r) : T(0);
+        zl[s] = ok ? at(PL_Z + r) : T(0);
+        laml[s] = ok ? at(PL_LAM + r) : T(0);
+        mul[s] = ok ? at(PL_MU + r) : T(0);
+        g0l[s] = ok ? at(PL_G0 + r) : T(0);
+    }
+    T Al[4][NX], Bl[NX];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + l;
+#pragma unroll
+        for (int r = 0; r < NX; ++r) Al[s][r] = (k >= 3 && k < NX) ? at(PL_AR + r * NXR + (k - 3)) : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) Bl[r] = at(PL_B + r * NU + cu);
+    T cpb[NS], dub[NS], lol[NS], hil[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = 4 * s + l;
+        const bool ok = k < NN;
+        const int bs = k < NX ? M::C_XBOX + k : M::C_UBOX + (k - NX);
+        cpb[s] = ok ? at(PL_CP + bs) : T(0);
+        dub[s] = ok ? at(PL_DU + bs) : T(0);
+        lol[s] = ok ? at(PL_LO + k) : T(0);
+        hil[s] = ok ? at(PL_HI + k) : T(0);
+    }
+    T Lr[NS][NN];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int row = 4 * s + l;
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            if (j < 4 * s + 4) Lr[s][j] = (row < NN && j <= row) ? at(PL_L + tri(row, j)) : T(0);
+            else Lr[s][j] = T(0);
+        }
+    }
+    T own[KM], cph[KM], duh[KM];   // half-space j: a_l (l < 3) or b (l = 3); copy and dual of position l
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        own[j] = at(PL_HS + 4 * j + l);
+        cph[j] = l < 3 ? at(PL_CP + M::C_HS + 3 * j + l) : T(0);
+        duh[j] = l < 3 ? at(PL_DU + M::C_HS + 3 * j + l) : T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int r = 4 * s + l;
+        if (live && r < NX) {
+            sz[i][r] = zl[s];
+            smu[i][r] = mul[s];
+        }
+    }
+    const int K = kp.max_iters;
+    T xl[NS], dds[4];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xl[s] = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dds[s] = T(0);
+    __syncthreads();
+
+    for (int it = 1; it <= K; ++it) {
+        const bool chk = it == K;
+        // ---- Step 1 ----
+        T wl[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = 4 * s + l;
+            T zn = T(0), mn = T(0);
+            if (live && r < NX && !last) {
+                zn = sz[i + 1][r];
+                mn = smu[i + 1][r];
+            }
+            wl[s] = mn + rho_dyn * (zn - dl[s]);
+        }
+        T w[NX];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) w[r] = quad_bcast(wl[r / 4], r % 4);
+        T acc[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = 4 * s + l;
+            const int s4 = s < 4 ? s : 3;   // state components sit in slots 0..3
+            T v = T(0);
+            if (k < NX) {
+                T tx = wl[s4];
+                if (k >= 3) {
+                    tx = T(0);
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) tx = tx + Al[s4][r] * w[r];
+                }
+                v = (g0l[s4] + (rho_eq * zl[s4] - laml[s4])) + tx;
+                v = v + (rho_geo * cpb[s] - dub[s]);
+                if (k < 3) {
+#pragma unroll
+                    for (int j = 0; j < KM; ++j) {
+                        const T rj = group_rho<M>(id, rho_geo, 3 + j);
+                        v = v + (rj * cph[j] - duh[j]);
+                    }
+                }
+            } else if (k < NN) {
+                T tu = T(0);
+#pragma unroll
+                for (int r = 0; r < NX; ++r) tu = tu + Bl[r] * w[r];
+                v = tu + (rho_geo * cpb[s] - dub[s]);
+            }
+            acc[s] = v;
+        }
+        T yl[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) yl[s] = T(0);
+#pragma unroll
+        for (int k = 0; k < NN; ++k) {
+            const T yk = quad_bcast(acc[k / 4] * Lr[k / 4][k], k % 4);
+            yl[k / 4] = (l == k % 4) ? yk : yl[k / 4];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (4 * s + 3 > k) acc[s] = acc[s] - Lr[s][k] * yk;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) xl[s] = T(0);
+#pragma unroll
+        for (int k = NN - 1; k >= 0; --k) {
+            T p = T(0);
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (4 * s + 3 > k) p = p + Lr[s][k] * xl[s];
+            const T xk = quad_bcast((yl[k / 4] - quad_sum(p)) * Lr[k / 4][k], k % 4);
+            xl[k / 4] = (l == k % 4) ? xk : xl[k / 4];
+        }
+        T q[NX];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) q[r] = T(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = 4 * s + l;
+            if (k < NX) {
+                if (s == 0) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) q[r] = q[r] + (k == r ? xl[s] : T(0));
+                }
+#pragma unroll
+                for (int r = 0; r < NX; ++r) q[r] = q[r] + Al[s < 4 ? s : 3][r] * xl[s];
+            } else if (k < NN) {
+                if (last) xl[s] = T(0);
+#pragma unroll
+                for (int r = 0; r < NX; ++r) q[r] = q[r] + Bl[r] * xl[s];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+            const T dd = quad_sum(q[r]) + dl[r / 4];
+            if (l == r % 4) {
+                dds[r / 4] = last ? T(0) : dd;   // no interval after node N
+                if (live) sdd[i][r] = dds[r / 4];
+            }
+        }
+        __syncthreads();
+        // ---- Steps 2-4 ----
+        T pm = T(0), sp0 = T(0), xpos = T(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = 4 * s + l;
+            const int s4 = s < 4 ? s : 3;
+            if (k < NX) {
+                const T x = xl[s], z0 = zl[s4];
+                const T dp = (!first && live) ? sdd[i - 1][k] : T(0);
+                const T z = first ? z0 : (((rho_eq * x + laml[s4]) + rho_dyn * dp) - mul[s4]) * inv_sum;
+                const T cpo = cpb[s];
+                const T cp = clampv(x + dub[s] * inv_geo, lol[s], hil[s]);
+                if (!first) {
+                    laml[s4] = laml[s4] + rho_eq * (x - z);
+                    mul[s4] = mul[s4] + rho_dyn * (z - dp);
+                }
+                dub[s] = dub[s] + rho_geo * (x - cp);
+                cpb[s] = cp;
+                zl[s4] = z;
+                if (chk) {
+                    const T dz = z - z0;
+                    const T spk = (first ? T(0) : rho_eq * dz) + rho_geo * (cp - cpo);
+                    put(PL_DZ + k, dz);
+                    if (s == 0 && k < 3) sp0 = spk;
+                    else put(PL_SP + k, spk);
+                    if (!first) {
+                        pm = nmax(pm, tabs(x - z));
+                        pm = nmax(pm, tabs(z - dp));
+                    }
+                    pm = nmax(pm, tabs(x - cp));
+                }
+                if (s == 0) xpos = x;
+            } else if (k < NN) {
+                const T u = xl[s];
+                const T cpo = cpb[s];
+                T cp = clampv(u + dub[s] * inv_geo, lol[s], hil[s]);
+                const bool act = !last;
+                dub[s] = act ? dub[s] + rho_geo * (u - cp) : T(0);
+                if (!act) cp = T(0);
+                cpb[s] = cp;
+                if (chk) {
+                    put(PL_SP + NX + cu, act ? rho_geo * (cp - cpo) : T(0));
+                    if (act) pm = nmax(pm, tabs(u - cp));
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+            if (first || j >= id.K) continue;   // uniform over the four lanes of a node
+            const T a0 = quad_bcast(own[j], 0), a1 = quad_bcast(own[j], 1), a2 = quad_bcast(own[j], 2);
+            const T b = quad_bcast(own[j], 3);
+            const T v = xpos + duh[j] * inv_geo;
+            const T v0 = quad_bcast(v, 0), v1 = quad_bcast(v, 1), v2 = quad_bcast(v, 2);
+            const T tt = tmaxv(T(0), b - ((a0 * v0 + a1 * v1) + a2 * v2));
+            const T cp = v + tt * own[j];
+            if (l < 3) {
+                const T cpo = cph[j];
+                duh[j] = duh[j] + rho_geo * (xpos - cp);
+                cph[j] = cp;
+                if (chk) {
+                    sp0 = sp0 + rho_geo * (cp - cpo);
+                    pm = nmax(pm, tabs(xpos - cp));
+                }
+            }
+        }
+        if (chk) {
+            if (l < 3) put(PL_SP + l, sp0);
+            pm = nmax(pm, quad_perm<0xB1>(pm));
+            pm = nmax(pm, quad_perm<0x4E>(pm));
+            if (l == 0) put(PL_RP, pm);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = 4 * s + l;
+            if (live && r < NX) {
+                sz[i][r] = zl[s];
+                smu[i][r] = mul[s];
+            }
+        }
+        __syncthreads();
+    }
+    if (K == 0) return;
+    // the final iterate back to the planes
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = 4 * s + l;
+        const int s4 = s < 4 ? s : 3;
+        if (k < NX) {
+            put(PL_X + k, xl[s]);
+            put(PL_Z + k, zl[s4]);
+            put(PL_LAM + k, laml[s4]);
+            put(PL_MU + k, mul[s4]);
+            put(PL_DD + k, dds[s4]);
+            put(PL_CP + M::C_XBOX + k, cpb[s]);
+            put(PL_DU + M::C_XBOX + k, dub[s]);
+        } else if (k < NN) {
+            put(PL_U + cu, xl[s]);
+            put(PL_CP + M::C_UBOX + cu, cpb[s]);
+            put(PL_DU + M::C_UBOX + cu, dub[s]);
+        }
+    }
+    if (l < 3 && !first) {
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+            if (j < id.K) {
+                put(PL_CP + M::C_HS + 3 * j + l, cph[j]);
+                put(PL_DU + M::C_HS + 3 * j + l, duh[j]);
+            }
+        }
     }
 }
 
@@ -884,8 +1199,19 @@ hipError_t launch_gather(const Dev<T>& dv, int plane, int width, int mode, T* ou
     return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_resident(const Dev<T>& dv, const KParams<T>& kp, int n_traj, int block, int kmax, hipStream_t s) {
+    if (n_traj <= 0) return hipSuccess;
+    if (block <= 0 || block > 256 || block % 64 != 0 || block > 4 * RESIDENT_MAX_NODES) return hipErrorInvalidValue;
+    if (kmax <= 4) hipLaunchKernelGGL((k_admm_quad6_resident<T, 4>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+    else hipLaunchKernelGGL((k_admm_quad6_resident<T, 8>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+    return hipGetLastError();
+}
+
 template hipError_t launch_plain<float>(PlainOp, const Dev<float>&, const KParams<float>&, int, int, int, int, hipStream_t);
 template hipError_t launch_plain<double>(PlainOp, const Dev<double>&, const KParams<double>&, int, int, int, int, hipStream_t);
+template hipError_t launch_resident<float>(const Dev<float>&, const KParams<float>&, int, int, int, hipStream_t);
+template hipError_t launch_resident<double>(const Dev<double>&, const KParams<double>&, int, int, int, hipStream_t);
 template hipError_t launch_gather<float>(const Dev<float>&, int, int, int, float*, hipStream_t);
 template hipError_t launch_gather<double>(const Dev<double>&, int, int, int, double*, hipStream_t);
 

@@ -14,7 +14,11 @@ the FP64 oracle.
   quaternion in one nominal (the thrust direction is undefined there) sets SCP_ST_NONFINITE on
   that trajectory only, the others equal their lone solves bit for bit.
 * A scenario group (consensus on the first control) in FP64 to 1e-9.
-* The persistent form and the request server refuse this model with an error, not a fallback.
+* The persistent form of this model keeps the ADMM iterations resident in one workgroup per
+  trajectory (four lanes per node); it performs the plain kernels' operations in their order, so
+  both forms give the same bits (FP32 and FP64, full budget), and it meets the oracle bars above.
+  It refuses trajectories over 64 nodes, consensus groups and residual-test cadences; the request
+  server refuses the model.
 
 The mirror copies of this model sit in the quadrotor layout [x box 13][u box 4][ball 3][half-
 space k: 3 each]; the ball slots never hold a group and must read 0.  They are dropped before the
@@ -82,11 +86,12 @@ def test_admm_fixed_iterations(B, prec, tol):
     prob.close()
 
 
-def test_parameter_study_scene_fp64(B):
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_parameter_study_scene_fp64(B, form):
     insts = [scpgen.quad6_scene()]
-    _say("quad6 scene fp64 20x200")
+    _say("quad6 scene fp64 20x200", form)
     prob = B.Problem(insts, precision="f64")
-    prob.solve(B.scp_params(20, 200, form="plain", **SCHED))
+    prob.solve(B.scp_params(20, 200, form=form, **SCHED))
     f = _fields(prob)
     _, _, info = prob.result()
     trajs, oinfo = oracle_scp(insts, 20, 200, **OSCHED)
@@ -108,11 +113,12 @@ def test_parameter_study_scene_fp64(B):
 SAMPLE = [0, 137, 999]
 
 
-def test_benchmark_batch_fullsize_fp64_samples(B):
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_benchmark_batch_fullsize_fp64_samples(B, form):
     insts = scpgen.config5(1000)
-    _say("quad6 1000 x 41 fp64 20x200")
+    _say("quad6 1000 x 41 fp64 20x200", form)
     prob = B.Problem(insts, precision="f64")
-    prob.solve(B.scp_params(20, 200, form="plain", **SCHED))
+    prob.solve(B.scp_params(20, 200, form=form, **SCHED))
     x, u, info = (a.cpu().numpy() for a in prob.result())
     for i in SAMPLE:
         (t,), _ = oracle_scp([insts[i]], 20, 200, **OSCHED)
@@ -124,11 +130,12 @@ def test_benchmark_batch_fullsize_fp64_samples(B):
     prob.close()
 
 
-def test_benchmark_batch_fullsize_fp32(B):
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_benchmark_batch_fullsize_fp32(B, form):
     insts = scpgen.config5(1000)
-    _say("quad6 1000 x 41 fp32 first SCP iteration")
+    _say("quad6 1000 x 41 fp32 first SCP iteration", form)
     prob = B.Problem(insts, precision="f32")
-    prob.solve(B.scp_params(1, 200, form="plain", **SCHED))
+    prob.solve(B.scp_params(1, 200, form=form, **SCHED))
     f = _fields(prob)
     for i in SAMPLE:
         (t,), _ = oracle_scp([insts[i]], 1, 200, **OSCHED)
@@ -137,7 +144,7 @@ def test_benchmark_batch_fullsize_fp32(B):
         assert max(worst.values()) < TOL32
     # full budget: every trajectory alone equals its row in the batch, bit for bit
     prob.reset()
-    prm = B.scp_params(20, 200, form="plain", **SCHED)
+    prm = B.scp_params(20, 200, form=form, **SCHED)
     prob.solve(prm)
     x, u, info = (a.cpu().numpy() for a in prob.result())
     for i in SAMPLE:
@@ -216,10 +223,54 @@ def test_zero_quaternion_is_flagged_and_contained(B):
     prob.close()
 
 
-def test_persistent_form_and_server_refuse_the_model(B):
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_resident_and_plain_forms_agree_bitwise(B, prec):
+    insts = scpgen.config5(160)
+    prm = dict(**SCHED)
+    out = {}
+    for form in ("plain", "persistent"):
+        prob = B.Problem(insts, precision=prec)
+        prob.solve(B.scp_params(20, 200, form=form, **prm))
+        f = gpu_fields(prob, ("x", "u", "z", "lam", "mu", "copy", "dual"))
+        x, u, info = (a.cpu().numpy() for a in prob.result())
+        out[form] = (f, x, u, info)
+        prob.close()
+    (fp, xp, up, ip), (fr, xr, ur, ir) = out["plain"], out["persistent"]
+    for k in fp:
+        np.testing.assert_array_equal(fr[k], fp[k], err_msg=k)
+    np.testing.assert_array_equal(xr, xp)
+    np.testing.assert_array_equal(ur, up)
+    np.testing.assert_array_equal(ir, ip)
+
+
+def test_resident_edge_horizons_fp64(B):
+    """Horizons N = 1, 2, 5 (no obstacles) and 63 (the longest resident trajectory) together."""
+    insts = [scpgen.quad6_benchmark_instance(60, N=1), scpgen.quad6_benchmark_instance(61, N=2),
+             scpgen.quad6_benchmark_instance(62, N=5, K=0), scpgen.quad6_benchmark_instance(63, N=63)]
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(3, 20, form="persistent", **SCHED))
+    f = _fields(prob)
+    trajs, _ = oracle_scp(insts, 3, 20, **OSCHED)
+    worst = compare(prob, f, insts, trajs)
+    _say("resident edge", worst)
+    assert max(worst.values()) < TOL64
+    prob.close()
+
+
+def test_persistent_form_limits_and_server_refuse(B):
+    long = [scpgen.quad6_benchmark_instance(70, N=64)]        # 65 nodes: over the resident limit
+    prob = B.Problem(long, precision="f32")
+    with pytest.raises(RuntimeError, match="64 nodes"):
+        prob.solve(B.scp_params(2, 10, form="persistent"))
+    prob.close()
     insts = scpgen.config5(2)
     prob = B.Problem(insts, precision="f32")
-    with pytest.raises(RuntimeError, match="plain form"):
+    with pytest.raises(RuntimeError, match="fixed budgets"):
+        prob.solve(B.scp_params(2, 10, form="persistent", check_every=5, eps=1e-4))
+    prob.close()
+    grouped = [dict(d, group=2) for d in [scpgen.quad6_benchmark_instance(71, N=9)] * 2]
+    prob = B.Problem(grouped, precision="f32")
+    with pytest.raises(RuntimeError, match="64 nodes"):
         prob.solve(B.scp_params(2, 10, form="persistent"))
     prob.close()
     srv = B.Server(B.scp_params(2, 10), precision="f32", block=256, max_nodes=1 << 12, max_traj=16, max_wg=16,
