@@ -76,11 +76,11 @@ def workload(name: str):
                          "1e2 -> 1e3 geometric, trust region 1, FP32, ADMM resident per trajectory")
     if name == "lander6_1000":
         return dict(name=name, insts=scpgen.config6(1000), scp=20, admm=200, rho=100.0, rho_final=1e3, prec="f32",
-                    plain_only=True,
+                    plain_only=True, form="persistent",
                     desc="6-DOF powered-descent Monte Carlo (14 states, body-frame thrust, gimbal, tilt, rate and "
                          "glide-slope limits, linearized lower thrust bound): 1000 descents with 5% initial "
                          "dispersion, N=30, horizon 5, 20 SCP x 200 ADMM, rho 1e2 -> 1e3 geometric, trust region "
-                         "1, FP32, plain form")
+                         "1, FP32, ADMM resident per trajectory")
     if name == "mix2048":
         return dict(name=name, insts=scpgen.config3(2048), scp=15, admm=200, rho=1.0, prec="f32", eps=1e-4,
                     cadences=(1, 5, 10, 25),
@@ -221,9 +221,9 @@ def load_pmc(wl_name: str, khash: str):
 def plain_main(a, wl, cpu):
     """The 6-DOF workloads: every step is a fresh solve (scp_reset, then scp_solve replayed as one
     hipGraph on its own stream), timed with HIP events on that stream; the unit of the roofline is
-    one solve (one graph launch).  Plain form (lander): the ADMM kernels stream the node state
+    one solve (one graph launch).  Plain form: the ADMM kernels stream the node state
     from HBM, so the bound is HBM bandwidth and the algorithmic bytes are node-iterations x
-    bytes_per_node_iter.  Resident form (quadrotor): the ADMM state stays in registers, so the
+    bytes_per_node_iter.  Resident form (the default for both): the ADMM state stays in registers, so the
     bound is the vector ALU (algorithmic flops, as for the persistent kernel); the plain form is
     timed beside it."""
     import torch
@@ -295,7 +295,7 @@ def plain_main(a, wl, cpu):
         peak = PEAK_FP32_TFLOPS if wl["prec"] == "f32" else PEAK_FP64_TFLOPS
         roof = {"bound": "alu", "achieved": round(tf, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
                 "traffic": traffic,
-                "kernel": "one solve (hipGraph of k_lin, k_admm_quad6_resident, k_resid, k_acc_* per SCP iteration)",
+                "kernel": "one solve (hipGraph of k_lin, k_admm_resident, k_resid, k_acc_* per SCP iteration)",
                 "flops_per_launch": flops, "kernel_ms": round(kernel_ms, 4)}
     out = {
         "metric": METRIC, "value": round(n * a.steps / wall, 1), "unit": "solves/s", "n_gpus": 1,

@@ -34,7 +34,7 @@ int model_bit(int m) {
 }
 const char* const kNoPersistent =
     "the persistent form needs trajectories of at most 256 nodes, consensus groups of at most 64 members and the "
-    "point-mass quadrotor or 3-DOF powered-descent model, or a batch of 6-DOF quadrotors alone with at most 64 "
+    "point-mass quadrotor or 3-DOF powered-descent model, or a batch of one 6-DOF model alone with at most 64 "
     "nodes per trajectory and no consensus groups (resident ADMM); use the plain form";
 
 // Pack units (single trajectories or whole consensus groups) of one model into workgroups of
@@ -264,11 +264,11 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
         L.n_gslots = 0;
         L.lane.assign(1, -1);
     }
-    // a batch of 6-DOF quadrotors alone, without consensus groups: ADMM resident in one workgroup
+    // a batch of one 6-DOF model alone, without consensus groups: ADMM resident in one workgroup
     // per trajectory, four lanes per node
     int max_nodes = 0;
     for (int q = 0; q < L.n_traj; ++q) max_nodes = std::max(max_nodes, horizon[q] + 1);
-    L.resident_ok = L.models == 4 && L.n_groups == 0 && max_nodes <= RESIDENT_MAX_NODES;
+    L.resident_ok = (L.models == 4 || L.models == 8) && L.n_groups == 0 && max_nodes <= RESIDENT_MAX_NODES;
     L.resident_block = L.resident_ok ? (4 * max_nodes + 63) / 64 * 64 : 0;
     // arena
     size_t o = 0;
@@ -423,13 +423,13 @@ scp_status run_plain_admm(scp_problem* p, const Dev<T>& dv, const KParams<T>& kp
     return SCP_OK;
 }
 
-// ADMM of a 6-DOF quadrotor batch resident in one workgroup per trajectory, then the residual
+// ADMM of a 6-DOF batch resident in one workgroup per trajectory, then the residual
 // reduction of its last iteration (fixed budget)
 template <class T>
 scp_status run_resident_admm(scp_problem* p, const Dev<T>& dv, const KParams<T>& kp) {
     const Layout& L = p->L;
     if (kp.max_iters <= 0) return SCP_OK;
-    hipError_t e = launch_resident<T>(dv, kp, L.n_traj, L.resident_block, L.kmax, p->stream);
+    hipError_t e = launch_resident<T>(dv, kp, L.n_traj, L.resident_block, L.models, L.kmax, p->stream);
     if (e == hipSuccess) e = launch_plain<T>(PlainOp::Resid, dv, kp, L.models, L.kmax, 0, kp.max_iters, p->stream);
     return hip_check(p, e, "resident ADMM launch");
 }
@@ -649,7 +649,7 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && !p->L.resident_ok)
         return fail(p, SCP_ERR_UNSUPPORTED, kNoPersistent);
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && prm->admm.check_every > 0)
-        return fail(p, SCP_ERR_UNSUPPORTED, "the resident ADMM of 6-DOF quadrotor batches runs fixed budgets "
+        return fail(p, SCP_ERR_UNSUPPORTED, "the resident ADMM of 6-DOF batches runs fixed budgets "
                                              "(check_every = 0)");
     scp_status st = SCP_OK;
     if (!prm->graph) {

@@ -23,11 +23,13 @@ template <class T>
 hipError_t launch_persistent(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int block, int models, int kmax,
                              hipStream_t s);
 
-// ADMM iterations of a 6-DOF quadrotor batch resident in one workgroup per trajectory
-// (`block` = 4 (N_max + 1) lanes rounded up to 64, at most 256): kp.max_iters iterations, fixed
-// budget; the last one leaves the residual pieces that the Resid op completes.
+// ADMM iterations of a batch of one 6-DOF model (models: 4 quadrotor, 8 lander) resident in one
+// workgroup per trajectory (`block` = 4 (N_max + 1) lanes rounded up to 64, at most 256):
+// kp.max_iters iterations, fixed budget; the last one leaves the residual pieces that the Resid
+// op completes.
 template <class T>
-hipError_t launch_resident(const Dev<T>& dv, const KParams<T>& kp, int n_traj, int block, int kmax, hipStream_t s);
+hipError_t launch_resident(const Dev<T>& dv, const KParams<T>& kp, int n_traj, int block, int models, int kmax,
+                           hipStream_t s);
 
 // Static LDS of one persistent workgroup of `block` lanes (element size esz) for quadrotor
 // launches with up to 8 obstacles, the largest workgroup state; 0 for an unsupported size.

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 }
 
 // ------------------------------------------------------------------------------------------
-// a5-a8 of the 6-DOF quadrotor resident in one workgroup per trajectory
+// a5-a8 of the 6-DOF models resident in one workgroup per trajectory
 // ------------------------------------------------------------------------------------------
 // The plain kernels stream every node from HBM twice per ADMM iteration.  Here one workgroup holds
 // a whole trajectory (N + 1 <= 64 nodes, four lanes per node with the components split as in
@@ -403,11 +403,15 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 // reaches every barrier: lanes past the trajectory's last node compute on zeros and store
 // nothing.  The arithmetic of every component is that of k_step1_lanes4 and k_step234.  The last
 // iteration also leaves the node-local residual pieces for k_resid, and the final iterate goes
-// back to the planes.  Fixed budgets only (no residual test inside).
-template <class T, int KM>
-__global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<T> kp) {
-    using M = Quad6<KM>;
+// back to the planes.  Fixed budgets only (no residual test inside).  The lander's sets that
+// couple components (cones, balls, the thrust half-space) are projected by every lane of the node
+// on the components broadcast from their owners; each owner keeps its own component.
+template <class M, class T>
+__global__ __launch_bounds__(256) void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = 5, MAXN = RESIDENT_MAX_NODES;
+    constexpr int KM = M::KM, KA = KM > 0 ? KM : 1;
+    constexpr bool LD = M::ID == SCP_MODEL_LANDER6;
+    static_assert(NN <= 4 * NS && NX <= 16 && (M::QL || LD), "6-DOF models");
     __shared__ T sz[MAXN][16], smu[MAXN][16], sdd[MAXN][16];
     const int tr = blockIdx.x;
     if (tr >= dv.n_traj || dv.flags[tr * FL_FIELDS + FL_DONE]) return;   // uniform over the workgroup
@@ -425,11 +429,13 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
     const int P = dv.P;
     const T rho_eq = kp.rho_eq, rho_dyn = kp.rho_dyn, rho_geo = kp.rho_geo;
     const T inv_geo = T(1) / kp.rho_geo, inv_sum = T(1) / (kp.rho_eq + kp.rho_dyn);
+    const T* prm = dv.params + (size_t)tr * SCP_PARAM_STRIDE;
     auto at = [&](int plane) -> T { return live ? dv.planes[(size_t)plane * P + g] : T(0); };
     auto put = [&](int plane, T v) {
         if (live) dv.planes[(size_t)plane * P + g] = v;
     };
-    const int cu = (l - NX % 4 + 4) % 4;   // control component of this lane (every lane has one)
+    const int cu = (l - NX % 4 + 4) % 4;   // control component of this lane, if cu < NU
+    const bool has_u = cu < NU;
 
     // node data of the owned components
     T dl[4], zl[4], laml[4], mul[4], g0l[4];
@@ -451,7 +457,7 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
         for (int r = 0; r < NX; ++r) Al[s][r] = (k >= 3 && k < NX) ? at(PL_AR + r * NXR + (k - 3)) : T(0);
     }
 #pragma unroll
-    for (int r = 0; r < NX; ++r) Bl[r] = at(PL_B + r * NU + cu);
+    for (int r = 0; r < NX; ++r) Bl[r] = has_u ? at(PL_B + r * NU + cu) : T(0);
     T cpb[NS], dub[NS], lol[NS], hil[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -473,12 +479,49 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
             else Lr[s][j] = T(0);
         }
     }
-    T own[KM], cph[KM], duh[KM];   // half-space j: a_l (l < 3) or b (l = 3); copy and dual of position l
+    // quadrotor: half-space j: a_l (l < 3) or b (l = 3); copy and dual of position component l
+    T own[KA], cph[KA], duh[KA];
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-        own[j] = at(PL_HS + 4 * j + l);
-        cph[j] = l < 3 ? at(PL_CP + M::C_HS + 3 * j + l) : T(0);
-        duh[j] = l < 3 ? at(PL_DU + M::C_HS + 3 * j + l) : T(0);
+    for (int j = 0; j < KA; ++j) own[j] = cph[j] = duh[j] = T(0);
+    // lander: the one further group of each owned state component (glide cone on r, tilt on
+    // q_y, q_z, rate ball on w), the three thrust groups of the owned control component, and the
+    // thrust half-space's normal and offset (a_l, or b in lane 3)
+    T cpe[4], due[4], cu3[3], du3[3], own_h = T(0);
+    int xslot[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        cpe[s] = due[s] = T(0);
+        xslot[s] = -1;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) cu3[j] = du3[j] = T(0);
+    if constexpr (M::QL) {
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+            own[j] = at(PL_HS + 4 * j + l);
+            cph[j] = l < 3 ? at(PL_CP + M::C_HS + 3 * j + l) : T(0);
+            duh[j] = l < 3 ? at(PL_DU + M::C_HS + 3 * j + l) : T(0);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + l;
+            xslot[s] = k < 3 ? M::C_GLIDE + (k + 2) % 3 : (k == 8 || k == 9) ? M::C_TILT + (k - 8)
+                     : (k >= 10 && k < 13) ? M::C_RATE + (k - 10) : -1;
+            if (xslot[s] >= 0) {
+                cpe[s] = at(PL_CP + xslot[s]);
+                due[s] = at(PL_DU + xslot[s]);
+            }
+        }
+        if (has_u) {
+            const int us[3] = {M::C_TBALL + cu, M::C_THS + cu, M::C_GIMB + (cu + 2) % 3};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                cu3[j] = at(PL_CP + us[j]);
+                du3[j] = at(PL_DU + us[j]);
+            }
+        }
+        own_h = at(PL_HS + l);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -528,18 +571,27 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
                 }
                 v = (g0l[s4] + (rho_eq * zl[s4] - laml[s4])) + tx;
                 v = v + (rho_geo * cpb[s] - dub[s]);
-                if (k < 3) {
+                if constexpr (M::QL) {
+                    if (k < 3) {
 #pragma unroll
-                    for (int j = 0; j < KM; ++j) {
-                        const T rj = group_rho<M>(id, rho_geo, 3 + j);
-                        v = v + (rj * cph[j] - duh[j]);
+                        for (int j = 0; j < KM; ++j) {
+                            const T rj = group_rho<M>(id, rho_geo, 3 + j);
+                            v = v + (rj * cph[j] - duh[j]);
+                        }
                     }
+                } else {
+                    if (xslot[s4] >= 0) v = v + (group_rho<M>(id, rho_geo, 2) * cpe[s4] - due[s4]);
                 }
             } else if (k < NN) {
                 T tu = T(0);
 #pragma unroll
                 for (int r = 0; r < NX; ++r) tu = tu + Bl[r] * w[r];
                 v = tu + (rho_geo * cpb[s] - dub[s]);
+                if constexpr (LD) {
+                    const T ru = group_rho<M>(id, rho_geo, 5);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) v = v + (ru * cu3[j] - du3[j]);
+                }
             }
             acc[s] = v;
         }
@@ -594,7 +646,10 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
         }
         __syncthreads();
         // ---- Steps 2-4 ----
-        T pm = T(0), sp0 = T(0), xpos = T(0);
+        T pm = T(0), xpos = T(0), uval = T(0), spu = T(0);
+        T spv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) spv[s] = T(0);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int k = 4 * s + l;
@@ -614,10 +669,8 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
                 zl[s4] = z;
                 if (chk) {
                     const T dz = z - z0;
-                    const T spk = (first ? T(0) : rho_eq * dz) + rho_geo * (cp - cpo);
+                    spv[s4] = (first ? T(0) : rho_eq * dz) + rho_geo * (cp - cpo);
                     put(PL_DZ + k, dz);
-                    if (s == 0 && k < 3) sp0 = spk;
-                    else put(PL_SP + k, spk);
                     if (!first) {
                         pm = nmax(pm, tabs(x - z));
                         pm = nmax(pm, tabs(z - dp));
@@ -633,12 +686,14 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
                 dub[s] = act ? dub[s] + rho_geo * (u - cp) : T(0);
                 if (!act) cp = T(0);
                 cpb[s] = cp;
+                uval = u;
                 if (chk) {
-                    put(PL_SP + NX + cu, act ? rho_geo * (cp - cpo) : T(0));
+                    spu = act ? rho_geo * (cp - cpo) : T(0);
                     if (act) pm = nmax(pm, tabs(u - cp));
                 }
             }
         }
+        if constexpr (M::QL) {
 #pragma unroll
         for (int j = 0; j < KM; ++j) {
             if (first || j >= id.K) continue;   // uniform over the four lanes of a node
@@ -653,13 +708,86 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
                 duh[j] = duh[j] + rho_geo * (xpos - cp);
                 cph[j] = cp;
                 if (chk) {
-                    sp0 = sp0 + rho_geo * (cp - cpo);
+                    spv[0] = spv[0] + rho_geo * (cp - cpo);
                     pm = nmax(pm, tabs(xpos - cp));
                 }
             }
         }
+        } else {
+            // lander: the sets coupling components; a group exists at nodes 1..N (state) or
+            // 0..N-1 (thrust), and where it does not its copy and dual stay 0
+            const bool xact = !first, uact = !last;
+            auto upd_x = [&](int s, T var, T cp) {
+                const T cpo = cpe[s];
+                due[s] = xact ? due[s] + rho_geo * (var - cp) : T(0);
+                cpe[s] = xact ? cp : T(0);
+                if (chk && xact) {
+                    spv[s] = spv[s] + rho_geo * (cpe[s] - cpo);
+                    pm = nmax(pm, tabs(var - cp));
+                }
+            };
+            auto upd_u = [&](int j, T cp) {
+                const T cpo = cu3[j];
+                du3[j] = uact ? du3[j] + rho_geo * (uval - cp) : T(0);
+                cu3[j] = uact ? cp : T(0);
+                if (chk && uact) {
+                    spu = spu + rho_geo * (cu3[j] - cpo);
+                    pm = nmax(pm, tabs(uval - cp));
+                }
+            };
+            {   // glide cone on (r_E, r_N, r_U): owners lanes 1, 2, 0 (slot 0)
+                const T kg = prm[SCP_P_GLIDE];
+                const T vv = l < 3 ? xl[0] + due[0] * inv_geo : T(0);
+                T v[3] = {quad_bcast(vv, 1), quad_bcast(vv, 2), quad_bcast(vv, 0)};
+                proj_cone<3>(kg, T(1) / (T(1) + kg * kg), v);
+                const int o = (l + 2) % 3;
+                if (l < 3) upd_x(0, xl[0], o == 0 ? v[0] : o == 1 ? v[1] : v[2]);
+            }
+            {   // tilt on (q_y, q_z): owners lanes 0, 1 (slot 2)
+                const T vv = l < 2 ? xl[2] + due[2] * inv_geo : T(0);
+                T v[2] = {quad_bcast(vv, 0), quad_bcast(vv, 1)};
+                proj_ball2(prm[SCP_P_TILT], v);
+                if (l < 2) upd_x(2, xl[2], l == 0 ? v[0] : v[1]);
+            }
+            {   // rate ball on w: owners lanes 2, 3 (slot 2) and 0 (slot 3)
+                const T vv = (l >= 2) ? xl[2] + due[2] * inv_geo : (l == 0 ? xl[3] + due[3] * inv_geo : T(0));
+                T v[3] = {quad_bcast(vv, 2), quad_bcast(vv, 3), quad_bcast(vv, 0)};
+                proj_ball3(prm[SCP_P_WMAX], v);
+                if (l >= 2) upd_x(2, xl[2], l == 2 ? v[0] : v[1]);
+                if (l == 0) upd_x(3, xl[3], v[2]);
+            }
+            // thrust component c is held by lane (NX + c) mod 4
+            constexpr int L0 = (NX + 0) % 4, L1 = (NX + 1) % 4, L2 = (NX + 2) % 4;
+            {   // thrust magnitude upper bound
+                const T vb = has_u ? uval + du3[0] * inv_geo : T(0);
+                T v[3] = {quad_bcast(vb, L0), quad_bcast(vb, L1), quad_bcast(vb, L2)};
+                proj_ball3(prm[SCP_P_TMAX], v);
+                if (has_u) upd_u(0, cu == 0 ? v[0] : cu == 1 ? v[1] : v[2]);
+            }
+            {   // linearized lower thrust bound
+                const T a[3] = {quad_bcast(own_h, 0), quad_bcast(own_h, 1), quad_bcast(own_h, 2)};
+                const T bh = quad_bcast(own_h, 3);
+                const T vh = has_u ? uval + du3[1] * inv_geo : T(0);
+                T v[3] = {quad_bcast(vh, L0), quad_bcast(vh, L1), quad_bcast(vh, L2)};
+                proj_halfspace(a, bh, v);
+                if (has_u) upd_u(1, cu == 0 ? v[0] : cu == 1 ? v[1] : v[2]);
+            }
+            {   // gimbal cone on (T_y, T_z, T_x)
+                const T kq = prm[SCP_P_GIMBAL];
+                const T vq = has_u ? uval + du3[2] * inv_geo : T(0);
+                T v[3] = {quad_bcast(vq, L1), quad_bcast(vq, L2), quad_bcast(vq, L0)};
+                proj_cone<3>(kq, T(1) / (T(1) + kq * kq), v);
+                const int o = (cu + 2) % 3;
+                if (has_u) upd_u(2, o == 0 ? v[0] : o == 1 ? v[1] : v[2]);
+            }
+        }
         if (chk) {
-            if (l < 3) put(PL_SP + l, sp0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 4 * s + l;
+                if (k < NX) put(PL_SP + k, spv[s]);
+            }
+            if (has_u) put(PL_SP + NX + cu, spu);
             pm = nmax(pm, quad_perm<0xB1>(pm));
             pm = nmax(pm, quad_perm<0x4E>(pm));
             if (l == 0) put(PL_RP, pm);
@@ -694,12 +822,30 @@ __global__ __launch_bounds__(256) void k_admm_quad6_resident(Dev<T> dv, KParams<
             put(PL_DU + M::C_UBOX + cu, dub[s]);
         }
     }
-    if (l < 3 && !first) {
+    if constexpr (M::QL) {
+        if (l < 3 && !first) {
 #pragma unroll
-        for (int j = 0; j < KM; ++j) {
-            if (j < id.K) {
-                put(PL_CP + M::C_HS + 3 * j + l, cph[j]);
-                put(PL_DU + M::C_HS + 3 * j + l, duh[j]);
+            for (int j = 0; j < KM; ++j) {
+                if (j < id.K) {
+                    put(PL_CP + M::C_HS + 3 * j + l, cph[j]);
+                    put(PL_DU + M::C_HS + 3 * j + l, duh[j]);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (xslot[s] >= 0) {
+                put(PL_CP + xslot[s], cpe[s]);
+                put(PL_DU + xslot[s], due[s]);
+            }
+        }
+        if (has_u) {
+            const int us[3] = {M::C_TBALL + cu, M::C_THS + cu, M::C_GIMB + (cu + 2) % 3};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                put(PL_CP + us[j], cu3[j]);
+                put(PL_DU + us[j], du3[j]);
             }
         }
     }
@@ -1200,18 +1346,25 @@ hipError_t launch_gather(const Dev<T>& dv, int plane, int width, int mode, T* ou
 }
 
 template <class T>
-hipError_t launch_resident(const Dev<T>& dv, const KParams<T>& kp, int n_traj, int block, int kmax, hipStream_t s) {
+hipError_t launch_resident(const Dev<T>& dv, const KParams<T>& kp, int n_traj, int block, int models, int kmax,
+                           hipStream_t s) {
     if (n_traj <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || block % 64 != 0 || block > 4 * RESIDENT_MAX_NODES) return hipErrorInvalidValue;
-    if (kmax <= 4) hipLaunchKernelGGL((k_admm_quad6_resident<T, 4>), dim3(n_traj), dim3(block), 0, s, dv, kp);
-    else hipLaunchKernelGGL((k_admm_quad6_resident<T, 8>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+    if (models == 4) {
+        if (kmax <= 4) hipLaunchKernelGGL((k_admm_resident<Quad6<4>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_admm_resident<Quad6<8>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+    } else if (models == 8) {
+        hipLaunchKernelGGL((k_admm_resident<Lander6, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+    } else {
+        return hipErrorInvalidValue;   // one 6-DOF model per batch
+    }
     return hipGetLastError();
 }
 
 template hipError_t launch_plain<float>(PlainOp, const Dev<float>&, const KParams<float>&, int, int, int, int, hipStream_t);
 template hipError_t launch_plain<double>(PlainOp, const Dev<double>&, const KParams<double>&, int, int, int, int, hipStream_t);
-template hipError_t launch_resident<float>(const Dev<float>&, const KParams<float>&, int, int, int, hipStream_t);
-template hipError_t launch_resident<double>(const Dev<double>&, const KParams<double>&, int, int, int, hipStream_t);
+template hipError_t launch_resident<float>(const Dev<float>&, const KParams<float>&, int, int, int, int, hipStream_t);
+template hipError_t launch_resident<double>(const Dev<double>&, const KParams<double>&, int, int, int, int, hipStream_t);
 template hipError_t launch_gather<float>(const Dev<float>&, int, int, int, float*, hipStream_t);
 template hipError_t launch_gather<double>(const Dev<double>&, int, int, int, double*, hipStream_t);
 

@@ -98,7 +98,7 @@ def pmc_plain(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, sc
 
     kf, kw = per_kernel(fetch_dir), per_kernel(write_dir)
     admm = scp_iters * admm_iters
-    count = {"k_step1": admm, "k_step1_lanes4": admm, "k_step234": admm, "k_admm_quad6_resident": scp_iters,
+    count = {"k_step1": admm, "k_step1_lanes4": admm, "k_step234": admm, "k_admm_resident": scp_iters,
              "k_resid": scp_iters, "k_lin": scp_iters,
              "k_acc_nodes": scp_iters, "k_acc_traj": scp_iters, "k_acc_apply": scp_iters, "k_check": scp_iters,
              "k_reset": 2, "k_reset_state": 1, "k_met_nodes": 1, "k_met_traj": 1}

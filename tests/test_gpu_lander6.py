@@ -12,7 +12,10 @@ oracle.
   iteration of the samples to 1e-4 and, at the full budget, every sample bit-identical alone and
   in the batch.
 * Edge cases: horizons N = 1, 2 and 240 in one batch (FP64, 1e-9).
-* The persistent form, the request server and consensus groups refuse the model with an error.
+* The persistent form of this model keeps the ADMM iterations resident in one workgroup per
+  trajectory; it gives the plain form's bits (FP32 and FP64, full budget) and meets the same
+  oracle bars, on horizons up to 63 intervals.  It refuses longer trajectories and residual-test
+  cadences; the request server and consensus groups refuse the model with an error.
 
 The lander's mirror copies [x box 14][u box 3][glide 3][tilt 2][rate 3][thrust ball 3][lower
 bound 3][gimbal 3] list the cones' components axis last, exactly as the oracle's groups do, so the
@@ -95,11 +98,12 @@ def test_admm_fixed_iterations(B, prec, tol):
     prob.close()
 
 
-def test_nominal_descent_fp64(B):
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_nominal_descent_fp64(B, form):
     insts = [scpgen.lander6_instance()]
-    _say("lander nominal fp64 20x200")
+    _say("lander nominal fp64 20x200", form)
     prob = B.Problem(insts, precision="f64")
-    prob.solve(B.scp_params(20, 200, form="plain", **SCHED))
+    prob.solve(B.scp_params(20, 200, form=form, **SCHED))
     f = gpu_fields(prob)
     _, _, info = prob.result()
     trajs, oinfo = oracle_scp(insts, 20, 200, **OSCHED)
@@ -120,11 +124,12 @@ def test_nominal_descent_fp64(B):
 SAMPLE = [0, 421, 999]
 
 
-def test_monte_carlo_fullsize_fp64_samples(B):
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_monte_carlo_fullsize_fp64_samples(B, form):
     insts = scpgen.config6(1000)
-    _say("lander 1000 x 31 fp64 20x200")
+    _say("lander 1000 x 31 fp64 20x200", form)
     prob = B.Problem(insts, precision="f64")
-    prob.solve(B.scp_params(20, 200, form="plain", **SCHED))
+    prob.solve(B.scp_params(20, 200, form=form, **SCHED))
     x, u, info = (a.cpu().numpy() for a in prob.result())
     for i in SAMPLE:
         (t,), _ = oracle_scp([insts[i]], 20, 200, **OSCHED)
@@ -136,11 +141,12 @@ def test_monte_carlo_fullsize_fp64_samples(B):
     prob.close()
 
 
-def test_monte_carlo_fullsize_fp32(B):
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_monte_carlo_fullsize_fp32(B, form):
     insts = scpgen.config6(1000)
-    _say("lander 1000 x 31 fp32 first SCP iteration")
+    _say("lander 1000 x 31 fp32 first SCP iteration", form)
     prob = B.Problem(insts, precision="f32")
-    prob.solve(B.scp_params(1, 200, form="plain", **SCHED))
+    prob.solve(B.scp_params(1, 200, form=form, **SCHED))
     f = gpu_fields(prob)
     for i in SAMPLE:
         (t,), _ = oracle_scp([insts[i]], 1, 200, **OSCHED)
@@ -148,7 +154,7 @@ def test_monte_carlo_fullsize_fp32(B):
         _say(i, worst)
         assert max(worst.values()) < TOL32
     prob.reset()
-    prm = B.scp_params(20, 200, form="plain", **SCHED)
+    prm = B.scp_params(20, 200, form=form, **SCHED)
     prob.solve(prm)
     x, u, info = (a.cpu().numpy() for a in prob.result())
     for i in SAMPLE:
@@ -181,11 +187,50 @@ def test_edge_horizons_fp64(B):
     prob.close()
 
 
-def test_persistent_server_and_groups_refuse_the_model(B):
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_resident_and_plain_forms_agree_bitwise(B, prec):
+    insts = scpgen.config6(160)
+    out = {}
+    for form in ("plain", "persistent"):
+        prob = B.Problem(insts, precision=prec)
+        prob.solve(B.scp_params(20, 200, form=form, **SCHED))
+        f = gpu_fields(prob, ("x", "u", "z", "lam", "mu", "copy", "dual"))
+        x, u, info = (a.cpu().numpy() for a in prob.result())
+        out[form] = (f, x, u, info)
+        prob.close()
+    (fp, xp, up, ip), (fr, xr, ur, ir) = out["plain"], out["persistent"]
+    for k in fp:
+        np.testing.assert_array_equal(fr[k], fp[k], err_msg=k)
+    np.testing.assert_array_equal(xr, xp)
+    np.testing.assert_array_equal(ur, up)
+    np.testing.assert_array_equal(ir, ip)
+
+
+def test_resident_edge_horizons_fp64(B):
+    """Horizons N = 1, 2 and 63 (the longest resident trajectory) together."""
+    x0s = [scpgen.lander6_perturbed(80 + i)["x_init"] for i in range(3)]
+    insts = [scpgen.lander6_instance(x0s[0], N=1, tf=5.0 / 30), scpgen.lander6_instance(x0s[1], N=2, tf=10.0 / 30),
+             scpgen.lander6_instance(x0s[2], N=63, tf=5.0 * 63 / 30)]
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(3, 20, form="persistent", **SCHED))
+    f = gpu_fields(prob)
+    trajs, _ = oracle_scp(insts, 3, 20, **OSCHED)
+    worst = compare(prob, f, insts, trajs)
+    _say("lander resident edge", worst)
+    assert max(worst.values()) < TOL64
+    prob.close()
+
+
+def test_persistent_limits_server_and_groups_refuse(B):
+    long = [scpgen.lander6_instance(N=64, tf=5.0 * 64 / 30)]    # 65 nodes: over the resident limit
+    prob = B.Problem(long, precision="f32")
+    with pytest.raises(RuntimeError, match="64 nodes"):
+        prob.solve(B.scp_params(2, 10, form="persistent"))
+    prob.close()
     insts = scpgen.config6(2)
     prob = B.Problem(insts, precision="f32")
-    with pytest.raises(RuntimeError, match="plain form"):
-        prob.solve(B.scp_params(2, 10, form="persistent"))
+    with pytest.raises(RuntimeError, match="fixed budgets"):
+        prob.solve(B.scp_params(2, 10, form="persistent", check_every=5, eps=1e-4))
     prob.close()
     srv = B.Server(B.scp_params(2, 10), precision="f32", block=256, max_nodes=1 << 12, max_traj=16, max_wg=16,
                    max_span=4, max_requests=4)
