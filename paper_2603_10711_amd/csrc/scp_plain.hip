@@ -407,7 +407,8 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 // couple components (cones, balls, the thrust half-space) are projected by every lane of the node
 // on the components broadcast from their owners; each owner keeps its own component.
 template <class M, class T>
-__global__ __launch_bounds__(256) void k_admm_resident(Dev<T> dv, KParams<T> kp) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
+void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = 5, MAXN = RESIDENT_MAX_NODES;
     constexpr int KM = M::KM, KA = KM > 0 ? KM : 1;
     constexpr bool LD = M::ID == SCP_MODEL_LANDER6;
@@ -487,12 +488,13 @@ __global__ __launch_bounds__(256) void k_admm_resident(Dev<T> dv, KParams<T> kp)
     // q_y, q_z, rate ball on w), the three thrust groups of the owned control component, and the
     // thrust half-space's normal and offset (a_l, or b in lane 3)
     T cpe[4], due[4], cu3[3], du3[3], own_h = T(0);
-    int xslot[4];
+    // mirror slot of the further group of state component k (lander), -1 if none
+    auto xslot_of = [](int k) -> int {
+        return k < 3 ? Lander6::C_GLIDE + (k + 2) % 3 : (k == 8 || k == 9) ? Lander6::C_TILT + (k - 8)
+             : (k >= 10 && k < 13) ? Lander6::C_RATE + (k - 10) : -1;
+    };
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        cpe[s] = due[s] = T(0);
-        xslot[s] = -1;
-    }
+    for (int s = 0; s < 4; ++s) cpe[s] = due[s] = T(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) cu3[j] = du3[j] = T(0);
     if constexpr (M::QL) {
@@ -505,12 +507,10 @@ __global__ __launch_bounds__(256) void k_admm_resident(Dev<T> dv, KParams<T> kp)
     } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int k = 4 * s + l;
-            xslot[s] = k < 3 ? M::C_GLIDE + (k + 2) % 3 : (k == 8 || k == 9) ? M::C_TILT + (k - 8)
-                     : (k >= 10 && k < 13) ? M::C_RATE + (k - 10) : -1;
-            if (xslot[s] >= 0) {
-                cpe[s] = at(PL_CP + xslot[s]);
-                due[s] = at(PL_DU + xslot[s]);
+            const int xs = xslot_of(4 * s + l);
+            if (xs >= 0) {
+                cpe[s] = at(PL_CP + xs);
+                due[s] = at(PL_DU + xs);
             }
         }
         if (has_u) {
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(256) void k_admm_resident(Dev<T> dv, KParams<T> kp)
                         }
                     }
                 } else {
-                    if (xslot[s4] >= 0) v = v + (group_rho<M>(id, rho_geo, 2) * cpe[s4] - due[s4]);
+                    if (xslot_of(k) >= 0) v = v + (group_rho<M>(id, rho_geo, 2) * cpe[s4] - due[s4]);
                 }
             } else if (k < NN) {
                 T tu = T(0);
@@ -835,9 +835,10 @@ __global__ __launch_bounds__(256) void k_admm_resident(Dev<T> dv, KParams<T> kp)
     } else {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            if (xslot[s] >= 0) {
-                put(PL_CP + xslot[s], cpe[s]);
-                put(PL_DU + xslot[s], due[s]);
+            const int xs = xslot_of(4 * s + l);
+            if (xs >= 0) {
+                put(PL_CP + xs, cpe[s]);
+                put(PL_DU + xs, due[s]);
             }
         }
         if (has_u) {
