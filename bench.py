@@ -283,7 +283,7 @@ def plain_main(a, wl, cpu):
     flops = float(sum((d["N"] + 1) * it * flops_per_node_iter(d["model"], d["obstacles"].shape[0])
                       for d, it in zip(insts, iters)))
     kernel_ms = float(np.mean(step_ms))
-    traffic = load_pmc_plain(wl["name"], kernel_source_hash())
+    traffic = load_pmc_solve(wl["name"], form, kernel_source_hash())
     if form == "plain":
         roof = {"bound": "hbm", "achieved": round(nbytes / (kernel_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(nbytes / (kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
@@ -322,10 +322,12 @@ def plain_main(a, wl, cpu):
     print(json.dumps(out))
 
 
-def load_pmc_plain(wl_name: str, khash: str):
-    """HBM bytes of one plain solve from the committed rocprofv3 counter summary, if the kernel
-    sources are unchanged since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"pmc_plain_{wl_name}.json")
+def load_pmc_solve(wl_name: str, form: str, khash: str):
+    """HBM bytes of one solve of the given form (plain, or the resident ADMM of the 6-DOF models)
+    from the committed rocprofv3 counter summary, if the kernel sources are unchanged since the
+    counters were taken."""
+    kind = "plain" if form == "plain" else "resident"
+    path = os.path.join(ROOT, "profiles", f"pmc_{kind}_{wl_name}.json")
     if not os.path.exists(path):
         return None
     try:

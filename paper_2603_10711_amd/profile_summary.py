@@ -5,8 +5,8 @@
         <workload> <out.json> --cmd "<command>"
     python -m paper_2603_10711_amd.profile_summary pmcplain <fetch dir> <write dir> <copy fetch dir> <copy write dir> \
         <workload> <scp iters> <admm iters> <out.json> --cmd "<command>"
-    python -m paper_2603_10711_amd.profile_summary sq <counter dir> <title> <admm iterations per solve> <out.md> \
-        --cmd "<command>"
+    python -m paper_2603_10711_amd.profile_summary sq <counter dir> <title> <admm iterations per dispatch> <out.md> \
+        --cmd "<command>" [--kernel <kernel name prefix, default k_persistent>]
 
 ``pmc`` scales FETCH_SIZE / WRITE_SIZE of k_persistent by what the same counters read for a
 1 GiB device copy (copy_probe.py) and records the hash of the kernel sources the counters were
@@ -119,24 +119,24 @@ def pmc_plain(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, sc
     json.dump(d, open(out, "w"), indent=1)
 
 
-def sq(dirpath: str, title: str, iters: int, out: str, cmd: str) -> None:
-    """SQ counters of k_persistent per dispatch and per wave, and the VALU issue share."""
+def sq(dirpath: str, title: str, iters: int, out: str, cmd: str, kernel: str = "k_persistent") -> None:
+    """SQ counters of one kernel per dispatch and per wave, and the VALU issue share."""
     path = glob.glob(os.path.join(dirpath, "*counter_collection.csv"))[0]
     per = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in csv.DictReader(open(path)):
-        if r["Kernel_Name"].startswith("void scp::k_persistent"):
+        if r["Kernel_Name"].startswith("void scp::" + kernel):
             per[r["Counter_Name"]][r["Dispatch_Id"]].append(float(r["Counter_Value"]))
     val = {c: sum(sum(v) for v in d.values()) / len(d) for c, d in per.items()}
     waves = val["SQ_WAVES"]
-    lines = [f"# rocprofv3 SQ counters of k_persistent, {title}", "", f"Command: `{cmd}`", "",
+    lines = [f"# rocprofv3 SQ counters of {kernel}, {title}", "", f"Command: `{cmd}`", "",
              f"Kernel sources hash: `{kernel_source_hash()}`", "", "| counter | per dispatch | per wave |", "|---|---|---|"]
     for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"):
         if c in val:
             lines.append(f"| {c} | {val[c]:.4g} | {val[c] / waves:.4g} |")
     valu = val["SQ_INSTS_VALU"] / waves
     share = val["SQ_INSTS_VALU"] / val["SQ_WAVE_CYCLES"]
-    lines += ["", f"VALU instructions per wave per ADMM iteration ({iters} iterations per solve, SCP-level work "
-                  f"amortized): {valu / iters:.0f}.",
+    lines += ["", f"VALU instructions per wave per ADMM iteration ({iters} iterations per dispatch, work outside "
+                  f"the ADMM loop amortized): {valu / iters:.0f}.",
               "SQ_WAVE_CYCLES counts quad-cycles; one wave64 FP32 VALU instruction occupies its SIMD for one "
               f"quad-cycle, so the VALU issue share of the wave's life is {share:.3f}."]
     open(out, "w").write("\n".join(lines) + "\n")
@@ -164,13 +164,14 @@ def main(argv=None):
     for k in ("dir", "title", "iters", "out"):
         q.add_argument(k)
     q.add_argument("--cmd", required=True)
+    q.add_argument("--kernel", default="k_persistent")
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.csv, a.out, a.cmd)
     elif a.mode == "pmcplain":
         pmc_plain(a.fetch, a.write, a.copy_fetch, a.copy_write, a.workload, a.scp_iters, a.admm_iters, a.out, a.cmd)
     elif a.mode == "sq":
-        sq(a.dir, a.title, int(a.iters), a.out, a.cmd)
+        sq(a.dir, a.title, int(a.iters), a.out, a.cmd, a.kernel)
     else:
         pmc(a.fetch, a.write, a.copy_fetch, a.copy_write, a.workload, a.out, a.cmd)
 
