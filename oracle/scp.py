@@ -27,8 +27,10 @@ from .dynamics import rk4, rk4_jac, QUAD, MARS, QUAD6, LANDER6
 def default_params(**kw) -> dict:
     """Solver parameters; the defaults are the fixed-budget settings of the workloads
     (rho = 1 for all three penalties, always-accept steps, fixed trust radius).  rho_final > 0
-    turns on the penalty schedule of penalty_factors."""
+    turns on the penalty schedule of penalty_factors; adapt_mu > 0 the residual balancing of
+    adapt_penalty."""
     p = dict(scp_iters=10, admm_iters=100, rho_eq=1.0, rho_dyn=1.0, rho_geo=1.0, rho_final=0.0,
+             adapt_mu=0.0, adapt_tau=2.0,
              check_every=0, eps_p=0.0, eps_d=0.0,
              eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
              merit_w=1.0e3)
@@ -58,6 +60,29 @@ def penalty_factors(params: dict) -> list[float]:
 # ------------------------------------------------------------------------------------------
 # a2: linearization
 # ------------------------------------------------------------------------------------------
+
+def adapt_penalty(scale: float, r_p: float, r_d: float, params: dict) -> float:
+    """Adaptive penalty by residual balancing, applied between SCP iterations.
+
+    The paper fixes the penalties or scales them on a schedule (Sec. IV-A.2) and gives no
+    adaptive rule.  Reading: the residual-balancing rule of Boyd et al., "Distributed
+    Optimization and Statistical Learning via ADMM" (2011), Sec. 3.4.1: when the primal residual
+    exceeds mu times the dual one the penalty grows by tau, when the dual residual exceeds mu
+    times the primal one it shrinks by tau, otherwise it stays.  Here one factor scales all three
+    penalties of a group (on top of the schedule's factor), decided from the residuals of the
+    last ADMM iteration of an SCP iteration, in double precision; the next SCP iteration builds
+    its factor with the new penalties.  The duals are the unscaled multipliers and carry over
+    unchanged.  NaN residuals leave the factor alone.  adapt_mu <= 0 turns the rule off."""
+    mu = params.get("adapt_mu", 0.0) or 0.0
+    if mu <= 0.0:
+        return scale
+    tau = params["adapt_tau"]
+    if r_p > mu * r_d:
+        return scale * tau
+    if r_d > mu * r_p:
+        return scale / tau
+    return scale
+
 
 def linearize(inst: dict, xbar: np.ndarray, ubar: np.ndarray):
     """A_i, B_i, d_i for i < N at the nominal (first-order expansion of the RK4 map)."""
@@ -335,8 +360,10 @@ def scp_group(trajs: list[Traj], params: dict, delta: float | None = None) -> di
     n_accept = 0
     rp = rd = float("nan")
     status = 0
+    scale = 1.0   # adaptive factor of the penalties (adapt_penalty)
     for k in range(params["scp_iters"]):
-        rho = (params["rho_eq"] * factors[k], params["rho_dyn"] * factors[k], params["rho_geo"] * factors[k])
+        rho = (params["rho_eq"] * factors[k] * scale, params["rho_dyn"] * factors[k] * scale,
+               params["rho_geo"] * factors[k] * scale)
         packs = _prepare(trajs, delta, rho)
         it, rp, rd = admm_run(packs, rho, params["admm_iters"], params["check_every"],
                               params["eps_p"], params["eps_d"], couple_u0=coupled)
@@ -366,7 +393,9 @@ def scp_group(trajs: list[Traj], params: dict, delta: float | None = None) -> di
             delta = delta * params["shrink"]
         elif ratio > params["eta2"]:
             delta = min(delta * params["grow"], params["delta_max"])
-    return dict(admm_iters=iters_total, r_p=rp, r_d=rd, n_accept=n_accept, delta=delta, status=status)
+        scale = adapt_penalty(scale, rp, rd, params)
+    return dict(admm_iters=iters_total, r_p=rp, r_d=rd, n_accept=n_accept, delta=delta, status=status,
+                rho_scale=scale)
 
 
 def scp_solve(insts: list[dict], params: dict | None = None):
