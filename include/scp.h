@@ -219,6 +219,20 @@ typedef struct {
                                          handle, later calls with equal parameters replay it.
                                          Needs a stream other than the legacy default stream
                                          (SCP_ERR_HIP otherwise).  0: direct launches.        */
+    double adapt_mu;                  /* > 1: adaptive penalty by residual balancing (Boyd et
+                                         al. 2011, Sec. 3.4.1; the paper gives no adaptive
+                                         rule): after each SCP iteration a trajectory's three
+                                         penalties are multiplied by adapt_tau when its primal
+                                         residual of the last ADMM iteration exceeds adapt_mu
+                                         times the dual one, divided by adapt_tau when the dual
+                                         residual exceeds adapt_mu times the primal one
+                                         (compared in double), on top of the schedule's factor;
+                                         the next SCP iteration factors with the new penalties
+                                         and the duals carry over unscaled.  Each scp_solve call
+                                         starts from factor 1.  Needs check_every = 0 and no
+                                         consensus groups (SCP_ERR_UNSUPPORTED otherwise).
+                                         0: off.                                              */
+    double adapt_tau;                 /* > 1 when adapt_mu > 0                                */
 } scp_params;
 
 typedef struct scp_problem scp_problem;

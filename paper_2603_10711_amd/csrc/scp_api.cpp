@@ -360,6 +360,8 @@ KParams<T> kparams(const admm_params* a, const scp_params* s) {
     k.rho_base[2] = a->rho_geo;
     k.sched_s0 = 1.0;
     k.sched_q = 1.0;
+    k.adapt_mu = 0.0;
+    k.adapt_tau = 1.0;
     if (s) {
         k.eta0 = T(s->eta0);
         k.eta1 = T(s->eta1);
@@ -369,6 +371,10 @@ KParams<T> kparams(const admm_params* a, const scp_params* s) {
         k.delta_max = T(s->delta_max);
         k.merit_w = T(s->merit_w);
         k.sched_q = sched_ratio(*s);
+        if (s->adapt_mu > 0.0) {
+            k.adapt_mu = s->adapt_mu;
+            k.adapt_tau = s->adapt_tau;
+        }
     }
     k.n_scp = 1;
     return k;
@@ -406,7 +412,8 @@ bool same_params(const scp_params& a, const scp_params& b) {
            a.admm.eps_dual == b.admm.eps_dual && std::memcmp(&a.eta0, &b.eta0, sizeof(double)) == 0 &&
            a.eta1 == b.eta1 && a.eta2 == b.eta2 && a.shrink == b.shrink && a.grow == b.grow &&
            std::memcmp(&a.delta_max, &b.delta_max, sizeof(double)) == 0 && a.merit_w == b.merit_w &&
-           a.form == b.form && a.scp_per_launch == b.scp_per_launch && a.rho_final == b.rho_final;
+           a.form == b.form && a.scp_per_launch == b.scp_per_launch && a.rho_final == b.rho_final &&
+           a.adapt_mu == b.adapt_mu && a.adapt_tau == b.adapt_tau;
 }
 
 template <class T>
@@ -646,6 +653,12 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
     if (prm->form != SCP_FORM_PLAIN && prm->form != SCP_FORM_PERSISTENT) return fail(p, SCP_ERR_ARG, "invalid form");
     if (prm->graph != 0 && prm->graph != 1) return fail(p, SCP_ERR_ARG, "graph must be 0 or 1");
     if (!(prm->rho_final >= 0.0)) return fail(p, SCP_ERR_ARG, "rho_final must be >= 0");
+    if (!(prm->adapt_mu == 0.0 || (prm->adapt_mu > 1.0 && prm->adapt_tau > 1.0 && std::isfinite(prm->adapt_mu) &&
+                                   std::isfinite(prm->adapt_tau))))
+        return fail(p, SCP_ERR_ARG, "adaptive penalty: adapt_mu must be 0 (off) or > 1 with adapt_tau > 1");
+    if (prm->adapt_mu > 0.0 && (prm->admm.check_every > 0 || p->L.n_groups > 0))
+        return fail(p, SCP_ERR_UNSUPPORTED, "the adaptive penalty runs fixed budgets (check_every = 0) "
+                                             "without consensus groups");
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && !p->L.resident_ok)
         return fail(p, SCP_ERR_UNSUPPORTED, kNoPersistent);
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && prm->admm.check_every > 0)

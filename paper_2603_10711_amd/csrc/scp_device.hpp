@@ -107,6 +107,15 @@ struct Rho {
     T eq, dyn, geo, inv_geo, inv_sum;
 };
 
+// Adaptive penalty by residual balancing between SCP iterations (Boyd et al. 2011, Sec. 3.4.1;
+// the paper gives no adaptive rule): the factor after an SCP iteration whose last ADMM iteration
+// left residuals rp, rd, compared in double.  NaN residuals keep the factor.
+__host__ __device__ inline double adapt_factor(double f, double rp, double rd, double mu, double tau) {
+    if (rp > mu * rd) return f * tau;
+    if (rd > mu * rp) return f / tau;
+    return f;
+}
+
 // ------------------------------------------------------------------------------------------
 // scalar helpers (NaN-propagating max; the comparisons keep a NaN once it appears)
 // ------------------------------------------------------------------------------------------
@@ -159,6 +168,16 @@ template <int SEL>
 __device__ __forceinline__ double quad_perm(double v) {
     const long long b = __builtin_bit_cast(long long, v);
     const int lo = quad_perm_i<SEL>((int)(b & 0xffffffffll)), hi = quad_perm_i<SEL>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// a value the same in every active lane of the wavefront, moved to scalar registers (it then
+// takes no vector register, as a kernel argument would not)
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 // the value of lane k of this lane's group (k a constant after unrolling)

@@ -59,7 +59,7 @@ enum : int { TR_MODEL = 0, TR_N = 1, TR_OFF = 2, TR_GFIRST = 3, TR_GSIZE = 4, TR
              TR_MEMBER = 7, TR_FIELDS = 8 };
 
 // per-trajectory runtime values (problem precision)
-enum : int { RT_DELTA = 0, RT_FIELDS = 2 };
+enum : int { RT_DELTA = 0, RT_RHOS = 1, RT_FIELDS = 2 };
 
 // per-trajectory integer flags
 enum : int { FL_DONE = 0, FL_ITERS = 1, FL_ACCEPT = 2, FL_STATUS = 3, FL_FIELDS = 4 };
@@ -134,6 +134,9 @@ struct KParams {
     // s_0 = sched_s0 and s_{k+1} = s_k * sched_q, in double (rho_base in double too)
     double rho_base[3];
     double sched_s0, sched_q;
+    // adaptive penalty (residual balancing between SCP iterations): on when adapt_mu > 0; the
+    // factor of trajectory t is rt[t * RT_FIELDS + RT_RHOS] and multiplies the penalties above
+    double adapt_mu, adapt_tau;
 };
 
 }  // namespace scp

@@ -1,5 +1,5 @@
 // Persistent form: launch entry (the kernel templates live in scp_persistent.hpp; their
-// instantiations are split over scp_persistent_{f32,f64}{,_span}.hip).
+// instantiations are split over scp_persistent_{f32,f64}{,_span,_adapt}.hip).
 #include "scp_persistent.hpp"
 
 namespace scp {
@@ -13,6 +13,14 @@ SCP_EXTERN_VARIANTS(double, false)
 SCP_EXTERN_VARIANTS(double, true)
 extern template void launch_models<float, 256, false>(const Dev<float>&, const KParams<float>&, int, int, int, hipStream_t);
 extern template void launch_models<float, 256, true>(const Dev<float>&, const KParams<float>&, int, int, int, hipStream_t);
+#define SCP_EXTERN_ADAPT(T, BLOCK) \
+    extern template void launch_models<T, BLOCK, false, true>(const Dev<T>&, const KParams<T>&, int, int, int, hipStream_t);
+SCP_EXTERN_ADAPT(float, 64)
+SCP_EXTERN_ADAPT(float, 128)
+SCP_EXTERN_ADAPT(float, 256)
+SCP_EXTERN_ADAPT(double, 64)
+SCP_EXTERN_ADAPT(double, 128)
+#undef SCP_EXTERN_ADAPT
 #undef SCP_EXTERN_VARIANTS
 
 // Barrier counters of the spanning groups start every launch at zero.
@@ -24,8 +32,14 @@ __global__ void k_zero_sync(unsigned* __restrict__ c, int n) {
 template <class T, int BLOCK>
 static hipError_t launch_block(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int models, int kmax,
                                hipStream_t s) {
-    if (dv.n_gslots > 0) launch_models<T, BLOCK, true>(dv, kp, n_wg, models, kmax, s);
-    else launch_models<T, BLOCK, false>(dv, kp, n_wg, models, kmax, s);
+    if (kp.adapt_mu > 0.0) {   // no consensus groups with the adaptive penalty (refused on the host)
+        if (dv.n_gslots > 0) return hipErrorInvalidValue;
+        launch_models<T, BLOCK, false, true>(dv, kp, n_wg, models, kmax, s);
+    } else if (dv.n_gslots > 0) {
+        launch_models<T, BLOCK, true>(dv, kp, n_wg, models, kmax, s);
+    } else {
+        launch_models<T, BLOCK, false>(dv, kp, n_wg, models, kmax, s);
+    }
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct StridedLds {
 // One-wavefront workgroups exchange neighbours with DPP, so their exchange arrays shrink to one
 // row; the LDS this frees holds the Cholesky factors instead (LR rows, 1 where unused): with the
 // factor out of the registers, the ADMM state stays in VGPRs instead of spilling to AGPRs.
-template <class T, int BLOCK, int HSR, int LR>
+template <class T, int BLOCK, int HSR, int LR, int AR = 1>
 struct Shared {
     static constexpr int XR = BLOCK == 64 ? 1 : PERSIST_MAX_NX;
     T ex[2 * XR][BLOCK + 1];       // z, mu of every node (backward exchange); x / xbar at accept;
@@ -57,6 +57,8 @@ struct Shared {
                                    // normals (3 per group)
     T gxw[GX_WIDTH][BLOCK];        // spanning groups: member rows staged for publication
     int gxm[BLOCK];                // member index of the row staged at a lane, -1 none
+    T arho[AR];                    // adaptive-penalty kernels (AR = BLOCK): the factor of the
+                                   // lane's trajectory, own slot, out of the ADMM loop's registers
 };
 
 // Spanning consensus group of a workgroup (on = false for every other workgroup).
@@ -92,8 +94,8 @@ __device__ __forceinline__ T gx_read(const T* p) {
 // and stops waiting, so a group whose workgroups are not all resident cannot hold the queue.
 // nbar counts the group barriers this workgroup has passed in this launch; rows of barrier b
 // live in buffer b & 1.
-template <class T, int BLOCK, int HSR, int LR>
-__device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR, LR>& sh, const Span& sp, unsigned& nbar,
+template <class T, int BLOCK, int HSR, int LR, int AR>
+__device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR, LR, AR>& sh, const Span& sp, unsigned& nbar,
                                            const int t) {
     __syncthreads();
     if (t < 64) {
@@ -132,9 +134,12 @@ __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HS
 // WAVE1: no trajectory of this workgroup straddles a wavefront boundary, so neighbour values
 // move with DPP wavefront shifts instead of LDS and the two exchange barriers of every ADMM
 // iteration disappear.  The per-trajectory reductions still go through LDS.
-template <class M, class T, int BLOCK, bool WAVE1, bool SPAN, int HSR, int LR>
-__device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR, LR>& sh,
-                                                const int t, const int gn, const Span span_in) {
+// ADAPT: the adaptive penalty (residual balancing between SCP iterations) is on; a kernel variant
+// of its own, so the fixed-penalty kernels compile without it.
+template <class M, class T, int BLOCK, bool WAVE1, bool SPAN, bool ADAPT, int HSR, int LR, int AR>
+__device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp,
+                                                Shared<T, BLOCK, HSR, LR, AR>& sh, const int t, const int gn,
+                                                const Span span_in) {
     // SPAN: this kernel variant may hold spanning groups (compiled out of the other variant)
     const Span span{SPAN && span_in.on, span_in.slot, span_in.nwg};
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, C = M::C;
@@ -196,7 +201,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     constexpr int HSN = HSQ ? M::KM : 1;
     static_assert(!HSQ || HSR == 3 * HSN, "half-space rows of the workgroup state");
     constexpr bool LDSL = LR >= Dims<M>::NL;  // the factor lives in LDS
-    static_assert(WAVE1 || Shared<T, BLOCK, HSR, LR>::XR == PERSIST_MAX_NX, "LDS exchange needs full rows");
+    static_assert(WAVE1 || Shared<T, BLOCK, HSR, LR, AR>::XR == PERSIST_MAX_NX, "LDS exchange needs full rows");
     static_assert(M::NX <= PERSIST_MAX_NX && M::C <= PERSIST_MAX_C, "model too large for the workgroup state");
     T sig[HSN], kap[HSN];
 #pragma unroll
@@ -221,10 +226,16 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         if (t < PERSIST_MAX_NX) sh.fw[t][0] = T(0);
     }
     if (t < BLOCK) sh.gxm[t] = -1;
+    if constexpr (ADAPT) sh.arho[t] = valid ? dv.rt[tr * RT_FIELDS + RT_RHOS] : T(1);
 
     for (int k = 0; k < kp.n_scp; ++k, sfac *= kp.sched_q) {
         {
-            const T re = T(kp.rho_base[0] * sfac), rd = T(kp.rho_base[1] * sfac), rg = T(kp.rho_base[2] * sfac);
+            // schedule factor, then the adaptive factor: (rho_base * s_k) * f
+            auto pen = [&](double base) -> T {
+                if constexpr (ADAPT) return T(base * sfac * (double)sh.arho[t]);
+                return T(base * sfac);
+            };
+            const T re = pen(kp.rho_base[0]), rd = pen(kp.rho_base[1]), rg = pen(kp.rho_base[2]);
             rho = Rho<T>{re, rd, rg, T(1) / rg, T(1) / (re + rd)};
         }
         // ---------------- a2: linearization at the nominal ----------------
@@ -696,6 +707,10 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             }
             iters_sum += iters_here;
             conv_last = conv_here;
+            // the group's residuals of this SCP iteration's last ADMM iteration
+            if constexpr (ADAPT)
+                sh.arho[t] = T(adapt_factor((double)sh.arho[t], (double)rp_last, (double)rd_last, kp.adapt_mu,
+                                            kp.adapt_tau));
         }
         __syncthreads();
     }
@@ -770,6 +785,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
     if (first_lane) {
         dv.rt[tr * RT_FIELDS + RT_DELTA] = delta;
+        if constexpr (ADAPT) dv.rt[tr * RT_FIELDS + RT_RHOS] = sh.arho[t];
         double* inf = dv.info + (size_t)tr * SCP_INFO_FIELDS;
         int st = sh.st[tb];
         if (!kp.reset_info) st |= (int)inf[SCP_I_STATUS] & ~SCP_ST_CONVERGED;
@@ -800,14 +816,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
 }
 
-template <class M, class T, int BLOCK, bool SPAN, int HSR, int LR>
-__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR, LR>& sh, const int t,
-                                         const int gn, const bool cross, const Span& sp) {
+template <class M, class T, int BLOCK, bool SPAN, bool ADAPT, int HSR, int LR, int AR>
+__device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR, LR, AR>& sh,
+                                         const int t, const int gn, const bool cross, const Span& sp) {
     if constexpr (BLOCK == 64) {
-        persistent_body<M, T, BLOCK, true, SPAN>(dv, kp, sh, t, gn, sp);
+        persistent_body<M, T, BLOCK, true, SPAN, ADAPT>(dv, kp, sh, t, gn, sp);
     } else {
-        if (cross) persistent_body<M, T, BLOCK, false, SPAN>(dv, kp, sh, t, gn, sp);
-        else persistent_body<M, T, BLOCK, true, SPAN>(dv, kp, sh, t, gn, sp);
+        if (cross) persistent_body<M, T, BLOCK, false, SPAN, ADAPT>(dv, kp, sh, t, gn, sp);
+        else persistent_body<M, T, BLOCK, true, SPAN, ADAPT>(dv, kp, sh, t, gn, sp);
     }
 }
 
@@ -820,9 +836,10 @@ constexpr int persistent_lds_factor_rows(int block, int models) {
 
 // MODELS: 1 quadrotor only, 2 powered descent only, 3 both (each workgroup holds one model).
 // SPAN: the launch has consensus groups spanning several workgroups.
-template <class T, int BLOCK, int MODELS, int KM, bool SPAN>
+template <class T, int BLOCK, int MODELS, int KM, bool SPAN, bool ADAPT>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) {
-    __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM : 1, persistent_lds_factor_rows(BLOCK, MODELS)> sh;
+    __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM : 1, persistent_lds_factor_rows(BLOCK, MODELS),
+                      ADAPT ? BLOCK : 1> sh;
     const int t = threadIdx.x;
     const int w = dv.wg_list ? dv.wg_list[blockIdx.x] : (int)blockIdx.x;
     const int gn = dv.lane_node[(size_t)w * BLOCK + t];
@@ -831,28 +848,28 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) 
     Span sp{false, 0, 1};
     if (wi & WG_SPAN) sp = Span{true, dv.wg_group[2 * w], dv.wg_group[2 * w + 1]};
     if constexpr (MODELS == 1) {
-        body_for<Quad<KM>, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
+        body_for<Quad<KM>, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
     } else if constexpr (MODELS == 2) {
-        body_for<Mars, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
+        body_for<Mars, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
     } else {
-        if ((wi & 0xff) == SCP_MODEL_QUAD_PM) body_for<Quad<KM>, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
-        else body_for<Mars, T, BLOCK, SPAN>(dv, kp, sh, t, gn, cross, sp);
+        if ((wi & 0xff) == SCP_MODEL_QUAD_PM) body_for<Quad<KM>, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
+        else body_for<Mars, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
     }
 }
 
-// Launch of the persistent kernel variant for BLOCK and SPAN (instantiated per precision and
-// variant in their own translation units, compiled in parallel).
-template <class T, int BLOCK, bool SPAN>
+// Launch of the persistent kernel variant for BLOCK, SPAN and ADAPT (instantiated per precision
+// and variant in their own translation units, compiled in parallel).
+template <class T, int BLOCK, bool SPAN, bool ADAPT = false>
 void launch_models(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int models, int kmax, hipStream_t s) {
     const dim3 g(n_wg), b(BLOCK);
     if (models == 1) {
-        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 4, SPAN>), g, b, 0, s, dv, kp);
-        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 8, SPAN>), g, b, 0, s, dv, kp);
+        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 4, SPAN, ADAPT>), g, b, 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 8, SPAN, ADAPT>), g, b, 0, s, dv, kp);
     } else if (models == 2) {
-        hipLaunchKernelGGL((k_persistent<T, BLOCK, 2, 0, SPAN>), g, b, 0, s, dv, kp);
+        hipLaunchKernelGGL((k_persistent<T, BLOCK, 2, 0, SPAN, ADAPT>), g, b, 0, s, dv, kp);
     } else {
-        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 4, SPAN>), g, b, 0, s, dv, kp);
-        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 8, SPAN>), g, b, 0, s, dv, kp);
+        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 4, SPAN, ADAPT>), g, b, 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 8, SPAN, ADAPT>), g, b, 0, s, dv, kp);
     }
 }
 

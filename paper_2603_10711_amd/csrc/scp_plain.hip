@@ -46,6 +46,18 @@ __device__ __forceinline__ void stp(T* __restrict__ pl, int P, int g, const T* v
 template <class T>
 __device__ __forceinline__ T* PL(const Dev<T>& dv, int plane) { return dv.planes + (size_t)plane * dv.P; }
 
+// adaptive penalty factor of trajectory tr (exactly 1 while the rule is off), and the penalties
+// of this SCP iteration scaled by it
+template <class T>
+__device__ __forceinline__ T rho_factor(const Dev<T>& dv, const KParams<T>& kp, int tr) {
+    return kp.adapt_mu > 0.0 ? dv.rt[tr * RT_FIELDS + RT_RHOS] : T(1);
+}
+template <class T>
+__device__ __forceinline__ Rho<T> rho_of(const KParams<T>& kp, T f) {
+    const T re = kp.rho_eq * f, rd = kp.rho_dyn * f, rg = kp.rho_geo * f;
+    return Rho<T>{re, rd, rg, T(1) / rg, T(1) / (re + rd)};
+}
+
 // Resolve the node handled by this thread: returns the trajectory or -1.
 template <class M, class T>
 __device__ __forceinline__ int node_of(const Dev<T>& dv, int g, NodeId& id, const T*& prm) {
@@ -89,7 +101,7 @@ __global__ __launch_bounds__(256) void k_lin(Dev<T> dv, KParams<T> kp) {
     if (tr < 0) return;
     const int P = dv.P;
     const int* rec = dv.traj + tr * TR_FIELDS;
-    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    const Rho<T> rho = rho_of<T>(kp, rho_factor<T>(dv, kp, tr));
     NodeConst<M, T> nc;
     T xbar[NX], ubar[NU], F[NX];
     ldp<NX>(PL(dv, PL_XBAR), P, g, xbar);
@@ -184,7 +196,7 @@ __global__ __launch_bounds__(256) void k_step1(Dev<T> dv, KParams<T> kp) {
     const int tr = node_of<M>(dv, g, id, prm);
     if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
     const int P = dv.P;
-    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    const Rho<T> rho = rho_of<T>(kp, rho_factor<T>(dv, kp, tr));
     NodeConst<M, T> nc;
     load_const<M, T>(dv, g, nc);
     NodeState<M, T> s;
@@ -235,8 +247,9 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
     const int tr = node_of<M>(dv, g, id, prm);   // the lanes of a group share g and leave together
     if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
     const int P = dv.P;
-    const T rho_eq = kp.rho_eq, rho_dyn = kp.rho_dyn, rho_geo = kp.rho_geo;
     const bool last = id.last();
+    const T rf = rho_factor<T>(dv, kp, tr);
+    const T rho_eq = kp.rho_eq * rf, rho_dyn = kp.rho_dyn * rf, rho_geo = kp.rho_geo * rf;
     auto at = [&](int plane, int node) -> T { return dv.planes[(size_t)plane * P + node]; };
 
     // w = mu_{i+1} + rho_dyn (z_{i+1} - d_i) on the owned rows (z, mu of node N+1 read as 0)
@@ -428,8 +441,11 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     id.ball = false;
     const bool first = id.first(), last = id.last();
     const int P = dv.P;
-    const T rho_eq = kp.rho_eq, rho_dyn = kp.rho_dyn, rho_geo = kp.rho_geo;
-    const T inv_geo = T(1) / kp.rho_geo, inv_sum = T(1) / (kp.rho_eq + kp.rho_dyn);
+    // penalties of this trajectory: the same in every lane of the workgroup
+    const T rf = rho_factor<T>(dv, kp, tr);
+    const T rho_eq = wave_uniform(kp.rho_eq * rf), rho_dyn = wave_uniform(kp.rho_dyn * rf);
+    const T rho_geo = wave_uniform(kp.rho_geo * rf);
+    const T inv_geo = wave_uniform(T(1) / rho_geo), inv_sum = wave_uniform(T(1) / (rho_eq + rho_dyn));
     const T* prm = dv.params + (size_t)tr * SCP_PARAM_STRIDE;
     auto at = [&](int plane) -> T { return live ? dv.planes[(size_t)plane * P + g] : T(0); };
     auto put = [&](int plane, T v) {
@@ -865,7 +881,7 @@ __global__ __launch_bounds__(256) void k_step234(Dev<T> dv, KParams<T> kp, int c
     if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
     const int P = dv.P;
     const bool grouped0 = id.first() && dv.traj[tr * TR_FIELDS + TR_GSIZE] > 1;
-    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    const Rho<T> rho = rho_of<T>(kp, rho_factor<T>(dv, kp, tr));
     NodeConst<M, T> nc;
     ldp<NN>(PL(dv, PL_LO), P, g, nc.lo);
     ldp<NN>(PL(dv, PL_HI), P, g, nc.hi);
@@ -1004,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_resid(Dev<T> dv, KParams<T> kp) {
     const int tr = node_of<M>(dv, g, id, prm);
     if (tr < 0 || dv.flags[tr * FL_FIELDS + FL_DONE]) return;
     const int P = dv.P;
-    Rho<T> rho{kp.rho_eq, kp.rho_dyn, kp.rho_geo, T(1) / kp.rho_geo, T(1) / (kp.rho_eq + kp.rho_dyn)};
+    const Rho<T> rho = rho_of<T>(kp, rho_factor<T>(dv, kp, tr));
     T Ar[NX * NXR], B[NX * NU], sp[NN], dzn[NX];
     ldp<NX * NXR>(PL(dv, PL_AR), P, g, Ar);
     ldp<NX * NU>(PL(dv, PL_B), P, g, B);
@@ -1126,6 +1142,12 @@ __global__ void k_acc_traj(Dev<T> dv, KParams<T> kp) {
         fl[FL_ACCEPT] = a.accept ? 1 : 0;
         dv.rt[t * RT_FIELDS + RT_DELTA] = a.delta;
     }
+    if (kp.adapt_mu > 0.0) {   // residuals of this SCP iteration's last ADMM iteration (k_check)
+        const double* li = dv.info + (size_t)tr * SCP_INFO_FIELDS;
+        const T f = T(adapt_factor((double)dv.rt[tr * RT_FIELDS + RT_RHOS], li[SCP_I_RP], li[SCP_I_RD], kp.adapt_mu,
+                                   kp.adapt_tau));
+        for (int m = 0; m < S; ++m) dv.rt[(tr + m) * RT_FIELDS + RT_RHOS] = f;
+    }
 }
 
 template <class T>
@@ -1203,7 +1225,10 @@ __global__ void k_reset(Dev<T> dv, int reset_delta) {
     fl[FL_STATUS] = 0;
     dv.red[2 * tr] = 0ull;
     dv.red[2 * tr + 1] = 0ull;
-    if (reset_delta) dv.rt[tr * RT_FIELDS + RT_DELTA] = dv.params[(size_t)tr * SCP_PARAM_STRIDE + SCP_P_DELTA];
+    if (reset_delta) {
+        dv.rt[tr * RT_FIELDS + RT_DELTA] = dv.params[(size_t)tr * SCP_PARAM_STRIDE + SCP_P_DELTA];
+        dv.rt[tr * RT_FIELDS + RT_RHOS] = T(1);
+    }
     inf[SCP_I_DELTA] = (double)dv.rt[tr * RT_FIELDS + RT_DELTA];
 }
 

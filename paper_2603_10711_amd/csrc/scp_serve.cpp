@@ -111,7 +111,10 @@ bool valid_config(const scp_server_config* c, std::string& err) {
         return false;
     }
     if (c->scp_per_step < 1 || q.scp_iters % c->scp_per_step != 0) { err = "scp_per_step must divide scp_iters"; return false; }
-    if (q.rho_final != 0.0) { err = "the server runs fixed penalties (rho_final = 0)"; return false; }
+    if (q.rho_final != 0.0 || q.adapt_mu != 0.0) {
+        err = "the server runs fixed penalties (rho_final = 0, adapt_mu = 0)";
+        return false;
+    }
     if (c->max_inflight < 1 || c->max_inflight > 8) { err = "max_inflight must be in 1..8"; return false; }
     return true;
 }

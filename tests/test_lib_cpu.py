@@ -46,11 +46,12 @@ def test_server_config_validation(B):
     prm = B.scp_params(10, 100)
     good = B.ServerConfig(0, 256, 0, 1 << 14, 256, 256, 32, 32, 0, prm, 1, 2)
     assert lib.scp_server_device_bytes(byref(good)) > (1 << 14) * 350 * 4
-    bad = [dict(block=96), dict(prec=1, block=256), dict(scp_per_step=3), dict(max_nodes=0), dict(max_inflight=0)]
+    bad = [dict(block=96), dict(prec=1, block=256), dict(scp_per_step=3), dict(max_nodes=0), dict(max_inflight=0),
+           dict(adapt_mu=10.0), dict(rho_final=1e3)]
     for kw in bad:
         c = B.ServerConfig(0, 256, 0, 1 << 14, 256, 256, 32, 32, 0, prm, 1, 2)
         for k, v in kw.items():
-            setattr(c, k, v)
+            setattr(c.solve if k in ("adapt_mu", "rho_final") else c, k, v)
         assert lib.scp_server_device_bytes(byref(c)) == 0, kw
         h = c_void_p()
         assert lib.scp_server_create(byref(c), None, 0, None, byref(h)) == 1 and not h.value
