@@ -227,19 +227,34 @@ __global__ __launch_bounds__(256) void k_step1(Dev<T> dv, KParams<T> kp) {
 // ------------------------------------------------------------------------------------------
 // At n = 17 one lane per node underfills the chip (a 1000-trajectory batch of 41 nodes makes 641
 // wavefronts for 1024 SIMDs) and every lane works through a long chain of dependent loads.  Here
-// the four lanes of a DPP group share a node.  Lane l owns the components k = 4s + l (slot s):
-// their rows of w, their columns of A and B, and their rows of the factor, so each lane loads
-// about a third of the node's data.
+// the four lanes of a DPP group share a node.  Lane l owns the state components k = 4s + l
+// (slots s = 0..3) and the control component l (slot 4): their rows of w, their columns of A and
+// B, and their rows of the factor, so each lane loads about a third of the node's data.  A slot
+// holds states only or controls only, so no slot runs both the state and the control code.
 //  * w rows go to every lane of the group by broadcast;
 //  * the forward substitution is right-looking: y_k comes from its owner by broadcast and every
 //    lane updates its rows below k (the same subtraction sequence as the one-lane solve);
 //  * the backward substitution sums each lane's products over its rows below k across the group;
 //  * A x + B u is summed over the group the same way, and the owner of each row stores it.
 // Rows of the factor above the diagonal are held as zeros, so no step needs a lane mask.
+template <class M>
+struct Lanes4 {
+    static constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NS = 5;
+    static_assert(NX <= 16 && NU <= 4 && NN == NX + NU, "four lanes hold the node");
+    // component in slot s of lane l, and whether the node has it
+    __device__ static constexpr int comp(int s, int l) { return s < 4 ? 4 * s + l : NX + l; }
+    __device__ static constexpr bool held(int s, int l) { return s < 4 ? 4 * s + l < NX : l < NU; }
+    // slot and lane of component k
+    __device__ static constexpr int slot(int k) { return k < NX ? k / 4 : 4; }
+    __device__ static constexpr int lane(int k) { return k < NX ? k % 4 : k - NX; }
+    // largest component any lane holds in slot s
+    __device__ static constexpr int top(int s) { return s < 4 ? (4 * s + 3 < NX ? 4 * s + 3 : NX - 1) : NN - 1; }
+};
+
 template <class M, class T>
 __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) {
-    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, KM = M::KM, NS = 5;
-    static_assert(NN <= 4 * NS && NX <= 16, "four lanes hold the node");
+    using LY = Lanes4<M>;
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, KM = M::KM, NS = LY::NS;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int g = (int)(gid >> 2), l = (int)(gid & 3);
     NodeId id;
@@ -280,9 +295,9 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 #pragma unroll
         for (int r = 0; r < NX; ++r) Al[s][r] = (k >= 3 && k < NX) ? at(PL_AR + r * NXR + (k - 3), g) : T(0);
     }
-    // the control component of this lane, if any: k = NX + cu with k = l (mod 4)
-    const int cu = (l - NX % 4 + 4) % 4;
-    const bool has_u = cu < NU;
+    // the control component of this lane, if any: k = NX + l, slot 4
+    const int cu = l;
+    const bool has_u = l < NU;
 #pragma unroll
     for (int r = 0; r < NX; ++r) Bl[r] = has_u ? at(PL_B + r * NU + cu, g) : T(0);
 
@@ -293,7 +308,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
         const int k = 4 * s + l;
         const int s4 = s < 4 ? s : 3;   // state components sit in slots 0..3
         T v = T(0);
-        if (k < NX) {
+        if (s < 4 && k < NX) {
             T tx = wl[s4];   // unit columns of A: (A'w)_k = w_k, the lane's own row k
             if (k >= 3) {
                 tx = T(0);
@@ -320,7 +335,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
                     v = v + (rx * at(PL_CP + slot, g) - at(PL_DU + slot, g));
                 }
             }
-        } else if (k < NN) {
+        } else if (s == 4 && has_u) {
             T tu = T(0);
 #pragma unroll
             for (int r = 0; r < NX; ++r) tu = tu + Bl[r] * w[r];
@@ -341,10 +356,11 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
     T Lr[NS][NN];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const int row = 4 * s + l;
+        const int row = LY::comp(s, l);
+        const bool ok = LY::held(s, l);
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
-            if (j < 4 * s + 4) Lr[s][j] = (row < NN && j <= row) ? at(PL_L + tri(row, j), g) : T(0);
+            if (j <= LY::top(s)) Lr[s][j] = (ok && j <= row) ? at(PL_L + tri(row, j), g) : T(0);
             else Lr[s][j] = T(0);
         }
     }
@@ -355,11 +371,12 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
     for (int s = 0; s < NS; ++s) yl[s] = T(0);
 #pragma unroll
     for (int k = 0; k < NN; ++k) {
-        const T yk = quad_bcast(acc[k / 4] * Lr[k / 4][k], k % 4);
-        yl[k / 4] = (l == k % 4) ? yk : yl[k / 4];
+        const int sk = LY::slot(k), lk = LY::lane(k);
+        const T yk = quad_bcast(acc[sk] * Lr[sk][k], lk);
+        yl[sk] = (l == lk) ? yk : yl[sk];
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            if (4 * s + 3 > k) acc[s] = acc[s] - Lr[s][k] * yk;
+            if (LY::top(s) > k) acc[s] = acc[s] - Lr[s][k] * yk;
     }
     // backward substitution L' x = y
     T xl[NS];
@@ -370,9 +387,10 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
         T p = T(0);
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            if (4 * s + 3 > k) p = p + Lr[s][k] * xl[s];   // rows not below k hold 0 here
-        const T xk = quad_bcast((yl[k / 4] - quad_sum(p)) * Lr[k / 4][k], k % 4);
-        xl[k / 4] = (l == k % 4) ? xk : xl[k / 4];
+            if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];   // rows not below k hold 0 here
+        const int sk = LY::slot(k), lk = LY::lane(k);
+        const T xk = quad_bcast((yl[sk] - quad_sum(p)) * Lr[sk][k], lk);
+        xl[sk] = (l == lk) ? xk : xl[sk];
     }
 
     // x, u of the owned components (u = 0 at node N), then d_dyn = A x + B u + d
@@ -382,7 +400,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int k = 4 * s + l;
-        if (k < NX) {
+        if (s < 4 && k < NX) {
             dv.planes[(size_t)(PL_X + k) * P + g] = xl[s];
             if (s == 0) {
 #pragma unroll
@@ -390,7 +408,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
             }
 #pragma unroll
             for (int r = 0; r < NX; ++r) q[r] = q[r] + Al[s < 4 ? s : 3][r] * xl[s];
-        } else if (k < NN) {
+        } else if (s == 4 && has_u) {
             const T u = last ? T(0) : xl[s];
             dv.planes[(size_t)(PL_U + cu) * P + g] = u;
 #pragma unroll
@@ -422,10 +440,11 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 template <class M, class T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
 void k_admm_resident(Dev<T> dv, KParams<T> kp) {
-    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = 5, MAXN = RESIDENT_MAX_NODES;
+    using LY = Lanes4<M>;
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = LY::NS, MAXN = RESIDENT_MAX_NODES;
     constexpr int KM = M::KM, KA = KM > 0 ? KM : 1;
     constexpr bool LD = M::ID == SCP_MODEL_LANDER6;
-    static_assert(NN <= 4 * NS && NX <= 16 && (M::QL || LD), "6-DOF models");
+    static_assert(M::QL || LD, "6-DOF models");
     __shared__ T sz[MAXN][16], smu[MAXN][16], sdd[MAXN][16];
     const int tr = blockIdx.x;
     if (tr >= dv.n_traj || dv.flags[tr * FL_FIELDS + FL_DONE]) return;   // uniform over the workgroup
@@ -451,8 +470,8 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     auto put = [&](int plane, T v) {
         if (live) dv.planes[(size_t)plane * P + g] = v;
     };
-    const int cu = (l - NX % 4 + 4) % 4;   // control component of this lane, if cu < NU
-    const bool has_u = cu < NU;
+    const int cu = l;   // control component of this lane (slot 4), if l < NU
+    const bool has_u = l < NU;
 
     // node data of the owned components
     T dl[4], zl[4], laml[4], mul[4], g0l[4];
@@ -478,9 +497,9 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     T cpb[NS], dub[NS], lol[NS], hil[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const int k = 4 * s + l;
-        const bool ok = k < NN;
-        const int bs = k < NX ? M::C_XBOX + k : M::C_UBOX + (k - NX);
+        const int k = LY::comp(s, l);
+        const bool ok = LY::held(s, l);
+        const int bs = s < 4 ? M::C_XBOX + k : M::C_UBOX + l;
         cpb[s] = ok ? at(PL_CP + bs) : T(0);
         dub[s] = ok ? at(PL_DU + bs) : T(0);
         lol[s] = ok ? at(PL_LO + k) : T(0);
@@ -489,10 +508,11 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     T Lr[NS][NN];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const int row = 4 * s + l;
+        const int row = LY::comp(s, l);
+        const bool ok = LY::held(s, l);
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
-            if (j < 4 * s + 4) Lr[s][j] = (row < NN && j <= row) ? at(PL_L + tri(row, j)) : T(0);
+            if (j <= LY::top(s)) Lr[s][j] = (ok && j <= row) ? at(PL_L + tri(row, j)) : T(0);
             else Lr[s][j] = T(0);
         }
     }
@@ -578,7 +598,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             const int k = 4 * s + l;
             const int s4 = s < 4 ? s : 3;   // state components sit in slots 0..3
             T v = T(0);
-            if (k < NX) {
+            if (s < 4 && k < NX) {
                 T tx = wl[s4];
                 if (k >= 3) {
                     tx = T(0);
@@ -598,7 +618,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                 } else {
                     if (xslot_of(k) >= 0) v = v + (group_rho<M>(id, rho_geo, 2) * cpe[s4] - due[s4]);
                 }
-            } else if (k < NN) {
+            } else if (s == 4 && has_u) {
                 T tu = T(0);
 #pragma unroll
                 for (int r = 0; r < NX; ++r) tu = tu + Bl[r] * w[r];
@@ -616,11 +636,12 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
         for (int s = 0; s < NS; ++s) yl[s] = T(0);
 #pragma unroll
         for (int k = 0; k < NN; ++k) {
-            const T yk = quad_bcast(acc[k / 4] * Lr[k / 4][k], k % 4);
-            yl[k / 4] = (l == k % 4) ? yk : yl[k / 4];
+            const int sk = LY::slot(k), lk = LY::lane(k);
+            const T yk = quad_bcast(acc[sk] * Lr[sk][k], lk);
+            yl[sk] = (l == lk) ? yk : yl[sk];
 #pragma unroll
             for (int s = 0; s < NS; ++s)
-                if (4 * s + 3 > k) acc[s] = acc[s] - Lr[s][k] * yk;
+                if (LY::top(s) > k) acc[s] = acc[s] - Lr[s][k] * yk;
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) xl[s] = T(0);
@@ -629,9 +650,10 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             T p = T(0);
 #pragma unroll
             for (int s = 0; s < NS; ++s)
-                if (4 * s + 3 > k) p = p + Lr[s][k] * xl[s];
-            const T xk = quad_bcast((yl[k / 4] - quad_sum(p)) * Lr[k / 4][k], k % 4);
-            xl[k / 4] = (l == k % 4) ? xk : xl[k / 4];
+                if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];
+            const int sk = LY::slot(k), lk = LY::lane(k);
+            const T xk = quad_bcast((yl[sk] - quad_sum(p)) * Lr[sk][k], lk);
+            xl[sk] = (l == lk) ? xk : xl[sk];
         }
         T q[NX];
 #pragma unroll
@@ -639,14 +661,14 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int k = 4 * s + l;
-            if (k < NX) {
+            if (s < 4 && k < NX) {
                 if (s == 0) {
 #pragma unroll
                     for (int r = 0; r < 3; ++r) q[r] = q[r] + (k == r ? xl[s] : T(0));
                 }
 #pragma unroll
                 for (int r = 0; r < NX; ++r) q[r] = q[r] + Al[s < 4 ? s : 3][r] * xl[s];
-            } else if (k < NN) {
+            } else if (s == 4 && has_u) {
                 if (last) xl[s] = T(0);
 #pragma unroll
                 for (int r = 0; r < NX; ++r) q[r] = q[r] + Bl[r] * xl[s];
@@ -670,7 +692,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
         for (int s = 0; s < NS; ++s) {
             const int k = 4 * s + l;
             const int s4 = s < 4 ? s : 3;
-            if (k < NX) {
+            if (s < 4 && k < NX) {
                 const T x = xl[s], z0 = zl[s4];
                 const T dp = (!first && live) ? sdd[i - 1][k] : T(0);
                 const T z = first ? z0 : (((rho_eq * x + laml[s4]) + rho_dyn * dp) - mul[s4]) * inv_sum;
@@ -694,7 +716,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                     pm = nmax(pm, tabs(x - cp));
                 }
                 if (s == 0) xpos = x;
-            } else if (k < NN) {
+            } else if (s == 4 && has_u) {
                 const T u = xl[s];
                 const T cpo = cpb[s];
                 T cp = clampv(u + dub[s] * inv_geo, lol[s], hil[s]);
@@ -772,8 +794,8 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                 if (l >= 2) upd_x(2, xl[2], l == 2 ? v[0] : v[1]);
                 if (l == 0) upd_x(3, xl[3], v[2]);
             }
-            // thrust component c is held by lane (NX + c) mod 4
-            constexpr int L0 = (NX + 0) % 4, L1 = (NX + 1) % 4, L2 = (NX + 2) % 4;
+            // thrust component c is held by lane c (slot 4)
+            constexpr int L0 = 0, L1 = 1, L2 = 2;
             {   // thrust magnitude upper bound
                 const T vb = has_u ? uval + du3[0] * inv_geo : T(0);
                 T v[3] = {quad_bcast(vb, L0), quad_bcast(vb, L1), quad_bcast(vb, L2)};
@@ -824,7 +846,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     for (int s = 0; s < NS; ++s) {
         const int k = 4 * s + l;
         const int s4 = s < 4 ? s : 3;
-        if (k < NX) {
+        if (s < 4 && k < NX) {
             put(PL_X + k, xl[s]);
             put(PL_Z + k, zl[s4]);
             put(PL_LAM + k, laml[s4]);
@@ -832,7 +854,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             put(PL_DD + k, dds[s4]);
             put(PL_CP + M::C_XBOX + k, cpb[s]);
             put(PL_DU + M::C_XBOX + k, dub[s]);
-        } else if (k < NN) {
+        } else if (s == 4 && has_u) {
             put(PL_U + cu, xl[s]);
             put(PL_CP + M::C_UBOX + cu, cpb[s]);
             put(PL_DU + M::C_UBOX + cu, dub[s]);
