@@ -190,6 +190,25 @@ __device__ __forceinline__ T quad_bcast(T v, int k) {
         default: return quad_perm<0xFF>(v);
     }
 }
+// the value of lane l xor c of this lane's group (c a constant after unrolling)
+template <class T>
+__device__ __forceinline__ T quad_xor(T v, int c) {
+    switch (c & 3) {
+        case 0: return v;
+        case 1: return quad_perm<0xB1>(v);
+        case 2: return quad_perm<0x4E>(v);
+        default: return quad_perm<0x1B>(v);
+    }
+}
+// Sums over the group of four rows at once: lane l holds its term of row l xor c in v[c], and
+// receives the sum of row l as (v_l + v_{l^1}) + (v_{l^2} + v_{l^3}) (subscripts: lanes), the
+// bits quad_sum gives that row in every lane.
+template <class T>
+__device__ __forceinline__ T quad_reduce_scatter(const T* v) {
+    const T a = v[0] + quad_perm<0xB1>(v[1]);   // row l: own term + lane l^1's
+    const T b = v[2] + quad_perm<0xB1>(v[3]);   // row l^2: own term + lane l^1's
+    return a + quad_perm<0x4E>(b);              // + lane l^2's pair sum of row l
+}
 // sum over the group as (v0 + v1) + (v2 + v3); addition commutes exactly, so every lane of the
 // group gets the same bits
 template <class T>

@@ -235,7 +235,10 @@ __global__ __launch_bounds__(256) void k_step1(Dev<T> dv, KParams<T> kp) {
 //  * the forward substitution is right-looking: y_k comes from its owner by broadcast and every
 //    lane updates its rows below k (the same subtraction sequence as the one-lane solve);
 //  * the backward substitution sums each lane's products over its rows below k across the group;
-//  * A x + B u is summed over the group the same way, and the owner of each row stores it.
+//  * A x + B u: a lane's copies of its columns of A and B hold row 4n + (l xor c) at entry
+//    4n + c, so one reduce-scatter of three exchanges per four rows hands every lane the sums of
+//    its own rows, with the bits of the full group sum (the last rows use that sum);
+//  * A'w sums over the rows in the same lane-permuted order.
 // Rows of the factor above the diagonal are held as zeros, so no step needs a lane mask.
 template <class M>
 struct Lanes4 {
@@ -249,6 +252,11 @@ struct Lanes4 {
     __device__ static constexpr int lane(int k) { return k < NX ? k % 4 : k - NX; }
     // largest component any lane holds in slot s
     __device__ static constexpr int top(int s) { return s < 4 ? (4 * s + 3 < NX ? 4 * s + 3 : NX - 1) : NN - 1; }
+    // Row of A and B that entry m of a lane's column copy holds: rows 4n + (l xor c) at m = 4n + c
+    // below RB, so that quad_reduce_scatter hands the sum of row 4n + l to lane l; rows from RB on
+    // in order.
+    static constexpr int RB = NX / 4 * 4;
+    __device__ static constexpr int row(int m, int l) { return m < RB ? 4 * (m / 4) + (l ^ (m % 4)) : m; }
 };
 
 template <class M, class T>
@@ -285,7 +293,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
     }
     T w[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) w[r] = quad_bcast(wl[r / 4], r % 4);
+    for (int m = 0; m < NX; ++m) w[m] = m < LY::RB ? quad_xor(wl[m / 4], m % 4) : quad_bcast(wl[m / 4], m % 4);
 
     // owned columns of A (non-unit part) and of B
     T Al[4][NX], Bl[NX];
@@ -293,15 +301,15 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
     for (int s = 0; s < 4; ++s) {
         const int k = 4 * s + l;
 #pragma unroll
-        for (int r = 0; r < NX; ++r) Al[s][r] = (k >= 3 && k < NX) ? at(PL_AR + r * NXR + (k - 3), g) : T(0);
+        for (int m = 0; m < NX; ++m) Al[s][m] = (k >= 3 && k < NX) ? at(PL_AR + LY::row(m, l) * NXR + (k - 3), g) : T(0);
     }
     // the control component of this lane, if any: k = NX + l, slot 4
     const int cu = l;
     const bool has_u = l < NU;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) Bl[r] = has_u ? at(PL_B + r * NU + cu, g) : T(0);
+    for (int m = 0; m < NX; ++m) Bl[m] = has_u ? at(PL_B + LY::row(m, l) * NU + cu, g) : T(0);
 
-    // right-hand side of the owned components, summed as in the one-lane Step 1
+    // right-hand side of the owned components (A'w over the rows in the lane's permuted order)
     T acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -403,8 +411,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
         if (s < 4 && k < NX) {
             dv.planes[(size_t)(PL_X + k) * P + g] = xl[s];
             if (s == 0) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) q[r] = q[r] + (k == r ? xl[s] : T(0));
+                q[0] = q[0] + (k < 3 ? xl[s] : T(0));   // entry 0 holds row l = k
             }
 #pragma unroll
             for (int r = 0; r < NX; ++r) q[r] = q[r] + Al[s < 4 ? s : 3][r] * xl[s];
@@ -415,10 +422,16 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
             for (int r = 0; r < NX; ++r) q[r] = q[r] + Bl[r] * u;
         }
     }
+    // rows below RB: each lane receives the sums of its own rows; the rest by a sum over the group
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
+    for (int n = 0; n < LY::RB / 4; ++n) {
+        const T dd = quad_reduce_scatter(q + 4 * n) + dl[n];
+        dv.planes[(size_t)(PL_DD + 4 * n + l) * P + g] = last ? T(0) : dd;   // no interval after node N
+    }
+#pragma unroll
+    for (int r = LY::RB; r < NX; ++r) {
         const T dd = quad_sum(q[r]) + dl[r / 4];
-        if (l == r % 4) dv.planes[(size_t)(PL_DD + r) * P + g] = last ? T(0) : dd;   // no interval after node N
+        if (l == r % 4) dv.planes[(size_t)(PL_DD + r) * P + g] = last ? T(0) : dd;
     }
 }
 
@@ -490,10 +503,10 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     for (int s = 0; s < 4; ++s) {
         const int k = 4 * s + l;
 #pragma unroll
-        for (int r = 0; r < NX; ++r) Al[s][r] = (k >= 3 && k < NX) ? at(PL_AR + r * NXR + (k - 3)) : T(0);
+        for (int m = 0; m < NX; ++m) Al[s][m] = (k >= 3 && k < NX) ? at(PL_AR + LY::row(m, l) * NXR + (k - 3)) : T(0);
     }
 #pragma unroll
-    for (int r = 0; r < NX; ++r) Bl[r] = has_u ? at(PL_B + r * NU + cu) : T(0);
+    for (int m = 0; m < NX; ++m) Bl[m] = has_u ? at(PL_B + LY::row(m, l) * NU + cu) : T(0);
     T cpb[NS], dub[NS], lol[NS], hil[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -591,7 +604,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
         }
         T w[NX];
 #pragma unroll
-        for (int r = 0; r < NX; ++r) w[r] = quad_bcast(wl[r / 4], r % 4);
+        for (int m = 0; m < NX; ++m) w[m] = m < LY::RB ? quad_xor(wl[m / 4], m % 4) : quad_bcast(wl[m / 4], m % 4);
         T acc[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -663,8 +676,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             const int k = 4 * s + l;
             if (s < 4 && k < NX) {
                 if (s == 0) {
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) q[r] = q[r] + (k == r ? xl[s] : T(0));
+                    q[0] = q[0] + (k < 3 ? xl[s] : T(0));   // entry 0 holds row l = k
                 }
 #pragma unroll
                 for (int r = 0; r < NX; ++r) q[r] = q[r] + Al[s < 4 ? s : 3][r] * xl[s];
@@ -674,11 +686,18 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                 for (int r = 0; r < NX; ++r) q[r] = q[r] + Bl[r] * xl[s];
             }
         }
+        // rows below RB: each lane receives the sums of its own rows; the rest by a sum over the group
 #pragma unroll
-        for (int r = 0; r < NX; ++r) {
+        for (int n = 0; n < LY::RB / 4; ++n) {
+            const T dd = quad_reduce_scatter(q + 4 * n) + dl[n];
+            dds[n] = last ? T(0) : dd;   // no interval after node N
+            if (live) sdd[i][4 * n + l] = dds[n];
+        }
+#pragma unroll
+        for (int r = LY::RB; r < NX; ++r) {
             const T dd = quad_sum(q[r]) + dl[r / 4];
             if (l == r % 4) {
-                dds[r / 4] = last ? T(0) : dd;   // no interval after node N
+                dds[r / 4] = last ? T(0) : dd;
                 if (live) sdd[i][r] = dds[r / 4];
             }
         }
