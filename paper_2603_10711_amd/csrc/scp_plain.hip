@@ -234,7 +234,8 @@ __global__ __launch_bounds__(256) void k_step1(Dev<T> dv, KParams<T> kp) {
 //  * w rows go to every lane of the group by broadcast;
 //  * the forward substitution is right-looking: y_k comes from its owner by broadcast and every
 //    lane updates its rows below k (the same subtraction sequence as the one-lane solve);
-//  * the backward substitution sums each lane's products over its rows below k across the group;
+//  * the backward substitution sums each lane's products over its rows below k across the group
+//    (the same bits in every lane) and the owner of row k finishes x_k;
 //  * A x + B u: a lane's copies of its columns of A and B hold row 4n + (l xor c) at entry
 //    4n + c, so one reduce-scatter of three exchanges per four rows hands every lane the sums of
 //    its own rows, with the bits of the full group sum (the last rows use that sum);
@@ -396,8 +397,9 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];   // rows not below k hold 0 here
+        // the sum is the same in every lane, so the owner finishes x_k alone
         const int sk = LY::slot(k), lk = LY::lane(k);
-        const T xk = quad_bcast((yl[sk] - quad_sum(p)) * Lr[sk][k], lk);
+        const T xk = (yl[sk] - quad_sum(p)) * Lr[sk][k];
         xl[sk] = (l == lk) ? xk : xl[sk];
     }
 
@@ -664,8 +666,9 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
 #pragma unroll
             for (int s = 0; s < NS; ++s)
                 if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];
+            // the sum is the same in every lane, so the owner finishes x_k alone
             const int sk = LY::slot(k), lk = LY::lane(k);
-            const T xk = quad_bcast((yl[sk] - quad_sum(p)) * Lr[sk][k], lk);
+            const T xk = (yl[sk] - quad_sum(p)) * Lr[sk][k];
             xl[sk] = (l == lk) ? xk : xl[sk];
         }
         T q[NX];
