@@ -1139,10 +1139,14 @@ __global__ __launch_bounds__(256) void k_acc_nodes(Dev<T> dv, KParams<T> kp) {
     PL(dv, PL_MER)[(size_t)MER_PEN_MOD * P + g] = pmod;
 }
 
+// One wavefront per trajectory (group leader): the lanes stage the node terms of up to 64 nodes
+// at a time in LDS with coalesced loads, and lane 0 sums them in node order (the sums are those
+// of a single thread walking the nodes, without its chain of dependent global loads).
 template <class T>
-__global__ void k_acc_traj(Dev<T> dv, KParams<T> kp) {
-    const int tr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tr >= dv.n_traj) return;
+__global__ __launch_bounds__(64) void k_acc_traj(Dev<T> dv, KParams<T> kp) {
+    __shared__ T sm[5][64];
+    const int tr = blockIdx.x, t = threadIdx.x;
+    if (tr >= dv.n_traj) return;   // uniform over the workgroup, as the next test
     const int* rec = dv.traj + tr * TR_FIELDS;
     if (rec[TR_MEMBER] != 0) return;
     const int S = rec[TR_GSIZE];
@@ -1153,19 +1157,36 @@ __global__ void k_acc_traj(Dev<T> dv, KParams<T> kp) {
         const int* r = dv.traj + (tr + m) * TR_FIELDS;
         const int off = r[TR_OFF], n = r[TR_N] + 1;
         T J0 = T(0), p0 = T(0), J1 = T(0), p1 = T(0), pm = T(0);
-        for (int i = 0; i < n; ++i) {
-            J0 = J0 + mer[(size_t)MER_COST_NOM * P + off + i];
-            J1 = J1 + mer[(size_t)MER_COST_NEW * P + off + i];
-        }
-        for (int i = 0; i + 1 < n; ++i) {
-            p0 = p0 + mer[(size_t)MER_PEN_NOM * P + off + i];
-            p1 = p1 + mer[(size_t)MER_PEN_NEW * P + off + i];
-            pm = pm + mer[(size_t)MER_PEN_MOD * P + off + i];
+        for (int c = 0; c < n; c += 64) {
+            const int i = c + t;
+            if (i < n) {
+                sm[0][t] = mer[(size_t)MER_COST_NOM * P + off + i];
+                sm[1][t] = mer[(size_t)MER_COST_NEW * P + off + i];
+                sm[2][t] = mer[(size_t)MER_PEN_NOM * P + off + i];
+                sm[3][t] = mer[(size_t)MER_PEN_NEW * P + off + i];
+                sm[4][t] = mer[(size_t)MER_PEN_MOD * P + off + i];
+            }
+            __syncthreads();
+            if (t == 0) {
+                const int e = min(64, n - c);          // nodes of this chunk
+                const int ep = min(64, n - 1 - c);     // of them, nodes with an interval after them
+                for (int q = 0; q < e; ++q) {
+                    J0 = J0 + sm[0][q];
+                    J1 = J1 + sm[1][q];
+                }
+                for (int q = 0; q < ep; ++q) {
+                    p0 = p0 + sm[2][q];
+                    p1 = p1 + sm[3][q];
+                    pm = pm + sm[4][q];
+                }
+            }
+            __syncthreads();
         }
         mnom = mnom + (J0 + kp.merit_w * p0);
         mnew = mnew + (J1 + kp.merit_w * p1);
         mmod = mmod + (J1 + kp.merit_w * pm);
     }
+    if (t != 0) return;
     const AcceptOut<T> a = accept_rule<T>(kp.eta0, kp.eta1, kp.eta2, kp.shrink, kp.grow, kp.delta_max, mnom, mnew,
                                           mmod, dv.rt[tr * RT_FIELDS + RT_DELTA]);
     for (int m = 0; m < S; ++m) {
@@ -1391,7 +1412,7 @@ hipError_t launch_plain(PlainOp op, const Dev<T>& dv, const KParams<T>& kp, int 
             break;
         case PlainOp::Accept:
             each([&](auto m) { hipLaunchKernelGGL((k_acc_nodes<decltype(m), T>), gn, b, 0, s, dv, kp); });
-            hipLaunchKernelGGL((k_acc_traj<T>), gt, b, 0, s, dv, kp);
+            hipLaunchKernelGGL((k_acc_traj<T>), dim3(dv.n_traj), dim3(64), 0, s, dv, kp);
             hipLaunchKernelGGL((k_acc_apply<T>), gn, b, 0, s, dv);
             break;
         case PlainOp::Metrics:
