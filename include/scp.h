@@ -159,8 +159,8 @@ enum {
 #define SCP_ST_EMPTYSET 4     /* a hard box has lo > hi                                     */
 #define SCP_ST_CONVERGED 8    /* ADMM residual test passed in the last SCP iteration        */
 #define SCP_ST_SYNC 16        /* a consensus group spanning several workgroups waited too
-                                 long at its group barrier (its workgroups were not all
-                                 resident); the group's results are invalid               */
+                                 long at a group barrier (scp_params.group_wait_ms); set on
+                                 every member of the group, whose results are invalid      */
 
 typedef struct {
     int32_t n_traj;           /* number of trajectories, >= 1                              */
@@ -233,6 +233,12 @@ typedef struct {
                                          consensus groups (SCP_ERR_UNSUPPORTED otherwise).
                                          0: off.                                              */
     double adapt_tau;                 /* > 1 when adapt_mu > 0                                */
+    double group_wait_ms;             /* persistent form with consensus groups spanning several
+                                         workgroups: longest wait at one group barrier before the
+                                         whole group is flagged SCP_ST_SYNC (0 = 20 ms; < 0 = give
+                                         up at the first wait, which exercises the failure path).
+                                         Once a member gives up, every member of the group stops
+                                         waiting and reports SCP_ST_SYNC.                       */
 } scp_params;
 
 typedef struct scp_problem scp_problem;

@@ -59,7 +59,7 @@ class ScpParams(ctypes.Structure):
     _fields_ = [("scp_iters", c_int32), ("admm", AdmmParams), ("eta0", c_double), ("eta1", c_double),
                 ("eta2", c_double), ("shrink", c_double), ("grow", c_double), ("delta_max", c_double),
                 ("merit_w", c_double), ("form", c_int32), ("scp_per_launch", c_int32), ("rho_final", c_double),
-                ("graph", c_int32), ("adapt_mu", c_double), ("adapt_tau", c_double)]
+                ("graph", c_int32), ("adapt_mu", c_double), ("adapt_tau", c_double), ("group_wait_ms", c_double)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -206,11 +206,11 @@ def admm_params(rho=1.0, iters=100, check_every=0, eps=0.0, rho_dyn=None, rho_ge
 def scp_params(scp_iters=10, admm_iters=100, rho=1.0, check_every=0, eps=0.0, form="persistent",
                scp_per_launch=0, eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
                merit_w=1.0e3, rho_dyn=None, rho_geo=None, graph=False, rho_final=0.0, adapt_mu=0.0,
-               adapt_tau=2.0) -> ScpParams:
+               adapt_tau=2.0, group_wait_ms=0.0) -> ScpParams:
     f = FORM_PERSISTENT if form == "persistent" else FORM_PLAIN
     return ScpParams(scp_iters, admm_params(rho, admm_iters, check_every, eps, rho_dyn, rho_geo), eta0, eta1, eta2,
                      shrink, grow, delta_max, merit_w, f, scp_per_launch, rho_final, 1 if graph else 0, adapt_mu,
-                     adapt_tau)
+                     adapt_tau, group_wait_ms)
 
 
 def _pad(a, w):
@@ -372,9 +372,20 @@ class Problem:
         fid = FIELDS[name]
         w = self.lib.scp_field_width(fid)
         out = self.torch.empty((self.n_nodes, w), dtype=self.dtype, device=self.arena.device)
+        self._enter(out)
         self._check(self.lib.scp_get_field(self.h, fid, c_void_p(out.data_ptr())), "scp_get_field")
         self._join()
         return out
+
+    def _enter(self, *outs):
+        """Before the library writes caller-side tensors on the problem's stream: that stream
+        waits for the caller's current stream (the allocator may hand out a block whose last use
+        there is still running), and the tensors are marked as used on it."""
+        cur = self.torch.cuda.current_stream(self.arena.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+            for o in outs:
+                o.record_stream(self.stream)
 
     def _join(self):
         """Order the caller's current stream after the work enqueued on the problem's stream."""
@@ -388,6 +399,7 @@ class Problem:
         x = t.empty((self.n_nodes, MAX_NX), dtype=self.dtype, device=self.arena.device)
         u = t.empty((self.n_nodes, MAX_NU), dtype=self.dtype, device=self.arena.device)
         info = t.empty((self.n_traj, INFO_FIELDS), dtype=t.float64, device=self.arena.device)
+        self._enter(x, u, info)
         self._check(self.lib.scp_get_result(self.h, c_void_p(x.data_ptr()), c_void_p(u.data_ptr()),
                                             c_void_p(info.data_ptr())), "scp_get_result")
         self._join()

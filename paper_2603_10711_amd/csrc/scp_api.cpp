@@ -328,6 +328,8 @@ struct scp_problem {
     Dev<float> df;
     Dev<double> dd;
     bool linearized = false;
+    // consensus groups spanning workgroups: workgroups the device keeps resident at once
+    int span_cap = 0;
     double lin_rho[3] = {1.0, 1.0, 1.0};
     std::string err;
     // scp_solve launch sequences captured into graphs, keyed by their parameters
@@ -362,6 +364,7 @@ KParams<T> kparams(const admm_params* a, const scp_params* s) {
     k.sched_q = 1.0;
     k.adapt_mu = 0.0;
     k.adapt_tau = 1.0;
+    k.spin_ticks = group_wait_ticks(0.0);
     if (s) {
         k.eta0 = T(s->eta0);
         k.eta1 = T(s->eta1);
@@ -371,6 +374,7 @@ KParams<T> kparams(const admm_params* a, const scp_params* s) {
         k.delta_max = T(s->delta_max);
         k.merit_w = T(s->merit_w);
         k.sched_q = sched_ratio(*s);
+        k.spin_ticks = group_wait_ticks(s->group_wait_ms);
         if (s->adapt_mu > 0.0) {
             k.adapt_mu = s->adapt_mu;
             k.adapt_tau = s->adapt_tau;
@@ -413,7 +417,7 @@ bool same_params(const scp_params& a, const scp_params& b) {
            a.eta1 == b.eta1 && a.eta2 == b.eta2 && a.shrink == b.shrink && a.grow == b.grow &&
            std::memcmp(&a.delta_max, &b.delta_max, sizeof(double)) == 0 && a.merit_w == b.merit_w &&
            a.form == b.form && a.scp_per_launch == b.scp_per_launch && a.rho_final == b.rho_final &&
-           a.adapt_mu == b.adapt_mu && a.adapt_tau == b.adapt_tau;
+           a.adapt_mu == b.adapt_mu && a.adapt_tau == b.adapt_tau && a.group_wait_ms == b.group_wait_ms;
 }
 
 template <class T>
@@ -612,6 +616,7 @@ scp_status scp_problem_create(const scp_problem_desc* desc, void* arena_dev, siz
     }
     p->df = make_dev<float>(L, p->arena);
     p->dd = make_dev<double>(L, p->arena);
+    if (L.persistent_ok && L.n_gslots > 0) p->span_cap = persistent_span_resident_cap((int)L.esz, L.block, L.models, L.kmax);
     *out = p;
     return SCP_OK;
 }
@@ -661,6 +666,11 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
                                              "without consensus groups");
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && !p->L.resident_ok)
         return fail(p, SCP_ERR_UNSUPPORTED, kNoPersistent);
+    if (prm->form == SCP_FORM_PERSISTENT && p->L.persistent_ok && p->L.n_gslots > 0 && p->L.n_wg > p->span_cap)
+        return fail(p, SCP_ERR_UNSUPPORTED, "consensus groups spanning several workgroups need every workgroup of "
+                                             "the launch resident at once: the batch has " + std::to_string(p->L.n_wg) +
+                                             " workgroups, the device keeps " + std::to_string(p->span_cap) +
+                                             " resident; use the plain form or smaller batches");
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && prm->admm.check_every > 0)
         return fail(p, SCP_ERR_UNSUPPORTED, "the resident ADMM of 6-DOF batches runs fixed budgets "
                                              "(check_every = 0)");
@@ -872,6 +882,10 @@ scp_status scp_autotune(const scp_problem_desc* desc, const scp_params* prm, con
             if (fits) {
                 st = scp_problem_create(&d, arena_dev, arena_bytes, hip_stream, &p);
                 if (st != SCP_OK) break;
+                if (p->L.n_gslots > 0 && p->L.n_wg > p->span_cap) {   // spanning groups not all resident
+                    scp_problem_destroy(p);
+                    p = nullptr;
+                }
             }
             for (int c : cads) {
                 scp_tune_entry en{blk, pk, c, 0, 0.0};

@@ -665,6 +665,7 @@ __device__ __forceinline__ int convexify(const T* __restrict__ prm, const NodeId
             lo = prm[SCP_P_XTGT + r];
             hi = lo;
         }
+        if (!(lo <= hi)) st |= SCP_ST_NONFINITE;   // a NaN bound: non-finite nominal or boundary value
         nc.lo[r] = lo;
         nc.hi[r] = hi;
         nc.g0[r] = id.last() ? -prm[SCP_P_QNV + r] : T(0);
@@ -673,6 +674,7 @@ __device__ __forceinline__ int convexify(const T* __restrict__ prm, const NodeId
     for (int r = 0; r < NU; ++r) {
         T lo, hi;
         if (trust_box(ucenter[r], delta, prm[SCP_P_ULO + r], prm[SCP_P_UHI + r], lo, hi)) st |= SCP_ST_EMPTYSET;
+        if (!(lo <= hi)) st |= SCP_ST_NONFINITE;
         nc.lo[NX + r] = id.last() ? T(0) : lo;
         nc.hi[NX + r] = id.last() ? T(0) : hi;
     }

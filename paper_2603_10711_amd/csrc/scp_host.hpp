@@ -37,6 +37,20 @@ struct Layout {
 // Validate the description and lay out its arena (packing included).
 bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err);
 
+// Longest wait at a spanning-group barrier in ticks of the device wall clock (100 MHz) for
+// scp_params.group_wait_ms: 0 = 20 ms, < 0 = give up at the first wait.
+inline unsigned long long group_wait_ticks(double ms) {
+    if (ms < 0.0) return 0ull;
+    if (ms == 0.0) ms = 20.0;
+    const double t = ms * 1.0e5;
+    return t >= 1.8e19 ? ~0ull : (unsigned long long)t;
+}
+
+// Workgroups of `block` lanes of the persistent kernel variant for consensus groups spanning
+// several workgroups that the device keeps resident at once (occupancy of that kernel times the
+// device's compute units); 0 if the query fails.  esz: element size (4 or 8).
+int persistent_span_resident_cap(int esz, int block, int models, int kmax);
+
 // Device views of an arena laid out by build_layout.
 template <class T>
 Dev<T> make_dev(const Layout& L, char* base);

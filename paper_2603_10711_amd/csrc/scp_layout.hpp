@@ -67,7 +67,8 @@ enum : int { FL_DONE = 0, FL_ITERS = 1, FL_ACCEPT = 2, FL_STATUS = 3, FL_FIELDS 
 // Consensus groups larger than one workgroup ("spanning groups") get whole workgroups of their
 // own and exchange their per-member values through HBM records: two buffers (alternating by
 // the parity of the group barrier), GX_MEMBERS member rows of GX_WIDTH values each.  The
-// group barrier counts workgroup arrivals in one 32-bit word per 128-byte line.
+// group barrier counts workgroup arrivals in one 32-bit word per 128-byte line; the next word
+// of that line is the group's failure word (nonzero once a member gave up waiting).
 constexpr int GX_MEMBERS = 64;
 constexpr int GX_WIDTH = 8;
 constexpr int GX_SYNC_STRIDE = 32;
@@ -137,6 +138,9 @@ struct KParams {
     // adaptive penalty (residual balancing between SCP iterations): on when adapt_mu > 0; the
     // factor of trajectory t is rt[t * RT_FIELDS + RT_RHOS] and multiplies the penalties above
     double adapt_mu, adapt_tau;
+    // spanning consensus groups: longest wait at one group barrier, in ticks of the device wall
+    // clock (100 MHz), before the group is declared failed (0: give up at the first wait)
+    unsigned long long spin_ticks;
 };
 
 }  // namespace scp

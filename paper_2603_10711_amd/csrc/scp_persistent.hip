@@ -1,6 +1,7 @@
 // Persistent form: launch entry (the kernel templates live in scp_persistent.hpp; their
 // instantiations are split over scp_persistent_{f32,f64}{,_span,_adapt}.hip).
 #include "scp_persistent.hpp"
+#include "scp_host.hpp"
 
 namespace scp {
 
@@ -78,6 +79,17 @@ static size_t shared_bytes(int block) {
 
 size_t persistent_shared_bytes(int esz, int block) {
     return esz == 4 ? shared_bytes<float>(block) : shared_bytes<double>(block);
+}
+
+int span_blocks_per_cu_f32(int block, int models, int kmax);
+int span_blocks_per_cu_f64(int block, int models, int kmax);
+
+int persistent_span_resident_cap(int esz, int block, int models, int kmax) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const int per_cu = esz == 4 ? span_blocks_per_cu_f32(block, models, kmax) : span_blocks_per_cu_f64(block, models, kmax);
+    return per_cu * cus;
 }
 
 template hipError_t launch_persistent<float>(const Dev<float>&, const KParams<float>&, int, int, int, int, hipStream_t);

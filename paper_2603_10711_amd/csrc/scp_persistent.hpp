@@ -68,11 +68,6 @@ struct Span {
     int nwg;   // workgroups of the group
 };
 
-// Longest wait at a group barrier, in ticks of the device wall clock (100 MHz: 20 ms), before
-// the barrier is declared failed; it then stops waiting, so every workgroup still reaches the
-// end of the kernel quickly.
-constexpr unsigned long long kSpinTicks = 2000000ull;
-
 template <class T>
 __device__ __forceinline__ T* gx_row(const Dev<T>& dv, const Span& sp, unsigned nbar, int member) {
     return dv.gx + ((size_t)(sp.slot * 2 + (int)(nbar & 1u)) * GX_MEMBERS + member) * GX_WIDTH;
@@ -89,14 +84,17 @@ __device__ __forceinline__ T gx_read(const T* p) {
 // write-back), polls the arrival counter with relaxed agent-scope loads (no cache maintenance
 // per poll) and takes one agent-scope acquire fence (one L2 invalidation).  Readers then load
 // the rows with agent-scope atomic loads.  Both fences are required on gfx950: without them
-// arrivals and rows written on other XCDs can stay invisible.  A wait longer than
-// kSpinTicks of the device wall clock marks the workgroup's results invalid (SCP_ST_SYNC)
-// and stops waiting, so a group whose workgroups are not all resident cannot hold the queue.
-// nbar counts the group barriers this workgroup has passed in this launch; rows of barrier b
-// live in buffer b & 1.
+// arrivals and rows written on other XCDs can stay invisible.
+// Failure: a workgroup that has waited spin ticks of the device wall clock (or finds the group's
+// failure word set) gives up, sets the failure word and never waits again; it still arrives at
+// every later barrier, so the counts stay consistent and every workgroup reaches the end of the
+// kernel quickly.  Every member reads the failure word at the end of the launch and reports
+// SCP_ST_SYNC, so a member that never had to wait (it found the counter already past its
+// target) is flagged too.  nbar counts the group barriers this workgroup has passed in this
+// launch; rows of barrier b live in buffer b & 1.
 template <class T, int BLOCK, int HSR, int LR, int AR>
 __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR, LR, AR>& sh, const Span& sp, unsigned& nbar,
-                                           const int t) {
+                                           const int t, const unsigned long long spin) {
     __syncthreads();
     if (t < 64) {
         for (int j = t; j < BLOCK; j += 64) {
@@ -119,11 +117,13 @@ __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HS
             const unsigned target = nbar * (unsigned)sp.nwg;
             const unsigned long long t0 = wall_clock64();
             while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > kSpinTicks) {
+                if (wall_clock64() - t0 >= spin ||
+                    __hip_atomic_load(c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                     sh.sync_fail = 1;
+                    __hip_atomic_fetch_or(c + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
+                __builtin_amdgcn_s_sleep(1);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -296,7 +296,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                 for (int r = 0; r < NU; ++r) sh.gxw[r][t] = ubar[r];
                 sh.gxm[t] = mem;
             }
-            group_sync(dv, sh, span, nbar, t);
+            group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
             if (g0) {
                 T acc[NU];
 #pragma unroll
@@ -452,7 +452,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                         if (slot_is_u<M>(q)) sh.gxw[slot_comp_u<M>(q)][t] = s.cp[q];
                     sh.gxm[t] = mem;
                 }
-                group_sync(dv, sh, span, nbar, t);
+                group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
                 if (g0) {
 #pragma unroll
                     for (int q = 0; q < C; ++q) {
@@ -559,7 +559,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                         sh.mx[0][tb] = 0ull;
                         sh.mx[1][tb] = 0ull;
                     }
-                    group_sync(dv, sh, span, nbar, t);
+                    group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
                     if (!done && leader) {
                         T grp = T(0), grd = T(0);
                         for (int m = 0; m < S; ++m) {
@@ -673,7 +673,7 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         }
         if (span.on) {
             const unsigned b = nbar;
-            group_sync(dv, sh, span, nbar, t);
+            group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
             if (leader) {
                 for (int m = 0; m < S; ++m) {
                     const T* row = gx_row(dv, span, b, m);
@@ -746,7 +746,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         sh.red[3][t] = m_bnd;
         __syncthreads();
     }
-    if (span.on && sh.sync_fail) status |= SCP_ST_SYNC;
+    if (span.on) {
+        // the group failed if any member gave up waiting (see group_sync)
+        if (t == 0 && __hip_atomic_load(dv.gsync + (size_t)span.slot * GX_SYNC_STRIDE + 1, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            sh.sync_fail = 1;
+        __syncthreads();
+        if (sh.sync_fail) status |= SCP_ST_SYNC;
+    }
     if (valid && status) atomicOr(&sh.st[tb], status);
     __syncthreads();
 
@@ -871,6 +878,23 @@ void launch_models(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int models,
         if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 4, SPAN, ADAPT>), g, b, 0, s, dv, kp);
         else hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 8, SPAN, ADAPT>), g, b, 0, s, dv, kp);
     }
+}
+
+// Workgroups per compute unit of the spanning-group variant (occupancy of the exact kernel the
+// launch would use); 0 if the query fails.
+template <class T, int BLOCK>
+int span_blocks_per_cu(int models, int kmax) {
+    int n = 0;
+    hipError_t e;
+    if (models == 1)
+        e = kmax <= 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 1, 4, true, false>, BLOCK, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 1, 8, true, false>, BLOCK, 0);
+    else if (models == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 2, 0, true, false>, BLOCK, 0);
+    else
+        e = kmax <= 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 3, 4, true, false>, BLOCK, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 3, 8, true, false>, BLOCK, 0);
+    return e == hipSuccess ? n : 0;
 }
 
 }  // namespace scp

@@ -651,6 +651,7 @@ scp_status do_step(scp_server* s, int wait, int32_t* pending) {
     kp.rho_base[2] = q.admm.rho_geo;
     kp.sched_s0 = 1.0;
     kp.sched_q = 1.0;
+    kp.spin_ticks = group_wait_ticks(q.group_wait_ms);
     kp.n_scp = s->cfg.scp_per_step;
     kp.final_metrics = 1;
     kp.reset_info = 0;
@@ -724,10 +725,20 @@ scp_status scp_server_create(const scp_server_config* cfg, void* arena_dev, size
     s->trajs.reset(cfg->max_traj);
     s->wgs.reset(cfg->max_wg);
     for (int g = cfg->max_span - 1; g >= 0; --g) s->span_free.push_back(g);
-    // one wave per SIMD (4 per CU) and the LDS of the persistent kernel's workgroup state
-    const size_t lds = std::max<size_t>(1, persistent_shared_bytes(s->esz, cfg->block));
-    const int per_cu = std::max(1, std::min(4 / (cfg->block / 64), (int)(163840 / lds)));
-    s->wg_cap_running = 256 * per_cu;
+    // workgroups the device keeps resident at once: occupancy of the spanning-group kernel variant
+    // (the largest state: both models, 8 obstacles) times the compute units; if the query fails,
+    // one wave per SIMD, the LDS of the workgroup state and the device's CU count and LDS size
+    s->wg_cap_running = persistent_span_resident_cap(s->esz, cfg->block, 3, 8);
+    if (s->wg_cap_running <= 0) {
+        int dev = 0, cus = 0, lds_cu = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+        if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+            lds_cu = 0;
+        const size_t lds = std::max<size_t>(1, persistent_shared_bytes(s->esz, cfg->block));
+        const int per_cu = std::max(1, std::min(4 / (cfg->block / 64), (int)((size_t)lds_cu / lds)));
+        s->wg_cap_running = std::max(1, cus) * per_cu;
+    }
     const int slots = cfg->max_inflight + 1;
     hipError_t e = hipSuccess;
     for (int k = 0; k < slots && e == hipSuccess; ++k) {

@@ -3,7 +3,8 @@
 Quadrotor batch: 1024 instances, N = 50, 8 obstacles, 15 SCP x 200 ADMM, FP32, persistent form.
 Powered descent: 4096 instances, N = 60, 15 x 200, FP32.
 * sampled instances after the first SCP iteration of the full batch: FP32 vs oracle at 1e-4;
-* sampled instances at the full budget: FP64 mode vs oracle at 1e-9;
+* sampled instances in FP64 mode vs oracle: 1e-9 after 5 SCP iterations, a fixed 1e-6 at the full
+  budget (the SCP map amplifies rounding-order differences; measured on the oracle itself);
 * every sampled trajectory of the full FP32 batch is bitwise equal to the same trajectory solved
   alone (placement independence), and plain and persistent forms agree to 1e-4 after SCP 1;
 * properties that hold at any size: finite iterates, boundary conditions, metrics consistent.
@@ -70,10 +71,17 @@ def _oracle_cholesky_variant(sample, K, J):
         oa.np.linalg.solve = lu
 
 
+# FP64 bar at the full 15 x 200 budget.  Over 15 SCP iterations the map amplifies rounding-order
+# differences: the oracle itself, with its Step-1 solves done by Cholesky instead of LU (an equally
+# valid rounding order), moves its own nominal by up to 5.8e-8 relative on these samples (instance
+# 1023; 1.4e-10 to 6.6e-10 on the others).  The bar is a fixed 1e-6, 17 x that measured
+# amplification; after 5 SCP iterations the bar stays 1e-9.
+TOL64_FULL = 1e-6
+
+
 def test_quad_full_budget_fp64_samples(B, quad_batch):
-    """FP64 mode: 1e-9 after 5 SCP iterations; at the full 15 x 200 budget the bar is
-    max(1e-9, 20 x the oracle's own LU-vs-Cholesky disagreement), because the SCP map amplifies
-    rounding-order differences to ~1e-8 there (measured on the oracle alone)."""
+    """FP64 mode against the oracle: 1e-9 after 5 SCP iterations, TOL64_FULL at the full budget;
+    the oracle's own LU-vs-Cholesky gap is printed beside it."""
     sample = [quad_batch[i] for i in SAMPLE]
     for K in (5, 15):
         print(f"quad samples {K} x 200 fp64 persistent", flush=True)
@@ -82,12 +90,11 @@ def test_quad_full_budget_fp64_samples(B, quad_batch):
         f = gpu_fields(prob)
         trajs, _ = oracle_scp(sample, K, 200)
         worst = compare(prob, f, sample, trajs)
-        tol = 1e-9
+        tol = 1e-9 if K == 5 else TOL64_FULL
         if K == 15:
             alt = _oracle_cholesky_variant(sample, K, 200)
             self_gap = max(rel_err(a.xbar, t.xbar) for a, t in zip(alt, trajs))
-            tol = max(1e-9, 20.0 * self_gap)
-            print(f"oracle self-disagreement {self_gap:.2e} -> tol {tol:.2e}", flush=True)
+            print(f"oracle self-disagreement {self_gap:.2e}; bar {tol:.0e}", flush=True)
         print(worst, flush=True)
         assert max(worst.values()) < tol
         prob.close()
