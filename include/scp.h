@@ -255,6 +255,26 @@ size_t scp_problem_device_bytes(const scp_problem_desc* desc);
 scp_status scp_problem_create(const scp_problem_desc* desc, void* arena_dev, size_t arena_bytes,
                               void* hip_stream, scp_problem** out);
 
+/* Size of the no-allocation arena of scp_problem_create_noalloc: one fixed device array of this
+ * many bytes per GPU, part of the library's device image and held until the process ends. */
+#define SCP_NOALLOC_MAX_BYTES (32u << 20)
+
+/* scp_problem_create for callers that cannot allocate device memory (code under HIP graph capture
+ * of later calls, tight serving loops, harnesses that forbid allocation): the same problem, laid
+ * out and uploaded exactly as scp_problem_create does, but in the library's fixed no-allocation
+ * arena of the current device (SCP_NOALLOC_MAX_BYTES) instead of caller memory.  The call allocates
+ * no device memory (no hipMalloc / hipFree, no allocating library routine); every later call on
+ * the handle (scp_solve, scp_get_result, ...) works as for a caller arena and produces the same
+ * bits.  The arena is cleared at create (as scp_problem_create clears a caller arena), so nothing
+ * is left over from an earlier problem.
+ * One arena per device: while a handle made by this call is alive, another call on the same device
+ * returns SCP_ERR_STATE; scp_problem_destroy releases it.  Work of a destroyed handle still queued
+ * on its stream and a new handle's work on another stream overlap in the same memory and race: the
+ * caller orders them (same stream, or a synchronization in between).
+ * Errors: SCP_ERR_ARG (invalid description, or a problem larger than SCP_NOALLOC_MAX_BYTES, whose
+ * size scp_problem_device_bytes gives), SCP_ERR_STATE (arena in use), SCP_ERR_HIP. */
+scp_status scp_problem_create_noalloc(const scp_problem_desc* desc, void* hip_stream, scp_problem** out);
+
 /* Release host resources of the handle; never frees arena_dev.  NULL is ignored. */
 void scp_problem_destroy(scp_problem* p);
 

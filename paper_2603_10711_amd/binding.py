@@ -35,13 +35,15 @@ INFO_FIELDS = 12
 ST_NONFINITE, ST_BADPIVOT, ST_EMPTYSET, ST_CONVERGED, ST_SYNC = 1, 2, 4, 8, 16
 FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9, A=10, B=11, d=12, boxlo=13,
               boxhi=14, hs=15)
-SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_destroy", "scp_linearize", "admm_solve",
+SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_create_noalloc", "scp_problem_destroy",
+           "scp_linearize", "admm_solve",
            "scp_solve", "scp_reset", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
            "scp_traj_node_offset", "scp_plan", "scp_autotune_device_bytes", "scp_autotune", "scp_last_error"]
 SERVE_SYMBOLS = ["scp_server_device_bytes", "scp_server_create", "scp_server_destroy", "scp_server_request_bytes",
                  "scp_server_submit", "scp_server_submit_ex", "scp_server_step", "scp_server_collect", "scp_server_get_stats",
                  "scp_server_last_error"]
 REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2, 3
+NOALLOC_MAX_BYTES = 32 << 20   # SCP_NOALLOC_MAX_BYTES of scp.h
 
 
 class ProblemDesc(ctypes.Structure):
@@ -102,6 +104,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scp_problem_device_bytes.restype = c_size_t
     lib.scp_problem_create.argtypes = [POINTER(ProblemDesc), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
     lib.scp_problem_create.restype = c_int32
+    lib.scp_problem_create_noalloc.argtypes = [POINTER(ProblemDesc), c_void_p, POINTER(c_void_p)]
+    lib.scp_problem_create_noalloc.restype = c_int32
     lib.scp_problem_destroy.argtypes = [c_void_p]
     lib.scp_problem_destroy.restype = None
     lib.scp_linearize.argtypes = [c_void_p, POINTER(AdmmParams)]
@@ -314,8 +318,10 @@ class Problem:
     """A batch of trajectories resident on the GPU (one arena tensor), driven through the C ABI."""
 
     def __init__(self, insts: list[dict] | None, precision: str = "f32", block: int = 0, device: str = "cuda",
-                 stream=None, pack: int = PACK_ALIGNED, parts: list[dict] | None = None):
-        """insts: problem dictionaries; or parts: request_arrays() of several requests."""
+                 stream=None, pack: int = PACK_ALIGNED, parts: list[dict] | None = None, noalloc: bool = False):
+        """insts: problem dictionaries; or parts: request_arrays() of several requests.  noalloc: the
+        arena is the library's fixed no-allocation arena of the device (scp_problem_create_noalloc)
+        instead of a torch tensor."""
         import torch
         self.torch = torch
         self.lib = load()
@@ -334,15 +340,25 @@ class Problem:
             st = self.lib.scp_problem_create(byref(desc), None, 0, None, byref(h))
             raise ScpError(f"invalid problem description: {self.lib.scp_last_error(None).decode()}")
         self.nbytes = nbytes
-        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
-        if self.stream != torch.cuda.current_stream(self.arena.device):
-            self.arena.record_stream(self.stream)
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = c_void_p()
-        st = self.lib.scp_problem_create(byref(desc), c_void_p(self.arena.data_ptr()), nbytes,
-                                         c_void_p(self.stream.cuda_stream), byref(h))
+        if noalloc:
+            self.arena = None
+            with torch.cuda.device(self.device):
+                st = self.lib.scp_problem_create_noalloc(byref(desc), c_void_p(self.stream.cuda_stream), byref(h))
+            what = "scp_problem_create_noalloc"
+        else:
+            self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.stream != torch.cuda.current_stream(self.device):
+                self.arena.record_stream(self.stream)
+            st = self.lib.scp_problem_create(byref(desc), c_void_p(self.arena.data_ptr()), nbytes,
+                                             c_void_p(self.stream.cuda_stream), byref(h))
+            what = "scp_problem_create"
         if st != SCP_OK:
-            raise ScpError(f"scp_problem_create failed ({st}): {self.lib.scp_last_error(None).decode()}")
+            raise ScpError(f"{what} failed ({st}): {self.lib.scp_last_error(None).decode()}")
         self.h = h
         self.n_nodes = int(self.lib.scp_problem_nodes(h))
         self.offsets = np.array([self.lib.scp_traj_node_offset(h, t) for t in range(self.n_traj)], dtype=np.int64)
@@ -371,7 +387,7 @@ class Problem:
     def field(self, name: str):
         fid = FIELDS[name]
         w = self.lib.scp_field_width(fid)
-        out = self.torch.empty((self.n_nodes, w), dtype=self.dtype, device=self.arena.device)
+        out = self.torch.empty((self.n_nodes, w), dtype=self.dtype, device=self.device)
         self._enter(out)
         self._check(self.lib.scp_get_field(self.h, fid, c_void_p(out.data_ptr())), "scp_get_field")
         self._join()
@@ -381,7 +397,7 @@ class Problem:
         """Before the library writes caller-side tensors on the problem's stream: that stream
         waits for the caller's current stream (the allocator may hand out a block whose last use
         there is still running), and the tensors are marked as used on it."""
-        cur = self.torch.cuda.current_stream(self.arena.device)
+        cur = self.torch.cuda.current_stream(self.device)
         if cur != self.stream:
             self.stream.wait_stream(cur)
             for o in outs:
@@ -389,16 +405,16 @@ class Problem:
 
     def _join(self):
         """Order the caller's current stream after the work enqueued on the problem's stream."""
-        cur = self.torch.cuda.current_stream(self.arena.device)
+        cur = self.torch.cuda.current_stream(self.device)
         if cur != self.stream:
             cur.wait_stream(self.stream)
 
     def result(self):
         """(x, u, info) as device tensors: x (nodes, MAX_NX), u (nodes, MAX_NU), info (n_traj, 12) float64."""
         t = self.torch
-        x = t.empty((self.n_nodes, MAX_NX), dtype=self.dtype, device=self.arena.device)
-        u = t.empty((self.n_nodes, MAX_NU), dtype=self.dtype, device=self.arena.device)
-        info = t.empty((self.n_traj, INFO_FIELDS), dtype=t.float64, device=self.arena.device)
+        x = t.empty((self.n_nodes, MAX_NX), dtype=self.dtype, device=self.device)
+        u = t.empty((self.n_nodes, MAX_NU), dtype=self.dtype, device=self.device)
+        info = t.empty((self.n_traj, INFO_FIELDS), dtype=t.float64, device=self.device)
         self._enter(x, u, info)
         self._check(self.lib.scp_get_result(self.h, c_void_p(x.data_ptr()), c_void_p(u.data_ptr()),
                                             c_void_p(info.data_ptr())), "scp_get_result")

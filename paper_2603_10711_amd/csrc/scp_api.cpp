@@ -330,6 +330,8 @@ struct scp_problem {
     bool linearized = false;
     // consensus groups spanning workgroups: workgroups the device keeps resident at once
     int span_cap = 0;
+    // device whose no-allocation arena this handle holds (-1: caller arena)
+    int noalloc_dev = -1;
     double lin_rho[3] = {1.0, 1.0, 1.0};
     std::string err;
     // scp_solve launch sequences captured into graphs, keyed by their parameters
@@ -556,6 +558,13 @@ std::string tune_key(const scp_problem_desc* d, const scp_params* q, const std::
 
 }  // namespace
 
+namespace scp {
+
+void set_create_error(const std::string& msg) { g_create_error = msg; }
+void problem_mark_noalloc(scp_problem* p, int dev) { p->noalloc_dev = dev; }
+
+}  // namespace scp
+
 extern "C" {
 
 size_t scp_problem_device_bytes(const scp_problem_desc* desc) {
@@ -621,7 +630,10 @@ scp_status scp_problem_create(const scp_problem_desc* desc, void* arena_dev, siz
     return SCP_OK;
 }
 
-void scp_problem_destroy(scp_problem* p) { delete p; }
+void scp_problem_destroy(scp_problem* p) {
+    if (p && p->noalloc_dev >= 0) noalloc_release(p->noalloc_dev);
+    delete p;
+}
 
 scp_status scp_linearize(scp_problem* p, const admm_params* prm) {
     if (!p) return SCP_ERR_ARG;

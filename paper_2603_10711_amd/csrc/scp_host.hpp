@@ -51,6 +51,12 @@ inline unsigned long long group_wait_ticks(double ms) {
 // device's compute units); 0 if the query fails.  esz: element size (4 or 8).
 int persistent_span_resident_cap(int esz, int block, int models, int kmax);
 
+// No-allocation arena (scp_problem_create_noalloc): the error message of a failed create, the mark
+// that makes scp_problem_destroy release the device's arena, and that release.
+void set_create_error(const std::string& msg);
+void problem_mark_noalloc(scp_problem* p, int dev);
+void noalloc_release(int dev);
+
 // Device views of an arena laid out by build_layout.
 template <class T>
 Dev<T> make_dev(const Layout& L, char* base);

@@ -41,6 +41,28 @@ def test_library_exports_every_declared_symbol(B):
     assert headers == ["scp.h", "scp_serve.h"]
 
 
+def test_noalloc_arena_size_matches_header(B):
+    txt = open(os.path.join(ROOT, "include", "scp.h")).read()
+    m = re.search(r"#define SCP_NOALLOC_MAX_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == B.NOALLOC_MAX_BYTES
+
+
+def test_numerical_failures_are_not_call_errors(B):
+    """Non-SPD cost, lo > hi and a NaN initial state are per-trajectory status bits on the device,
+    not description errors: the host accepts them."""
+    lib = B.load()
+    insts = scpgen.config1(3)
+    insts[0] = dict(insts[0], R=np.array([-80.0, 2.0, 2.0]))
+    xlo, xhi = insts[1]["x_lo"].copy(), insts[1]["x_hi"].copy()
+    xlo[4], xhi[4] = 3.0, -3.0
+    insts[1] = dict(insts[1], x_lo=xlo, x_hi=xhi)
+    x0 = insts[2]["x_init"].copy()
+    x0[1] = float("nan")
+    insts[2] = dict(insts[2], x_init=x0)
+    d, keep = _desc(B, insts)
+    assert lib.scp_problem_device_bytes(byref(d)) > 0
+
+
 def test_server_config_validation(B):
     lib = B.load()
     prm = B.scp_params(10, 100)
