@@ -239,6 +239,20 @@ typedef struct {
                                          up at the first wait, which exercises the failure path).
                                          Once a member gives up, every member of the group stops
                                          waiting and reports SCP_ST_SYNC.                       */
+    int32_t lanes_per_node;           /* persistent form, lanes of a wavefront that share one
+                                         node: 1 = one lane per node, the whole solve in one
+                                         fused kernel (point-mass quadrotor, powered descent);
+                                         4 = lane groups of four (DPP quad exchanges): the node's
+                                         components, factor rows and A, B columns split over the
+                                         four lanes, ADMM iterations resident in one workgroup per
+                                         trajectory, linearization and acceptance as in the plain
+                                         form (at most 64 nodes per trajectory, no consensus
+                                         groups, check_every = 0; the only form of the 6-DOF
+                                         models).  0 = the model's default (1 for the point-mass
+                                         quadrotor and powered descent, 4 for the 6-DOF models).
+                                         A combination the batch does not allow returns
+                                         SCP_ERR_UNSUPPORTED.  Results agree within rounding
+                                         (the sums run in another order).                        */
 } scp_params;
 
 typedef struct scp_problem scp_problem;
@@ -355,14 +369,17 @@ typedef struct {
     int32_t check_every;  /* residual-test cadence c                                 */
     int32_t valid;        /* 0 if the candidate does not fit (no timing)             */
     double ms;            /* mean wall time of one fresh solve on the device, in ms  */
+    int32_t lanes;        /* lanes per node (scp_params.lanes_per_node)              */
 } scp_tune_entry;
 
 /* Largest arena any candidate of scp_autotune needs (pure host computation); 0 if the
  * description is invalid. */
 size_t scp_autotune_device_bytes(const scp_problem_desc* desc);
 
-/* Time every candidate (block in {64, 128, 256} (FP64: {64, 128}), pack in {aligned, dense},
- * check_every in cadences[0..n_cad-1]) on the description's own problem: each candidate
+/* Time every candidate (lanes per node 1: block in {64, 128, 256} (FP64: {64, 128}), pack in
+ * {aligned, dense}; lanes per node 4: its one workgroup size; each with check_every in
+ * cadences[0..n_cad-1]; a lane-group candidate is valid only for check_every = 0 and batches it
+ * holds) on the description's own problem: each candidate
  * builds the problem in arena_dev, runs one untimed fresh solve with prm (form forced to
  * persistent) and then `reps` timed fresh solves (HIP events on hip_stream).  Writes up to
  * table_cap entries to table (n_out = number of candidates) and the fastest valid one to

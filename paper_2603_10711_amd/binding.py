@@ -61,15 +61,16 @@ class ScpParams(ctypes.Structure):
     _fields_ = [("scp_iters", c_int32), ("admm", AdmmParams), ("eta0", c_double), ("eta1", c_double),
                 ("eta2", c_double), ("shrink", c_double), ("grow", c_double), ("delta_max", c_double),
                 ("merit_w", c_double), ("form", c_int32), ("scp_per_launch", c_int32), ("rho_final", c_double),
-                ("graph", c_int32), ("adapt_mu", c_double), ("adapt_tau", c_double), ("group_wait_ms", c_double)]
+                ("graph", c_int32), ("adapt_mu", c_double), ("adapt_tau", c_double), ("group_wait_ms", c_double),
+                ("lanes_per_node", c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("block", c_int32), ("pack", c_int32), ("check_every", c_int32), ("valid", c_int32),
-                ("ms", c_double)]
+                ("ms", c_double), ("lanes", c_int32)]
 
     def as_dict(self) -> dict:
-        return dict(block=self.block, pack="dense" if self.pack == PACK_DENSE else "aligned",
+        return dict(lanes_per_node=self.lanes, block=self.block, pack="dense" if self.pack == PACK_DENSE else "aligned",
                     check_every=self.check_every, valid=bool(self.valid), ms=self.ms)
 
 
@@ -210,11 +211,11 @@ def admm_params(rho=1.0, iters=100, check_every=0, eps=0.0, rho_dyn=None, rho_ge
 def scp_params(scp_iters=10, admm_iters=100, rho=1.0, check_every=0, eps=0.0, form="persistent",
                scp_per_launch=0, eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
                merit_w=1.0e3, rho_dyn=None, rho_geo=None, graph=False, rho_final=0.0, adapt_mu=0.0,
-               adapt_tau=2.0, group_wait_ms=0.0) -> ScpParams:
+               adapt_tau=2.0, group_wait_ms=0.0, lanes_per_node=0) -> ScpParams:
     f = FORM_PERSISTENT if form == "persistent" else FORM_PLAIN
     return ScpParams(scp_iters, admm_params(rho, admm_iters, check_every, eps, rho_dyn, rho_geo), eta0, eta1, eta2,
                      shrink, grow, delta_max, merit_w, f, scp_per_launch, rho_final, 1 if graph else 0, adapt_mu,
-                     adapt_tau, group_wait_ms)
+                     adapt_tau, group_wait_ms, lanes_per_node)
 
 
 def _pad(a, w):

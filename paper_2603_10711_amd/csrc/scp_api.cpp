@@ -269,7 +269,9 @@ bool build_layout(const scp_problem_desc* d, Layout& L, std::string& err) {
     int max_nodes = 0;
     for (int q = 0; q < L.n_traj; ++q) max_nodes = std::max(max_nodes, horizon[q] + 1);
     L.resident_ok = (L.models == 4 || L.models == 8) && L.n_groups == 0 && max_nodes <= RESIDENT_MAX_NODES;
-    L.resident_block = L.resident_ok ? (4 * max_nodes + 63) / 64 * 64 : 0;
+    // the point-mass models in lane groups of four: the same resident ADMM
+    L.lanes4_ok = (L.models & ~3) == 0 && L.n_groups == 0 && max_nodes <= RESIDENT_MAX_NODES;
+    L.resident_block = (L.resident_ok || L.lanes4_ok) ? (4 * max_nodes + 63) / 64 * 64 : 0;
     // arena
     size_t o = 0;
     L.o_traj = o; o = align_up(o + L.traj.size() * 4);
@@ -419,7 +421,8 @@ bool same_params(const scp_params& a, const scp_params& b) {
            a.eta1 == b.eta1 && a.eta2 == b.eta2 && a.shrink == b.shrink && a.grow == b.grow &&
            std::memcmp(&a.delta_max, &b.delta_max, sizeof(double)) == 0 && a.merit_w == b.merit_w &&
            a.form == b.form && a.scp_per_launch == b.scp_per_launch && a.rho_final == b.rho_final &&
-           a.adapt_mu == b.adapt_mu && a.adapt_tau == b.adapt_tau && a.group_wait_ms == b.group_wait_ms;
+           a.adapt_mu == b.adapt_mu && a.adapt_tau == b.adapt_tau && a.group_wait_ms == b.group_wait_ms &&
+           a.lanes_per_node == b.lanes_per_node;
 }
 
 template <class T>
@@ -470,7 +473,9 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
     kp.has_groups = L.n_groups > 0 ? 1 : 0;
     hipError_t e = launch_plain<T>(PlainOp::Reset, dv, kp, L.models, L.kmax, 1, 0, p->stream);
     if (e != hipSuccess) return hip_check(p, e, "reset launch");
-    const bool resident = s->form == SCP_FORM_PERSISTENT && !L.persistent_ok && L.resident_ok;
+    // lane groups of four: the 6-DOF models always, the point-mass models when asked for
+    const bool resident = s->form == SCP_FORM_PERSISTENT &&
+                          ((!L.persistent_ok && L.resident_ok) || (s->lanes_per_node == 4 && L.lanes4_ok));
     if (s->form == SCP_FORM_PLAIN || resident) {
         double f = 1.0;
         for (int k = 0; k < s->scp_iters; ++k, f *= kp.sched_q) {
@@ -547,10 +552,10 @@ std::string tune_key(const scp_problem_desc* d, const scp_params* q, const std::
              std::to_string(same) + ";";
     }
     char buf[512];
-    std::snprintf(buf, sizeof buf, "|%d|%.17g,%.17g,%.17g,%d,%.17g,%.17g|%.17g,%.17g,%.17g,%.17g,%.17g,%.17g,%.17g|%d|%.17g|",
+    std::snprintf(buf, sizeof buf, "|%d|%.17g,%.17g,%.17g,%d,%.17g,%.17g|%.17g,%.17g,%.17g,%.17g,%.17g,%.17g,%.17g|%d|%.17g|%.17g,%.17g|",
                   q->scp_iters, q->admm.rho_eq, q->admm.rho_dyn, q->admm.rho_geo, q->admm.max_iters,
                   q->admm.eps_prim, q->admm.eps_dual, q->eta0, q->eta1, q->eta2, q->shrink, q->grow, q->delta_max,
-                  q->merit_w, q->scp_per_launch, q->rho_final);
+                  q->merit_w, q->scp_per_launch, q->rho_final, q->adapt_mu, q->adapt_tau);
     k += buf;
     for (int c : cads) k += std::to_string(c) + ",";
     return k;
@@ -678,7 +683,20 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm) {
                                              "without consensus groups");
     if (prm->form == SCP_FORM_PERSISTENT && !p->L.persistent_ok && !p->L.resident_ok)
         return fail(p, SCP_ERR_UNSUPPORTED, kNoPersistent);
-    if (prm->form == SCP_FORM_PERSISTENT && p->L.persistent_ok && p->L.n_gslots > 0 && p->L.n_wg > p->span_cap)
+    if (prm->lanes_per_node != 0 && prm->lanes_per_node != 1 && prm->lanes_per_node != 4)
+        return fail(p, SCP_ERR_ARG, "lanes_per_node must be 0, 1 or 4");
+    if (prm->form == SCP_FORM_PERSISTENT && prm->lanes_per_node == 1 && !p->L.persistent_ok)
+        return fail(p, SCP_ERR_UNSUPPORTED, "one lane per node: the fused persistent kernel does not hold this batch "
+                                             "(6-DOF models, or trajectories / groups too long)");
+    if (prm->form == SCP_FORM_PERSISTENT && prm->lanes_per_node == 4 && !p->L.resident_ok) {
+        if (!p->L.lanes4_ok)
+            return fail(p, SCP_ERR_UNSUPPORTED, "lane groups of four need trajectories of at most 64 nodes and no "
+                                                 "consensus groups");
+        if (prm->admm.check_every > 0)
+            return fail(p, SCP_ERR_UNSUPPORTED, "lane groups of four run fixed ADMM budgets (check_every = 0)");
+    }
+    if (prm->form == SCP_FORM_PERSISTENT && prm->lanes_per_node != 4 && p->L.persistent_ok && p->L.n_gslots > 0 &&
+        p->L.n_wg > p->span_cap)
         return fail(p, SCP_ERR_UNSUPPORTED, "consensus groups spanning several workgroups need every workgroup of "
                                              "the launch resident at once: the batch has " + std::to_string(p->L.n_wg) +
                                              " workgroups, the device keeps " + std::to_string(p->span_cap) +
@@ -881,6 +899,30 @@ scp_status scp_autotune(const scp_problem_desc* desc, const scp_params* prm, con
     int count = 0;
     bool found = false;
     scp_tune_entry b{};
+    // one candidate: `reps` timed fresh solves after an untimed one
+    auto time_one = [&](scp_problem* p, const scp_params& q, scp_tune_entry& en) {
+        st = scp_reset(p);
+        if (st == SCP_OK) st = scp_solve(p, &q);
+        if (st == SCP_OK) e = hipEventRecord(ev0, stream);
+        for (int r = 0; r < reps && st == SCP_OK && e == hipSuccess; ++r) {
+            st = scp_reset(p);
+            if (st == SCP_OK) st = scp_solve(p, &q);
+        }
+        if (st == SCP_OK && e == hipSuccess) e = hipEventRecord(ev1, stream);
+        if (st == SCP_OK && e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0.f;
+        if (st == SCP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (st != SCP_OK) g_create_error = p->err;
+        if (st != SCP_OK || e != hipSuccess) return false;
+        en.valid = 1;
+        en.ms = (double)ms / reps;
+        if (!found || en.ms < b.ms) {
+            b = en;
+            found = true;
+        }
+        return true;
+    };
+    // one lane per node: workgroup size x packing x cadence
     for (int blk : {64, 128, 256}) {
         for (int pk : {SCP_PACK_ALIGNED, SCP_PACK_DENSE}) {
             if (e != hipSuccess || st != SCP_OK) break;
@@ -900,37 +942,42 @@ scp_status scp_autotune(const scp_problem_desc* desc, const scp_params* prm, con
                 }
             }
             for (int c : cads) {
-                scp_tune_entry en{blk, pk, c, 0, 0.0};
+                scp_tune_entry en{blk, pk, c, 0, 0.0, 1};
                 if (p) {
                     scp_params q = *prm;
                     q.form = SCP_FORM_PERSISTENT;
                     q.graph = 0;
+                    q.lanes_per_node = 1;
                     q.admm.check_every = c;
-                    st = scp_reset(p);
-                    if (st == SCP_OK) st = scp_solve(p, &q);
-                    if (st == SCP_OK) e = hipEventRecord(ev0, stream);
-                    for (int r = 0; r < reps && st == SCP_OK && e == hipSuccess; ++r) {
-                        st = scp_reset(p);
-                        if (st == SCP_OK) st = scp_solve(p, &q);
-                    }
-                    if (st == SCP_OK && e == hipSuccess) e = hipEventRecord(ev1, stream);
-                    if (st == SCP_OK && e == hipSuccess) e = hipEventSynchronize(ev1);
-                    float ms = 0.f;
-                    if (st == SCP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-                    if (st != SCP_OK) g_create_error = p->err;
-                    if (st != SCP_OK || e != hipSuccess) break;
-                    en.valid = 1;
-                    en.ms = (double)ms / reps;
-                    if (!found || en.ms < b.ms) {
-                        b = en;
-                        found = true;
-                    }
+                    if (!time_one(p, q, en)) break;
                 }
                 if (table && count < table_cap) table[count] = en;
                 ++count;
             }
             scp_problem_destroy(p);
         }
+    }
+    // lane groups of four (one workgroup per trajectory): fixed ADMM budgets only
+    if (e == hipSuccess && st == SCP_OK) {
+        Layout L;
+        const bool ok = build_layout(desc, L, err) && L.lanes4_ok && L.total <= arena_bytes;
+        scp_problem* p = nullptr;
+        if (ok) st = scp_problem_create(desc, arena_dev, arena_bytes, hip_stream, &p);
+        for (int c : cads) {
+            if (st != SCP_OK || e != hipSuccess) break;
+            scp_tune_entry en{ok ? L.resident_block : 0, SCP_PACK_ALIGNED, c, 0, 0.0, 4};
+            if (p && c == 0) {
+                scp_params q = *prm;
+                q.form = SCP_FORM_PERSISTENT;
+                q.graph = 0;
+                q.lanes_per_node = 4;
+                q.admm.check_every = 0;
+                if (!time_one(p, q, en)) break;
+            }
+            if (table && count < table_cap) table[count] = en;
+            ++count;
+        }
+        scp_problem_destroy(p);
     }
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);

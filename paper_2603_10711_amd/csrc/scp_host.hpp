@@ -22,6 +22,9 @@ struct Layout {
     // lanes (four per node)
     bool resident_ok = false;
     int resident_block = 0;
+    // point-mass quadrotor / powered descent batches in lane groups of four (lanes_per_node = 4):
+    // at most RESIDENT_MAX_NODES nodes per trajectory, no consensus groups; resident_block lanes
+    bool lanes4_ok = false;
     int n_groups = 0;
     size_t esz = 4;
     // byte offsets inside the arena

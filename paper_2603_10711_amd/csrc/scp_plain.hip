@@ -459,11 +459,13 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = LY::NS, MAXN = RESIDENT_MAX_NODES;
     constexpr int KM = M::KM, KA = KM > 0 ? KM : 1;
     constexpr bool LD = M::ID == SCP_MODEL_LANDER6;
-    static_assert(M::QL || LD, "6-DOF models");
+    constexpr bool QP = M::ID == SCP_MODEL_QUAD_PM;      // point-mass quadrotor: control ball
+    constexpr bool MS = M::ID == SCP_MODEL_MARS3DOF;     // powered descent: glide cone, SOC
     __shared__ T sz[MAXN][16], smu[MAXN][16], sdd[MAXN][16];
     const int tr = blockIdx.x;
     if (tr >= dv.n_traj || dv.flags[tr * FL_FIELDS + FL_DONE]) return;   // uniform over the workgroup
     const int* rec = dv.traj + tr * TR_FIELDS;
+    if (rec[TR_MODEL] != M::ID) return;   // a mixed batch launches one kernel per model
     const int N = rec[TR_N], off = rec[TR_OFF];
     const int t = threadIdx.x, i = t >> 2, l = t & 3;
     const bool live = i <= N;
@@ -472,7 +474,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     id.i = live ? i : 0;
     id.N = N;
     id.K = rec[TR_K];
-    id.ball = false;
+    id.ball = QP && rec[TR_BALL] != 0;
     const bool first = id.first(), last = id.last();
     const int P = dv.P;
     // penalties of this trajectory: the same in every lane of the workgroup
@@ -531,18 +533,31 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             else Lr[s][j] = T(0);
         }
     }
-    // quadrotor: half-space j: a_l (l < 3) or b (l = 3); copy and dual of position component l
+    // quadrotors: half-space j: a_l (l < 3) or b (l = 3); copy and dual of position component l
     T own[KA], cph[KA], duh[KA];
 #pragma unroll
     for (int j = 0; j < KA; ++j) own[j] = cph[j] = duh[j] = T(0);
-    // lander: the one further group of each owned state component (glide cone on r, tilt on
-    // q_y, q_z, rate ball on w), the three thrust groups of the owned control component, and the
-    // thrust half-space's normal and offset (a_l, or b in lane 3)
+    // the one further group of each owned state component (lander: glide cone on r, tilt on
+    // q_y, q_z, rate ball on w; powered descent: glide cone on r), the further groups of the owned
+    // control component (lander: thrust ball, lower bound, gimbal cone; point-mass quadrotor: the
+    // control ball; powered descent: the SOC), and the lander's thrust half-space (a_l, or b in
+    // lane 3)
+    constexpr int NUG = LD ? 3 : (QP || MS) ? 1 : 0;
     T cpe[4], due[4], cu3[3], du3[3], own_h = T(0);
-    // mirror slot of the further group of state component k (lander), -1 if none
+    // mirror slot of the further group of state component k, -1 if none
     auto xslot_of = [](int k) -> int {
-        return k < 3 ? Lander6::C_GLIDE + (k + 2) % 3 : (k == 8 || k == 9) ? Lander6::C_TILT + (k - 8)
-             : (k >= 10 && k < 13) ? Lander6::C_RATE + (k - 10) : -1;
+        if constexpr (LD)
+            return k < 3 ? Lander6::C_GLIDE + (k + 2) % 3 : (k == 8 || k == 9) ? Lander6::C_TILT + (k - 8)
+                 : (k >= 10 && k < 13) ? Lander6::C_RATE + (k - 10) : -1;
+        if constexpr (MS) return k < 3 ? Mars::C_CONE + k : -1;
+        return -1;
+    };
+    // mirror slots of the further groups of control component c
+    auto uslot_of = [](int c, int j) -> int {
+        if constexpr (LD) return j == 0 ? Lander6::C_TBALL + c : j == 1 ? Lander6::C_THS + c : Lander6::C_GIMB + (c + 2) % 3;
+        if constexpr (QP) return M::C_BALL + c;
+        if constexpr (MS) return Mars::C_SOC + c;
+        return -1;
     };
 #pragma unroll
     for (int s = 0; s < 4; ++s) cpe[s] = due[s] = T(0);
@@ -564,15 +579,14 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                 due[s] = at(PL_DU + xs);
             }
         }
-        if (has_u) {
-            const int us[3] = {M::C_TBALL + cu, M::C_THS + cu, M::C_GIMB + (cu + 2) % 3};
+        if constexpr (LD) own_h = at(PL_HS + l);
+    }
+    if (has_u) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                cu3[j] = at(PL_CP + us[j]);
-                du3[j] = at(PL_DU + us[j]);
-            }
+        for (int j = 0; j < NUG; ++j) {
+            cu3[j] = at(PL_CP + uslot_of(cu, j));
+            du3[j] = at(PL_DU + uslot_of(cu, j));
         }
-        own_h = at(PL_HS + l);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -642,6 +656,10 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                     const T ru = group_rho<M>(id, rho_geo, 5);
 #pragma unroll
                     for (int j = 0; j < 3; ++j) v = v + (ru * cu3[j] - du3[j]);
+                } else if constexpr (QP) {
+                    v = v + (group_rho<M>(id, rho_geo, 2) * cu3[0] - du3[0]);   // control ball
+                } else if constexpr (MS) {
+                    v = v + (rho_geo * cu3[0] - du3[0]);                         // SOC
                 }
             }
             acc[s] = v;
@@ -773,6 +791,60 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                 }
             }
         }
+        if constexpr (QP) {
+            // control ball on the components held by lanes 0..2 (slot 4); absent where the
+            // trajectory has none and at node N, where its copy and dual stay 0
+            const bool bact = !last && id.ball;
+            const T vb = has_u ? uval + du3[0] * inv_geo : T(0);
+            T v[3] = {quad_bcast(vb, 0), quad_bcast(vb, 1), quad_bcast(vb, 2)};
+            proj_ball3(prm[SCP_P_UBALL], v);
+            if (has_u) {
+                const T cp = cu == 0 ? v[0] : cu == 1 ? v[1] : v[2];
+                const T cpo = cu3[0];
+                du3[0] = bact ? du3[0] + rho_geo * (uval - cp) : T(0);
+                cu3[0] = bact ? cp : T(0);
+                if (chk && bact) {
+                    spu = spu + rho_geo * (cu3[0] - cpo);
+                    pm = nmax(pm, tabs(uval - cp));
+                }
+            }
+        }
+        } else if constexpr (MS) {
+            // powered descent: glide cone on r (components 0..2, lanes 0..2 of slot 0) at nodes
+            // 1..N, SOC on (T, Gamma) (the four controls, slot 4) at nodes 0..N-1; where a group
+            // does not exist its copy and dual stay 0
+            const bool xact = !first, uact = !last;
+            {
+                const T kg = prm[SCP_P_GLIDE];
+                const T vv = l < 3 ? xl[0] + due[0] * inv_geo : T(0);
+                T v[3] = {quad_bcast(vv, 0), quad_bcast(vv, 1), quad_bcast(vv, 2)};
+                proj_cone<3>(kg, T(1) / (T(1) + kg * kg), v);
+                if (l < 3) {
+                    const T cp = l == 0 ? v[0] : l == 1 ? v[1] : v[2];
+                    const T cpo = cpe[0];
+                    due[0] = xact ? due[0] + rho_geo * (xl[0] - cp) : T(0);
+                    cpe[0] = xact ? cp : T(0);
+                    if (chk && xact) {
+                        spv[0] = spv[0] + rho_geo * (cpe[0] - cpo);
+                        pm = nmax(pm, tabs(xl[0] - cp));
+                    }
+                }
+            }
+            {
+                const T vs = has_u ? uval + du3[0] * inv_geo : T(0);
+                T v[4] = {quad_bcast(vs, 0), quad_bcast(vs, 1), quad_bcast(vs, 2), quad_bcast(vs, 3)};
+                proj_cone<4>(T(1), T(0.5), v);
+                if (has_u) {
+                    const T cp = cu == 0 ? v[0] : cu == 1 ? v[1] : cu == 2 ? v[2] : v[3];
+                    const T cpo = cu3[0];
+                    du3[0] = uact ? du3[0] + rho_geo * (uval - cp) : T(0);
+                    cu3[0] = uact ? cp : T(0);
+                    if (chk && uact) {
+                        spu = spu + rho_geo * (cu3[0] - cpo);
+                        pm = nmax(pm, tabs(uval - cp));
+                    }
+                }
+            }
         } else {
             // lander: the sets coupling components; a group exists at nodes 1..N (state) or
             // 0..N-1 (thrust), and where it does not its copy and dual stay 0
@@ -901,13 +973,12 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
                 put(PL_DU + xs, due[s]);
             }
         }
-        if (has_u) {
-            const int us[3] = {M::C_TBALL + cu, M::C_THS + cu, M::C_GIMB + (cu + 2) % 3};
+    }
+    if (has_u) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                put(PL_CP + us[j], cu3[j]);
-                put(PL_DU + us[j], du3[j]);
-            }
+        for (int j = 0; j < NUG; ++j) {
+            put(PL_CP + uslot_of(cu, j), cu3[j]);
+            put(PL_DU + uslot_of(cu, j), du3[j]);
         }
     }
 }
@@ -1446,6 +1517,14 @@ hipError_t launch_resident(const Dev<T>& dv, const KParams<T>& kp, int n_traj, i
         else hipLaunchKernelGGL((k_admm_resident<Quad6<8>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
     } else if (models == 8) {
         hipLaunchKernelGGL((k_admm_resident<Lander6, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+    } else if (models >= 1 && models <= 3) {
+        // point-mass quadrotor and powered descent in lane groups of four: one launch per model
+        // present, each workgroup of the other model returns at once
+        if (models & 1) {
+            if (kmax <= 4) hipLaunchKernelGGL((k_admm_resident<Quad<4>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+            else hipLaunchKernelGGL((k_admm_resident<Quad<8>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        }
+        if (models & 2) hipLaunchKernelGGL((k_admm_resident<Mars, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
     } else {
         return hipErrorInvalidValue;   // one 6-DOF model per batch
     }

@@ -136,8 +136,13 @@ def test_autotune_small_mix(B):
     prm = B.scp_params(2, 40, check_every=5, eps=1e-4)
     best, table = B.autotune(insts, prm, cadences=(1, 5), reps=1)
     _say(best, table)
-    assert len(table) == 5 * 2
-    assert not any(e["valid"] for e in table if e["block"] == 64)     # 121 nodes need 128 lanes
+    assert len(table) == 6 * 2
+    one = [e for e in table if e["lanes_per_node"] == 1]
+    assert len(one) == 5 * 2
+    assert not any(e["valid"] for e in one if e["block"] == 64)       # 121 nodes need 128 lanes
+    # lane groups of four: trajectories over 64 nodes and a residual-test cadence rule them out
+    four = [e for e in table if e["lanes_per_node"] == 4]
+    assert len(four) == 2 and not any(e["valid"] for e in four)
     valid = [e for e in table if e["valid"]]
     assert len(valid) == 8 and best["valid"]
     assert best["ms"] == min(e["ms"] for e in valid)
