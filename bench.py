@@ -586,21 +586,31 @@ def batch_main(a, wl, cpu):
     n = len(insts)
     eps = wl.get("eps", 0.0)
     check = 0
-    block, pack = a.block, B.PACK_ALIGNED
+    block, pack, lanes = a.block, B.PACK_ALIGNED, 1
     tune = None
-    if "cadences" in wl:
-        prm0 = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], eps=eps, form="persistent")
+    if a.tune and ("cadences" in wl or wl["name"] == "quad1024"):
+        # the library's autotuner: lanes per node x workgroup size x packing x residual cadence
+        prm0 = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], rho_final=wl.get("rho_final", 0.0), eps=eps,
+                            form="persistent")
         t_tune = time.perf_counter()
-        best, table = B.autotune(insts, prm0, cadences=wl["cadences"], reps=2, precision=wl["prec"], device="cuda:0")
+        best, table = B.autotune(insts, prm0, cadences=wl.get("cadences", (0,)), reps=2, precision=wl["prec"],
+                                 device="cuda:0")
         tune = {"best": best, "table": table, "seconds": round(time.perf_counter() - t_tune, 2)}
+        print(f"[bench] autotune {tune}", file=sys.stderr, flush=True)
         check = best["check_every"]
+        lanes = best["lanes_per_node"]
         if not a.block:
             block, pack = best["block"], B.PACK_DENSE if best["pack"] == "dense" else B.PACK_ALIGNED
+    elif "cadences" in wl:
+        check = 25
+    if lanes == 4:
+        block = 0
     prm = B.scp_params(wl["scp"], wl["admm"], rho=wl["rho"], rho_final=wl.get("rho_final", 0.0), check_every=check,
-                       eps=eps, form="persistent")
+                       eps=eps, form="persistent", lanes_per_node=lanes)
     head = batch_leg(B, insts, wl["prec"], prm, a.steps, a.warmup, block, pack)
     khash = kernel_source_hash()
-    summ = leg_summary(head, wl["prec"], traffic=load_pmc(wl["name"], khash))
+    kname = "k_persistent" if lanes == 1 else "k_admm_resident (with k_lin, k_resid, k_acc_* per SCP iteration)"
+    summ = leg_summary(head, wl["prec"], kernel=kname, traffic=load_pmc(wl["name"], khash) if lanes == 1 else None)
     print(f"[bench] headline {summ}", file=sys.stderr, flush=True)
 
     # the workload's fixed budget (rho = 1), as the configuration states it
@@ -676,7 +686,7 @@ def batch_main(a, wl, cpu):
                    "nodes": int(sum(d["N"] + 1 for d in insts)), "scp_iters": wl["scp"], "admm_iters": wl["admm"],
                    "rho": wl["rho"], "rho_final": wl.get("rho_final", 0.0),
                    "block": block or "auto", "pack": "dense" if pack == B.PACK_DENSE else "aligned",
-                   "check_every": check},
+                   "check_every": check, "lanes_per_node": lanes},
         "value_definition": "solves per second whose returned nominal has max dynamics defect <= 1e-5",
         "all_solves_per_s": summ["solves_per_s"],
         "defect_le_1e-5": summ["defect_le_1e-5"],
@@ -716,6 +726,9 @@ def main(argv=None):
     ap.add_argument("--capacity-requests", type=int, default=2000)
     ap.add_argument("--sched-steps", type=int, default=5, help="steps of the fixed-budget and schedule legs")
     ap.add_argument("--other-steps", type=int, default=5, help="steps of the mars4096 and mix2048 legs (0: none)")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the autotuner (profiled runs: one lane per node, default workgroup, cadence 25 for "
+                         "the mix)")
     ap.add_argument("--scp-iters", type=int, default=0, help="override the workload's SCP budget (profiling runs)")
     ap.add_argument("--admm-iters", type=int, default=0, help="override the workload's ADMM budget (profiling runs)")
     a = ap.parse_args(argv)

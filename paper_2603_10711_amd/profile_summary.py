@@ -6,11 +6,14 @@
     python -m paper_2603_10711_amd.profile_summary pmcplain <fetch dir> <write dir> <copy fetch dir> <copy write dir> \
         <workload> <scp iters> <admm iters> <out.json> --cmd "<command>"
     python -m paper_2603_10711_amd.profile_summary sq <counter dir> <title> <admm iterations per dispatch> <out.md> \
-        --cmd "<command>" [--kernel <kernel name prefix, default k_persistent>]
+        --cmd "<command>" [--kernel <kernel name prefix, default k_persistent>] [--extra <counter dir> ...]
+    python -m paper_2603_10711_amd.profile_summary calibrate
 
-``pmc`` scales FETCH_SIZE / WRITE_SIZE of k_persistent by what the same counters read for a
-1 GiB device copy (copy_probe.py) and records the hash of the kernel sources the counters were
-taken with; bench.py reports the traffic only while that hash still matches.
+``calibrate`` is a plain 1 GiB device-to-device copy (run under rocprofv3 --pmc FETCH_SIZE, then
+WRITE_SIZE): a kernel whose HBM traffic is known exactly.  ``pmc`` scales FETCH_SIZE / WRITE_SIZE of
+k_persistent by what the same counters read for that copy and records the hash of the kernel
+sources the counters were taken with; bench.py reports the traffic only while that hash still
+matches.
 """
 from __future__ import annotations
 
@@ -119,18 +122,30 @@ def pmc_plain(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, sc
     json.dump(d, open(out, "w"), indent=1)
 
 
-def sq(dirpath: str, title: str, iters: int, out: str, cmd: str, kernel: str = "k_persistent") -> None:
-    """SQ counters of one kernel per dispatch and per wave, and the VALU issue share."""
+def _sq_values(dirpath: str, kernel: str) -> dict:
+    """Counter value per dispatch (mean over dispatches) of the kernels whose name starts with
+    ``void scp::<kernel>``."""
     path = glob.glob(os.path.join(dirpath, "*counter_collection.csv"))[0]
     per = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in csv.DictReader(open(path)):
         if r["Kernel_Name"].startswith("void scp::" + kernel):
             per[r["Counter_Name"]][r["Dispatch_Id"]].append(float(r["Counter_Value"]))
-    val = {c: sum(sum(v) for v in d.values()) / len(d) for c, d in per.items()}
+    return {c: sum(sum(v) for v in d.values()) / len(d) for c, d in per.items()}
+
+
+def sq(dirpath: str, title: str, iters: int, out: str, cmd: str, kernel: str = "k_persistent", extra=()) -> None:
+    """SQ counters of one kernel per dispatch and per wave, the VALU issue share, and (from further
+    counter passes) the LDS bank-conflict share and the FMA count."""
+    val = _sq_values(dirpath, kernel)
+    for d in extra:
+        for c, v in _sq_values(d, kernel).items():
+            val.setdefault(c, v)
     waves = val["SQ_WAVES"]
     lines = [f"# rocprofv3 SQ counters of {kernel}, {title}", "", f"Command: `{cmd}`", "",
              f"Kernel sources hash: `{kernel_source_hash()}`", "", "| counter | per dispatch | per wave |", "|---|---|---|"]
-    for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"):
+    for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_SALU",
+              "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_LDS_IDX_ACTIVE",
+              "SQ_LDS_BANK_CONFLICT"):
         if c in val:
             lines.append(f"| {c} | {val[c]:.4g} | {val[c] / waves:.4g} |")
     valu = val["SQ_INSTS_VALU"] / waves
@@ -139,7 +154,25 @@ def sq(dirpath: str, title: str, iters: int, out: str, cmd: str, kernel: str = "
                   f"the ADMM loop amortized): {valu / iters:.0f}.",
               "SQ_WAVE_CYCLES counts quad-cycles; one wave64 FP32 VALU instruction occupies its SIMD for one "
               f"quad-cycle, so the VALU issue share of the wave's life is {share:.3f}."]
+    for fma in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_FMA_F64"):
+        if fma in val:
+            lines.append(f"{fma} per wave per ADMM iteration: {val[fma] / waves / iters:.0f} "
+                         f"({val[fma] / val['SQ_INSTS_VALU']:.3f} of the VALU instructions).")
+    if "SQ_LDS_BANK_CONFLICT" in val and val.get("SQ_LDS_IDX_ACTIVE", 0) > 0:
+        lines.append(f"LDS bank conflicts: {val['SQ_LDS_BANK_CONFLICT'] / val['SQ_LDS_IDX_ACTIVE']:.4f} of the "
+                     "LDS indexed-active cycles (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE).")
     open(out, "w").write("\n".join(lines) + "\n")
+
+
+def calibrate(n_bytes: int = 1 << 30) -> None:
+    """A plain device-to-device copy of n_bytes (the counters' calibration kernel)."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {n_bytes} bytes", flush=True)
 
 
 def main(argv=None):
@@ -165,13 +198,17 @@ def main(argv=None):
         q.add_argument(k)
     q.add_argument("--cmd", required=True)
     q.add_argument("--kernel", default="k_persistent")
+    q.add_argument("--extra", nargs="*", default=[])
+    sub.add_parser("calibrate")
     a = ap.parse_args(argv)
+    if a.mode == "calibrate":
+        return calibrate()
     if a.mode == "stats":
         stats(a.csv, a.out, a.cmd)
     elif a.mode == "pmcplain":
         pmc_plain(a.fetch, a.write, a.copy_fetch, a.copy_write, a.workload, a.scp_iters, a.admm_iters, a.out, a.cmd)
     elif a.mode == "sq":
-        sq(a.dir, a.title, int(a.iters), a.out, a.cmd, a.kernel)
+        sq(a.dir, a.title, int(a.iters), a.out, a.cmd, a.kernel, a.extra)
     else:
         pmc(a.fetch, a.write, a.copy_fetch, a.copy_write, a.workload, a.out, a.cmd)
 
