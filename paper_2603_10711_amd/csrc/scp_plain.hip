@@ -461,7 +461,12 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     constexpr bool LD = M::ID == SCP_MODEL_LANDER6;
     constexpr bool QP = M::ID == SCP_MODEL_QUAD_PM;      // point-mass quadrotor: control ball
     constexpr bool MS = M::ID == SCP_MODEL_MARS3DOF;     // powered descent: glide cone, SOC
-    __shared__ T sz[MAXN][16], smu[MAXN][16], sdd[MAXN][16];
+    // Neighbour rows, one per node.  A wavefront holds 16 nodes (four lanes each) and reads one
+    // component slot of every node at once, i.e. 16 rows x 4 consecutive values; a row stride of
+    // 20 values puts the 32 reads of each half-wavefront in 32 different LDS banks (a stride of 16
+    // folds them onto 8 banks, a four-way conflict).
+    constexpr int SR = 20;
+    __shared__ T sz[MAXN][SR], smu[MAXN][SR], sdd[MAXN][SR];
     const int tr = blockIdx.x;
     if (tr >= dv.n_traj || dv.flags[tr * FL_FIELDS + FL_DONE]) return;   // uniform over the workgroup
     const int* rec = dv.traj + tr * TR_FIELDS;
