@@ -48,6 +48,9 @@ typedef struct {
     int32_t scp_per_step;     /* SCP iterations per scheduling step; must divide
                                  solve.scp_iters (1 = admission at every SCP boundary)       */
     int32_t max_inflight;     /* scheduling steps enqueued ahead of the device, >= 1         */
+    double timeout_ms;        /* > 0: a request still queued, or still running, this long after
+                                 its submission ends without a result (SCP_REQ_TIMEOUT) at the
+                                 next scheduling step and frees its place; 0: no limit        */
 } scp_server_config;
 
 typedef struct scp_server scp_server;
@@ -56,7 +59,9 @@ typedef enum {
     SCP_REQ_UNKNOWN = 0,      /* no such id, or already collected                         */
     SCP_REQ_QUEUED = 1,       /* waiting for admission                                    */
     SCP_REQ_RUNNING = 2,      /* resident, SCP iterations in progress                     */
-    SCP_REQ_DONE = 3          /* finished; results ready for scp_server_collect            */
+    SCP_REQ_DONE = 3,         /* finished; results ready for scp_server_collect            */
+    SCP_REQ_CANCELLED = 4,    /* ended by scp_server_cancel, no result                     */
+    SCP_REQ_TIMEOUT = 5       /* ended by the configured timeout, no result                */
 } scp_req_state;
 
 typedef struct {
@@ -67,6 +72,12 @@ typedef struct {
     int64_t warm_starts;                      /* requests started from a session state  */
     size_t resident_bytes;                    /* summed footprint of resident requests  */
     size_t peak_resident_bytes;
+    int64_t cancelled, timed_out;             /* requests ended without a result        */
+    double latency_ms_p50, latency_ms_p99;    /* over every completed request: submission
+                                                 to the host observing its completion
+                                                 (nearest-rank quantiles; 0 if none)    */
+    double solves_per_s;                      /* completed requests per second from the
+                                                 first submission to the last completion */
 } scp_server_stats;
 
 /* Arena bytes the configuration needs (0 if invalid).  Pure host computation. */
@@ -113,10 +124,22 @@ scp_status scp_server_step(scp_server* s, int32_t wait, int32_t* pending);
 /* State of a request; for SCP_REQ_DONE also its latency (submission to the host observing its
  * completion, in ms) and its host results: info (n_traj * SCP_INFO_FIELDS doubles), x (rows
  * of SCP_MAX_NX, N+1 per trajectory) and u (rows of SCP_MAX_NU, N per trajectory), as doubles;
- * any pointer may be NULL.  `release` = 1 drops the result record afterwards (the warm state
- * stays resident for the session). */
+ * any pointer may be NULL.  For SCP_REQ_CANCELLED and SCP_REQ_TIMEOUT the latency is the time
+ * to its end and there are no results.  `release` = 1 drops the record afterwards (the warm
+ * state stays resident for the session); the id is then SCP_REQ_UNKNOWN. */
 scp_status scp_server_collect(scp_server* s, int64_t id, int32_t release, int32_t* state, double* latency_ms,
                               double* info, double* x, double* u);
+
+/* Cancel a queued or running request: a queued one ends at once, a running one at the next
+ * scheduling step (its place in the pool is freed; with a session, the session's warm state goes
+ * with it), one whose results are already being copied when they arrive (they are discarded).
+ * Its state becomes SCP_REQ_CANCELLED.  Errors: SCP_ERR_STATE (unknown id, or already ended). */
+scp_status scp_server_cancel(scp_server* s, int64_t id);
+
+/* Ids of requests that ended (done, cancelled, timed out) since the last call, oldest first, at
+ * most cap of them (the rest stay for the next call); *n = number written.  Lets a client
+ * collect only the requests that changed instead of polling every pending id. */
+scp_status scp_server_take_done(scp_server* s, int64_t* ids, int32_t cap, int32_t* n);
 
 scp_status scp_server_get_stats(const scp_server* s, scp_server_stats* out);
 

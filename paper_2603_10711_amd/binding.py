@@ -40,9 +40,9 @@ SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_create
            "scp_solve", "scp_reset", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
            "scp_traj_node_offset", "scp_plan", "scp_autotune_device_bytes", "scp_autotune", "scp_last_error"]
 SERVE_SYMBOLS = ["scp_server_device_bytes", "scp_server_create", "scp_server_destroy", "scp_server_request_bytes",
-                 "scp_server_submit", "scp_server_submit_ex", "scp_server_step", "scp_server_collect", "scp_server_get_stats",
-                 "scp_server_last_error"]
-REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2, 3
+                 "scp_server_submit", "scp_server_submit_ex", "scp_server_step", "scp_server_collect",
+                 "scp_server_cancel", "scp_server_take_done", "scp_server_get_stats", "scp_server_last_error"]
+REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_TIMEOUT = 0, 1, 2, 3, 4, 5
 NOALLOC_MAX_BYTES = 32 << 20   # SCP_NOALLOC_MAX_BYTES of scp.h
 
 
@@ -78,13 +78,15 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("prec", c_int32), ("block", c_int32), ("pack", c_int32), ("max_nodes", c_int64),
                 ("max_traj", c_int32), ("max_wg", c_int32), ("max_span", c_int32), ("max_requests", c_int32),
                 ("budget_bytes", c_size_t), ("solve", ScpParams), ("scp_per_step", c_int32),
-                ("max_inflight", c_int32)]
+                ("max_inflight", c_int32), ("timeout_ms", c_double)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_int64), ("completed", c_int64), ("rejected", c_int64), ("queued", c_int32),
                 ("running", c_int32), ("resident", c_int32), ("steps", c_int64), ("evictions", c_int64),
-                ("warm_starts", c_int64), ("resident_bytes", c_size_t), ("peak_resident_bytes", c_size_t)]
+                ("warm_starts", c_int64), ("resident_bytes", c_size_t), ("peak_resident_bytes", c_size_t),
+                ("cancelled", c_int64), ("timed_out", c_int64), ("latency_ms_p50", c_double),
+                ("latency_ms_p99", c_double), ("solves_per_s", c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -154,6 +156,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scp_server_collect.argtypes = [c_void_p, c_int64, c_int32, POINTER(c_int32), POINTER(c_double),
                                        POINTER(c_double), POINTER(c_double), POINTER(c_double)]
     lib.scp_server_collect.restype = c_int32
+    lib.scp_server_cancel.argtypes = [c_void_p, c_int64]
+    lib.scp_server_cancel.restype = c_int32
+    lib.scp_server_take_done.argtypes = [c_void_p, POINTER(c_int64), c_int32, POINTER(c_int32)]
+    lib.scp_server_take_done.restype = c_int32
     lib.scp_server_get_stats.argtypes = [c_void_p, POINTER(ServerStats)]
     lib.scp_server_get_stats.restype = c_int32
     lib.scp_server_last_error.argtypes = [c_void_p]
@@ -453,13 +459,13 @@ class Server:
     def __init__(self, prm: ScpParams, precision: str = "f32", block: int = 256, pack: int = PACK_ALIGNED,
                  max_nodes: int = 1 << 16, max_traj: int = 1024, max_wg: int = 1024, max_span: int = 256,
                  max_requests: int = 256, budget_bytes: int | None = None, scp_per_step: int = 1,
-                 max_inflight: int = 2, device: str = "cuda", stream=None):
+                 max_inflight: int = 2, device: str = "cuda", stream=None, timeout_ms: float = 0.0):
         import torch
         self.torch = torch
         self.lib = load()
         self.prec = F32 if precision == "f32" else F64
         cfg = ServerConfig(self.prec, block, pack, max_nodes, max_traj, max_wg, max_span, max_requests, 0, prm,
-                           scp_per_step, max_inflight)
+                           scp_per_step, max_inflight, timeout_ms)
         nbytes = self.lib.scp_server_device_bytes(byref(cfg))
         if nbytes == 0:
             h = c_void_p()
@@ -479,10 +485,25 @@ class Server:
             raise ScpError(f"scp_server_create failed ({st}): {self.lib.scp_server_last_error(None).decode()}")
         self.h = h
         self.shapes = {}
+        self._ended = set()     # ended requests reported by take_done that no drain asked for yet
 
     def _check(self, st, what):
         if st != SCP_OK:
             raise ScpError(f"{what} failed ({st}): {self.lib.scp_server_last_error(self.h).decode()}")
+
+    def take_done(self, cap: int = 4096) -> list[int]:
+        """Ids of the requests that ended (done, cancelled, timed out) since the last call."""
+        buf = (c_int64 * cap)()
+        n = c_int32(0)
+        out = []
+        while True:
+            self._check(self.lib.scp_server_take_done(self.h, buf, cap, byref(n)), "scp_server_take_done")
+            out.extend(buf[:n.value])
+            if n.value < cap:
+                return out
+
+    def cancel(self, rid: int):
+        self._check(self.lib.scp_server_cancel(self.h, rid), "scp_server_cancel")
 
     def request_bytes(self, insts: list[dict]) -> int:
         desc, keep = make_desc(insts, self.prec)
@@ -505,7 +526,8 @@ class Server:
         return rid.value
 
     def poll(self, rid: int, release: bool = True):
-        """None while queued or running, else (latency_ms, info array (n_traj, 12))."""
+        """None while queued or running, else (latency_ms, info array (n_traj, 12)); a request that
+        ended without a result (cancelled, timed out) gives (latency_ms, None)."""
         shape = self.shapes[rid]
         state = c_int32(0)
         lat = c_double(0.0)
@@ -513,6 +535,10 @@ class Server:
         self._check(self.lib.scp_server_collect(self.h, rid, 1 if release else 0, byref(state), byref(lat),
                                                 info.ctypes.data_as(POINTER(c_double)), None, None),
                     "scp_server_collect")
+        if state.value in (REQ_CANCELLED, REQ_TIMEOUT):
+            if release:
+                self.shapes.pop(rid, None)
+            return lat.value, None
         if state.value != REQ_DONE:
             if state.value == REQ_UNKNOWN:
                 raise ScpError(f"request {rid} unknown or already collected")
@@ -543,6 +569,11 @@ class Server:
         dp = lambda a: a.ctypes.data_as(POINTER(c_double))
         self._check(self.lib.scp_server_collect(self.h, rid, 1 if release else 0, byref(state), byref(lat), dp(info),
                                                 dp(x), dp(u)), "scp_server_collect")
+        if state.value in (REQ_CANCELLED, REQ_TIMEOUT):
+            if release:
+                self.shapes.pop(rid, None)
+            return dict(latency_ms=lat.value, state="cancelled" if state.value == REQ_CANCELLED else "timeout",
+                        info=None, x=None, u=None)
         if state.value != REQ_DONE:
             if state.value == REQ_UNKNOWN:
                 raise ScpError(f"request {rid} unknown or already collected")
@@ -556,7 +587,7 @@ class Server:
             xo += N + 1
             uo += N
         infos = [{k: float(info[t, v]) for k, v in INFO.items()} for t in range(nt)]
-        return dict(latency_ms=lat.value, info=infos, x=xs, u=us)
+        return dict(latency_ms=lat.value, state="done", info=infos, x=xs, u=us)
 
     def stats(self) -> dict:
         out = ServerStats()
@@ -564,23 +595,26 @@ class Server:
         return out.as_dict()
 
     def drain(self, ids, timeout_s: float = 60.0) -> dict:
-        """Step until every request in ids is done; returns {id: result}."""
+        """Step until every request in ids has ended; returns {id: result}.  Only the requests the
+        library reports as ended are collected (no polling of every pending id)."""
         import time
         out = {}
         t0 = time.perf_counter()
-        todo = list(ids)
+        todo = set(ids)
+        for rid in list(todo & self._ended):
+            out[rid] = self.collect(rid)
+            todo.discard(rid)
+            self._ended.discard(rid)
         while todo:
             self.step(wait=True)
-            rest = []
-            for rid in todo:
-                r = self.collect(rid)
-                if r is None:
-                    rest.append(rid)
+            for rid in self.take_done():
+                if rid in todo:
+                    out[rid] = self.collect(rid)
+                    todo.discard(rid)
                 else:
-                    out[rid] = r
-            todo = rest
-            if time.perf_counter() - t0 > timeout_s:
-                raise ScpError(f"requests not done after {timeout_s} s: {todo[:8]}")
+                    self._ended.add(rid)
+            if todo and time.perf_counter() - t0 > timeout_s:
+                raise ScpError(f"requests not done after {timeout_s} s: {sorted(todo)[:8]}")
         return out
 
     def close(self):

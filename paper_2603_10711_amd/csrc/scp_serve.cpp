@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -20,6 +21,7 @@
 #include "scp_host.hpp"
 #include "scp_launch.hpp"
 #include "scp_layout.hpp"
+#include "scp_sched.hpp"
 
 using namespace scp;
 
@@ -31,46 +33,6 @@ double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
-
-// First-fit allocator of [0, cap) ranges with coalescing on release.
-class RangeAlloc {
-  public:
-    explicit RangeAlloc(long long cap = 0) { reset(cap); }
-    void reset(long long cap) {
-        free_.clear();
-        if (cap > 0) free_[0] = cap;
-    }
-    long long alloc(long long n) {
-        if (n <= 0) return 0;
-        for (auto it = free_.begin(); it != free_.end(); ++it)
-            if (it->second >= n) {
-                const long long off = it->first, len = it->second;
-                free_.erase(it);
-                if (len > n) free_[off + n] = len - n;
-                return off;
-            }
-        return -1;
-    }
-    void release(long long off, long long n) {
-        if (n <= 0) return;
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<long long, long long> free_;
-};
 
 // Bytes of the pool one unit of each kind occupies (the footprint of a request).
 struct Unitsz {
@@ -116,6 +78,7 @@ bool valid_config(const scp_server_config* c, std::string& err) {
         return false;
     }
     if (c->max_inflight < 1 || c->max_inflight > 8) { err = "max_inflight must be in 1..8"; return false; }
+    if (!(c->timeout_ms >= 0.0) || !std::isfinite(c->timeout_ms)) { err = "timeout_ms must be finite and >= 0"; return false; }
     return true;
 }
 
@@ -150,33 +113,6 @@ ServerLayout server_layout(const scp_server_config* c) {
     return S;
 }
 
-enum class RState { Queued, Running, Done };
-
-struct Request {
-    int64_t id = 0;
-    int32_t session = -1;
-    // copy of the description
-    std::vector<int32_t> model, horizon, group;
-    std::vector<double> params, xg, ug;
-    scp_problem_desc desc{};
-    Layout L;           // request-local plan (offsets from 0)
-    size_t bytes = 0;   // footprint
-    // placement in the pool (valid while resident)
-    bool resident = false;
-    long long node_off = 0;
-    int traj_first = 0, wg_first = 0;
-    std::vector<int> gslots;
-    // progress
-    RState state = RState::Queued;
-    uint32_t flags = 0;  // SCP_SUBMIT_*
-    int scp_enq = 0;
-    bool warm = false;
-    double t_submit = 0, t_done = 0;
-    double last_use = 0;
-    // results (host, doubles)
-    std::vector<double> info, x, u;
-};
-
 struct StepRec {
     hipEvent_t ev = nullptr;
     int slot = 0;                     // pinned staging slot
@@ -193,25 +129,14 @@ struct scp_server {
     size_t esz = 4;
     hipStream_t stream = nullptr;
     char* arena = nullptr;
-    Dev<float> df;
-    Dev<double> dd;
-    RangeAlloc nodes, trajs, wgs;
-    std::vector<int> span_free;
-    int wg_cap_running = 0;       // workgroups one launch keeps resident at one wave per SIMD
-    // requests
-    int64_t next_id = 1;
-    std::unordered_map<int64_t, Request> reqs;
-    std::deque<int64_t> queue;
-    std::vector<int64_t> running;
-    std::unordered_map<int32_t, int64_t> session_last;   // session -> last admitted request
-    std::unordered_map<int32_t, int64_t> session_warm;   // session -> resident finished request
+    Scheduler sched;   // admission, placement, sessions, timeouts, statistics
     // pipeline
     std::vector<unsigned char*> pin_in, pin_out;          // pinned host staging, one per slot
     std::vector<bool> slot_busy;
     std::deque<StepRec> inflight;
-    scp_server_stats st{};
     std::string err;
 
+    explicit scp_server(const SchedLimits& lim) : sched(lim, now_ms) {}
     ~scp_server() {
         if (stream) (void)hipStreamSynchronize(stream);
         for (auto& r : inflight)
@@ -270,7 +195,7 @@ bool plan_request(const scp_server* s, const scp_problem_desc* d, Layout& L, std
                              : "request does not fit the server's workgroups (longest trajectory, or a group over 64 members)";
         return false;
     }
-    if (L.n_wg > s->wg_cap_running) {
+    if (L.n_wg > s->sched.lim.wg_cap_running) {
         err = "request needs more workgroups than one launch keeps resident";
         return false;
     }
@@ -280,80 +205,6 @@ bool plan_request(const scp_server* s, const scp_problem_desc* d, Layout& L, std
 size_t request_bytes(const scp_server* s, const Layout& L) {
     return (size_t)L.n_nodes * s->us.node + (size_t)L.n_traj * s->us.traj + (size_t)L.n_wg * s->us.wg +
            (size_t)L.n_gslots * s->us.span;
-}
-
-bool same_shape(const Request& a, const Request& b) {
-    return a.model == b.model && a.horizon == b.horizon && a.L.n_wg == b.L.n_wg && a.L.n_gslots == b.L.n_gslots &&
-           a.L.n_nodes == b.L.n_nodes;
-}
-
-void release_placement(scp_server* s, Request& r) {
-    if (!r.resident) return;
-    s->nodes.release(r.node_off, r.L.n_nodes);
-    s->trajs.release(r.traj_first, r.L.n_traj);
-    s->wgs.release(r.wg_first, r.L.n_wg);
-    for (int g : r.gslots) s->span_free.push_back(g);
-    r.gslots.clear();
-    r.resident = false;
-    s->st.resident -= 1;
-    s->st.resident_bytes -= r.bytes;
-}
-
-bool take_placement(scp_server* s, Request& r) {
-    if ((int)s->span_free.size() < r.L.n_gslots) return false;
-    const long long n = s->nodes.alloc(r.L.n_nodes);
-    if (n < 0) return false;
-    const long long t = s->trajs.alloc(r.L.n_traj);
-    if (t < 0) {
-        s->nodes.release(n, r.L.n_nodes);
-        return false;
-    }
-    const long long w = s->wgs.alloc(r.L.n_wg);
-    if (w < 0) {
-        s->nodes.release(n, r.L.n_nodes);
-        s->trajs.release(t, r.L.n_traj);
-        return false;
-    }
-    r.node_off = n;
-    r.traj_first = (int)t;
-    r.wg_first = (int)w;
-    r.gslots.clear();
-    for (int k = 0; k < r.L.n_gslots; ++k) {
-        r.gslots.push_back(s->span_free.back());
-        s->span_free.pop_back();
-    }
-    r.resident = true;
-    s->st.resident += 1;
-    s->st.resident_bytes += r.bytes;
-    s->st.peak_resident_bytes = std::max(s->st.peak_resident_bytes, s->st.resident_bytes);
-    return true;
-}
-
-// Drop the warm state of the least recently used idle session.
-bool evict_one(scp_server* s) {
-    int32_t victim = -1;
-    double oldest = 0;
-    for (auto& kv : s->session_warm) {
-        const Request& r = s->reqs.at(kv.second);
-        if (victim < 0 || r.last_use < oldest) {
-            victim = kv.first;
-            oldest = r.last_use;
-        }
-    }
-    if (victim < 0) return false;
-    const int64_t id = s->session_warm[victim];
-    s->session_warm.erase(victim);
-    Request& r = s->reqs.at(id);
-    release_placement(s, r);
-    if (r.info.empty() && r.state == RState::Done) s->reqs.erase(id);  // already collected
-    s->st.evictions += 1;
-    return true;
-}
-
-int running_wgs(const scp_server* s) {
-    int n = 0;
-    for (int64_t id : s->running) n += s->reqs.at(id).L.n_wg;
-    return n;
 }
 
 // Staged admission of one request into the blob; returns false if the blob is full.
@@ -438,10 +289,9 @@ void drain(scp_server* s, bool wait_one) {
         hipError_t q = wait_one ? hipEventSynchronize(sr.ev) : hipEventQuery(sr.ev);
         wait_one = false;
         if (q == hipErrorNotReady) break;
-        const double t = now_ms();
         const size_t esz = s->esz;
         for (size_t k = 0; k < sr.finishing.size(); ++k) {
-            Request& r = s->reqs.at(sr.finishing[k]);
+            Request& r = s->sched.reqs.at(sr.finishing[k]);
             const unsigned char* o = s->pin_out[sr.slot] + sr.out_off[k];
             const int nt = r.L.n_traj, nn = r.L.n_nodes;
             r.info.assign(reinterpret_cast<const double*>(o), reinterpret_cast<const double*>(o) + (size_t)nt * SCP_INFO_FIELDS);
@@ -453,21 +303,7 @@ void drain(scp_server* s, bool wait_one) {
                 r.x[k2] = esz == 4 ? (double)reinterpret_cast<const float*>(xo)[k2] : reinterpret_cast<const double*>(xo)[k2];
             for (size_t k2 = 0; k2 < r.u.size(); ++k2)
                 r.u[k2] = esz == 4 ? (double)reinterpret_cast<const float*>(uo)[k2] : reinterpret_cast<const double*>(uo)[k2];
-            r.state = RState::Done;
-            r.t_done = t;
-            r.last_use = t;
-            s->st.completed += 1;
-            if (r.session >= 0) {
-                // the solution stays resident as the session's warm state (the newest one wins)
-                auto it = s->session_warm.find(r.session);
-                if (it != s->session_warm.end() && it->second != r.id) {
-                    Request& old = s->reqs.at(it->second);
-                    release_placement(s, old);
-                }
-                s->session_warm[r.session] = r.id;
-            } else {
-                release_placement(s, r);
-            }
+            s->sched.finished(r.id);
         }
         (void)hipEventDestroy(sr.ev);
         s->slot_busy[sr.slot] = false;
@@ -475,12 +311,19 @@ void drain(scp_server* s, bool wait_one) {
     }
 }
 
+int32_t in_flight_count(const scp_server* s) {
+    int32_t n = 0;
+    for (const auto& r : s->inflight) n += (int32_t)r.finishing.size();
+    return n;
+}
+
 template <class T>
 scp_status do_step(scp_server* s, int wait, int32_t* pending) {
+    Scheduler& sc = s->sched;
     drain(s, false);
     if ((int)s->inflight.size() >= s->cfg.max_inflight) {
         if (!wait) {
-            if (pending) *pending = (int32_t)(s->queue.size() + s->running.size());
+            if (pending) *pending = (int32_t)(sc.queue.size() + sc.running.size()) + in_flight_count(s);
             return SCP_OK;
         }
         drain(s, true);
@@ -495,110 +338,22 @@ scp_status do_step(scp_server* s, int wait, int32_t* pending) {
     unsigned char* blob = s->pin_in[slot];
     size_t used = 0;
     std::vector<AdmitRec> recs;
-    // ---- admission, FIFO; a session's requests run one after the other ----
-    int run_wg = running_wgs(s);
-    std::vector<int64_t> keep;
-    bool blocked = false;
-    std::unordered_map<int32_t, bool> session_busy;
-    for (int64_t id : s->running) {
-        const Request& r = s->reqs.at(id);
-        if (r.session >= 0) session_busy[r.session] = true;
-    }
-    for (const StepRec& sr : s->inflight)
-        for (int64_t id : sr.finishing) {
-            const Request& r = s->reqs.at(id);
-            if (r.session >= 0) session_busy[r.session] = true;   // result not drained yet
-        }
-    for (int64_t id : s->queue) {
-        Request& r = s->reqs.at(id);
-        if (blocked || (r.session >= 0 && session_busy.count(r.session))) {
-            keep.push_back(id);
-            if (r.session >= 0) session_busy[r.session] = true;
-            continue;
-        }
-        if (run_wg + r.L.n_wg > s->wg_cap_running || (int)s->running.size() >= s->cfg.max_requests) {
-            keep.push_back(id);
-            blocked = true;
-            continue;
-        }
-        // warm start in place from the session's resident solution
-        long long x1 = -1;
-        Request* prev = nullptr;
-        if (r.session >= 0) {
-            auto it = s->session_warm.find(r.session);
-            if (it != s->session_warm.end()) {
-                Request& p = s->reqs.at(it->second);
-                if (p.resident && same_shape(p, r)) prev = &p;
-            }
-        }
-        bool placed = false;
-        if (prev) {
-            r.node_off = prev->node_off;
-            r.traj_first = prev->traj_first;
-            r.wg_first = prev->wg_first;
-            r.gslots = prev->gslots;
-            x1 = prev->node_off + prev->L.traj[TR_OFF] + 1;
-            placed = true;
-        } else {
-            if (r.session >= 0) {
-                auto it = s->session_warm.find(r.session);
-                if (it != s->session_warm.end()) {  // different shape: the old state goes
-                    release_placement(s, s->reqs.at(it->second));
-                    s->session_warm.erase(it);
-                }
-            }
-            while (!(s->st.resident_bytes + r.bytes <= s->cfg.budget_bytes && take_placement(s, r)))
-                if (!evict_one(s)) break;
-            placed = r.resident;
-        }
-        if (!placed) {
-            keep.push_back(id);
-            blocked = true;
-            continue;
-        }
-        const size_t used0 = used;
-        const size_t nrec0 = recs.size();
-        if (!stage_admit<T>(s, r, blob, used, recs, x1)) {
-            used = used0;
-            recs.resize(nrec0);
-            if (!prev) release_placement(s, r);
-            keep.push_back(id);
-            blocked = true;
-            continue;
-        }
-        if (prev) {
-            // the new request takes over the session's placement
-            prev->resident = false;
-            prev->gslots.clear();
-            s->session_warm.erase(r.session);
-            if (prev->info.empty() && prev->state == RState::Done) s->reqs.erase(prev->id);
-            r.resident = true;
-            s->st.warm_starts += 1;
-            r.warm = true;
-        }
-        r.state = RState::Running;
-        r.scp_enq = 0;
-        s->running.push_back(id);
-        run_wg += r.L.n_wg;
-        if (r.session >= 0) session_busy[r.session] = true;
-    }
-    s->queue.assign(keep.begin(), keep.end());
+    StepPlan plan;
+    sc.plan([&](Request& r, long long x1) { return stage_admit<T>(s, r, blob, used, recs, x1); }, plan);
     // ---- launch one step of every running request ----
     std::vector<int> wg_list;
     int models = 0, kmax = 0;
     bool span = false;
-    std::vector<int64_t> finishing;
-    for (int64_t id : s->running) {
-        Request& r = s->reqs.at(id);
+    for (int64_t id : plan.running) {
+        const Request& r = sc.reqs.at(id);
         for (int w = 0; w < r.L.n_wg; ++w) wg_list.push_back(r.wg_first + w);
         models |= r.L.models;
         kmax = std::max(kmax, r.L.kmax);
         span = span || r.L.n_gslots > 0;
-        r.scp_enq += s->cfg.scp_per_step;
-        if (r.scp_enq >= s->cfg.solve.scp_iters) finishing.push_back(id);
     }
+    const std::vector<int64_t>& finishing = plan.finishing;
     if (wg_list.empty()) {
-        if (pending) *pending = (int32_t)(s->queue.size() + s->running.size());
+        if (pending) *pending = (int32_t)(sc.queue.size() + sc.running.size()) + in_flight_count(s);
         return SCP_OK;
     }
     // records and lists after the admission arrays
@@ -615,7 +370,7 @@ scp_status do_step(scp_server* s, int wait, int32_t* pending) {
     std::vector<long long> out_off;
     size_t out_used = 0;
     for (int64_t id : finishing) {
-        const Request& r = s->reqs.at(id);
+        const Request& r = sc.reqs.at(id);
         const size_t o = (out_used + 15) / 16 * 16;
         const size_t n = (size_t)r.L.n_traj * SCP_INFO_FIELDS * 8 + (size_t)r.L.n_nodes * (SCP_MAX_NX + SCP_MAX_NU) * s->esz;
         crec.push_back(CollectRec{r.traj_first, r.L.n_traj, (int)r.node_off, r.L.n_nodes, (long long)o});
@@ -672,13 +427,9 @@ scp_status do_step(scp_server* s, int wait, int32_t* pending) {
     sr.finishing = finishing;
     sr.out_off = out_off;
     s->inflight.push_back(std::move(sr));
-    s->st.steps += 1;
     // finishing requests leave the running set now (their collection is enqueued)
-    std::vector<int64_t> still;
-    for (int64_t id : s->running)
-        if (std::find(finishing.begin(), finishing.end(), id) == finishing.end()) still.push_back(id);
-    s->running.swap(still);
-    if (pending) *pending = (int32_t)(s->queue.size() + s->running.size() + finishing.size());
+    sc.launched(plan);
+    if (pending) *pending = (int32_t)(sc.queue.size() + sc.running.size()) + in_flight_count(s);
     return SCP_OK;
 }
 
@@ -710,35 +461,43 @@ scp_status scp_server_create(const scp_server_config* cfg, void* arena_dev, size
         g_server_error = "arena missing, too small (need " + std::to_string(S.total) + " bytes) or not 256-byte aligned";
         return SCP_ERR_ARG;
     }
-    scp_server* s = new (std::nothrow) scp_server();
+    const size_t esz = cfg->prec == SCP_F32 ? 4 : 8;
+    // workgroups the device keeps resident at once: occupancy of the spanning-group kernel variant
+    // (the largest state: both models, 8 obstacles) times the compute units; if the query fails,
+    // one wave per SIMD, the LDS of the workgroup state and the device's CU count and LDS size
+    int cap = persistent_span_resident_cap((int)esz, cfg->block, 3, 8);
+    if (cap <= 0) {
+        int dev = 0, cus = 0, lds_cu = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+        if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+            lds_cu = 0;
+        const size_t lds = std::max<size_t>(1, persistent_shared_bytes(esz, cfg->block));
+        const int per_cu = std::max(1, std::min(4 / (cfg->block / 64), (int)((size_t)lds_cu / lds)));
+        cap = std::max(1, cus) * per_cu;
+    }
+    SchedLimits lim;
+    lim.max_nodes = cfg->max_nodes;
+    lim.max_traj = cfg->max_traj;
+    lim.max_wg = cfg->max_wg;
+    lim.max_span = cfg->max_span;
+    lim.max_requests = cfg->max_requests;
+    lim.budget_bytes = cfg->budget_bytes;
+    lim.wg_cap_running = cap;
+    lim.scp_iters = cfg->solve.scp_iters;
+    lim.scp_per_step = cfg->scp_per_step;
+    lim.timeout_ms = cfg->timeout_ms;
+    scp_server* s = new (std::nothrow) scp_server(lim);
     if (!s) {
         g_server_error = "host allocation failed";
         return SCP_ERR_NOMEM;
     }
     s->cfg = *cfg;
     s->S = S;
-    s->esz = cfg->prec == SCP_F32 ? 4 : 8;
+    s->esz = esz;
     s->us = unit_sizes(s->esz, cfg->block);
     s->stream = reinterpret_cast<hipStream_t>(hip_stream);
     s->arena = reinterpret_cast<char*>(arena_dev);
-    s->nodes.reset(cfg->max_nodes);
-    s->trajs.reset(cfg->max_traj);
-    s->wgs.reset(cfg->max_wg);
-    for (int g = cfg->max_span - 1; g >= 0; --g) s->span_free.push_back(g);
-    // workgroups the device keeps resident at once: occupancy of the spanning-group kernel variant
-    // (the largest state: both models, 8 obstacles) times the compute units; if the query fails,
-    // one wave per SIMD, the LDS of the workgroup state and the device's CU count and LDS size
-    s->wg_cap_running = persistent_span_resident_cap(s->esz, cfg->block, 3, 8);
-    if (s->wg_cap_running <= 0) {
-        int dev = 0, cus = 0, lds_cu = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
-        if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
-            lds_cu = 0;
-        const size_t lds = std::max<size_t>(1, persistent_shared_bytes(s->esz, cfg->block));
-        const int per_cu = std::max(1, std::min(4 / (cfg->block / 64), (int)((size_t)lds_cu / lds)));
-        s->wg_cap_running = std::max(1, cus) * per_cu;
-    }
     const int slots = cfg->max_inflight + 1;
     hipError_t e = hipSuccess;
     for (int k = 0; k < slots && e == hipSuccess; ++k) {
@@ -786,13 +545,13 @@ scp_status scp_server_submit_ex(scp_server* s, const scp_problem_desc* d, int32_
     Request r;
     std::string err;
     if (!plan_request(s, d, r.L, err)) {
-        s->st.rejected += 1;
+        s->sched.st.rejected += 1;
         return fail(s, SCP_ERR_ARG, err);
     }
     r.bytes = request_bytes(s, r.L);
     if (r.bytes > s->cfg.budget_bytes || r.L.n_nodes > s->cfg.max_nodes || r.L.n_traj > s->cfg.max_traj ||
         r.L.n_wg > s->cfg.max_wg || r.L.n_gslots > s->cfg.max_span) {
-        s->st.rejected += 1;
+        s->sched.st.rejected += 1;
         return fail(s, SCP_ERR_ARG, "request larger than the pool or the budget");
     }
     const int n = d->n_traj;
@@ -807,15 +566,9 @@ scp_status scp_server_submit_ex(scp_server* s, const scp_problem_desc* d, int32_
     }
     r.xg.assign(d->x_guess, d->x_guess + xrows * SCP_MAX_NX);
     r.ug.assign(d->u_guess, d->u_guess + urows * SCP_MAX_NU);
-    r.id = s->next_id++;
     r.session = session;
     r.flags = flags;
-    r.t_submit = now_ms();
-    r.last_use = r.t_submit;
-    *id = r.id;
-    s->queue.push_back(r.id);
-    s->reqs.emplace(r.id, std::move(r));
-    s->st.submitted += 1;
+    *id = s->sched.submit(std::move(r));
     return SCP_OK;
 }
 
@@ -827,44 +580,49 @@ scp_status scp_server_step(scp_server* s, int32_t wait, int32_t* pending) {
 scp_status scp_server_collect(scp_server* s, int64_t id, int32_t release, int32_t* state, double* latency_ms,
                               double* info, double* x, double* u) {
     if (!s) return SCP_ERR_ARG;
-    auto it = s->reqs.find(id);
-    if (it == s->reqs.end() || (it->second.state == RState::Done && it->second.info.empty())) {
-        if (state) *state = SCP_REQ_UNKNOWN;
-        return SCP_OK;
-    }
-    Request& r = it->second;
-    if (state) *state = r.state == RState::Queued ? SCP_REQ_QUEUED : r.state == RState::Running ? SCP_REQ_RUNNING : SCP_REQ_DONE;
-    if (r.state != RState::Done) return SCP_OK;
+    Scheduler& sc = s->sched;
+    const int32_t stt = sc.state_of(id);
+    if (state) *state = stt;
+    if (stt == SCP_REQ_UNKNOWN || stt == SCP_REQ_QUEUED || stt == SCP_REQ_RUNNING) return SCP_OK;
+    const Request& r = sc.reqs.at(id);
     if (latency_ms) *latency_ms = r.t_done - r.t_submit;
-    if (info) std::memcpy(info, r.info.data(), r.info.size() * sizeof(double));
-    if (x || u) {
-        // pool rows -> per-trajectory rows (N+1 states, N controls)
-        long long xr = 0, ur = 0;
-        for (int t = 0; t < r.L.n_traj; ++t) {
-            const int N = r.L.traj[(size_t)t * TR_FIELDS + TR_N], off = r.L.traj[(size_t)t * TR_FIELDS + TR_OFF];
-            for (int i = 0; i <= N; ++i, ++xr)
-                if (x) std::memcpy(x + xr * SCP_MAX_NX, &r.x[(size_t)(off + i) * SCP_MAX_NX], SCP_MAX_NX * sizeof(double));
-            for (int i = 0; i < N; ++i, ++ur)
-                if (u) std::memcpy(u + ur * SCP_MAX_NU, &r.u[(size_t)(off + i) * SCP_MAX_NU], SCP_MAX_NU * sizeof(double));
+    if (stt == SCP_REQ_DONE) {
+        if (info) std::memcpy(info, r.info.data(), r.info.size() * sizeof(double));
+        if (x || u) {
+            // pool rows -> per-trajectory rows (N+1 states, N controls)
+            long long xr = 0, ur = 0;
+            for (int t = 0; t < r.L.n_traj; ++t) {
+                const int N = r.L.traj[(size_t)t * TR_FIELDS + TR_N], off = r.L.traj[(size_t)t * TR_FIELDS + TR_OFF];
+                for (int i = 0; i <= N; ++i, ++xr)
+                    if (x) std::memcpy(x + xr * SCP_MAX_NX, &r.x[(size_t)(off + i) * SCP_MAX_NX], SCP_MAX_NX * sizeof(double));
+                for (int i = 0; i < N; ++i, ++ur)
+                    if (u) std::memcpy(u + ur * SCP_MAX_NU, &r.u[(size_t)(off + i) * SCP_MAX_NU], SCP_MAX_NU * sizeof(double));
+            }
         }
     }
-    if (release) {
-        r.info.clear();
-        r.x.clear();
-        r.u.clear();
-        r.info.shrink_to_fit();
-        const bool warm_holder = r.session >= 0 && s->session_warm.count(r.session) && s->session_warm[r.session] == r.id;
-        if (!warm_holder && !r.resident) s->reqs.erase(it);
-    }
+    if (release) sc.release(id);
+    return SCP_OK;
+}
+
+scp_status scp_server_cancel(scp_server* s, int64_t id) {
+    if (!s) return SCP_ERR_ARG;
+    if (!s->sched.cancel(id)) return fail(s, SCP_ERR_STATE, "no queued or running request with this id");
+    return SCP_OK;
+}
+
+scp_status scp_server_take_done(scp_server* s, int64_t* ids, int32_t cap, int32_t* n) {
+    if (!s || !n || cap < 0 || (cap > 0 && !ids)) return SCP_ERR_ARG;
+    std::vector<int64_t>& d = s->sched.done_ids;
+    const int32_t k = (int32_t)std::min<size_t>((size_t)cap, d.size());
+    for (int32_t i = 0; i < k; ++i) ids[i] = d[i];
+    d.erase(d.begin(), d.begin() + k);
+    *n = k;
     return SCP_OK;
 }
 
 scp_status scp_server_get_stats(const scp_server* s, scp_server_stats* out) {
     if (!s || !out) return SCP_ERR_ARG;
-    *out = s->st;
-    out->queued = (int32_t)s->queue.size();
-    out->running = (int32_t)s->running.size();
-    for (const auto& r : s->inflight) out->running += (int32_t)r.finishing.size();
+    *out = s->sched.stats(in_flight_count(s));
     return SCP_OK;
 }
 

@@ -48,12 +48,11 @@ def _pcts(lat: list[float]) -> dict:
 def run_served(srv, prepared: list, times, sess, progress: float = 5.0, drain_s: float = 30.0) -> dict:
     """Drive the server with the arrival trace.  prepared[s] = srv.prepare(request of session s)."""
     n = len(times)
-    lat, defect, conv = [], [], 0
+    lat, defect, conv, failed = [], [], 0, 0
     outstanding = {}
     t0 = time.perf_counter()
     i = 0
     last_print = 0.0
-    completed_seen = -1
     end_deadline = (times[-1] if n else 0.0) + drain_s
     while i < n or outstanding:
         now = time.perf_counter() - t0
@@ -64,19 +63,18 @@ def run_served(srv, prepared: list, times, sess, progress: float = 5.0, drain_s:
             outstanding[rid] = times[i]
             i += 1
         srv.step(wait=False)
-        done = srv.stats()["completed"]
-        if done != completed_seen:
-            completed_seen = done
+        ended = srv.take_done()
+        if ended:
             t_obs = time.perf_counter() - t0
-            for rid in list(outstanding):
+            for rid in ended:
                 r = srv.poll(rid)
-                if r is None:
-                    continue
                 arr = outstanding.pop(rid)
                 lat.append((t_obs - arr) * 1e3)
                 info = r[1]
                 defect.append(float(info[:, 6].max()))
-                conv += int(np.all(info[:, 5].astype(np.int64) & 8))
+                st = info[:, 5].astype(np.int64)
+                conv += int(np.all(st & 8))
+                failed += int(np.any(st & (1 | 2 | 4 | 16)))   # non-finite, pivot, empty set, group barrier
         if progress and now - last_print > progress:
             last_print = now
             print(f"[serve] t={now:.1f}s submitted={i}/{n} outstanding={len(outstanding)} done={len(lat)}",
@@ -87,6 +85,7 @@ def run_served(srv, prepared: list, times, sess, progress: float = 5.0, drain_s:
     st = srv.stats()
     return dict(offered=n, completed=len(lat), wall_s=round(wall, 3), latency_ms=_pcts(lat),
                 solves_per_s=round(len(lat) / max(wall, 1e-9), 1), unfinished=len(outstanding),
+                failure_status=failed,
                 defect_p50=float(np.median(defect)) if defect else None, steps=st["steps"],
                 warm_starts=st["warm_starts"], evictions=st["evictions"],
                 peak_resident_mb=round(st["peak_resident_bytes"] / 2**20, 2))

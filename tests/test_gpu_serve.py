@@ -194,3 +194,42 @@ def test_backpressure_small_budget(B):
         tiny.submit(reqs[0])
     tiny.close()
     srv.close()
+
+
+def test_cancel_timeout_done_list_and_stats(B):
+    """Cancellation (queued and running), the configured timeout, the done list and the library's
+    latency quantiles on the device path; the neighbours of a cancelled request are unaffected."""
+    reqs = [scpgen.config4_request(40 + k, S=4, N=30) for k in range(6)]
+    srv = _server(B, scp=4, admm=30, max_inflight=1)
+    ids = [srv.submit(r) for r in reqs]
+    srv.cancel(ids[5])                       # queued: ends at once
+    srv.step(wait=True)                      # the others are admitted and run one SCP iteration
+    srv.cancel(ids[1])                       # running: leaves at the next step
+    res = srv.drain(ids, timeout_s=120)
+    states = [res[i]["state"] for i in ids]
+    _say(states, srv.stats())
+    assert states == ["done", "cancelled", "done", "done", "done", "cancelled"]
+    st = srv.stats()
+    assert st["cancelled"] == 2 and st["completed"] == 4 and st["resident"] == 0
+    assert 0 < st["latency_ms_p50"] <= st["latency_ms_p99"] and st["solves_per_s"] > 0
+    assert srv.take_done() == []
+    # the completed ones equal the same requests served without the cancellations
+    ref = _server(B, scp=4, admm=30, max_inflight=1)
+    rids = [ref.submit(reqs[k]) for k in (0, 2, 3, 4)]
+    rres = ref.drain(rids)
+    for k, rid in zip((0, 2, 3, 4), rids):
+        for a, b in zip(res[ids[k]]["x"], rres[rid]["x"]):
+            np.testing.assert_array_equal(a, b)
+    ref.close()
+    with pytest.raises(B.ScpError):
+        srv.cancel(ids[0])                   # already ended
+    srv.close()
+    # a timeout shorter than one request's solve: every request ends without a result
+    slow = _server(B, scp=10, admm=200, max_inflight=1, timeout_ms=0.5)
+    tids = [slow.submit(r) for r in reqs[:3]]
+    tres = slow.drain(tids, timeout_s=120)
+    _say([tres[i]["state"] for i in tids], slow.stats())
+    assert all(tres[i]["state"] == "timeout" for i in tids)
+    st = slow.stats()
+    assert st["timed_out"] == 3 and st["resident"] == 0
+    slow.close()
