@@ -386,10 +386,16 @@ def serve_main(a, wl, cpu):
     n_cap = a.capacity_requests
     t0 = time.perf_counter()
     ids = [srv.submit(prepared[k % n_sess], session=-1) for k in range(n_cap)]
+    st0 = srv.stats()
     res = srv.drain(ids, timeout_s=600)
     cap_wall = time.perf_counter() - t0
-    capacity = {"requests": n_cap, "wall_s": round(cap_wall, 3), "solves_per_s": round(n_cap / cap_wall, 1)}
     st = srv.stats()
+    cap_fail = sum(1 for r in res.values() if r["state"] != "done" or
+                   any(int(i["status"]) & (B.ST_NONFINITE | B.ST_BADPIVOT | B.ST_EMPTYSET | B.ST_SYNC) for i in r["info"]))
+    capacity = {"requests": n_cap, "wall_s": round(cap_wall, 3), "solves_per_s": round(n_cap / cap_wall, 1),
+                "steps": int(st["steps"] - st0["steps"]),
+                "ms_per_step": round(cap_wall * 1e3 / max(1, st["steps"] - st0["steps"]), 3),
+                "failure_status": cap_fail}
     srv.close()
     print(f"[serve] capacity {capacity}", file=sys.stderr, flush=True)
     plain = None
@@ -422,6 +428,8 @@ def serve_main(a, wl, cpu):
         "served": served,
         "latency_ms_p50": served["latency_ms"]["p50"],
         "latency_ms_p99": served["latency_ms"]["p99"],
+        "server_stats": {k: st[k] for k in ("completed", "cancelled", "timed_out", "latency_ms_p50", "latency_ms_p99",
+                                            "solves_per_s", "warm_starts", "evictions", "steps")},
         "capacity": capacity,
         "plain": plain,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
