@@ -17,6 +17,7 @@
 #include "scp_host.hpp"
 #include "scp_launch.hpp"
 #include "scp_layout.hpp"
+#include "scp_trace.hpp"
 
 using namespace scp;
 
@@ -161,6 +162,7 @@ scp_status run_resident_admm(scp_problem* p, const Dev<T>& dv, const KParams<T>&
 
 template <class T>
 scp_status do_linearize(scp_problem* p, const admm_params* a) {
+    TraceRange tr("scp_linearize");
     const Dev<T>& dv = *reinterpret_cast<const Dev<T>*>(p->prec == SCP_F32 ? (const void*)&p->df : (const void*)&p->dd);
     KParams<T> kp = kparams<T>(a, nullptr);
     hipError_t e = launch_plain<T>(PlainOp::Lin, dv, kp, p->L.models, p->L.kmax, 0, 0, p->stream);
@@ -169,6 +171,7 @@ scp_status do_linearize(scp_problem* p, const admm_params* a) {
 
 template <class T>
 scp_status do_admm(scp_problem* p, const admm_params* a) {
+    TraceRange tr("admm_solve");
     const Dev<T>& dv = *reinterpret_cast<const Dev<T>*>(p->prec == SCP_F32 ? (const void*)&p->df : (const void*)&p->dd);
     KParams<T> kp = kparams<T>(a, nullptr);
     return run_plain_admm<T>(p, dv, kp);
@@ -176,6 +179,7 @@ scp_status do_admm(scp_problem* p, const admm_params* a) {
 
 template <class T>
 scp_status do_solve(scp_problem* p, const scp_params* s) {
+    TraceRange tr_solve("scp_solve");
     const Dev<T>& dv = *reinterpret_cast<const Dev<T>*>(p->prec == SCP_F32 ? (const void*)&p->df : (const void*)&p->dd);
     const Layout& L = p->L;
     KParams<T> kp = kparams<T>(&s->admm, s);
@@ -188,6 +192,8 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
     if (s->form == SCP_FORM_PLAIN || resident) {
         double f = 1.0;
         for (int k = 0; k < s->scp_iters; ++k, f *= kp.sched_q) {
+            TraceRange tr_it(resident ? "scp_iteration (linearize, resident ADMM, accept)"
+                                      : "scp_iteration (linearize, plain ADMM, accept)");
             scale_rho(kp, f);
             e = launch_plain<T>(PlainOp::Lin, dv, kp, L.models, L.kmax, 0, 0, p->stream);
             if (e != hipSuccess) return hip_check(p, e, "linearize launch");
@@ -218,7 +224,10 @@ scp_status do_solve(scp_problem* p, const scp_params* s) {
         for (int k = 0; k < n; ++k) f *= kp.sched_q;
         kp.reset_info = done == 0 ? 1 : 0;
         kp.final_metrics = (done + n == s->scp_iters) ? 1 : 0;
-        e = launch_persistent<T>(dv, kp, L.n_wg, L.block, L.models, L.kmax, p->stream);
+        {
+            TraceRange tr_it("scp_iterations (persistent launch)");
+            e = launch_persistent<T>(dv, kp, L.n_wg, L.block, L.models, L.kmax, p->stream);
+        }
         if (e != hipSuccess) return hip_check(p, e, "persistent launch");
         done += n;
     }

@@ -22,6 +22,7 @@
 #include "scp_launch.hpp"
 #include "scp_layout.hpp"
 #include "scp_sched.hpp"
+#include "scp_trace.hpp"
 
 using namespace scp;
 
@@ -319,6 +320,7 @@ int32_t in_flight_count(const scp_server* s) {
 
 template <class T>
 scp_status do_step(scp_server* s, int wait, int32_t* pending) {
+    TraceRange tr_step("scp_server_step");
     Scheduler& sc = s->sched;
     drain(s, false);
     if ((int)s->inflight.size() >= s->cfg.max_inflight) {
@@ -339,7 +341,10 @@ scp_status do_step(scp_server* s, int wait, int32_t* pending) {
     size_t used = 0;
     std::vector<AdmitRec> recs;
     StepPlan plan;
-    sc.plan([&](Request& r, long long x1) { return stage_admit<T>(s, r, blob, used, recs, x1); }, plan);
+    {
+        TraceRange tr_plan("scp_server_step: admission and staging");
+        sc.plan([&](Request& r, long long x1) { return stage_admit<T>(s, r, blob, used, recs, x1); }, plan);
+    }
     // ---- launch one step of every running request ----
     std::vector<int> wg_list;
     int models = 0, kmax = 0;

@@ -8,6 +8,7 @@
     python -m paper_2603_10711_amd.profile_summary sq <counter dir> <title> <admm iterations per dispatch> <out.md> \
         --cmd "<command>" [--kernel <kernel name prefix, default k_persistent>] [--extra <counter dir> ...]
     python -m paper_2603_10711_amd.profile_summary calibrate
+    python -m paper_2603_10711_amd.profile_summary markers <marker-trace dir> <out.md> --cmd "<command>"
 
 ``calibrate`` is a plain 1 GiB device-to-device copy (run under rocprofv3 --pmc FETCH_SIZE, then
 WRITE_SIZE): a kernel whose HBM traffic is known exactly.  ``pmc`` scales FETCH_SIZE / WRITE_SIZE of
@@ -164,6 +165,24 @@ def sq(dirpath: str, title: str, iters: int, out: str, cmd: str, kernel: str = "
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+def markers(dirpath: str, out: str, cmd: str) -> None:
+    """Host trace ranges (roctx) from a --marker-trace run: per range name, count and durations."""
+    path = glob.glob(os.path.join(dirpath, "*marker_api_trace.csv"))[0]
+    rows = list(csv.DictReader(open(path)))
+    name_col = next(c for c in ("Message", "Function", "Name") if rows and c in rows[0])
+    dur = collections.defaultdict(list)
+    for r in rows:
+        t0, t1 = float(r["Start_Timestamp"]), float(r["End_Timestamp"])
+        if t1 > t0:
+            dur[r[name_col]].append((t1 - t0) / 1e3)
+    lines = ["# rocprofv3 host trace ranges (roctx)", "", f"Command: `{cmd}`", "",
+             f"Kernel sources hash: `{kernel_source_hash()}`", "",
+             "| range | count | avg (us) | min (us) | max (us) |", "|---|---|---|---|---|"]
+    for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{k}` | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 def calibrate(n_bytes: int = 1 << 30) -> None:
     """A plain device-to-device copy of n_bytes (the counters' calibration kernel)."""
     import torch
@@ -200,9 +219,15 @@ def main(argv=None):
     q.add_argument("--kernel", default="k_persistent")
     q.add_argument("--extra", nargs="*", default=[])
     sub.add_parser("calibrate")
+    mk = sub.add_parser("markers")
+    mk.add_argument("dir")
+    mk.add_argument("out")
+    mk.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
     if a.mode == "calibrate":
         return calibrate()
+    if a.mode == "markers":
+        return markers(a.dir, a.out, a.cmd)
     if a.mode == "stats":
         stats(a.csv, a.out, a.cmd)
     elif a.mode == "pmcplain":
