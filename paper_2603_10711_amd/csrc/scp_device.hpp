@@ -159,9 +159,12 @@ __device__ __forceinline__ double lane_prev(double v) {
 }
 
 // Lane permutations inside each aligned group of four lanes (DPP quad_perm; SEL packs the source
-// lane of lanes 0..3 in two bits each).  Every lane of a group must be active.
+// lane of lanes 0..3 in two bits each).  Every lane of a group must be active, so a source lane is
+// never out of range and the zero-fill flag changes no result; with it set the compiler folds the
+// permutation into a following two-operand addition, multiplication or min/max (v_add_f32_dpp ...),
+// one instruction instead of two (quad_sum, quad_reduce_scatter).
 template <int SEL>
-__device__ __forceinline__ int quad_perm_i(int v) { return __builtin_amdgcn_mov_dpp(v, SEL, 0xF, 0xF, false); }
+__device__ __forceinline__ int quad_perm_i(int v) { return __builtin_amdgcn_mov_dpp(v, SEL, 0xF, 0xF, true); }
 template <int SEL>
 __device__ __forceinline__ float quad_perm(float v) { return __builtin_bit_cast(float, quad_perm_i<SEL>(__builtin_bit_cast(int, v))); }
 template <int SEL>
