@@ -6,7 +6,7 @@ of the converged-solution bar).
 Calls only the oracle (FP64 NumPy): the 1024 point-mass quadrotor instances of the batch workload
 (N = 50, 8 obstacles, seeded generator) solved with the geometric penalty schedule of the paper's
 parameter study (Sec. IV-A.2: one rho for all three penalties, grown geometrically over the SCP
-iterations to a final value), here from 5 to 1e4 over 20 SCP iterations of 300 ADMM iterations each
+iterations to a final value), here from 5 to 1e4 over 18 SCP iterations of 290 ADMM iterations each
 (the headline setting of the benchmark), fixed trust radius, always-accept steps.  For every instance it stores the final cost, max
 dynamics defect, max constraint violation and boundary error of the returned nominal.
 """
@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-SETTING = dict(scp_iters=20, admm_iters=300, rho=5.0, rho_final=1e4)
+SETTING = dict(scp_iters=18, admm_iters=290, rho=5.0, rho_final=1e4)
 OUT = os.path.join(HERE, "quad1024_converged.json")
 
 
