@@ -316,6 +316,28 @@ scp_status scp_solve(scp_problem* p, const scp_params* prm);
  * scp_solve is then a fresh solve (instead of a warm start from the last one).  Async. */
 scp_status scp_reset(scp_problem* p);
 
+/* Checkpoint and resume.  The paper's only form of resumption is the MPC warm start (Sec.
+ * IV-A.4: the previous solution, shifted, seeds the next solve); these calls make any solve
+ * resumable across handles and processes.  The state is everything a later call reads: the
+ * nominal, the linearization and factors, the ADMM iterates and duals, the trust radii, the info
+ * records and flags (the whole arena, which holds offsets only, never addresses), plus the
+ * handle's host-side state (whether a linearization is current, and its penalties).
+ *
+ * scp_problem_state_bytes: size of an exported state (a header plus the arena bytes).
+ * scp_problem_export_state: waits for the handle's stream, then copies the state into `host`
+ *   (>= scp_problem_state_bytes bytes, any host memory).  Errors: SCP_ERR_ARG (NULL or too
+ *   small), SCP_ERR_HIP.
+ * scp_problem_import_state: restores a state exported from a handle created with the same
+ *   description (same trajectories, horizons, models, groups, precision and packing; checked by
+ *   a fingerprint of the layout in the header), enqueued on the handle's stream after its
+ *   earlier work; returns after the copy, so `host` may be reused at once.  The next scp_solve
+ *   or admm_solve then continues exactly as the exporting handle would have (bitwise, on the
+ *   same device).  Errors: SCP_ERR_ARG (NULL, wrong size, or a state of another layout),
+ *   SCP_ERR_HIP. */
+size_t scp_problem_state_bytes(const scp_problem* p);
+scp_status scp_problem_export_state(scp_problem* p, void* host, size_t bytes);
+scp_status scp_problem_import_state(scp_problem* p, const void* host, size_t bytes);
+
 /* Copy the nominal trajectory and info to caller device buffers (device-to-device, async):
  * x_dev gets rows of SCP_MAX_NX values per node (all trajectories concatenated, N+1 rows
  * each), u_dev rows of SCP_MAX_NU values (N+1 rows per trajectory, the last row zero), both

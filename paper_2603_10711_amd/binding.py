@@ -38,7 +38,8 @@ FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9
 SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_create_noalloc", "scp_problem_destroy",
            "scp_linearize", "admm_solve",
            "scp_solve", "scp_reset", "scp_get_result", "scp_field_width", "scp_get_field", "scp_problem_nodes",
-           "scp_traj_node_offset", "scp_plan", "scp_autotune_device_bytes", "scp_autotune", "scp_last_error"]
+           "scp_traj_node_offset", "scp_plan", "scp_autotune_device_bytes", "scp_autotune", "scp_last_error",
+           "scp_problem_state_bytes", "scp_problem_export_state", "scp_problem_import_state"]
 SERVE_SYMBOLS = ["scp_server_device_bytes", "scp_server_create", "scp_server_destroy", "scp_server_request_bytes",
                  "scp_server_submit", "scp_server_submit_ex", "scp_server_step", "scp_server_collect",
                  "scp_server_cancel", "scp_server_take_done", "scp_server_get_stats", "scp_server_last_error"]
@@ -86,7 +87,7 @@ class ServerStats(ctypes.Structure):
                 ("running", c_int32), ("resident", c_int32), ("steps", c_int64), ("evictions", c_int64),
                 ("warm_starts", c_int64), ("resident_bytes", c_size_t), ("peak_resident_bytes", c_size_t),
                 ("cancelled", c_int64), ("timed_out", c_int64), ("latency_ms_p50", c_double),
-                ("latency_ms_p99", c_double), ("solves_per_s", c_double)]
+                ("latency_ms_p99", c_double), ("solves_per_s", c_double), ("latency_ms_p999", c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -121,6 +122,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scp_reset.restype = c_int32
     lib.scp_get_result.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     lib.scp_get_result.restype = c_int32
+    lib.scp_problem_state_bytes.argtypes = [c_void_p]
+    lib.scp_problem_state_bytes.restype = c_size_t
+    lib.scp_problem_export_state.argtypes = [c_void_p, c_void_p, c_size_t]
+    lib.scp_problem_export_state.restype = c_int32
+    lib.scp_problem_import_state.argtypes = [c_void_p, c_void_p, c_size_t]
+    lib.scp_problem_import_state.restype = c_int32
     lib.scp_field_width.argtypes = [c_int32]
     lib.scp_field_width.restype = c_int32
     lib.scp_get_field.argtypes = [c_void_p, c_int32, c_void_p]
@@ -390,6 +397,21 @@ class Problem:
     def reset(self):
         """Back to the initial guess with zero duals: the next solve starts fresh."""
         self._check(self.lib.scp_reset(self.h), "scp_reset")
+
+    def export_state(self):
+        """Checkpoint: the whole solver state as a host uint8 array (waits for the problem's stream)."""
+        import numpy as np
+        buf = np.empty(self.lib.scp_problem_state_bytes(self.h), dtype=np.uint8)
+        self._check(self.lib.scp_problem_export_state(self.h, c_void_p(buf.ctypes.data), c_size_t(buf.nbytes)),
+                    "scp_problem_export_state")
+        return buf
+
+    def import_state(self, buf):
+        """Resume from export_state() of a problem with the same description."""
+        import numpy as np
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.scp_problem_import_state(self.h, c_void_p(buf.ctypes.data), c_size_t(buf.nbytes)),
+                    "scp_problem_import_state")
 
     def field(self, name: str):
         fid = FIELDS[name]

@@ -116,6 +116,40 @@ scp_status hip_check(scp_problem* p, hipError_t e, const char* what) {
     return fail(p, SCP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Checkpoint header: the arena follows it.  The fingerprint covers everything that fixes where a
+// trajectory's data sits in the arena (sizes, offsets, packing tables, precision).
+struct StateHeader {
+    uint64_t magic;
+    uint64_t fingerprint;
+    uint64_t arena_bytes;
+    int32_t linearized;
+    int32_t prec;
+    double lin_rho[3];
+};
+constexpr uint64_t STATE_MAGIC = 0x31544b4350435353ull;   // "SSCPCKT1"
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
+    return h;
+}
+
+uint64_t layout_fingerprint(const scp_problem* p) {
+    const Layout& L = p->L;
+    uint64_t h = 0xcbf29ce484222325ull;
+    const int64_t sizes[] = {L.n_traj, L.n_nodes, L.P, L.models, L.kmax, L.block, L.n_wg, L.n_groups,
+                             (int64_t)L.esz, L.n_gslots, (int64_t)p->prec};
+    h = fnv1a(h, sizes, sizeof sizes);
+    const size_t offs[] = {L.o_traj, L.o_node_traj, L.o_lane, L.o_groups, L.o_params, L.o_planes, L.o_rt,
+                           L.o_info, L.o_flags, L.o_red, L.o_gsync, L.o_gx, L.total};
+    h = fnv1a(h, offs, sizeof offs);
+    h = fnv1a(h, L.traj.data(), L.traj.size() * sizeof(int));
+    h = fnv1a(h, L.node_traj.data(), L.node_traj.size() * sizeof(int));
+    h = fnv1a(h, L.lane.data(), L.lane.size() * sizeof(int));
+    h = fnv1a(h, L.groups.data(), L.groups.size() * sizeof(int));
+    return h;
+}
+
 bool admm_valid(const admm_params* a, std::string& err) {
     if (!a) { err = "admm params NULL"; return false; }
     if (!(a->rho_eq > 0) || !(a->rho_dyn > 0) || !(a->rho_geo > 0)) { err = "penalties must be positive"; return false; }
@@ -514,6 +548,48 @@ scp_status scp_get_field(const scp_problem* cp, int32_t field, void* dst_dev) {
                        ? launch_gather<float>(p->df, plane, w, mode, reinterpret_cast<float*>(dst_dev), p->stream)
                        : launch_gather<double>(p->dd, plane, w, mode, reinterpret_cast<double*>(dst_dev), p->stream);
     return hip_check(p, e, "gather launch");
+}
+
+size_t scp_problem_state_bytes(const scp_problem* p) {
+    return p ? sizeof(StateHeader) + p->L.total : 0;
+}
+
+scp_status scp_problem_export_state(scp_problem* p, void* host, size_t bytes) {
+    if (!p) return SCP_ERR_ARG;
+    if (!host || bytes < scp_problem_state_bytes(p)) return fail(p, SCP_ERR_ARG, "export_state: buffer NULL or too small");
+    TraceRange tr("scp_problem_export_state");
+    StateHeader h{};
+    h.magic = STATE_MAGIC;
+    h.fingerprint = layout_fingerprint(p);
+    h.arena_bytes = p->L.total;
+    h.linearized = p->linearized ? 1 : 0;
+    h.prec = (int32_t)p->prec;
+    for (int k = 0; k < 3; ++k) h.lin_rho[k] = p->lin_rho[k];
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(static_cast<char*>(host) + sizeof h, p->arena, p->L.total, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_check(p, e, "export_state copy");
+    std::memcpy(host, &h, sizeof h);
+    return SCP_OK;
+}
+
+scp_status scp_problem_import_state(scp_problem* p, const void* host, size_t bytes) {
+    if (!p) return SCP_ERR_ARG;
+    if (!host || bytes != scp_problem_state_bytes(p)) return fail(p, SCP_ERR_ARG, "import_state: buffer NULL or of another size");
+    StateHeader h;
+    std::memcpy(&h, host, sizeof h);
+    if (h.magic != STATE_MAGIC || h.arena_bytes != p->L.total || h.prec != (int32_t)p->prec ||
+        h.fingerprint != layout_fingerprint(p))
+        return fail(p, SCP_ERR_ARG, "import_state: not a state of a problem with this layout");
+    TraceRange tr("scp_problem_import_state");
+    hipError_t e = hipMemcpyAsync(p->arena, static_cast<const char*>(host) + sizeof h, p->L.total, hipMemcpyHostToDevice,
+                                  p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_check(p, e, "import_state copy");
+    p->linearized = h.linearized != 0;
+    for (int k = 0; k < 3; ++k) p->lin_rho[k] = h.lin_rho[k];
+    return SCP_OK;
 }
 
 scp_status scp_get_result(const scp_problem* cp, void* x_dev, void* u_dev, void* info_dev) {
