@@ -78,6 +78,7 @@ typedef struct {
                                                  (nearest-rank quantiles; 0 if none)    */
     double solves_per_s;                      /* completed requests per second from the
                                                  first submission to the last completion */
+    double latency_ms_p999;                   /* as latency_ms_p50, the 99.9 % quantile  */
 } scp_server_stats;
 
 /* Arena bytes the configuration needs (0 if invalid).  Pure host computation. */

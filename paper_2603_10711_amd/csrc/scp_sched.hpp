@@ -472,7 +472,7 @@ class Scheduler {
         scp_server_stats o = st;
         o.queued = (int32_t)queue.size();
         o.running = (int32_t)running.size() + running_in_flight;
-        o.latency_ms_p50 = o.latency_ms_p99 = 0.0;
+        o.latency_ms_p50 = o.latency_ms_p99 = o.latency_ms_p999 = 0.0;
         if (!latencies.empty()) {
             std::vector<double> v(latencies);
             std::sort(v.begin(), v.end());
@@ -483,6 +483,7 @@ class Scheduler {
             };
             o.latency_ms_p50 = q(0.50);
             o.latency_ms_p99 = q(0.99);
+            o.latency_ms_p999 = q(0.999);
         }
         o.solves_per_s = (t_last_done > t_first_submit && st.completed > 0)
                              ? (double)st.completed / ((t_last_done - t_first_submit) * 1e-3)

@@ -194,6 +194,7 @@ static void scenario_budget() {
     const scp_server_stats s = sc.stats(0);
     CHECK(s.latency_ms_p50 == lat[4]);   // nearest rank: ceil(0.5 * 10) = 5th
     CHECK(s.latency_ms_p99 == lat[9]);
+    CHECK(s.latency_ms_p999 == lat[9]);  // ceil(0.999 * 10) = 10th
     CHECK(std::fabs(s.solves_per_s - 10.0 / (sc.t_last_done * 1e-3)) < 1e-9);
     for (int64_t id : ids) {
         CHECK(sc.state_of(id) == SCP_REQ_DONE);

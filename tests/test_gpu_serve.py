@@ -211,7 +211,7 @@ def test_cancel_timeout_done_list_and_stats(B):
     assert states == ["done", "cancelled", "done", "done", "done", "cancelled"]
     st = srv.stats()
     assert st["cancelled"] == 2 and st["completed"] == 4 and st["resident"] == 0
-    assert 0 < st["latency_ms_p50"] <= st["latency_ms_p99"] and st["solves_per_s"] > 0
+    assert 0 < st["latency_ms_p50"] <= st["latency_ms_p99"] <= st["latency_ms_p999"] and st["solves_per_s"] > 0
     assert srv.take_done() == []
     # the completed ones equal the same requests served without the cancellations
     ref = _server(B, scp=4, admm=30, max_inflight=1)
