@@ -260,6 +260,128 @@ struct Lanes4 {
     __device__ static constexpr int row(int m, int l) { return m < RB ? 4 * (m / 4) + (l ^ (m % 4)) : m; }
 };
 
+// Per-lane stride, in elements of T, of a lane-private LDS array of n entries read with 16-byte
+// loads: a multiple of 16 bytes whose length in 4-byte words is 4 or 12 modulo 16, so that the
+// 16-byte reads of 16 consecutive lanes start 4 words apart modulo 64 and hit distinct banks.
+template <class T>
+constexpr int lds_lane_stride(int n) {
+    constexpr int step = 16 / (int)sizeof(T);
+    int e = (n + step - 1) / step * step;
+    while ((e * (int)sizeof(T) / 4) % 16 != 4 && (e * (int)sizeof(T) / 4) % 16 != 12) e += step;
+    return e;
+}
+
+// The 6-DOF quadrotor solves Step 1 in FP32 with the explicit inverse M = H^-1 of the node's
+// matrix; FP64 and the other models keep the two triangular substitutions (Sec. III-B Step 1
+// caches a factorization; the inverse is computed from it once per SCP iteration).  At n = 17
+// the product x = M g is 17 broadcasts and 85 multiply-adds per lane in five independent chains,
+// against ~230 instructions in two dependent chains of 17 steps for the substitutions; H is well
+// conditioned here (condition numbers below 60 at the benchmark penalties), where the FP32 error
+// of the product is that of the substitutions.  The lander keeps the substitutions: its rows of
+// M and the LDS copy of A that makes room for them cost more than they save (measured).
+template <class M, class T>
+struct StepInverse {
+    static constexpr bool value = sizeof(T) == 4 && M::ID == SCP_MODEL_QUAD_6DOF;
+};
+
+// The lane's rows of the node's factor (diagonal slot 1/L_kk, 0 above the diagonal) or, with the
+// inverse, its full rows of M (held as the lower triangle, packed like the factor).  ld(t) loads
+// packed entry t.
+template <class LY, class T, class LD>
+__device__ __forceinline__ void lanes4_load_rows(int l, bool inverse, LD&& ld, T (&R)[LY::NS][LY::NN]) {
+#pragma unroll
+    for (int s = 0; s < LY::NS; ++s) {
+        const int row = LY::comp(s, l);
+        const bool ok = LY::held(s, l);
+#pragma unroll
+        for (int j = 0; j < LY::NN; ++j) {
+            if (inverse) R[s][j] = ok ? ld(row >= j ? tri(row, j) : tri(j, row)) : T(0);
+            else if (j <= LY::top(s)) R[s][j] = (ok && j <= row) ? ld(tri(row, j)) : T(0);
+            else R[s][j] = T(0);
+        }
+    }
+}
+
+// L L' x = r on the node held by a group of four lanes (lane l holds rows comp(s, l)).
+//  * forward: y_k comes from its owner by broadcast and every lane updates its rows below k (the
+//    same subtraction sequence as the one-lane solve);
+//  * backward: each lane's products over its rows below k, summed across the group (the same
+//    bits in every lane), and the owner of row k finishes x_k.
+// r is overwritten.
+template <class LY, class T>
+__device__ __forceinline__ void lanes4_chol_solve(T (&r)[LY::NS], const T (&Lr)[LY::NS][LY::NN], int l, T (&xl)[LY::NS]) {
+    constexpr int NS = LY::NS, NN = LY::NN;
+    T yl[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) yl[s] = T(0);
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+        const int sk = LY::slot(k), lk = LY::lane(k);
+        const T yk = quad_bcast(r[sk] * Lr[sk][k], lk);
+        yl[sk] = (l == lk) ? yk : yl[sk];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (LY::top(s) > k) r[s] = r[s] - Lr[s][k] * yk;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xl[s] = T(0);
+#pragma unroll
+    for (int k = NN - 1; k >= 0; --k) {
+        T p = T(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];   // rows not below k hold 0 here
+        // the sum is the same in every lane, so the owner finishes x_k alone
+        const int sk = LY::slot(k), lk = LY::lane(k);
+        const T xk = (yl[sk] - quad_sum(p)) * Lr[sk][k];
+        xl[sk] = (l == lk) ? xk : xl[sk];
+    }
+}
+
+// x = M r: r_k comes from its owner by broadcast and every lane accumulates its rows, in order of k.
+template <class LY, class T>
+__device__ __forceinline__ void lanes4_inv_apply(const T (&r)[LY::NS], const T (&Mr)[LY::NS][LY::NN], T (&xl)[LY::NS]) {
+#pragma unroll
+    for (int s = 0; s < LY::NS; ++s) xl[s] = T(0);
+#pragma unroll
+    for (int k = 0; k < LY::NN; ++k) {
+        const T rk = quad_bcast(r[LY::slot(k)], LY::lane(k));
+#pragma unroll
+        for (int s = 0; s < LY::NS; ++s) xl[s] = xl[s] + Mr[s][k] * rk;
+    }
+}
+
+// M = H^-1 of every node of a 6-DOF model in FP32, column by column (column j solves
+// L L' m = e_j with the factor), written over the factor planes as a packed lower triangle.  Runs
+// after the factorization of every SCP iteration; each group of four lanes loads its node's
+// factor rows before it stores anything, and no other group touches the node.
+template <class M>
+__global__ __launch_bounds__(256) void k_minv_lanes4(Dev<float> dv) {
+    using T = float;
+    using LY = Lanes4<M>;
+    constexpr int NS = LY::NS, NN = LY::NN;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = (int)(gid >> 2), l = (int)(gid & 3);
+    NodeId id;
+    const T* prm;
+    if (node_of<M>(dv, g, id, prm) < 0) return;   // the lanes of a group leave together
+    const int P = dv.P;
+    T Lr[NS][NN];
+    lanes4_load_rows<LY>(l, false, [&](int t) { return dv.planes[(size_t)(PL_L + t) * P + g]; }, Lr);
+#pragma unroll 1
+    for (int j = 0; j < NN; ++j) {
+        T r[NS], x[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s] = (LY::held(s, l) && LY::comp(s, l) == j) ? T(1) : T(0);
+        lanes4_chol_solve<LY>(r, Lr, l, x);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int row = LY::comp(s, l);
+            if (LY::held(s, l) && row >= j) dv.planes[(size_t)(PL_L + tri(row, j)) * P + g] = x[s];
+        }
+    }
+}
+
 template <class M, class T>
 __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) {
     using LY = Lanes4<M>;
@@ -361,47 +483,14 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
         acc[s] = v;
     }
 
-    // owned rows of the factor (diagonal slots hold 1/L_kk); entries above the diagonal are 0
+    // owned rows of the factor (diagonal slots hold 1/L_kk; entries above the diagonal are 0) or of
+    // the inverse, then the solve
+    constexpr bool INV = StepInverse<M, T>::value;
     T Lr[NS][NN];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int row = LY::comp(s, l);
-        const bool ok = LY::held(s, l);
-#pragma unroll
-        for (int j = 0; j < NN; ++j) {
-            if (j <= LY::top(s)) Lr[s][j] = (ok && j <= row) ? at(PL_L + tri(row, j), g) : T(0);
-            else Lr[s][j] = T(0);
-        }
-    }
-
-    // forward substitution L y = g
-    T yl[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) yl[s] = T(0);
-#pragma unroll
-    for (int k = 0; k < NN; ++k) {
-        const int sk = LY::slot(k), lk = LY::lane(k);
-        const T yk = quad_bcast(acc[sk] * Lr[sk][k], lk);
-        yl[sk] = (l == lk) ? yk : yl[sk];
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-            if (LY::top(s) > k) acc[s] = acc[s] - Lr[s][k] * yk;
-    }
-    // backward substitution L' x = y
+    lanes4_load_rows<LY>(l, INV, [&](int t) { return at(PL_L + t, g); }, Lr);
     T xl[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) xl[s] = T(0);
-#pragma unroll
-    for (int k = NN - 1; k >= 0; --k) {
-        T p = T(0);
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-            if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];   // rows not below k hold 0 here
-        // the sum is the same in every lane, so the owner finishes x_k alone
-        const int sk = LY::slot(k), lk = LY::lane(k);
-        const T xk = (yl[sk] - quad_sum(p)) * Lr[sk][k];
-        xl[sk] = (l == lk) ? xk : xl[sk];
-    }
+    if constexpr (INV) lanes4_inv_apply<LY>(acc, Lr, xl);
+    else lanes4_chol_solve<LY>(acc, Lr, l, xl);
 
     // x, u of the owned components (u = 0 at node N), then d_dyn = A x + B u + d
     T q[NX];
@@ -452,11 +541,11 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
 // back to the planes.  Fixed budgets only (no residual test inside).  The lander's sets that
 // couple components (cones, balls, the thrust half-space) are projected by every lane of the node
 // on the components broadcast from their owners; each owner keeps its own component.
-template <class M, class T>
+template <class M, class T, int ROWS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
 void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     using LY = Lanes4<M>;
-    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = LY::NS, MAXN = RESIDENT_MAX_NODES;
+    constexpr int NX = M::NX, NU = M::NU, NN = M::NN, NXR = M::NXR, NS = LY::NS, MAXN = ROWS;
     constexpr int KM = M::KM, KA = KM > 0 ? KM : 1;
     constexpr bool LD = M::ID == SCP_MODEL_LANDER6;
     constexpr bool QP = M::ID == SCP_MODEL_QUAD_PM;      // point-mass quadrotor: control ball
@@ -467,6 +556,13 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     // folds them onto 8 banks, a four-way conflict).
     constexpr int SR = 20;
     __shared__ T sz[MAXN][SR], smu[MAXN][SR], sdd[MAXN][SR];
+    // With the inverse, the lane's columns of A live in LDS instead of registers, which leaves room
+    // for the rows of the inverse at 2 waves per SIMD: row r of every slot at [r][4], so one
+    // 16-byte read serves the four slots, with a lane stride that keeps the reads of 16 lanes in
+    // distinct banks.  The workgroup's row capacity ROWS sizes it.
+    constexpr bool ALDS = StepInverse<M, T>::value;
+    constexpr int SA = lds_lane_stride<T>(4 * NX);
+    __shared__ __attribute__((aligned(16))) T sA[ALDS ? 4 * MAXN : 1][ALDS ? SA : 4];
     const int tr = blockIdx.x;
     if (tr >= dv.n_traj || dv.flags[tr * FL_FIELDS + FL_DONE]) return;   // uniform over the workgroup
     const int* rec = dv.traj + tr * TR_FIELDS;
@@ -507,13 +603,22 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
         mul[s] = ok ? at(PL_MU + r) : T(0);
         g0l[s] = ok ? at(PL_G0 + r) : T(0);
     }
-    T Al[4][NX], Bl[NX];
+    T Al[ALDS ? 1 : 4][NX], Bl[NX];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int k = 4 * s + l;
 #pragma unroll
-        for (int m = 0; m < NX; ++m) Al[s][m] = (k >= 3 && k < NX) ? at(PL_AR + LY::row(m, l) * NXR + (k - 3)) : T(0);
+        for (int m = 0; m < NX; ++m) {
+            const T a = (k >= 3 && k < NX) ? at(PL_AR + LY::row(m, l) * NXR + (k - 3)) : T(0);
+            if constexpr (ALDS) sA[t][4 * m + s] = a;
+            else Al[s][m] = a;
+        }
     }
+    // entry m of the lane's column copy of slot s
+    auto acol = [&](int s, int m) -> T {
+        if constexpr (ALDS) return sA[t][4 * m + s];
+        else return Al[s][m];
+    };
 #pragma unroll
     for (int m = 0; m < NX; ++m) Bl[m] = has_u ? at(PL_B + LY::row(m, l) * NU + cu) : T(0);
     T cpb[NS], dub[NS], lol[NS], hil[NS];
@@ -527,17 +632,9 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
         lol[s] = ok ? at(PL_LO + k) : T(0);
         hil[s] = ok ? at(PL_HI + k) : T(0);
     }
+    constexpr bool INV = StepInverse<M, T>::value;
     T Lr[NS][NN];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int row = LY::comp(s, l);
-        const bool ok = LY::held(s, l);
-#pragma unroll
-        for (int j = 0; j < NN; ++j) {
-            if (j <= LY::top(s)) Lr[s][j] = (ok && j <= row) ? at(PL_L + tri(row, j)) : T(0);
-            else Lr[s][j] = T(0);
-        }
-    }
+    lanes4_load_rows<LY>(l, INV, [&](int t2) { return at(PL_L + t2); }, Lr);
     // quadrotors: half-space j: a_l (l < 3) or b (l = 3); copy and dual of position component l
     T own[KA], cph[KA], duh[KA];
 #pragma unroll
@@ -626,6 +723,16 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
         T w[NX];
 #pragma unroll
         for (int m = 0; m < NX; ++m) w[m] = m < LY::RB ? quad_xor(wl[m / 4], m % 4) : quad_bcast(wl[m / 4], m % 4);
+        // A'w of the four state slots, each summed over the rows in order (rows outermost, so that
+        // one read of A serves the four slots); columns the lane does not hold are 0
+        T txs[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) txs[s] = T(0);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) txs[s] = txs[s] + acol(s, r) * w[r];
+        }
         T acc[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -633,12 +740,7 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             const int s4 = s < 4 ? s : 3;   // state components sit in slots 0..3
             T v = T(0);
             if (s < 4 && k < NX) {
-                T tx = wl[s4];
-                if (k >= 3) {
-                    tx = T(0);
-#pragma unroll
-                    for (int r = 0; r < NX; ++r) tx = tx + Al[s4][r] * w[r];
-                }
+                const T tx = k >= 3 ? txs[s4] : wl[s4];   // unit columns of A: (A'w)_k = w_k
                 v = (g0l[s4] + (rho_eq * zl[s4] - laml[s4])) + tx;
                 v = v + (rho_geo * cpb[s] - dub[s]);
                 if constexpr (M::QL) {
@@ -669,48 +771,20 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             }
             acc[s] = v;
         }
-        T yl[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) yl[s] = T(0);
-#pragma unroll
-        for (int k = 0; k < NN; ++k) {
-            const int sk = LY::slot(k), lk = LY::lane(k);
-            const T yk = quad_bcast(acc[sk] * Lr[sk][k], lk);
-            yl[sk] = (l == lk) ? yk : yl[sk];
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-                if (LY::top(s) > k) acc[s] = acc[s] - Lr[s][k] * yk;
-        }
-#pragma unroll
-        for (int s = 0; s < NS; ++s) xl[s] = T(0);
-#pragma unroll
-        for (int k = NN - 1; k >= 0; --k) {
-            T p = T(0);
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-                if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];
-            // the sum is the same in every lane, so the owner finishes x_k alone
-            const int sk = LY::slot(k), lk = LY::lane(k);
-            const T xk = (yl[sk] - quad_sum(p)) * Lr[sk][k];
-            xl[sk] = (l == lk) ? xk : xl[sk];
-        }
+        if constexpr (INV) lanes4_inv_apply<LY>(acc, Lr, xl);
+        else lanes4_chol_solve<LY>(acc, Lr, l, xl);
+        // A x + B u: every entry gets its terms in slot order (rows outermost, one read of A per
+        // row); a slot the lane does not hold adds 0 * 0
+        if (has_u && last) xl[4] = T(0);
         T q[NX];
 #pragma unroll
         for (int r = 0; r < NX; ++r) q[r] = T(0);
+        q[0] = q[0] + (l < 3 ? xl[0] : T(0));   // unit columns: entry 0 holds row l of slot 0
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int k = 4 * s + l;
-            if (s < 4 && k < NX) {
-                if (s == 0) {
-                    q[0] = q[0] + (k < 3 ? xl[s] : T(0));   // entry 0 holds row l = k
-                }
+        for (int r = 0; r < NX; ++r) {
 #pragma unroll
-                for (int r = 0; r < NX; ++r) q[r] = q[r] + Al[s < 4 ? s : 3][r] * xl[s];
-            } else if (s == 4 && has_u) {
-                if (last) xl[s] = T(0);
-#pragma unroll
-                for (int r = 0; r < NX; ++r) q[r] = q[r] + Bl[r] * xl[s];
-            }
+            for (int s = 0; s < 4; ++s) q[r] = q[r] + acol(s, r) * xl[s];
+            q[r] = q[r] + Bl[r] * xl[4];
         }
         // rows below RB: each lane receives the sums of its own rows; the rest by a sum over the group
 #pragma unroll
@@ -1464,7 +1538,15 @@ hipError_t launch_plain(PlainOp op, const Dev<T>& dv, const KParams<T>& kp, int 
     };
     switch (op) {
         case PlainOp::Lin:
-            each([&](auto m) { hipLaunchKernelGGL((k_lin<decltype(m), T>), gn, b, 0, s, dv, kp); });
+            each([&](auto m) {
+                using MM = decltype(m);
+                hipLaunchKernelGGL((k_lin<MM, T>), gn, b, 0, s, dv, kp);
+                if constexpr (StepInverse<MM, T>::value) {
+                    // Step 1 of these models in FP32 applies the inverse: computed once per SCP iteration
+                    const dim3 g4((unsigned)(((size_t)dv.n_nodes * 4 + 255) / 256));
+                    hipLaunchKernelGGL((k_minv_lanes4<MM>), g4, b, 0, s, dv);
+                }
+            });
             break;
         case PlainOp::Step1:
             each([&](auto m) {
@@ -1517,19 +1599,28 @@ hipError_t launch_resident(const Dev<T>& dv, const KParams<T>& kp, int n_traj, i
                            hipStream_t s) {
     if (n_traj <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || block % 64 != 0 || block > 4 * RESIDENT_MAX_NODES) return hipErrorInvalidValue;
+    // 6-DOF models: workgroups of at most 128 lanes (32 nodes) take the 32-row variant, with less
+    // LDS per workgroup
+    const bool small = block <= 128;
     if (models == 4) {
-        if (kmax <= 4) hipLaunchKernelGGL((k_admm_resident<Quad6<4>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
-        else hipLaunchKernelGGL((k_admm_resident<Quad6<8>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        if (kmax <= 4) {
+            if (small) hipLaunchKernelGGL((k_admm_resident<Quad6<4>, T, 32>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+            else hipLaunchKernelGGL((k_admm_resident<Quad6<4>, T, 64>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        } else {
+            if (small) hipLaunchKernelGGL((k_admm_resident<Quad6<8>, T, 32>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+            else hipLaunchKernelGGL((k_admm_resident<Quad6<8>, T, 64>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        }
     } else if (models == 8) {
-        hipLaunchKernelGGL((k_admm_resident<Lander6, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        if (small) hipLaunchKernelGGL((k_admm_resident<Lander6, T, 32>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_admm_resident<Lander6, T, 64>), dim3(n_traj), dim3(block), 0, s, dv, kp);
     } else if (models >= 1 && models <= 3) {
         // point-mass quadrotor and powered descent in lane groups of four: one launch per model
         // present, each workgroup of the other model returns at once
         if (models & 1) {
-            if (kmax <= 4) hipLaunchKernelGGL((k_admm_resident<Quad<4>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
-            else hipLaunchKernelGGL((k_admm_resident<Quad<8>, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+            if (kmax <= 4) hipLaunchKernelGGL((k_admm_resident<Quad<4>, T, 64>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+            else hipLaunchKernelGGL((k_admm_resident<Quad<8>, T, 64>), dim3(n_traj), dim3(block), 0, s, dv, kp);
         }
-        if (models & 2) hipLaunchKernelGGL((k_admm_resident<Mars, T>), dim3(n_traj), dim3(block), 0, s, dv, kp);
+        if (models & 2) hipLaunchKernelGGL((k_admm_resident<Mars, T, 64>), dim3(n_traj), dim3(block), 0, s, dv, kp);
     } else {
         return hipErrorInvalidValue;   // one 6-DOF model per batch
     }
