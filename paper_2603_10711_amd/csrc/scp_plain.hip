@@ -287,15 +287,15 @@ struct StepInverse {
 // The lane's rows of the node's factor (diagonal slot 1/L_kk, 0 above the diagonal) or, with the
 // inverse, its full rows of M (held as the lower triangle, packed like the factor).  ld(t) loads
 // packed entry t.
-template <class LY, class T, class LD>
-__device__ __forceinline__ void lanes4_load_rows(int l, bool inverse, LD&& ld, T (&R)[LY::NS][LY::NN]) {
+template <bool INVERSE, class LY, class T, class LD>
+__device__ __forceinline__ void lanes4_load_rows(int l, LD&& ld, T (&R)[LY::NS][LY::NN]) {
 #pragma unroll
     for (int s = 0; s < LY::NS; ++s) {
         const int row = LY::comp(s, l);
         const bool ok = LY::held(s, l);
 #pragma unroll
         for (int j = 0; j < LY::NN; ++j) {
-            if (inverse) R[s][j] = ok ? ld(row >= j ? tri(row, j) : tri(j, row)) : T(0);
+            if constexpr (INVERSE) R[s][j] = ok ? ld(row >= j ? tri(row, j) : tri(j, row)) : T(0);
             else if (j <= LY::top(s)) R[s][j] = (ok && j <= row) ? ld(tri(row, j)) : T(0);
             else R[s][j] = T(0);
         }
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_minv_lanes4(Dev<float> dv) {
     if (node_of<M>(dv, g, id, prm) < 0) return;   // the lanes of a group leave together
     const int P = dv.P;
     T Lr[NS][NN];
-    lanes4_load_rows<LY>(l, false, [&](int t) { return dv.planes[(size_t)(PL_L + t) * P + g]; }, Lr);
+    lanes4_load_rows<false, LY>(l, [&](int t) { return dv.planes[(size_t)(PL_L + t) * P + g]; }, Lr);
 #pragma unroll 1
     for (int j = 0; j < NN; ++j) {
         T r[NS], x[NS];
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(256) void k_step1_lanes4(Dev<T> dv, KParams<T> kp) 
     // the inverse, then the solve
     constexpr bool INV = StepInverse<M, T>::value;
     T Lr[NS][NN];
-    lanes4_load_rows<LY>(l, INV, [&](int t) { return at(PL_L + t, g); }, Lr);
+    lanes4_load_rows<INV, LY>(l, [&](int t) { return at(PL_L + t, g); }, Lr);
     T xl[NS];
     if constexpr (INV) lanes4_inv_apply<LY>(acc, Lr, xl);
     else lanes4_chol_solve<LY>(acc, Lr, l, xl);
@@ -634,7 +634,23 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
     }
     constexpr bool INV = StepInverse<M, T>::value;
     T Lr[NS][NN];
-    lanes4_load_rows<LY>(l, INV, [&](int t2) { return at(PL_L + t2); }, Lr);
+    // (the factor's rows and its solve below are written out here rather than through the
+    // helpers of k_step1_lanes4: with the helpers the compiler allocates ~30 more registers for
+    // the point-mass variants and spills 8 bytes per lane for the lander; the arithmetic is the same)
+    if constexpr (INV) {
+        lanes4_load_rows<true, LY>(l, [&](int t2) { return at(PL_L + t2); }, Lr);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int row = LY::comp(s, l);
+            const bool ok = LY::held(s, l);
+#pragma unroll
+            for (int j = 0; j < NN; ++j) {
+                if (j <= LY::top(s)) Lr[s][j] = (ok && j <= row) ? at(PL_L + tri(row, j)) : T(0);
+                else Lr[s][j] = T(0);
+            }
+        }
+    }
     // quadrotors: half-space j: a_l (l < 3) or b (l = 3); copy and dual of position component l
     T own[KA], cph[KA], duh[KA];
 #pragma unroll
@@ -723,15 +739,18 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
         T w[NX];
 #pragma unroll
         for (int m = 0; m < NX; ++m) w[m] = m < LY::RB ? quad_xor(wl[m / 4], m % 4) : quad_bcast(wl[m / 4], m % 4);
-        // A'w of the four state slots, each summed over the rows in order (rows outermost, so that
-        // one read of A serves the four slots); columns the lane does not hold are 0
+        // With A in LDS: A'w of the four state slots first, each summed over the rows in order (rows
+        // outermost, so that one read of A serves the four slots; columns the lane does not hold
+        // are 0).  With A in registers each slot sums its own rows below, as the plain kernel does.
         T txs[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) txs[s] = T(0);
+        if constexpr (ALDS) {
 #pragma unroll
-        for (int r = 0; r < NX; ++r) {
+            for (int r = 0; r < NX; ++r) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) txs[s] = txs[s] + acol(s, r) * w[r];
+                for (int s = 0; s < 4; ++s) txs[s] = txs[s] + acol(s, r) * w[r];
+            }
         }
         T acc[NS];
 #pragma unroll
@@ -740,7 +759,16 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             const int s4 = s < 4 ? s : 3;   // state components sit in slots 0..3
             T v = T(0);
             if (s < 4 && k < NX) {
-                const T tx = k >= 3 ? txs[s4] : wl[s4];   // unit columns of A: (A'w)_k = w_k
+                T tx = wl[s4];   // unit columns of A: (A'w)_k = w_k
+                if (k >= 3) {
+                    if constexpr (ALDS) {
+                        tx = txs[s4];
+                    } else {
+                        tx = T(0);
+#pragma unroll
+                        for (int r = 0; r < NX; ++r) tx = tx + acol(s4, r) * w[r];
+                    }
+                }
                 v = (g0l[s4] + (rho_eq * zl[s4] - laml[s4])) + tx;
                 v = v + (rho_geo * cpb[s] - dub[s]);
                 if constexpr (M::QL) {
@@ -771,20 +799,65 @@ void k_admm_resident(Dev<T> dv, KParams<T> kp) {
             }
             acc[s] = v;
         }
-        if constexpr (INV) lanes4_inv_apply<LY>(acc, Lr, xl);
-        else lanes4_chol_solve<LY>(acc, Lr, l, xl);
-        // A x + B u: every entry gets its terms in slot order (rows outermost, one read of A per
-        // row); a slot the lane does not hold adds 0 * 0
-        if (has_u && last) xl[4] = T(0);
+        if constexpr (INV) {
+            lanes4_inv_apply<LY>(acc, Lr, xl);
+        } else {
+            // the steps of lanes4_chol_solve
+            T yl[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) yl[s] = T(0);
+#pragma unroll
+            for (int k = 0; k < NN; ++k) {
+                const int sk = LY::slot(k), lk = LY::lane(k);
+                const T yk = quad_bcast(acc[sk] * Lr[sk][k], lk);
+                yl[sk] = (l == lk) ? yk : yl[sk];
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (LY::top(s) > k) acc[s] = acc[s] - Lr[s][k] * yk;
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) xl[s] = T(0);
+#pragma unroll
+            for (int k = NN - 1; k >= 0; --k) {
+                T p = T(0);
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (LY::top(s) > k) p = p + Lr[s][k] * xl[s];
+                const int sk = LY::slot(k), lk = LY::lane(k);
+                const T xk = (yl[sk] - quad_sum(p)) * Lr[sk][k];
+                xl[sk] = (l == lk) ? xk : xl[sk];
+            }
+        }
+        // A x + B u: every entry gets its terms in slot order
         T q[NX];
 #pragma unroll
         for (int r = 0; r < NX; ++r) q[r] = T(0);
-        q[0] = q[0] + (l < 3 ? xl[0] : T(0));   // unit columns: entry 0 holds row l of slot 0
+        if constexpr (ALDS) {
+            // rows outermost, one read of A per row; a slot the lane does not hold adds 0 * 0
+            if (has_u && last) xl[4] = T(0);
+            q[0] = q[0] + (l < 3 ? xl[0] : T(0));   // unit columns: entry 0 holds row l of slot 0
 #pragma unroll
-        for (int r = 0; r < NX; ++r) {
+            for (int r = 0; r < NX; ++r) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) q[r] = q[r] + acol(s, r) * xl[s];
-            q[r] = q[r] + Bl[r] * xl[4];
+                for (int s = 0; s < 4; ++s) q[r] = q[r] + acol(s, r) * xl[s];
+                q[r] = q[r] + Bl[r] * xl[4];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int k = 4 * s + l;
+                if (s < 4 && k < NX) {
+                    if (s == 0) {
+                        q[0] = q[0] + (k < 3 ? xl[s] : T(0));   // entry 0 holds row l = k
+                    }
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) q[r] = q[r] + acol(s < 4 ? s : 3, r) * xl[s];
+                } else if (s == 4 && has_u) {
+                    if (last) xl[s] = T(0);
+#pragma unroll
+                    for (int r = 0; r < NX; ++r) q[r] = q[r] + Bl[r] * xl[s];
+                }
+            }
         }
         // rows below RB: each lane receives the sums of its own rows; the rest by a sum over the group
 #pragma unroll
