@@ -103,7 +103,7 @@ def pmc_plain(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, sc
     kf, kw = per_kernel(fetch_dir), per_kernel(write_dir)
     admm = scp_iters * admm_iters
     count = {"k_step1": admm, "k_step1_lanes4": admm, "k_step234": admm, "k_admm_resident": scp_iters,
-             "k_resid": scp_iters, "k_lin": scp_iters,
+             "k_resid": scp_iters, "k_lin": scp_iters, "k_minv_lanes4": scp_iters,
              "k_acc_nodes": scp_iters, "k_acc_traj": scp_iters, "k_acc_apply": scp_iters, "k_check": scp_iters,
              "k_reset": 2, "k_reset_state": 1, "k_met_nodes": 1, "k_met_traj": 1}
     kernels = {}
@@ -145,8 +145,9 @@ def sq(dirpath: str, title: str, iters: int, out: str, cmd: str, kernel: str = "
     lines = [f"# rocprofv3 SQ counters of {kernel}, {title}", "", f"Command: `{cmd}`", "",
              f"Kernel sources hash: `{kernel_source_hash()}`", "", "| counter | per dispatch | per wave |", "|---|---|---|"]
     for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_SALU",
-              "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_LDS_IDX_ACTIVE",
-              "SQ_LDS_BANK_CONFLICT"):
+              "SQ_INSTS_LDS", "SQ_INSTS_BRANCH", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_LDS",
+              "SQ_ACTIVE_INST_MISC", "SQ_ACTIVE_INST_ANY", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS",
+              "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT"):
         if c in val:
             lines.append(f"| {c} | {val[c]:.4g} | {val[c] / waves:.4g} |")
     valu = val["SQ_INSTS_VALU"] / waves
@@ -159,6 +160,13 @@ def sq(dirpath: str, title: str, iters: int, out: str, cmd: str, kernel: str = "
         if fma in val:
             lines.append(f"{fma} per wave per ADMM iteration: {val[fma] / waves / iters:.0f} "
                          f"({val[fma] / val['SQ_INSTS_VALU']:.3f} of the VALU instructions).")
+    parts = [("VALU", "SQ_ACTIVE_INST_VALU"), ("scalar ALU", "SQ_ACTIVE_INST_SCA"), ("LDS", "SQ_ACTIVE_INST_LDS"),
+             ("branch and other", "SQ_ACTIVE_INST_MISC"), ("waiting", "SQ_WAIT_ANY")]
+    if all(c in val for _, c in parts):
+        per = [(n, val[c] / waves / iters) for n, c in parts]
+        lines.append("Where a wave's quad-cycles go per ADMM iteration (issuing, by instruction kind, then waiting; "
+                     f"SQ_WAVE_CYCLES {val['SQ_WAVE_CYCLES'] / waves / iters:.0f}): "
+                     + ", ".join(f"{n} {v:.1f}" for n, v in per) + ".")
     if "SQ_LDS_BANK_CONFLICT" in val and val.get("SQ_LDS_IDX_ACTIVE", 0) > 0:
         lines.append(f"LDS bank conflicts: {val['SQ_LDS_BANK_CONFLICT'] / val['SQ_LDS_IDX_ACTIVE']:.4f} of the "
                      "LDS indexed-active cycles (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE).")
