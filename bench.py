@@ -379,7 +379,11 @@ def serve_main(a, wl, cpu):
     ids = [srv.submit(prepared[s], session=s) for s in range(4)]
     srv.drain(ids)
     times, sess = SL.arrivals(a.rate, a.duration, n_sess)
-    served = SL.run_served(srv, prepared, times, sess)
+    if a.jsonl:
+        with open(a.jsonl, "w") as log:
+            served = SL.run_served(srv, prepared, times, sess, log=log)
+    else:
+        served = SL.run_served(srv, prepared, times, sess)
     print(f"[serve] served {served}", file=sys.stderr, flush=True)
     # capacity: requests of the same shapes all queued at once, without sessions (a session's
     # requests run one after the other, so queued session requests would measure that order)
@@ -730,6 +734,7 @@ def main(argv=None):
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: offered requests/s")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
+    ap.add_argument("--jsonl", default="", help="serve: write one JSON record per served request to this file")
     ap.add_argument("--budget-mb", type=float, default=0.0, help="serve: HBM admission budget (0 = 64 GB)")
     ap.add_argument("--capacity-requests", type=int, default=2000)
     ap.add_argument("--sched-steps", type=int, default=5, help="steps of the fixed-budget and schedule legs")

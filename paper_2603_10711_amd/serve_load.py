@@ -15,6 +15,7 @@ Latency = completion observed by the client minus arrival time.
 """
 from __future__ import annotations
 
+import json
 import sys
 import time
 
@@ -45,8 +46,11 @@ def _pcts(lat: list[float]) -> dict:
                 mean=round(float(a.mean()), 3), max=round(float(a.max()), 3))
 
 
-def run_served(srv, prepared: list, times, sess, progress: float = 5.0, drain_s: float = 30.0) -> dict:
-    """Drive the server with the arrival trace.  prepared[s] = srv.prepare(request of session s)."""
+def run_served(srv, prepared: list, times, sess, progress: float = 5.0, drain_s: float = 30.0, log=None) -> dict:
+    """Drive the server with the arrival trace.  prepared[s] = srv.prepare(request of session s).
+    log: a text file that receives one JSON record per ended request (id, session, arrival and
+    observed completion in seconds from the start, latency, worst defect over the request's
+    trajectories, the OR of their status bits, whether all converged)."""
     n = len(times)
     lat, defect, conv, failed = [], [], 0, 0
     outstanding = {}
@@ -60,7 +64,7 @@ def run_served(srv, prepared: list, times, sess, progress: float = 5.0, drain_s:
             break
         while i < n and times[i] <= now:
             rid = srv.submit(prepared[int(sess[i])], session=int(sess[i]))
-            outstanding[rid] = times[i]
+            outstanding[rid] = (times[i], int(sess[i]))
             i += 1
         srv.step(wait=False)
         ended = srv.take_done()
@@ -68,13 +72,18 @@ def run_served(srv, prepared: list, times, sess, progress: float = 5.0, drain_s:
             t_obs = time.perf_counter() - t0
             for rid in ended:
                 r = srv.poll(rid)
-                arr = outstanding.pop(rid)
+                arr, ses = outstanding.pop(rid)
                 lat.append((t_obs - arr) * 1e3)
                 info = r[1]
                 defect.append(float(info[:, 6].max()))
                 st = info[:, 5].astype(np.int64)
                 conv += int(np.all(st & 8))
                 failed += int(np.any(st & (1 | 2 | 4 | 16)))   # non-finite, pivot, empty set, group barrier
+                if log is not None:
+                    log.write(json.dumps(dict(id=int(rid), session=ses, arrival_s=round(float(arr), 6),
+                                              done_s=round(t_obs, 6), latency_ms=round(lat[-1], 3),
+                                              max_defect=defect[-1], status=int(np.bitwise_or.reduce(st)),
+                                              converged=bool(np.all(st & 8)))) + "\n")
         if progress and now - last_print > progress:
             last_print = now
             print(f"[serve] t={now:.1f}s submitted={i}/{n} outstanding={len(outstanding)} done={len(lat)}",

@@ -233,3 +233,28 @@ def test_cancel_timeout_done_list_and_stats(B):
     st = slow.stats()
     assert st["timed_out"] == 3 and st["resident"] == 0
     slow.close()
+
+
+def test_served_trace_writes_one_record_per_request(B, tmp_path):
+    """The load generator's per-request JSON lines: one per served request of a short Poisson
+    trace, with the fields the summary is computed from."""
+    import json
+    from paper_2603_10711_amd import serve_load as SL
+    n_sess = 6
+    reqs = [scpgen.config4_request(90 + k, S=4, N=20) for k in range(n_sess)]
+    srv = _server(B, "f32")
+    prepared = [srv.prepare(r) for r in reqs]
+    times, sess = SL.arrivals(400.0, 0.05, n_sess)
+    path = tmp_path / "served.jsonl"
+    with open(path, "w") as log:
+        out = SL.run_served(srv, prepared, times, sess, progress=0.0, log=log)
+    srv.close()
+    recs = [json.loads(line) for line in open(path)]
+    _say(out, recs[:2])
+    assert out["completed"] == len(times) == len(recs) and out["unfinished"] == 0
+    assert len({r["id"] for r in recs}) == len(recs)
+    for r in recs:
+        assert r["latency_ms"] > 0 and r["done_s"] >= r["arrival_s"] and 0 <= r["session"] < n_sess
+        assert r["status"] & (1 | 2 | 4 | 16) == 0
+    lat = sorted(r["latency_ms"] for r in recs)
+    assert abs(np.median(lat) - out["latency_ms"]["p50"]) <= 1e-2 * max(1.0, out["latency_ms"]["p50"])
