@@ -2,6 +2,7 @@
 
 Quadrotor batch: 1024 instances, N = 50, 8 obstacles, 15 SCP x 200 ADMM, FP32, persistent form.
 Powered descent: 4096 instances, N = 60, 15 x 200, FP32.
+Uneven mix: 2048 instances, N ~ U{20..120}, residual stop 1e-4 every 25 iterations, 15 x 200 caps.
 * sampled instances after the first SCP iteration of the full batch: FP32 vs oracle at 1e-4;
 * sampled instances in FP64 mode vs oracle: 1e-9 after 5 SCP iterations, a fixed 1e-6 at the full
   budget (the SCP map amplifies rounding-order differences; measured on the oracle itself);
@@ -140,4 +141,35 @@ def test_mars_full_batch(B):
     worst = compare(prob, f, sample, trajs, idx=idx)
     print(worst, flush=True)
     assert max(worst.values()) < 1e-4
+    prob.close()
+
+
+def test_mix_full_batch_fp64_samples(B):
+    """The uneven mix at full size (2048 instances, half quadrotor and half powered descent, N ~
+    U{20..120}) in the benchmark's launch configuration (128 lanes, aligned, residual test every 25
+    iterations at 1e-4, caps 15 x 200), FP64 mode.  Sampled instances (the longest quadrotor and
+    powered descent, the shortest, two that straddle a wavefront and the two that stop earliest)
+    against the oracle with the same stopping rule: identical ADMM iteration counts, iterates at
+    the fixed full-budget bar."""
+    insts = scpgen.config3(2048)
+    print("mix 2048 fp64 persistent 15 x 200, block 128 aligned, check 25 at 1e-4", flush=True)
+    prob = B.Problem(insts, precision="f64", block=128, pack=B.PACK_ALIGNED)
+    prob.solve(B.scp_params(15, 200, check_every=25, eps=1e-4))
+    f = gpu_fields(prob)
+    info = prob.info_dicts(prob.result()[2].cpu().numpy())
+    iters = np.array([d["admm_iters"] for d in info])
+    Ns = np.array([d["N"] for d in insts])
+    models = np.array([d["model"] for d in insts])
+    idx = [int(np.argmax(np.where(models == 1, Ns, -1))), int(np.argmax(np.where(models == 2, Ns, -1))),
+           int(np.argmin(Ns))]
+    idx += [i for i in range(len(insts)) if 64 < Ns[i] + 1 < 70][:2]
+    idx += [int(i) for i in np.argsort(iters, kind="stable")[:2]]
+    idx = list(dict.fromkeys(idx))
+    sample = [insts[i] for i in idx]
+    print("sample", idx, Ns[idx].tolist(), iters[idx].tolist(), flush=True)
+    trajs, oinfo = oracle_scp(sample, 15, 200, check_every=25, eps_p=1e-4, eps_d=1e-4)
+    assert [o["admm_iters"] for o in oinfo] == iters[idx].tolist()
+    worst = compare(prob, f, sample, trajs, idx=idx)
+    print(worst, flush=True)
+    assert max(worst.values()) < TOL64_FULL
     prob.close()
