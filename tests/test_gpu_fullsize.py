@@ -173,3 +173,20 @@ def test_mix_full_batch_fp64_samples(B):
     print(worst, flush=True)
     assert max(worst.values()) < TOL64_FULL
     prob.close()
+
+
+def test_mars_full_budget_fp64_samples(B):
+    """The powered-descent batch at full size and full budget (4096 instances, 15 x 200) in FP64
+    mode, sampled instances against the oracle at the fixed full-budget bar."""
+    insts = scpgen.config2(4096)
+    print("mars 4096 x 61 fp64 persistent 15 x 200", flush=True)
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(15, 200))
+    f = gpu_fields(prob)
+    idx = [0, 2047, 4095]
+    sample = [insts[i] for i in idx]
+    trajs, _ = oracle_scp(sample, 15, 200)
+    worst = compare(prob, f, sample, trajs, idx=idx)
+    print(worst, flush=True)
+    assert max(worst.values()) < TOL64_FULL
+    prob.close()
