@@ -295,8 +295,9 @@ void scp_problem_destroy(scp_problem* p);
 /* Steps a2-a4 at the current nominal (Sec. III-A; Sec. III-B Step 1 factorization):
  * RK4 linearization with exact Jacobians, convexified constraint sets (trust box with the
  * current radius, boundary equalities, obstacle half-spaces), Step-1 Hessians and their
- * unpivoted Cholesky factors, and re-initialization of the ADMM primal state from the
- * nominal (duals are carried).  Uses rho from the last admm_params given to admm_solve or
+ * unpivoted Cholesky factors (for the 6-DOF quadrotor in FP32, then the inverse of each
+ * Hessian computed from its factor, which Step 1 multiplies by), and re-initialization of the
+ * ADMM primal state from the nominal (duals are carried).  Uses rho from the last admm_params given to admm_solve or
  * scp_solve, or rho = 1 before any.  Async on the handle's stream. */
 scp_status scp_linearize(scp_problem* p, const admm_params* prm);
 
