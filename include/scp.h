@@ -71,10 +71,11 @@ typedef enum {
     SCP_FORM_PLAIN = 0,       /* state in HBM; host-enqueued kernels per ADMM iteration       */
     SCP_FORM_PERSISTENT = 1   /* one kernel per SCP iteration (or per solve); every node's
                                  factor and ADMM state stay in registers/LDS.  For a batch of
-                                 6-DOF quadrotors alone (at most 64 nodes per trajectory, no
-                                 consensus groups, check_every = 0): linearization and
-                                 acceptance as in the plain form, the ADMM iterations of each
-                                 SCP iteration resident in one workgroup per trajectory     */
+                                 one 6-DOF model alone (at most 64 nodes per trajectory, no
+                                 consensus groups, check_every = 0), and for lanes_per_node =
+                                 4: linearization and acceptance as in the plain form, the
+                                 ADMM iterations of each SCP iteration resident in one
+                                 workgroup per trajectory, four lanes per node              */
 } scp_form;
 
 typedef enum { SCP_PACK_ALIGNED = 0, SCP_PACK_DENSE = 1 } scp_pack;
