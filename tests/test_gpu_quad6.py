@@ -223,9 +223,14 @@ def test_zero_quaternion_is_flagged_and_contained(B):
     prob.close()
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_resident_and_plain_forms_agree_bitwise(B, prec):
-    insts = scpgen.config5(160)
+def _short_batch():
+    # at most 32 nodes per trajectory: the resident kernel's 32-row variant (128-lane workgroups)
+    return [scpgen.quad6_benchmark_instance(80 + i, N=5 + (7 * i) % 27) for i in range(40)]
+
+
+@pytest.mark.parametrize("prec,batch", [("f32", "bench"), ("f64", "bench"), ("f32", "short")])
+def test_resident_and_plain_forms_agree_bitwise(B, prec, batch):
+    insts = scpgen.config5(160) if batch == "bench" else _short_batch()
     prm = dict(**SCHED)
     out = {}
     for form in ("plain", "persistent"):
@@ -280,3 +285,17 @@ def test_persistent_form_limits_and_server_refuse(B):
             srv.submit(insts, session=-1)
     finally:
         srv.close()
+
+
+def test_resident_short_horizons_fp32_match_oracle(B):
+    """The 32-row resident variant in FP32 (Step 1 through the inverse, A in LDS) against the
+    oracle at the FP32 bar, on a few SCP iterations."""
+    insts = _short_batch()[:8]
+    prob = B.Problem(insts, precision="f32")
+    prob.solve(B.scp_params(2, 30, form="persistent", **SCHED))
+    f = _fields(prob)
+    trajs, _ = oracle_scp(insts, 2, 30, **OSCHED)
+    worst = compare(prob, f, insts, trajs)
+    _say("resident short fp32", worst)
+    assert max(worst.values()) < TOL32
+    prob.close()
