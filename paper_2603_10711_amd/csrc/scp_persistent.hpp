@@ -92,9 +92,31 @@ __device__ __forceinline__ T gx_read(const T* p) {
 // SCP_ST_SYNC, so a member that never had to wait (it found the counter already past its
 // target) is flagged too.  nbar counts the group barriers this workgroup has passed in this
 // launch; rows of barrier b live in buffer b & 1.
-template <class T, int BLOCK, int HSR, int LR, int AR>
+// Gather: after the barrier the whole workgroup copies the first W values of every member row
+// into LDS (gx_at), every thread issuing all of its loads before it waits for any, so the group
+// pays one memory latency instead of one per member and value (a reader summing S rows straight
+// from HBM waits S x W times).  All GX_MEMBERS rows are copied (rows past the group's size are
+// never read), so the count is the same in every thread.  A spanning workgroup holds one group
+// and never uses the in-workgroup consensus array ucp, which holds the copy.
+// Columns of a member row that hold node-0 u copies (the u box, then the ball's or the SOC's).
+template <class M>
+__device__ __forceinline__ constexpr int u_copy_cols() {
+    int w = 0;
+    for (int q = 0; q < M::C; ++q)
+        if (slot_is_u<M>(q) && slot_comp_u<M>(q) + 1 > w) w = slot_comp_u<M>(q) + 1;
+    return w;
+}
+
+template <int W, class T, int BLOCK, int HSR, int LR, int AR>
+__device__ __forceinline__ T& gx_at(Shared<T, BLOCK, HSR, LR, AR>& sh, const int m, const int k) {
+    const int f = m * W + k;
+    return sh.ucp[f / BLOCK][f % BLOCK];
+}
+
+template <int W, class T, int BLOCK, int HSR, int LR, int AR>
 __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR, LR, AR>& sh, const Span& sp, unsigned& nbar,
                                            const int t, const unsigned long long spin) {
+    static_assert(W >= 1 && W <= GX_WIDTH && GX_MEMBERS * W <= 8 * BLOCK, "gather does not fit ucp");
     __syncthreads();
     if (t < 64) {
         for (int j = t; j < BLOCK; j += 64) {
@@ -127,6 +149,19 @@ __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HS
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    constexpr int NPER = (GX_MEMBERS * W + BLOCK - 1) / BLOCK;
+    T v[NPER];
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+        const int f = t + i * BLOCK;
+        v[i] = f < GX_MEMBERS * W ? gx_read(gx_row(dv, sp, nbar - 1u, f / W) + f % W) : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+        const int f = t + i * BLOCK;
+        if (f < GX_MEMBERS * W) sh.ucp[f / BLOCK][f % BLOCK] = v[i];
     }
     __syncthreads();
 }
@@ -290,21 +325,19 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         }
         if (span.on) {
             const bool g0 = valid && id.first();
-            const unsigned b = nbar;
             if (g0) {
 #pragma unroll
                 for (int r = 0; r < NU; ++r) sh.gxw[r][t] = ubar[r];
                 sh.gxm[t] = mem;
             }
-            group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
+            group_sync<NU>(dv, sh, span, nbar, t, kp.spin_ticks);
             if (g0) {
                 T acc[NU];
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc[r] = T(0);
                 for (int m = 0; m < S; ++m) {
-                    const T* row = gx_row(dv, span, b, m);
 #pragma unroll
-                    for (int r = 0; r < NU; ++r) acc[r] = acc[r] + gx_read(row + r);
+                    for (int r = 0; r < NU; ++r) acc[r] = acc[r] + gx_at<NU>(sh, m, r);
                 }
 #pragma unroll
                 for (int r = 0; r < NU; ++r) uc[r] = acc[r] / T(S);
@@ -445,20 +478,20 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             if (span.on) {
                 // scenario consensus across workgroups
                 const bool g0 = !done && id.first();
-                const unsigned b = nbar;
                 if (g0) {
 #pragma unroll
                     for (int q = 0; q < C; ++q)
                         if (slot_is_u<M>(q)) sh.gxw[slot_comp_u<M>(q)][t] = s.cp[q];
                     sh.gxm[t] = mem;
                 }
-                group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
+                constexpr int UW = u_copy_cols<M>();
+                group_sync<UW>(dv, sh, span, nbar, t, kp.spin_ticks);
                 if (g0) {
 #pragma unroll
                     for (int q = 0; q < C; ++q) {
                         if (!slot_is_u<M>(q)) continue;
                         T acc = T(0);
-                        for (int m = 0; m < S; ++m) acc = acc + gx_read(gx_row(dv, span, b, m) + slot_comp_u<M>(q));
+                        for (int m = 0; m < S; ++m) acc = acc + gx_at<UW>(sh, m, slot_comp_u<M>(q));
                         s.cp[q] = group_active<M>(id, slot_group<M>(q)) ? acc / T(S) : T(0);
                     }
                 }
@@ -551,7 +584,6 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                     }
                 } else {
                     // member maxima to HBM; the group maximum is the same in every workgroup
-                    const unsigned b = nbar;
                     if (!done && leader) {
                         sh.gxw[0][t] = T(bits_res(sh.mx[0][tb]));
                         sh.gxw[1][t] = T(bits_res(sh.mx[1][tb]));
@@ -559,13 +591,12 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                         sh.mx[0][tb] = 0ull;
                         sh.mx[1][tb] = 0ull;
                     }
-                    group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
+                    group_sync<2>(dv, sh, span, nbar, t, kp.spin_ticks);
                     if (!done && leader) {
                         T grp = T(0), grd = T(0);
                         for (int m = 0; m < S; ++m) {
-                            const T* row = gx_row(dv, span, b, m);
-                            grp = nmax(grp, gx_read(row));
-                            grd = nmax(grd, gx_read(row + 1));
+                            grp = nmax(grp, gx_at<2>(sh, m, 0));
+                            grd = nmax(grd, gx_at<2>(sh, m, 1));
                         }
                         sh.flag[lb] = (test && grp <= kp.eps_p && grd <= kp.eps_d) ? 1 : 0;
                         sh.red[0][lb] = grp;
@@ -672,14 +703,12 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
             }
         }
         if (span.on) {
-            const unsigned b = nbar;
-            group_sync(dv, sh, span, nbar, t, kp.spin_ticks);
+            group_sync<3>(dv, sh, span, nbar, t, kp.spin_ticks);
             if (leader) {
                 for (int m = 0; m < S; ++m) {
-                    const T* row = gx_row(dv, span, b, m);
-                    mnom = mnom + gx_read(row);
-                    mnew = mnew + gx_read(row + 1);
-                    mmod = mmod + gx_read(row + 2);
+                    mnom = mnom + gx_at<3>(sh, m, 0);
+                    mnew = mnew + gx_at<3>(sh, m, 1);
+                    mmod = mmod + gx_at<3>(sh, m, 2);
                 }
             }
         }
