@@ -1,14 +1,22 @@
-"""Write the oracle's converged solutions of the quadrotor batch (expected values for the GPU test
-of the converged-solution bar).
+"""Write the oracle's converged solutions of a batch (expected values for the GPU tests of the
+converged-solution bar).
 
-    python tests/golden/make_converged.py [--workers W]
+    python tests/golden/make_converged.py [--workload quad1024|quad6_1000] [--workers W] [--count C]
 
-Calls only the oracle (FP64 NumPy): the 1024 point-mass quadrotor instances of the batch workload
-(N = 50, 8 obstacles, seeded generator) solved with the geometric penalty schedule of the paper's
-parameter study (Sec. IV-A.2: one rho for all three penalties, grown geometrically over the SCP
-iterations to a final value), here from 5 to 1e4 over 18 SCP iterations of 290 ADMM iterations each
-(the headline setting of the benchmark), fixed trust radius, always-accept steps.  For every instance it stores the final cost, max
-dynamics defect, max constraint violation and boundary error of the returned nominal.
+Calls only the oracle (FP64 NumPy), with the geometric penalty schedule of the paper's parameter
+study (Sec. IV-A.2: one rho for all three penalties, grown geometrically over the SCP iterations to
+a final value):
+
+* quad1024: the 1024 point-mass quadrotor instances of the batch workload (N = 50, 8 obstacles,
+  seeded generator), rho 5 -> 1e4 over 18 SCP iterations of 290 ADMM iterations each (the headline
+  setting of the benchmark), fixed trust radius, always-accept steps;
+* quad6_1000: the first C (default 256) of the 1000 6-DOF quadrotor instances of the scalability
+  batch (Sec. IV-A.3: N = 40, three obstacles, noise-initialized), rho 10 -> 3e4 over 50 SCP
+  iterations of 300 ADMM iterations each, with the trust-region ratio test of the SCP step (accept
+  when the ratio is positive, radius halved below 0.25, doubled above 0.75 up to 4).
+
+For every instance it stores the final cost, max dynamics defect, max constraint violation and
+boundary error of the returned nominal.
 """
 import argparse
 import json
@@ -24,36 +32,52 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-SETTING = dict(scp_iters=18, admm_iters=290, rho=5.0, rho_final=1e4)
-OUT = os.path.join(HERE, "quad1024_converged.json")
+WORKLOADS = {
+    "quad1024": dict(setting=dict(scp_iters=18, admm_iters=290, rho=5.0, rho_final=1e4), count=1024,
+                     what="oracle (FP64) solutions of the point-mass quadrotor batch, 1024 x N=50, 8 obstacles"),
+    "quad6_1000": dict(setting=dict(scp_iters=50, admm_iters=300, rho=10.0, rho_final=3e4, eta0=0.0, eta1=0.25,
+                                    eta2=0.75, shrink=0.5, grow=2.0, delta_max=4.0), count=256,
+                       what="oracle (FP64) solutions of the first instances of the 6-DOF quadrotor batch, "
+                            "1000 x N=40, 3 obstacles"),
+}
 
 
-def _solve(i):
-    import oracle
+def _instance(workload, i):
     import scpgen
-    d = scpgen.config1(i + 1)[i]
-    p = oracle.default_params(scp_iters=SETTING["scp_iters"], admm_iters=SETTING["admm_iters"],
-                              rho_eq=SETTING["rho"], rho_dyn=SETTING["rho"], rho_geo=SETTING["rho"],
-                              rho_final=SETTING["rho_final"])
-    _, infos = oracle.scp_solve([d], p)
+    if workload == "quad1024":
+        return scpgen.config1(i + 1)[i]
+    return scpgen.config5(1, first=i)[0]
+
+
+def _solve(args):
+    workload, i = args
+    import oracle
+    s = dict(WORKLOADS[workload]["setting"])
+    rho = s.pop("rho")
+    p = oracle.default_params(rho_eq=rho, rho_dyn=rho, rho_geo=rho, **s)
+    _, infos = oracle.scp_solve([_instance(workload, i)], p)
     f = infos[0]
     return i, dict(cost=f["cost"], defect=f["defect"], viol=f["viol"], bnd_err=f["bnd_err"])
 
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="quad1024", choices=sorted(WORKLOADS))
     ap.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
-    ap.add_argument("--count", type=int, default=1024)
+    ap.add_argument("--count", type=int, default=0)
     a = ap.parse_args()
+    w = WORKLOADS[a.workload]
+    count = a.count or w["count"]
     t0 = time.time()
-    rows = [None] * a.count
+    rows = [None] * count
     with mp.get_context("fork").Pool(a.workers) as pool:
-        for k, (i, r) in enumerate(pool.imap_unordered(_solve, range(a.count))):
+        for k, (i, r) in enumerate(pool.imap_unordered(_solve, [(a.workload, i) for i in range(count)])):
             rows[i] = r
             if k % 32 == 0:
-                print(f"{k + 1}/{a.count} {time.time() - t0:.0f} s", flush=True)
-    out = {"what": "oracle (FP64) solutions of the point-mass quadrotor batch, 1024 x N=50, 8 obstacles",
-           "setting": SETTING, "generator": "tests/golden/make_converged.py", "instances": rows}
+                print(f"{k + 1}/{count} {time.time() - t0:.0f} s", flush=True)
+    out = {"what": w["what"], "setting": w["setting"], "generator": "tests/golden/make_converged.py",
+           "instances": rows}
+    OUT = os.path.join(HERE, f"{a.workload}_converged.json")
     with open(OUT, "w") as fh:
         json.dump(out, fh, indent=0)
     print(f"wrote {OUT} in {time.time() - t0:.0f} s")

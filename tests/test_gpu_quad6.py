@@ -14,6 +14,9 @@ the FP64 oracle.
   quaternion in one nominal (the thrust direction is undefined there) sets SCP_ST_NONFINITE on
   that trajectory only, the others equal their lone solves bit for bit.
 * A scenario group (consensus on the first control) in FP64 to 1e-9.
+* The trust-region ratio test of the SCP step (the benchmark's goodput setting: rho 10 -> 3e4,
+  accept when the ratio is positive, radius halved below 0.25, doubled above 0.75 up to 4) on a
+  small batch in FP64: accepted-step counts and final radii exact, iterates to 1e-9, both forms.
 * The persistent form of this model keeps the ADMM iterations resident in one workgroup per
   trajectory (four lanes per node); it performs the plain kernels' operations in their order, so
   both forms give the same bits (FP32 and FP64, full budget), and it meets the oracle bars above.
@@ -298,4 +301,28 @@ def test_resident_short_horizons_fp32_match_oracle(B):
     worst = compare(prob, f, insts, trajs)
     _say("resident short fp32", worst)
     assert max(worst.values()) < TOL32
+    prob.close()
+
+
+TR = dict(eta0=0.0, eta1=0.25, eta2=0.75, shrink=0.5, grow=2.0, delta_max=4.0)
+
+
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_trust_region_ratio_test_fp64(B, form):
+    insts = [scpgen.quad6_benchmark_instance(i, N=8 + 5 * i) for i in range(4)]
+    _say("quad6 ratio test fp64 12x80", form, [d["N"] for d in insts])
+    prob = B.Problem(insts, precision="f64")
+    prob.solve(B.scp_params(12, 80, form=form, rho=10.0, rho_final=3e4, **TR))
+    f = _fields(prob)
+    _, _, info = prob.result()
+    trajs, oinfo = oracle_scp(insts, 12, 80, rho_eq=10.0, rho_dyn=10.0, rho_geo=10.0, rho_final=3e4, **TR)
+    inf = prob.info_dicts(info.cpu().numpy())
+    _say([(a["n_accept"], a["delta"]) for a in inf], [(o["n_accept"], o["delta"]) for o in oinfo])
+    for a, o in zip(inf, oinfo):
+        assert a["n_accept"] == o["n_accept"] and a["delta"] == o["delta"]
+    # the test exercises rejections or radius changes, not only always-accepted unit steps
+    assert any(o["n_accept"] < 12 for o in oinfo) and any(o["delta"] != 1.0 for o in oinfo)
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < TOL64
     prob.close()
