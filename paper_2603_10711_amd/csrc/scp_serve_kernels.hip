@@ -7,38 +7,106 @@
 
 namespace scp {
 
-// Receding-horizon shift of one resident trajectory (Sec. IV-A.4, scenario MPC): state-indexed
+// Receding-horizon shift of resident trajectories (Sec. IV-A.4, scenario MPC): state-indexed
 // rows move one node earlier with the last repeated, control-indexed rows likewise over their N
-// rows; lambda_0 = mu_0 = 0 and every mirror dual where its group does not exist is 0.  One
-// thread walks the nodes in increasing order, so row i+1 is read before it is overwritten.
+// rows; lambda_0 = mu_0 = 0 and every mirror dual where its group does not exist is 0.
+// The nodes of an admission move in parallel, one thread per node, in chunks of the block: every
+// thread of a chunk loads its source row (node i + 1) into registers, the block synchronizes, then
+// every thread stores its row i.  A chunk's stores reach rows of that chunk only, and the rows the
+// next chunk loads lie past it, so each row is read before it is overwritten, as in a walk of the
+// nodes in increasing order.  Pure data movement: the result is the same bits whatever the order.
+constexpr int SHIFT_NV = 3 * PERSIST_MAX_NX + 4 + PERSIST_MAX_C;
+
 template <class M, class T>
-__device__ void shift_traj(T* __restrict__ pl, const int P, const int off, const int N, const int K, const bool ball) {
-    auto at = [&](int plane, int i) -> T& { return pl[(size_t)plane * P + off + i]; };
-    for (int i = 0; i < N; ++i) {
-        for (int r = 0; r < M::NX; ++r) {
-            at(PL_XBAR + r, i) = at(PL_XBAR + r, i + 1);
-            at(PL_LAM + r, i) = at(PL_LAM + r, i + 1);
-            at(PL_MU + r, i) = at(PL_MU + r, i + 1);
-        }
-        const bool urow = i + 1 < N;  // control rows 0..N-1: row i takes row i+1 for i < N-1
-        if (urow)
-            for (int r = 0; r < M::NU; ++r) at(PL_UBAR + r, i) = at(PL_UBAR + r, i + 1);
-        for (int q = 0; q < M::C; ++q)
-            if (!slot_is_u<M>(q) || urow) at(PL_DU + q, i) = at(PL_DU + q, i + 1);
-    }
+__device__ __forceinline__ void shift_load(const T* __restrict__ pl, const int P, const size_t src, const bool urow,
+                                           T (&v)[SHIFT_NV]) {
+    static_assert(3 * M::NX + M::NU + M::C <= SHIFT_NV, "shift row does not fit");
+#pragma unroll
     for (int r = 0; r < M::NX; ++r) {
-        at(PL_LAM + r, 0) = T(0);
-        at(PL_MU + r, 0) = T(0);
+        v[3 * r] = pl[(size_t)(PL_XBAR + r) * P + src];
+        v[3 * r + 1] = pl[(size_t)(PL_LAM + r) * P + src];
+        v[3 * r + 2] = pl[(size_t)(PL_MU + r) * P + src];
     }
-    for (int i = 0; i <= N; ++i) {
-        const NodeId id{i, N, K, ball};
-        for (int q = 0; q < M::C; ++q)
-            if (!group_active<M>(id, slot_group<M>(q))) at(PL_DU + q, i) = T(0);
+    if (urow) {
+#pragma unroll
+        for (int r = 0; r < M::NU; ++r) v[3 * M::NX + r] = pl[(size_t)(PL_UBAR + r) * P + src];
+    }
+#pragma unroll
+    for (int q = 0; q < M::C; ++q)
+        if (!slot_is_u<M>(q) || urow) v[3 * M::NX + M::NU + q] = pl[(size_t)(PL_DU + q) * P + src];
+}
+
+template <class M, class T>
+__device__ __forceinline__ void shift_store(T* __restrict__ pl, const int P, const size_t dst, const bool urow,
+                                            const T (&v)[SHIFT_NV]) {
+#pragma unroll
+    for (int r = 0; r < M::NX; ++r) {
+        pl[(size_t)(PL_XBAR + r) * P + dst] = v[3 * r];
+        pl[(size_t)(PL_LAM + r) * P + dst] = v[3 * r + 1];
+        pl[(size_t)(PL_MU + r) * P + dst] = v[3 * r + 2];
+    }
+    if (urow) {
+#pragma unroll
+        for (int r = 0; r < M::NU; ++r) pl[(size_t)(PL_UBAR + r) * P + dst] = v[3 * M::NX + r];
+    }
+#pragma unroll
+    for (int q = 0; q < M::C; ++q)
+        if (!slot_is_u<M>(q) || urow) pl[(size_t)(PL_DU + q) * P + dst] = v[3 * M::NX + M::NU + q];
+}
+
+template <class M, class T>
+__device__ __forceinline__ void shift_clear(T* __restrict__ pl, const int P, const size_t g, const NodeId& id) {
+    if (id.i == 0) {
+#pragma unroll
+        for (int r = 0; r < M::NX; ++r) {
+            pl[(size_t)(PL_LAM + r) * P + g] = T(0);
+            pl[(size_t)(PL_MU + r) * P + g] = T(0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < M::C; ++q)
+        if (!group_active<M>(id, slot_group<M>(q))) pl[(size_t)(PL_DU + q) * P + g] = T(0);
+}
+
+// Shift every trajectory of one admission record.  s_nt: the record's node -> trajectory map
+// (global trajectory indices), s_traj: its trajectory records.  Called by the whole block.
+template <class T>
+__device__ void shift_admission(T* __restrict__ pl, const int P, const int node_off, const int n_nodes,
+                                const int traj_first, const int* __restrict__ s_nt,
+                                const int* __restrict__ s_traj) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int base = 0; base < n_nodes; base += nt) {
+        const int k = base + tid;
+        bool mv = false, urow = false, quad = false;
+        T v[SHIFT_NV];
+        if (k < n_nodes) {
+            const int* rec = s_traj + (s_nt[k] - traj_first) * TR_FIELDS;
+            const int i = node_off + k - rec[TR_OFF], N = rec[TR_N];
+            mv = i < N;          // rows 0..N-1 take row i + 1; row N stays
+            urow = i + 1 < N;    // control rows 0..N-2 take row i + 1; row N-1 stays
+            quad = rec[TR_MODEL] == SCP_MODEL_QUAD_PM;
+            if (mv) {
+                if (quad) shift_load<Quad<8>, T>(pl, P, (size_t)node_off + k + 1, urow, v);
+                else shift_load<Mars, T>(pl, P, (size_t)node_off + k + 1, urow, v);
+            }
+        }
+        __syncthreads();
+        if (mv) {
+            if (quad) shift_store<Quad<8>, T>(pl, P, (size_t)node_off + k, urow, v);
+            else shift_store<Mars, T>(pl, P, (size_t)node_off + k, urow, v);
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k < n_nodes; k += nt) {
+        const int* rec = s_traj + (s_nt[k] - traj_first) * TR_FIELDS;
+        const NodeId id{node_off + k - rec[TR_OFF], rec[TR_N], rec[TR_K], rec[TR_BALL] != 0};
+        if (rec[TR_MODEL] == SCP_MODEL_QUAD_PM) shift_clear<Quad<8>, T>(pl, P, (size_t)node_off + k, id);
+        else shift_clear<Mars, T>(pl, P, (size_t)node_off + k, id);
     }
 }
 
 template <class T>
-__global__ void k_admit(Dev<T> dv, int block, const unsigned char* __restrict__ blob, int rec_off) {
+__global__ __launch_bounds__(256) void k_admit(Dev<T> dv, int block, const unsigned char* __restrict__ blob, int rec_off) {
     const AdmitRec r = reinterpret_cast<const AdmitRec*>(blob + rec_off)[blockIdx.x];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int P = dv.P;
@@ -94,13 +162,7 @@ __global__ void k_admit(Dev<T> dv, int block, const unsigned char* __restrict__ 
             prm[(size_t)(r.traj_first + k / SCP_MAX_NX) * SCP_PARAM_STRIDE + SCP_P_XINIT + k % SCP_MAX_NX] =
                 x1[k % SCP_MAX_NX];
     }
-    for (int t = tid; t < r.n_traj; t += nt) {
-        const int* rec = s_traj + t * TR_FIELDS;
-        if (rec[TR_MODEL] == SCP_MODEL_QUAD_PM)
-            shift_traj<Quad<8>, T>(pl, P, rec[TR_OFF], rec[TR_N], rec[TR_K], rec[TR_BALL] != 0);
-        else
-            shift_traj<Mars, T>(pl, P, rec[TR_OFF], rec[TR_N], 0, false);
-    }
+    shift_admission<T>(pl, P, r.node_off, r.n_nodes, r.traj_first, s_nt, s_traj);
 }
 
 template <class T>
