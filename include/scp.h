@@ -162,6 +162,13 @@ enum {
 #define SCP_ST_SYNC 16        /* a consensus group spanning several workgroups waited too
                                  long at a group barrier (scp_params.group_wait_ms); set on
                                  every member of the group, whose results are invalid      */
+#define SCP_ST_DIVERGED 32    /* residual blow-up (scp_params.detect_blowup): at the
+                                 acceptance step of an SCP iteration, the primal residual of
+                                 its last ADMM iteration exceeded SCP_RP_BLOWUP times the
+                                 first positive one since the problem was created or reset
+                                 (a served request: admitted).  Set by scp_solve and the
+                                 server only (admm_solve has no acceptance step).            */
+#define SCP_RP_BLOWUP 1.0e6
 
 typedef struct {
     int32_t n_traj;           /* number of trajectories, >= 1                              */
@@ -254,6 +261,9 @@ typedef struct {
                                          A combination the batch does not allow returns
                                          SCP_ERR_UNSUPPORTED.  Results agree within rounding
                                          (the sums run in another order).                        */
+    int32_t detect_blowup;            /* 1: residual blow-up detection (SCP_ST_DIVERGED), in
+                                         every form; the persistent form then runs a kernel
+                                         variant that carries the tracking.  0: off.             */
 } scp_params;
 
 typedef struct scp_problem scp_problem;

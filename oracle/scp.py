@@ -12,6 +12,11 @@ Per SCP iteration k (Fig. method_overview: linearize -> convex QP -> update nomi
   a10 candidate = last physical iterate; merit ratio test; nominal and trust radius update
       (the paper omits this logic and points to standard trust-region texts; the reading
       here is the classic ratio test on an l1 merit function)
+
+Status bits of a group's info: ST_NONFINITE (a non-finite merit), ST_DIVERGED (residual blow-up,
+with params["detect_blowup"]: the primal residual of an SCP iteration's last ADMM iteration above
+RP_BLOWUP times the first positive one of the solve; the paper gives no such rule, it is failure
+detection only).
 """
 from __future__ import annotations
 
@@ -23,14 +28,18 @@ import numpy as np
 from .admm import Group, QP, AdmmState, build_H, admm_run
 from .dynamics import rk4, rk4_jac, QUAD, MARS, QUAD6, LANDER6
 
+ST_NONFINITE = 1
+ST_DIVERGED = 32
+RP_BLOWUP = 1.0e6
+
 
 def default_params(**kw) -> dict:
     """Solver parameters; the defaults are the fixed-budget settings of the workloads
     (rho = 1 for all three penalties, always-accept steps, fixed trust radius).  rho_final > 0
     turns on the penalty schedule of penalty_factors; adapt_mu > 0 the residual balancing of
-    adapt_penalty."""
+    adapt_penalty; detect_blowup the ST_DIVERGED status bit."""
     p = dict(scp_iters=10, admm_iters=100, rho_eq=1.0, rho_dyn=1.0, rho_geo=1.0, rho_final=0.0,
-             adapt_mu=0.0, adapt_tau=2.0,
+             adapt_mu=0.0, adapt_tau=2.0, detect_blowup=False,
              check_every=0, eps_p=0.0, eps_d=0.0,
              eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
              merit_w=1.0e3)
@@ -359,6 +368,7 @@ def scp_group(trajs: list[Traj], params: dict, delta: float | None = None) -> di
     iters_total = 0
     n_accept = 0
     rp = rd = float("nan")
+    rp0 = 0.0     # blow-up reference: the first positive primal residual of the solve
     status = 0
     scale = 1.0   # adaptive factor of the penalties (adapt_penalty)
     for k in range(params["scp_iters"]):
@@ -383,7 +393,13 @@ def scp_group(trajs: list[Traj], params: dict, delta: float | None = None) -> di
         ratio = actual / pred if pred > 0.0 else -math.inf
         if not (math.isfinite(m_new) and math.isfinite(m_mod)):
             ratio = math.nan
-            status |= 1
+            status |= ST_NONFINITE
+        if params.get("detect_blowup"):
+            if rp0 > 0.0:
+                if rp > RP_BLOWUP * rp0:
+                    status |= ST_DIVERGED
+            elif rp > 0.0:
+                rp0 = rp
         if ratio >= params["eta0"]:
             n_accept += 1
             for t in trajs:

@@ -32,7 +32,7 @@ SUBMIT_MEASURED = 1
 INFO = dict(admm_iters=0, r_p=1, r_d=2, n_accept=3, delta=4, status=5, defect=6, cost=7, viol=8, bnd_err=9,
             merit=10, ratio=11)
 INFO_FIELDS = 12
-ST_NONFINITE, ST_BADPIVOT, ST_EMPTYSET, ST_CONVERGED, ST_SYNC = 1, 2, 4, 8, 16
+ST_NONFINITE, ST_BADPIVOT, ST_EMPTYSET, ST_CONVERGED, ST_SYNC, ST_DIVERGED = 1, 2, 4, 8, 16, 32
 FIELDS = dict(xbar=0, ubar=1, x=2, u=3, z=4, lam=5, mu=6, ddyn=7, copy=8, dual=9, A=10, B=11, d=12, boxlo=13,
               boxhi=14, hs=15)
 SYMBOLS = ["scp_problem_device_bytes", "scp_problem_create", "scp_problem_create_noalloc", "scp_problem_destroy",
@@ -63,7 +63,7 @@ class ScpParams(ctypes.Structure):
                 ("eta2", c_double), ("shrink", c_double), ("grow", c_double), ("delta_max", c_double),
                 ("merit_w", c_double), ("form", c_int32), ("scp_per_launch", c_int32), ("rho_final", c_double),
                 ("graph", c_int32), ("adapt_mu", c_double), ("adapt_tau", c_double), ("group_wait_ms", c_double),
-                ("lanes_per_node", c_int32)]
+                ("lanes_per_node", c_int32), ("detect_blowup", c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -224,11 +224,11 @@ def admm_params(rho=1.0, iters=100, check_every=0, eps=0.0, rho_dyn=None, rho_ge
 def scp_params(scp_iters=10, admm_iters=100, rho=1.0, check_every=0, eps=0.0, form="persistent",
                scp_per_launch=0, eta0=-math.inf, eta1=0.25, eta2=0.75, shrink=1.0, grow=1.0, delta_max=math.inf,
                merit_w=1.0e3, rho_dyn=None, rho_geo=None, graph=False, rho_final=0.0, adapt_mu=0.0,
-               adapt_tau=2.0, group_wait_ms=0.0, lanes_per_node=0) -> ScpParams:
+               adapt_tau=2.0, group_wait_ms=0.0, lanes_per_node=0, detect_blowup=False) -> ScpParams:
     f = FORM_PERSISTENT if form == "persistent" else FORM_PLAIN
     return ScpParams(scp_iters, admm_params(rho, admm_iters, check_every, eps, rho_dyn, rho_geo), eta0, eta1, eta2,
                      shrink, grow, delta_max, merit_w, f, scp_per_launch, rho_final, 1 if graph else 0, adapt_mu,
-                     adapt_tau, group_wait_ms, lanes_per_node)
+                     adapt_tau, group_wait_ms, lanes_per_node, 1 if detect_blowup else 0)
 
 
 def _pad(a, w):

@@ -23,6 +23,7 @@ LIB = os.path.join(HERE, "libscp.so")
 
 # largest translation units first, so the parallel build ends early
 SOURCES = ["scp_persistent_f64_span.hip", "scp_persistent_f64.hip", "scp_persistent_f64_adapt.hip",
+           "scp_persistent_f64_track.hip", "scp_persistent_f32_track.hip",
            "scp_persistent_f32_adapt.hip", "scp_persistent_f32_span.hip",
            "scp_persistent_f32.hip", "scp_plain.hip", "scp_persistent.hip", "scp_serve_kernels.hip", "scp_api.cpp",
            "scp_serve.cpp", "scp_noalloc.hip", "scp_plan.cpp"]

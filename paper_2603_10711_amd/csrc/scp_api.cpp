@@ -89,6 +89,7 @@ KParams<T> kparams(const admm_params* a, const scp_params* s) {
         k.merit_w = T(s->merit_w);
         k.sched_q = sched_ratio(*s);
         k.spin_ticks = group_wait_ticks(s->group_wait_ms);
+        k.blowup = s->detect_blowup != 0 ? 1 : 0;
         if (s->adapt_mu > 0.0) {
             k.adapt_mu = s->adapt_mu;
             k.adapt_tau = s->adapt_tau;
@@ -166,7 +167,7 @@ bool same_params(const scp_params& a, const scp_params& b) {
            std::memcmp(&a.delta_max, &b.delta_max, sizeof(double)) == 0 && a.merit_w == b.merit_w &&
            a.form == b.form && a.scp_per_launch == b.scp_per_launch && a.rho_final == b.rho_final &&
            a.adapt_mu == b.adapt_mu && a.adapt_tau == b.adapt_tau && a.group_wait_ms == b.group_wait_ms &&
-           a.lanes_per_node == b.lanes_per_node;
+           a.lanes_per_node == b.lanes_per_node && a.detect_blowup == b.detect_blowup;
 }
 
 template <class T>

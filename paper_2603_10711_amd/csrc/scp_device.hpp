@@ -1396,6 +1396,24 @@ __device__ __forceinline__ unsigned long long res_bits(T v) {
 }
 __device__ __forceinline__ double bits_res(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+// Residual blow-up (failure detection; the paper has no such rule).  At the acceptance step of
+// every SCP iteration, rp (the primal residual of the iteration's last ADMM iteration) updates
+// rp0, the first positive one since the problem was created, reset or admitted (0 = none yet),
+// and rpmax, the largest one since then (a NaN changes neither).  The trajectory has blown up
+// once rpmax exceeds SCP_RP_BLOWUP times rp0: the same as testing every rp against rp0 as it
+// comes, which is what the oracle does.  Compared in the problem precision (the factor is exact
+// in FP32).
+template <class T>
+__device__ __forceinline__ void blowup_track(T& rp0, T& rpmax, const T rp) {
+    rp0 = rp0 > T(0) ? rp0 : (rp > T(0) ? rp : T(0));
+    rpmax = rp > rpmax ? rp : rpmax;
+}
+
+template <class T>
+__device__ __forceinline__ int blowup_status(const T rp0, const T rpmax) {
+    return (rp0 > T(0) && rpmax > T(SCP_RP_BLOWUP) * rp0) ? SCP_ST_DIVERGED : 0;
+}
+
 // trust-region ratio test on the merit (reading of the omitted update logic, Sec. III-A)
 template <class T>
 struct AcceptOut {

@@ -59,7 +59,9 @@ enum : int { TR_MODEL = 0, TR_N = 1, TR_OFF = 2, TR_GFIRST = 3, TR_GSIZE = 4, TR
              TR_MEMBER = 7, TR_FIELDS = 8 };
 
 // per-trajectory runtime values (problem precision)
-enum : int { RT_DELTA = 0, RT_RHOS = 1, RT_FIELDS = 2 };
+// RT_RP0: the first positive primal residual since create / reset / admission (blow-up reference),
+// RT_RPMAX: the largest one since then
+enum : int { RT_DELTA = 0, RT_RHOS = 1, RT_RP0 = 2, RT_RPMAX = 3, RT_FIELDS = 4 };
 
 // per-trajectory integer flags
 enum : int { FL_DONE = 0, FL_ITERS = 1, FL_ACCEPT = 2, FL_STATUS = 3, FL_FIELDS = 4 };
@@ -141,6 +143,8 @@ struct KParams {
     // spanning consensus groups: longest wait at one group barrier, in ticks of the device wall
     // clock (100 MHz), before the group is declared failed (0: give up at the first wait)
     unsigned long long spin_ticks;
+    // residual blow-up detection (scp_params.detect_blowup): SCP_ST_DIVERGED on / off
+    int blowup;
 };
 
 }  // namespace scp

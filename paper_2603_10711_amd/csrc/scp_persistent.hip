@@ -1,5 +1,5 @@
 // Persistent form: launch entry (the kernel templates live in scp_persistent.hpp; their
-// instantiations are split over scp_persistent_{f32,f64}{,_span,_adapt}.hip).
+// instantiations are split over scp_persistent_{f32,f64}{,_span,_adapt,_track}.hip).
 #include "scp_persistent.hpp"
 #include "scp_host.hpp"
 
@@ -22,6 +22,14 @@ SCP_EXTERN_ADAPT(float, 256)
 SCP_EXTERN_ADAPT(double, 64)
 SCP_EXTERN_ADAPT(double, 128)
 #undef SCP_EXTERN_ADAPT
+#define SCP_EXTERN_TRACK(T, BLOCK) \
+    extern template void launch_models<T, BLOCK, false, false, true>(const Dev<T>&, const KParams<T>&, int, int, int, hipStream_t);
+SCP_EXTERN_TRACK(float, 64)
+SCP_EXTERN_TRACK(float, 128)
+SCP_EXTERN_TRACK(float, 256)
+SCP_EXTERN_TRACK(double, 64)
+SCP_EXTERN_TRACK(double, 128)
+#undef SCP_EXTERN_TRACK
 #undef SCP_EXTERN_VARIANTS
 
 // Barrier counters of the spanning groups start every launch at zero.
@@ -38,6 +46,8 @@ static hipError_t launch_block(const Dev<T>& dv, const KParams<T>& kp, int n_wg,
         launch_models<T, BLOCK, false, true>(dv, kp, n_wg, models, kmax, s);
     } else if (dv.n_gslots > 0) {
         launch_models<T, BLOCK, true>(dv, kp, n_wg, models, kmax, s);
+    } else if (kp.blowup) {
+        launch_models<T, BLOCK, false, false, true>(dv, kp, n_wg, models, kmax, s);
     } else {
         launch_models<T, BLOCK, false>(dv, kp, n_wg, models, kmax, s);
     }

@@ -59,6 +59,8 @@ struct Shared {
     int gxm[BLOCK];                // member index of the row staged at a lane, -1 none
     T arho[AR];                    // adaptive-penalty kernels (AR = BLOCK): the factor of the
                                    // lane's trajectory, own slot, out of the ADMM loop's registers
+    T rp0[BLOCK];                  // residual blow-up tracking (TRACK kernels): the group's
+    T rpm[BLOCK];                  // reference and largest primal residual, at the leader lane
 };
 
 // Spanning consensus group of a workgroup (on = false for every other workgroup).
@@ -171,7 +173,7 @@ __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HS
 // iteration disappear.  The per-trajectory reductions still go through LDS.
 // ADAPT: the adaptive penalty (residual balancing between SCP iterations) is on; a kernel variant
 // of its own, so the fixed-penalty kernels compile without it.
-template <class M, class T, int BLOCK, bool WAVE1, bool SPAN, bool ADAPT, int HSR, int LR, int AR>
+template <class M, class T, int BLOCK, bool WAVE1, bool SPAN, bool ADAPT, bool TRACK, int HSR, int LR, int AR>
 __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<T>& kp,
                                                 Shared<T, BLOCK, HSR, LR, AR>& sh, const int t, const int gn,
                                                 const Span span_in) {
@@ -206,6 +208,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     const T kappa = valid ? prm[SCP_P_GLIDE] : T(1);
     const T inv1k2 = T(1) / (T(1) + kappa * kappa);
     T delta = valid ? dv.rt[tr * RT_FIELDS + RT_DELTA] : T(0);
+    // residual blow-up tracking of the group (the same in every member: they share the residual),
+    // in LDS at the group leader's lane, out of the registers of the ADMM loop
+    if constexpr (TRACK) {
+        if (leader) {
+            sh.rp0[t] = dv.rt[tr * RT_FIELDS + RT_RP0];
+            sh.rpm[t] = dv.rt[tr * RT_FIELDS + RT_RPMAX];
+        }
+    }
 
     T xbar[NX], ubar[NU];
     NodeState<M, T> s;
@@ -578,9 +588,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                             sh.mx[1][lm] = 0ull;
                         }
                         const T grp = T(bits_res(bp)), grd = T(bits_res(bd));
-                        sh.flag[lb] = (test && grp <= kp.eps_p && grd <= kp.eps_d) ? 1 : 0;
+                        const bool conv = test && grp <= kp.eps_p && grd <= kp.eps_d;
+                        sh.flag[lb] = conv ? 1 : 0;
                         sh.red[0][lb] = grp;
                         sh.red[1][lb] = grd;
+                        // blow-up tracking on the SCP iteration's last residual (at convergence or
+                        // at the last ADMM iteration)
+                        if constexpr (TRACK)
+                            if (kp.blowup && (conv || j == kp.max_iters)) blowup_track<T>(sh.rp0[lb], sh.rpm[lb], grp);
                     }
                 } else {
                     // member maxima to HBM; the group maximum is the same in every workgroup
@@ -598,9 +613,12 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
                             grp = nmax(grp, gx_at<2>(sh, m, 0));
                             grd = nmax(grd, gx_at<2>(sh, m, 1));
                         }
-                        sh.flag[lb] = (test && grp <= kp.eps_p && grd <= kp.eps_d) ? 1 : 0;
+                        const bool conv = test && grp <= kp.eps_p && grd <= kp.eps_d;
+                        sh.flag[lb] = conv ? 1 : 0;
                         sh.red[0][lb] = grp;
                         sh.red[1][lb] = grd;
+                        if constexpr (TRACK)
+                            if (kp.blowup && (conv || j == kp.max_iters)) blowup_track<T>(sh.rp0[lb], sh.rpm[lb], grp);
                     }
                 }
                 __syncthreads();
@@ -824,6 +842,13 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
         if constexpr (ADAPT) dv.rt[tr * RT_FIELDS + RT_RHOS] = sh.arho[t];
         double* inf = dv.info + (size_t)tr * SCP_INFO_FIELDS;
         int st = sh.st[tb];
+        if constexpr (TRACK) {
+            if (kp.blowup) {
+                dv.rt[tr * RT_FIELDS + RT_RP0] = sh.rp0[lb];
+                dv.rt[tr * RT_FIELDS + RT_RPMAX] = sh.rpm[lb];
+                st |= blowup_status<T>(sh.rp0[lb], sh.rpm[lb]);
+            }
+        }
         if (!kp.reset_info) st |= (int)inf[SCP_I_STATUS] & ~SCP_ST_CONVERGED;
         if (conv_last) st |= SCP_ST_CONVERGED;
         const double it0 = kp.reset_info ? 0.0 : inf[SCP_I_ADMM_ITERS];
@@ -852,14 +877,14 @@ __device__ __forceinline__ void persistent_body(const Dev<T>& dv, const KParams<
     }
 }
 
-template <class M, class T, int BLOCK, bool SPAN, bool ADAPT, int HSR, int LR, int AR>
+template <class M, class T, int BLOCK, bool SPAN, bool ADAPT, bool TRACK, int HSR, int LR, int AR>
 __device__ __forceinline__ void body_for(const Dev<T>& dv, const KParams<T>& kp, Shared<T, BLOCK, HSR, LR, AR>& sh,
                                          const int t, const int gn, const bool cross, const Span& sp) {
     if constexpr (BLOCK == 64) {
-        persistent_body<M, T, BLOCK, true, SPAN, ADAPT>(dv, kp, sh, t, gn, sp);
+        persistent_body<M, T, BLOCK, true, SPAN, ADAPT, TRACK>(dv, kp, sh, t, gn, sp);
     } else {
-        if (cross) persistent_body<M, T, BLOCK, false, SPAN, ADAPT>(dv, kp, sh, t, gn, sp);
-        else persistent_body<M, T, BLOCK, true, SPAN, ADAPT>(dv, kp, sh, t, gn, sp);
+        if (cross) persistent_body<M, T, BLOCK, false, SPAN, ADAPT, TRACK>(dv, kp, sh, t, gn, sp);
+        else persistent_body<M, T, BLOCK, true, SPAN, ADAPT, TRACK>(dv, kp, sh, t, gn, sp);
     }
 }
 
@@ -872,7 +897,7 @@ constexpr int persistent_lds_factor_rows(int block, int models) {
 
 // MODELS: 1 quadrotor only, 2 powered descent only, 3 both (each workgroup holds one model).
 // SPAN: the launch has consensus groups spanning several workgroups.
-template <class T, int BLOCK, int MODELS, int KM, bool SPAN, bool ADAPT>
+template <class T, int BLOCK, int MODELS, int KM, bool SPAN, bool ADAPT, bool TRACK>
 __global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) {
     __shared__ Shared<T, BLOCK, (MODELS != 2 && KM > 0) ? 3 * KM : 1, persistent_lds_factor_rows(BLOCK, MODELS),
                       ADAPT ? BLOCK : 1> sh;
@@ -884,28 +909,31 @@ __global__ __launch_bounds__(BLOCK) void k_persistent(Dev<T> dv, KParams<T> kp) 
     Span sp{false, 0, 1};
     if (wi & WG_SPAN) sp = Span{true, dv.wg_group[2 * w], dv.wg_group[2 * w + 1]};
     if constexpr (MODELS == 1) {
-        body_for<Quad<KM>, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
+        body_for<Quad<KM>, T, BLOCK, SPAN, ADAPT, TRACK>(dv, kp, sh, t, gn, cross, sp);
     } else if constexpr (MODELS == 2) {
-        body_for<Mars, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
+        body_for<Mars, T, BLOCK, SPAN, ADAPT, TRACK>(dv, kp, sh, t, gn, cross, sp);
     } else {
-        if ((wi & 0xff) == SCP_MODEL_QUAD_PM) body_for<Quad<KM>, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
-        else body_for<Mars, T, BLOCK, SPAN, ADAPT>(dv, kp, sh, t, gn, cross, sp);
+        if ((wi & 0xff) == SCP_MODEL_QUAD_PM) body_for<Quad<KM>, T, BLOCK, SPAN, ADAPT, TRACK>(dv, kp, sh, t, gn, cross, sp);
+        else body_for<Mars, T, BLOCK, SPAN, ADAPT, TRACK>(dv, kp, sh, t, gn, cross, sp);
     }
 }
 
-// Launch of the persistent kernel variant for BLOCK, SPAN and ADAPT (instantiated per precision
-// and variant in their own translation units, compiled in parallel).
-template <class T, int BLOCK, bool SPAN, bool ADAPT = false>
+// Launch of the persistent kernel variant for BLOCK, SPAN, ADAPT and TRACK (instantiated per
+// precision and variant in their own translation units, compiled in parallel).  TRACK kernels
+// carry the residual blow-up tracking (active when kp.blowup is set); the spanning and adaptive
+// variants always do, the plain fixed-penalty one comes in both forms, so that the default
+// kernel keeps its code and registers.
+template <class T, int BLOCK, bool SPAN, bool ADAPT = false, bool TRACK = SPAN || ADAPT>
 void launch_models(const Dev<T>& dv, const KParams<T>& kp, int n_wg, int models, int kmax, hipStream_t s) {
     const dim3 g(n_wg), b(BLOCK);
     if (models == 1) {
-        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 4, SPAN, ADAPT>), g, b, 0, s, dv, kp);
-        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 8, SPAN, ADAPT>), g, b, 0, s, dv, kp);
+        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 4, SPAN, ADAPT, TRACK>), g, b, 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 1, 8, SPAN, ADAPT, TRACK>), g, b, 0, s, dv, kp);
     } else if (models == 2) {
-        hipLaunchKernelGGL((k_persistent<T, BLOCK, 2, 0, SPAN, ADAPT>), g, b, 0, s, dv, kp);
+        hipLaunchKernelGGL((k_persistent<T, BLOCK, 2, 0, SPAN, ADAPT, TRACK>), g, b, 0, s, dv, kp);
     } else {
-        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 4, SPAN, ADAPT>), g, b, 0, s, dv, kp);
-        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 8, SPAN, ADAPT>), g, b, 0, s, dv, kp);
+        if (kmax <= 4) hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 4, SPAN, ADAPT, TRACK>), g, b, 0, s, dv, kp);
+        else hipLaunchKernelGGL((k_persistent<T, BLOCK, 3, 8, SPAN, ADAPT, TRACK>), g, b, 0, s, dv, kp);
     }
 }
 
@@ -916,13 +944,13 @@ int span_blocks_per_cu(int models, int kmax) {
     int n = 0;
     hipError_t e;
     if (models == 1)
-        e = kmax <= 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 1, 4, true, false>, BLOCK, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 1, 8, true, false>, BLOCK, 0);
+        e = kmax <= 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 1, 4, true, false, true>, BLOCK, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 1, 8, true, false, true>, BLOCK, 0);
     else if (models == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 2, 0, true, false>, BLOCK, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 2, 0, true, false, true>, BLOCK, 0);
     else
-        e = kmax <= 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 3, 4, true, false>, BLOCK, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 3, 8, true, false>, BLOCK, 0);
+        e = kmax <= 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 3, 4, true, false, true>, BLOCK, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, BLOCK, 3, 8, true, false, true>, BLOCK, 0);
     return e == hipSuccess ? n : 0;
 }
 

@@ -1423,6 +1423,13 @@ __global__ __launch_bounds__(64) void k_acc_traj(Dev<T> dv, KParams<T> kp) {
         inf[SCP_I_MERIT] = (double)mnew;
         inf[SCP_I_DELTA] = (double)a.delta;
         int st = fl[FL_STATUS] | (a.nonfinite ? SCP_ST_NONFINITE : 0);
+        if (kp.blowup) {   // inf[SCP_I_RP]: the residual of this SCP iteration's last ADMM iteration (k_check)
+            T rp0 = dv.rt[t * RT_FIELDS + RT_RP0], rpmax = dv.rt[t * RT_FIELDS + RT_RPMAX];
+            blowup_track<T>(rp0, rpmax, T(inf[SCP_I_RP]));
+            st |= blowup_status<T>(rp0, rpmax);
+            dv.rt[t * RT_FIELDS + RT_RP0] = rp0;
+            dv.rt[t * RT_FIELDS + RT_RPMAX] = rpmax;
+        }
         if (fl[FL_DONE]) st |= SCP_ST_CONVERGED;
         else st &= ~SCP_ST_CONVERGED;
         fl[FL_STATUS] = st;
@@ -1516,6 +1523,8 @@ __global__ void k_reset(Dev<T> dv, int reset_delta) {
     if (reset_delta) {
         dv.rt[tr * RT_FIELDS + RT_DELTA] = dv.params[(size_t)tr * SCP_PARAM_STRIDE + SCP_P_DELTA];
         dv.rt[tr * RT_FIELDS + RT_RHOS] = T(1);
+        dv.rt[tr * RT_FIELDS + RT_RP0] = T(0);
+        dv.rt[tr * RT_FIELDS + RT_RPMAX] = T(0);
     }
     inf[SCP_I_DELTA] = (double)dv.rt[tr * RT_FIELDS + RT_DELTA];
 }

@@ -412,6 +412,7 @@ scp_status do_step(scp_server* s, int wait, int32_t* pending) {
     kp.sched_s0 = 1.0;
     kp.sched_q = 1.0;
     kp.spin_ticks = group_wait_ticks(q.group_wait_ms);
+    kp.blowup = q.detect_blowup != 0 ? 1 : 0;
     kp.n_scp = s->cfg.scp_per_step;
     kp.final_metrics = 1;
     kp.reset_info = 0;

@@ -134,7 +134,9 @@ __global__ __launch_bounds__(256) void k_admit(Dev<T> dv, int block, const unsig
     for (int k = tid; k < r.n_traj * 2; k += nt) dv.red[(size_t)r.traj_first * 2 + k] = 0ull;
     for (int k = tid; k < r.n_traj; k += nt) {
         dv.rt[(size_t)(r.traj_first + k) * RT_FIELDS + RT_DELTA] = s_prm[(size_t)k * SCP_PARAM_STRIDE + SCP_P_DELTA];
-        dv.rt[(size_t)(r.traj_first + k) * RT_FIELDS + 1] = T(0);
+        dv.rt[(size_t)(r.traj_first + k) * RT_FIELDS + RT_RHOS] = T(0);
+        dv.rt[(size_t)(r.traj_first + k) * RT_FIELDS + RT_RP0] = T(0);
+        dv.rt[(size_t)(r.traj_first + k) * RT_FIELDS + RT_RPMAX] = T(0);
     }
     T* pl = dv.planes;
     if (!r.warm) {

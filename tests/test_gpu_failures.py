@@ -1,8 +1,13 @@
 """Numerical failures are per-trajectory status bits, and they stay inside their trajectory.
 
 The C ABI reports a non-positive Cholesky pivot (SCP_ST_BADPIVOT), a hard box with lo > hi
-(SCP_ST_EMPTYSET) and non-finite iterates (SCP_ST_NONFINITE) in the info record of the
-trajectory they occur in and never fails the call.  Each case plants one bad trajectory in a batch
+(SCP_ST_EMPTYSET), non-finite iterates (SCP_ST_NONFINITE) and a residual blow-up
+(SCP_ST_DIVERGED) in the info record of the trajectory they occur in and never fails the call.
+Every solve here runs with residual blow-up detection on (scp_params.detect_blowup). The blow-up
+case is a negative control weight (the QP turns nonconvex while H stays positive
+definite, and ADMM diverges): in FP64 the residual grows past 1e6 times its first value before the
+iterates overflow, and the status equals the oracle's (NONFINITE | DIVERGED); in FP32 the first
+SCP iteration already overflows, so there is no finite reference and the bit is NONFINITE.  Each case plants one bad trajectory in a batch
 of good ones and checks, in both forms and both precisions:
   * the bad trajectory carries its bit;
   * every good trajectory is bit-identical to the same trajectory solved alone, and carries no
@@ -16,11 +21,12 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 import scpgen
 
 pytestmark = pytest.mark.gpu
 
-FAIL_BITS = 1 | 2 | 4 | 16
+FAIL_BITS = 1 | 2 | 4 | 16 | 32
 
 
 def _say(*a):
@@ -51,19 +57,21 @@ def _bad(kind):
         x0 = d["x_init"].copy()
         x0[1] = math.nan
         return dict(d, x_init=x0), 1
+    if kind == "diverge":       # nonconvex QP (negative control weight), H positive definite
+        return dict(d, R=np.full(3, -2.0)), None
     raise ValueError(kind)
 
 
 def _solve(B, insts, prec, form):
     prob = B.Problem(insts, precision=prec)
-    prob.solve(B.scp_params(3, 40, form=form))
+    prob.solve(B.scp_params(3, 40, form=form, detect_blowup=True))
     x, u, info = (a.cpu().numpy() for a in prob.result())
     offs = prob.offsets.copy()
     prob.close()
     return x, u, info, offs
 
 
-@pytest.mark.parametrize("kind", ["badpivot", "emptyset", "nan_xinit"])
+@pytest.mark.parametrize("kind", ["badpivot", "emptyset", "nan_xinit", "diverge"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("form", ["persistent", "plain"])
 def test_failure_is_flagged_and_contained(B, kind, prec, form):
@@ -74,6 +82,12 @@ def test_failure_is_flagged_and_contained(B, kind, prec, form):
     _say(kind, prec, form)
     x, u, info, offs = _solve(B, insts, prec, form)
     st = info[:, 5].astype(np.int64)
+    if kind == "diverge":
+        with np.errstate(all="ignore"):
+            _, oinf = oracle.scp_solve([bad], oracle.default_params(scp_iters=3, admm_iters=40, detect_blowup=True))
+        assert oinf[0]["status"] == B.ST_NONFINITE | B.ST_DIVERGED
+        bit = B.ST_NONFINITE | B.ST_DIVERGED if prec == "f64" else B.ST_NONFINITE
+        assert (st[pos] & (B.ST_NONFINITE | B.ST_DIVERGED)) == bit, f"status {st[pos]}, expected {bit}"
     assert st[pos] & bit, f"status {st[pos]} lacks bit {bit}"
     for t, d in enumerate(insts):
         if t == pos:
@@ -156,3 +170,19 @@ def test_spanning_batch_beyond_residency_is_refused(B):
     info = prob.result()[2].cpu().numpy()
     assert np.all(np.isfinite(info[:, 1]))
     prob.close()
+
+
+@pytest.mark.parametrize("form", ["persistent", "plain"])
+def test_blowup_detection_leaves_results_unchanged(B, form):
+    """Blow-up detection only adds the status bit: on a healthy batch the kernels with the tracking
+    (the persistent form's own variant) return the same bits as without it."""
+    insts = _good()
+    res = []
+    for detect in (False, True):
+        prob = B.Problem(insts, precision="f32")
+        prob.solve(B.scp_params(3, 40, form=form, detect_blowup=detect))
+        res.append([a.cpu().numpy() for a in prob.result()])
+        prob.close()
+    for a, b in zip(*res):
+        np.testing.assert_array_equal(a, b)
+    assert not np.any(res[1][2][:, 5].astype(np.int64) & B.ST_DIVERGED)

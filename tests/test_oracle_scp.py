@@ -6,7 +6,10 @@
 * with affine (drag-free) dynamics one SCP step solves the convex subproblem: the ADMM
   output satisfies the subproblem's KKT conditions, checked set by set;
 * nonlinear behaviour: defect and step shrink on a converging instance; the ratio test
-  never accepts a merit increase; scenario groups of identical copies equal one instance.
+  never accepts a merit increase; scenario groups of identical copies equal one instance;
+* failure detection: the residual blow-up bit follows its rule (first positive residual of the
+  solve as the reference, strictly above 1e6 times it) and is set when an indefinite cost makes
+  ADMM diverge.
 """
 import math
 
@@ -284,3 +287,39 @@ def test_penalty_schedule_improves_the_nonlinear_defect():
     sched = oracle.scp_solve([inst], oracle.default_params(scp_iters=15, admm_iters=200, rho_eq=100.0,
                                                            rho_dyn=100.0, rho_geo=100.0, rho_final=1e3))[1][0]
     assert sched["defect"] < 1e-3 * fixed["defect"]
+
+
+@pytest.mark.parametrize("seq,flagged", [
+    ([1e-3, 2e3], True),            # 2e6 times the reference
+    ([1e-3, 1e3], False),           # exactly 1e6 times: not above it
+    ([0.0, 1e-3, 9e2], False),      # a zero residual is no reference; 9e5 times the first positive one
+    ([0.0, 1e-3, 1.5e3], True),
+    ([5.0, 1e-9, 4e6], False),      # the reference is the first positive residual, not the smallest
+])
+def test_residual_blowup_rule(monkeypatch, seq, flagged):
+    """The blow-up bit compares each SCP iteration's primal residual with the first positive one of
+    the solve (fed here through a stand-in for the ADMM run, so only the rule is exercised)."""
+    import oracle.scp as S
+    vals = iter(seq)
+    monkeypatch.setattr(S, "admm_run", lambda *a, **k: (1, next(vals), 0.0))
+    t = init_traj(scpgen.quad_instance(1, 5, N=6, K=1))
+    info = scp_group([t], oracle.default_params(scp_iters=len(seq), admm_iters=1, detect_blowup=True))
+    assert bool(info["status"] & S.ST_DIVERGED) == flagged
+    vals = iter(seq)
+    off = scp_group([init_traj(scpgen.quad_instance(1, 5, N=6, K=1))],
+                    oracle.default_params(scp_iters=len(seq), admm_iters=1))
+    assert not off["status"] & S.ST_DIVERGED     # detection off: never set
+
+
+def test_indefinite_cost_diverges_and_is_flagged():
+    """A negative control weight makes the Step-1 Hessian indefinite: ADMM diverges and the blow-up
+    bit is set; the same instance with its own cost converges unflagged."""
+    import oracle.scp as S
+    d = scpgen.quad_instance(1, 3, N=10, K=2)
+    with np.errstate(all="ignore"):
+        t = init_traj(dict(d, R=np.full(3, -2.0)))
+        bad = scp_group([t], oracle.default_params(scp_iters=4, admm_iters=50, detect_blowup=True))
+    t = init_traj(d)
+    good = scp_group([t], oracle.default_params(scp_iters=4, admm_iters=50, detect_blowup=True))
+    assert bad["status"] & S.ST_DIVERGED
+    assert good["status"] == 0
