@@ -80,13 +80,29 @@ __device__ __forceinline__ T gx_read(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Columns of a member row that hold node-0 u copies (the u box, then the ball's or the SOC's).
+template <class M>
+__device__ __forceinline__ constexpr int u_copy_cols() {
+    int w = 0;
+    for (int q = 0; q < M::C; ++q)
+        if (slot_is_u<M>(q) && slot_comp_u<M>(q) + 1 > w) w = slot_comp_u<M>(q) + 1;
+    return w;
+}
+
+// Value k of member m's row in the LDS copy that group_sync<W> gathers (see there).
+template <int W, class T, int BLOCK, int HSR, int LR, int AR>
+__device__ __forceinline__ T& gx_at(Shared<T, BLOCK, HSR, LR, AR>& sh, const int m, const int k) {
+    const int f = m * W + k;
+    return sh.ucp[f / BLOCK][f % BLOCK];
+}
+
 // Barrier over the workgroups of a spanning group, with the exchange of member rows.  Writer
 // lanes stage their rows in LDS (gxw, gxm); wave 0 publishes them with agent-scope atomic
 // stores; after a workgroup barrier, thread 0 arrives once with an agent-scope release (one L2
 // write-back), polls the arrival counter with relaxed agent-scope loads (no cache maintenance
-// per poll) and takes one agent-scope acquire fence (one L2 invalidation).  Readers then load
-// the rows with agent-scope atomic loads.  Both fences are required on gfx950: without them
-// arrivals and rows written on other XCDs can stay invisible.
+// per poll) and takes one agent-scope acquire fence (one L2 invalidation).  The workgroup then
+// copies the rows with agent-scope atomic loads (the gather below).  Both fences are required on
+// gfx950: without them arrivals and rows written on other XCDs can stay invisible.
 // Failure: a workgroup that has waited spin ticks of the device wall clock (or finds the group's
 // failure word set) gives up, sets the failure word and never waits again; it still arrives at
 // every later barrier, so the counts stay consistent and every workgroup reaches the end of the
@@ -100,21 +116,6 @@ __device__ __forceinline__ T gx_read(const T* p) {
 // from HBM waits S x W times).  All GX_MEMBERS rows are copied (rows past the group's size are
 // never read), so the count is the same in every thread.  A spanning workgroup holds one group
 // and never uses the in-workgroup consensus array ucp, which holds the copy.
-// Columns of a member row that hold node-0 u copies (the u box, then the ball's or the SOC's).
-template <class M>
-__device__ __forceinline__ constexpr int u_copy_cols() {
-    int w = 0;
-    for (int q = 0; q < M::C; ++q)
-        if (slot_is_u<M>(q) && slot_comp_u<M>(q) + 1 > w) w = slot_comp_u<M>(q) + 1;
-    return w;
-}
-
-template <int W, class T, int BLOCK, int HSR, int LR, int AR>
-__device__ __forceinline__ T& gx_at(Shared<T, BLOCK, HSR, LR, AR>& sh, const int m, const int k) {
-    const int f = m * W + k;
-    return sh.ucp[f / BLOCK][f % BLOCK];
-}
-
 template <int W, class T, int BLOCK, int HSR, int LR, int AR>
 __device__ __forceinline__ void group_sync(const Dev<T>& dv, Shared<T, BLOCK, HSR, LR, AR>& sh, const Span& sp, unsigned& nbar,
                                            const int t, const unsigned long long spin) {

@@ -15,7 +15,7 @@ namespace scp {
 // every thread stores its row i.  A chunk's stores reach rows of that chunk only, and the rows the
 // next chunk loads lie past it, so each row is read before it is overwritten, as in a walk of the
 // nodes in increasing order.  Pure data movement: the result is the same bits whatever the order.
-constexpr int SHIFT_NV = 3 * PERSIST_MAX_NX + 4 + PERSIST_MAX_C;
+constexpr int SHIFT_NV = 3 * PERSIST_MAX_NX + 4 + PERSIST_MAX_C;   // x, lambda, mu rows; u (<= 4); copies' duals
 
 template <class M, class T>
 __device__ __forceinline__ void shift_load(const T* __restrict__ pl, const int P, const size_t src, const bool urow,
