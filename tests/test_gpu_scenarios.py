@@ -1,5 +1,5 @@
 """Scenario consensus groups in the persistent kernel, inside one workgroup and spanning several
-(16-scenario robust-MPC requests with N up to 80).
+(16-scenario robust-MPC requests with N up to 80, and the largest group, 64 members).
 
 A spanning group exchanges its member values through HBM with a group barrier, summing over
 members in member order exactly as a group held by one workgroup does, so the two placements
@@ -110,3 +110,28 @@ def test_sixteen_scenario_request_fp32(B, N):
         _, _, info = prob.result()
         assert not np.any(info.cpu().numpy()[:, 5].astype(np.int64) & B.ST_SYNC)
         prob.close()
+
+
+def test_largest_spanning_group_fp64_matches_oracle(B):
+    """The largest group the persistent form takes, 64 members, spread over 13 workgroups of 64
+    lanes (five 11-node members per wavefront): every barrier exchanges all 64 member rows
+    (scenario mean of the nominal, first-control copies, residual test, merit), FP64 against the
+    oracle to 1e-9 with the residual test on, and the ADMM iteration counts exactly."""
+    req = scpgen.config4_request(21, S=64, N=10)
+    insts = [scpgen.quad_instance(4, 600, N=12, K=2)] + req
+    pl = B.plan(insts, block=64)
+    _say("64-member group", pl)
+    assert pl["spanning"] == 1
+    kw = dict(check_every=5, eps_p=1e-4, eps_d=1e-4, rho_eq=3.0, rho_dyn=3.0, rho_geo=3.0)
+    trajs, oinfo = oracle_scp(insts, 2, 30, **kw)
+    prob = B.Problem(insts, precision="f64", block=64)
+    prob.solve(B.scp_params(2, 30, check_every=5, eps=1e-4, rho=3.0))
+    f = gpu_fields(prob)
+    worst = compare(prob, f, insts, trajs)
+    _say(worst)
+    assert max(worst.values()) < TOL64
+    _, _, info = prob.result()
+    inf = prob.info_dicts(info.cpu().numpy())
+    assert [i["admm_iters"] for i in inf] == [o["admm_iters"] for o in oinfo]
+    assert not np.any(info.cpu().numpy()[:, 5].astype(np.int64) & B.ST_SYNC)
+    prob.close()
