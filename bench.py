@@ -777,7 +777,7 @@ def batch_main(a, wl, cpu):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="quad1024")
     ap.add_argument("--plain-steps", type=int, default=3)
