@@ -258,3 +258,26 @@ def test_served_trace_writes_one_record_per_request(B, tmp_path):
         assert r["status"] & (1 | 2 | 4 | 16) == 0
     lat = sorted(r["latency_ms"] for r in recs)
     assert abs(np.median(lat) - out["latency_ms"]["p50"]) <= 1e-2 * max(1.0, out["latency_ms"]["p50"])
+
+
+def test_served_blowup_detection_changes_no_result(B):
+    """The server with residual blow-up detection (the kernel variants that carry the tracking, a
+    warm-started session and a spanning request) returns the same bits as without it, and no
+    healthy request is flagged."""
+    reqs = [scpgen.config4_request(13, S=16, N=40), _session_reqs(5, 2)[0], _session_reqs(5, 2)[1],
+            [scpgen.quad_instance(4, 720, N=30, K=4)]]
+    out = []
+    for detect in (False, True):
+        prm = B.scp_params(2, 30, detect_blowup=detect)
+        srv = B.Server(prm, precision="f32", block=256, max_nodes=1 << 15, max_traj=512, max_wg=512, max_span=64,
+                       max_requests=64)
+        ids = [srv.submit(reqs[0], session=-1), srv.submit(reqs[1], session=5), srv.submit(reqs[2], session=5),
+               srv.submit(reqs[3])]
+        res = srv.drain(ids)
+        out.append([res[i] for i in ids])
+        srv.close()
+    for a, b in zip(*out):
+        for m in range(len(a["x"])):
+            np.testing.assert_array_equal(a["x"][m], b["x"][m])
+            np.testing.assert_array_equal(a["u"][m], b["u"][m])
+        assert all(not (int(i["status"]) & B.ST_DIVERGED) for i in b["info"])
