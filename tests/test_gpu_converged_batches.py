@@ -1,0 +1,100 @@
+"""The converged-solution bar on the powered-descent Monte Carlo and on the uneven mix, each at the
+penalty schedule under which it reaches the defect bound.
+
+Workloads, solved in FP32 exactly as the benchmark times them (the whole batch in one persistent
+launch, the same launch configuration):
+
+* mars4096: the 4096 powered-descent instances (N = 60, tf = 50 s), rho 1 -> 1e4 geometric over
+  30 SCP iterations of 400 ADMM iterations (Sec. IV-A.2), fixed trust radius, automatic workgroup
+  size, aligned packing;
+* mix2048: the 2048 instances of the uneven mix (half quadrotor, half powered descent, N ~
+  U{20..120}), rho 5 -> 1e4 over 25 SCP x 400 ADMM, residual stop 1e-4 tested every 25 ADMM
+  iterations, 128-lane workgroups, aligned packing.
+
+Expected values: the FP64 oracle's final cost and max dynamics defect of the first 256 instances
+of each batch (tests/golden/{mars4096,mix2048}_converged.json, written by
+tests/golden/make_converged.py, which calls only the oracle).
+
+An instance passes when the oracle and the GPU both reach max defect <= 1e-5 and the GPU's cost is
+within 1e-3 relative of the oracle's.  The FP32 pass rate is reported and held to a floor; every
+FP32 miss among the oracle-converged instances is re-run in FP64 mode, where the cost must agree to
+COST_TOL64 (rounding order only) and the defect bound must hold.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import scpgen
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFECT = 1e-5
+COST_TOL = 1e-3
+COST_TOL64 = 1e-10       # FP64 mode against the FP64 oracle: measured 2.2e-14 on the FP32 misses
+
+# workload -> (batch, launch configuration, FP32 pass-rate floor).  Measured: 214 of the 219
+# oracle-converged descents and 163 of the 166 oracle-converged mix instances; every miss ends with
+# the FP32 defect just above the bound (1.00-1.15e-5) and the cost within 2e-5.
+CASES = {
+    "mars4096": dict(insts=lambda: scpgen.config2(4096), block=0, min_pass=0.95),
+    "mix2048": dict(insts=lambda: scpgen.config3(2048), block=128, min_pass=0.95),
+}
+
+
+@pytest.fixture(scope="module")
+def B(lib):
+    from paper_2603_10711_amd import binding
+    return binding
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", f"{name}_converged.json")) as fh:
+        g = json.load(fh)
+    cost = np.array([r["cost"] for r in g["instances"]])
+    defect = np.array([r["defect"] for r in g["instances"]])
+    return g["setting"], cost, defect
+
+
+def _solve(B, insts, prec, s, block):
+    prob = B.Problem(insts, precision=prec, block=block, pack=B.PACK_ALIGNED)
+    prob.solve(B.scp_params(s["scp_iters"], s["admm_iters"], rho=s["rho"], rho_final=s["rho_final"],
+                            check_every=s.get("check_every", 0), eps=s.get("eps_p", 0.0), form="persistent"))
+    info = prob.result()[2].cpu().numpy()
+    prob.close()
+    return info
+
+
+def _passes(info, cost_o, def_o, tol):
+    rel = np.abs(info[:, 7] - cost_o) / np.abs(cost_o)
+    ok = (def_o <= DEFECT) & (info[:, 6] <= DEFECT) & (rel <= tol)
+    return ok, rel
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp32_converged_cost_and_defect(B, name):
+    case = CASES[name]
+    s, cost_o, def_o = _golden(name)
+    assert s.get("eps_p", 0.0) == s.get("eps_d", 0.0)   # the C ABI's eps sets both residual bounds
+    n = len(cost_o)
+    insts = case["insts"]()
+    conv_o = def_o <= DEFECT
+    print(f"{name}: setting {s}; oracle defect <= 1e-5 on {int(np.sum(conv_o))}/{n}", flush=True)
+    info = _solve(B, insts, "f32", s, case["block"])
+    print(f"GPU FP32 defect <= 1e-5 on {int(np.sum(info[:, 6] <= DEFECT))}/{len(insts)}", flush=True)
+    ok, rel = _passes(info[:n], cost_o, def_o, COST_TOL)
+    rate = float(np.sum(ok)) / float(np.sum(conv_o))
+    print(f"FP32 pass rate {int(np.sum(ok))}/{int(np.sum(conv_o))} = {rate:.4f}; cost rel diff over the "
+          f"oracle-converged p50 {np.median(rel[conv_o]):.2e} max {rel[conv_o].max():.2e}", flush=True)
+    miss = [i for i in range(n) if conv_o[i] and not ok[i]]
+    print("FP32 misses (instance, cost rel diff, GPU defect, oracle defect): "
+          f"{[(i, float(rel[i]), float(info[i, 6]), float(def_o[i])) for i in miss]}", flush=True)
+    if miss:
+        info64 = _solve(B, [insts[i] for i in miss], "f64", s, case["block"])
+        ok64, rel64 = _passes(info64, cost_o[miss], def_o[miss], COST_TOL64)
+        print(f"FP64 re-run of the misses: cost rel diff max {rel64.max():.2e}, defects "
+              f"{[float(v) for v in info64[:, 6]]}", flush=True)
+        assert np.all(ok64), [(miss[k], rel64[k], info64[k, 6]) for k in range(len(miss)) if not ok64[k]]
+    assert rate >= case["min_pass"]
