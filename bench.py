@@ -730,7 +730,8 @@ def batch_main(a, wl, cpu):
         lg = batch_leg(B, w6["insts"], w6["prec"], p6, min(3, a.other_steps), 1)
         others["quad6_1000"] = dict(workload=w6["desc"], **leg_summary(
             lg, w6["prec"], kernel="one solve (hipGraph of k_lin, k_minv_lanes4, k_admm_resident, k_resid, k_acc_* "
-                                   "per SCP iteration)"))
+                                   "per SCP iteration)",
+            traffic=load_pmc_solve("quad6_1000", "persistent", khash)))
         print(f"[bench] quad6_1000 {others['quad6_1000']}", file=sys.stderr, flush=True)
 
     out = {
