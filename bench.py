@@ -799,7 +799,7 @@ def main(argv=None):
     ap.add_argument("--admm-iters", type=int, default=0, help="override the workload's ADMM budget (profiling runs)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (instances shard across GPUs "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (instances shard across GPUs "
               "with no communication; see the design notes).", file=sys.stderr)
         sys.exit(2)
     wl = workload(a.workload)

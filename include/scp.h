@@ -39,7 +39,7 @@ typedef enum {
     SCP_ERR_NOMEM = 2,        /* host allocation failed */
     SCP_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed */
     SCP_ERR_STATE = 4,        /* call out of order (e.g. admm_solve before scp_linearize) */
-    SCP_ERR_UNSUPPORTED = 5   /* valid request this build cannot serve (e.g. block size) */
+    SCP_ERR_UNSUPPORTED = 5   /* valid request the library cannot serve (e.g. block size) */
 } scp_status;
 
 /* Dynamics models (hand-derived device functions; a problem names a model id). */

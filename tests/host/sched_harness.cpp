@@ -6,7 +6,7 @@
 //     cancellation, the done list and the latency quantiles;
 //   * the batch planner (scp_plan.cpp) on seeded random descriptions: every node placed exactly once,
 //     trajectories and consensus groups whole, wavefront alignment and the exchange flags.
-// Every check failure prints its line and the driver exits with status 1.
+// Every check failure prints its line and the harness exits with status 1.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>

@@ -4,7 +4,7 @@ tests/host/sched_harness.cpp drives the request server's scheduling core (csrc/s
 against a simulated executor and clock (admission, budget, workgroup cap, sessions, warm starts,
 eviction, staging back-pressure, timeouts, cancellation, the done list, latency quantiles) and the
 batch planner (csrc/scp_plan.cpp) on seeded random descriptions.  Both sources are free of device
-code, so the driver is built with the host compiler and both sanitizers, and any report or failed
+code, so the harness is built with the host compiler and both sanitizers, and any report or failed
 check fails the test.
 """
 import os
