@@ -328,7 +328,8 @@ def init_traj(inst: dict) -> Traj:
 
 
 def _prepare(trajs: list[Traj], delta: float, rho):
-    """a2-a4 plus the primal re-initialization of R10 for every trajectory of one group."""
+    """a2-a4 plus the primal re-initialization (primal state from the nominal, duals carried over)
+    for every trajectory of one group."""
     u0c = None
     if len(trajs) > 1:
         acc = np.zeros(trajs[0].inst["nu"])

@@ -165,7 +165,7 @@ def test_benchmark_batch_fullsize_fp32(B, form):
 
 
 def test_scenario_group_fp64(B):
-    """Scenarios sharing their first control by consensus (R8) on the 6-DOF model: node 0 of the
+    """Scenarios sharing their first control by consensus (Sec. IV-A.4) on the 6-DOF model: node 0 of the
     group takes the averaged copies; every block against the oracle, next to a lone trajectory."""
     base = scpgen.quad6_benchmark_instance(7, N=18)
     insts = []
