@@ -14,7 +14,9 @@ Default workload (quad1024): the 1024 point-mass quadrotor instances of the batc
 paper's parameter study (Sec. IV-A.2) from 5 to 1e4 at 18 SCP x 290 ADMM: the cheapest setting of a
 measured sweep under which at least 99 % of the batch meets the defect bound.  The configuration's
 own fixed budget (15 x 200, rho = 1) is measured beside it (``fixed_budget``): no solve reaches the
-bound there.  The default run also measures, in fixed configurations (``other_workloads``), each
+bound there.  ``cpu_baseline`` times the FP64 oracle on the first instances of the workload at the
+same setting, and ``oracle_checked`` counts the GPU solves of those instances that meet the defect
+bound with a final cost within 1e-3 of the oracle's.  The default run also measures, in fixed configurations (``other_workloads``), each
 with its roofline and goodput: the powered-descent Monte Carlo (mars4096) and the uneven mix
 (mix2048), each at its fixed budget and under the penalty schedule, and the 6-DOF quadrotor batch
 (quad6_1000) at its goodput setting.
@@ -185,7 +187,7 @@ def _oracle_worker(args):
                               check_every=check_every, eps_p=eps, eps_d=eps, rho_final=rho_final, **tr)
     t = oracle.init_traj(inst)
     oracle.scp.scp_group([t], p)
-    return oracle.defect(inst, t.xbar, t.ubar)
+    return oracle.defect(inst, t.xbar, t.ubar), oracle.cost(inst, t.xbar, t.ubar)
 
 
 def _oracle_request_worker(args):
@@ -224,8 +226,9 @@ def cpu_baseline(wl, sample: int, cores: int) -> dict:
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        defects = pool.map(_oracle_worker, args, chunksize=1)
+        res = pool.map(_oracle_worker, args, chunksize=1)
     dt = time.perf_counter() - t0
+    defects = [r[0] for r in res]
     stop = f", residual stop {eps:g} tested every 10 iterations" if eps > 0 else ""
     if wl.get("rho_final", 0.0) > 0:
         stop += f", rho {wl['rho']:g} -> {wl['rho_final']:g}"
@@ -237,7 +240,28 @@ def cpu_baseline(wl, sample: int, cores: int) -> dict:
                       f"{cores} single-threaded worker processes, {dt:.1f} s wall; value = solves meeting defect "
                       f"<= {DEFECT_BOUND:g} per second",
             "all_solves_per_s": round(sample / dt, 3), "defect_le_1e-5": f"{good}/{sample}",
-            "defect_p50": float(np.median(defects))}
+            "defect_p50": float(np.median(defects)),
+            "_per_instance": [(float(d), float(c)) for d, c in res]}
+
+
+def oracle_checked(cpu, info) -> dict | None:
+    """The GPU's solves of the baseline's sample checked against the oracle's: an instance counts
+    when both reach max defect <= 1e-5 and the GPU's final cost is within 1e-3 relative of the
+    oracle's (info: the GPU's info records, first rows = the sample).  Removes the per-instance
+    oracle values from the baseline record."""
+    if not cpu or "_per_instance" not in cpu:
+        return None
+    ref = np.array(cpu.pop("_per_instance"))
+    n = len(ref)
+    d_o, c_o = ref[:, 0], ref[:, 1]
+    d_g, c_g = info[:n, 6], info[:n, 7]
+    rel = np.abs(c_g - c_o) / np.maximum(np.abs(c_o), 1e-300)
+    ok = (d_o <= DEFECT_BOUND) & (d_g <= DEFECT_BOUND) & (rel <= 1e-3)
+    conv = d_o <= DEFECT_BOUND
+    return {"sample": f"the cpu_baseline sample (first {n} instances), GPU solves of the timed run",
+            "defect_and_cost_within_1e-3": f"{int(ok.sum())}/{n}",
+            "oracle_defect_le_1e-5": f"{int(conv.sum())}/{n}",
+            "cost_rel_diff_max": float(rel[conv].max()) if conv.any() else None}
 
 
 def load_pmc(wl_name: str, khash: str):
@@ -365,6 +389,7 @@ def plain_main(a, wl, cpu):
         "fixed_budget": fixed,
         "plain": plain,
         "roofline": roof,
+        "oracle_checked": oracle_checked(cpu, info),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -769,6 +794,7 @@ def batch_main(a, wl, cpu):
         "adaptive_penalty": adaptive or None,
         "other_workloads": others or None,
         "roofline": summ["roofline"],
+        "oracle_checked": oracle_checked(cpu, head["info"]),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
