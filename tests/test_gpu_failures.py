@@ -12,6 +12,8 @@ of good ones and checks, in both forms and both precisions:
   * the bad trajectory carries its bit;
   * every good trajectory is bit-identical to the same trajectory solved alone, and carries no
     failure bit.
+The 6-DOF quadrotor (resident ADMM and plain form) is held to the same containment for the first three
+cases.
 Spanning consensus groups: a group barrier that gives up (scp_params.group_wait_ms < 0 gives up
 at the first wait) flags every member of the group with SCP_ST_SYNC, and a batch whose spanning
 groups cannot all be resident at once is refused before any launch.
@@ -186,3 +188,54 @@ def test_blowup_detection_leaves_results_unchanged(B, form):
     for a, b in zip(*res):
         np.testing.assert_array_equal(a, b)
     assert not np.any(res[1][2][:, 5].astype(np.int64) & B.ST_DIVERGED)
+
+
+def _bad6(kind):
+    d = scpgen.quad6_benchmark_instance(9, N=15)
+    if kind == "badpivot":      # control Hessian far from positive definite
+        return dict(d, R=np.array([-80.0, 2.0, 2.0, 2.0])), 2
+    if kind == "emptyset":      # hard state box with lo > hi on one velocity component
+        xlo, xhi = d["x_lo"].copy(), d["x_hi"].copy()
+        xlo[4], xhi[4] = 3.0, -3.0
+        return dict(d, x_lo=xlo, x_hi=xhi), 4
+    if kind == "nan_xinit":     # non-finite initial state
+        x0 = d["x_init"].copy()
+        x0[1] = math.nan
+        return dict(d, x_init=x0), 1
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["badpivot", "emptyset", "nan_xinit"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("form", ["persistent", "plain"])
+def test_failure_is_flagged_and_contained_6dof(B, kind, prec, form):
+    """The same containment on the 6-DOF quadrotor: the resident ADMM (one workgroup per
+    trajectory) and the plain form flag the bad trajectory and leave its neighbours bit-identical
+    to their lone solves."""
+    good = [scpgen.quad6_benchmark_instance(i, N=12 + 3 * i) for i in range(4)]
+    bad, bit = _bad6(kind)
+    pos = 1
+    insts = good[:pos] + [bad] + good[pos:]
+    _say("6dof", kind, prec, form)
+
+    def solve(batch):
+        prob = B.Problem(batch, precision=prec)
+        prob.solve(B.scp_params(3, 30, rho=10.0, form=form, detect_blowup=True))
+        x, u, info = (a.cpu().numpy() for a in prob.result())
+        offs = prob.offsets.copy()
+        prob.close()
+        return x, u, info, offs
+
+    x, u, info, offs = solve(insts)
+    st = info[:, 5].astype(np.int64)
+    assert st[pos] & bit, f"status {st[pos]} lacks bit {bit}"
+    for t, d in enumerate(insts):
+        if t == pos:
+            continue
+        assert (st[t] & FAIL_BITS) == 0, (t, st[t])
+        xa, ua, ia, _ = solve([d])
+        n = d["N"] + 1
+        o = offs[t]
+        np.testing.assert_array_equal(xa[:n], x[o:o + n])
+        np.testing.assert_array_equal(ua[:n], u[o:o + n])
+        np.testing.assert_array_equal(ia[0], info[t])
