@@ -12,8 +12,8 @@ of good ones and checks, in both forms and both precisions:
   * the bad trajectory carries its bit;
   * every good trajectory is bit-identical to the same trajectory solved alone, and carries no
     failure bit.
-The 6-DOF quadrotor (resident ADMM and plain form) is held to the same containment for the first three
-cases.
+The 6-DOF quadrotor and lander (resident ADMM and plain form) are held to the same containment for the
+first three cases.
 Spanning consensus groups: a group barrier that gives up (scp_params.group_wait_ms < 0 gives up
 at the first wait) flags every member of the group with SCP_ST_SYNC, and a batch whose spanning
 groups cannot all be resident at once is refused before any launch.
@@ -190,10 +190,18 @@ def test_blowup_detection_leaves_results_unchanged(B, form):
     assert not np.any(res[1][2][:, 5].astype(np.int64) & B.ST_DIVERGED)
 
 
-def _bad6(kind):
-    d = scpgen.quad6_benchmark_instance(9, N=15)
+def _good6(model):
+    if model == "quad6":
+        return [scpgen.quad6_benchmark_instance(i, N=12 + 3 * i) for i in range(4)]
+    return [scpgen.lander6_perturbed(i) for i in range(4)]
+
+
+def _bad6(model, kind):
+    d = scpgen.quad6_benchmark_instance(9, N=15) if model == "quad6" else scpgen.lander6_perturbed(9)
     if kind == "badpivot":      # control Hessian far from positive definite
-        return dict(d, R=np.array([-80.0, 2.0, 2.0, 2.0])), 2
+        R = np.full(d["nu"], 2.0)
+        R[0] = -80.0
+        return dict(d, R=R), 2
     if kind == "emptyset":      # hard state box with lo > hi on one velocity component
         xlo, xhi = d["x_lo"].copy(), d["x_hi"].copy()
         xlo[4], xhi[4] = 3.0, -3.0
@@ -208,15 +216,16 @@ def _bad6(kind):
 @pytest.mark.parametrize("kind", ["badpivot", "emptyset", "nan_xinit"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("form", ["persistent", "plain"])
-def test_failure_is_flagged_and_contained_6dof(B, kind, prec, form):
-    """The same containment on the 6-DOF quadrotor: the resident ADMM (one workgroup per
+@pytest.mark.parametrize("model", ["quad6", "lander6"])
+def test_failure_is_flagged_and_contained_6dof(B, model, kind, prec, form):
+    """The same containment on the 6-DOF models: the resident ADMM (one workgroup per
     trajectory) and the plain form flag the bad trajectory and leave its neighbours bit-identical
     to their lone solves."""
-    good = [scpgen.quad6_benchmark_instance(i, N=12 + 3 * i) for i in range(4)]
-    bad, bit = _bad6(kind)
+    good = _good6(model)
+    bad, bit = _bad6(model, kind)
     pos = 1
     insts = good[:pos] + [bad] + good[pos:]
-    _say("6dof", kind, prec, form)
+    _say("6dof", model, kind, prec, form)
 
     def solve(batch):
         prob = B.Problem(batch, precision=prec)
