@@ -326,3 +326,40 @@ def test_trust_region_ratio_test_fp64(B, form):
     _say(worst)
     assert max(worst.values()) < TOL64
     prob.close()
+
+
+@pytest.mark.parametrize("model", ["quad6", "lander6"])
+@pytest.mark.parametrize("form", ["persistent", "plain"])
+def test_graph_replay_equals_direct_launches_6dof(B, model, form):
+    """The 6-DOF solve as the benchmark times it (one hipGraph per solve, penalty schedule, and for
+    the quadrotor the trust-region ratio test): every replay, with eager work and a
+    synchronization between replays, equals the solve launched directly, bit for bit."""
+    import torch
+    if model == "quad6":
+        insts = [scpgen.quad6_benchmark_instance(i, N=20 + 4 * i) for i in range(5)]
+        tr = dict(eta0=0.0, eta1=0.25, eta2=0.75, shrink=0.5, grow=2.0, delta_max=4.0)
+    else:
+        insts = [scpgen.lander6_perturbed(i) for i in range(5)]
+        tr = {}
+    s = torch.cuda.Stream()
+
+    def prm(graph):
+        return B.scp_params(4, 30, rho=10.0, rho_final=1e3, form=form, graph=graph, **tr)
+
+    direct = B.Problem(insts, precision="f32", stream=s)
+    direct.solve(prm(False))
+    ref = [a.cpu().numpy() for a in direct.result()]
+    direct.close()
+    g = B.Problem(insts, precision="f32", stream=s)
+    for rep in range(3):
+        g.reset()
+        g.solve(prm(True))
+        out = [a.cpu().numpy() for a in g.result()]
+        print("graph replay", model, form, rep, flush=True)
+        for a, b in zip(out, ref):
+            np.testing.assert_array_equal(a, b)
+        # eager work of the program between replays
+        with torch.cuda.stream(s):
+            torch.ones(1 << 20, device="cuda").mul_(2.0).sum().item()
+        torch.cuda.synchronize()
+    g.close()
