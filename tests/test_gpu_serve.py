@@ -12,6 +12,8 @@
 * backpressure: under a small HBM budget every request still completes, the resident footprint
   never exceeds the budget, and idle warm states are evicted.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -281,3 +283,38 @@ def test_served_blowup_detection_changes_no_result(B):
             np.testing.assert_array_equal(a["x"][m], b["x"][m])
             np.testing.assert_array_equal(a["u"][m], b["u"][m])
         assert all(not (int(i["status"]) & B.ST_DIVERGED) for i in b["info"])
+
+
+def test_served_failure_is_flagged_and_contained(B):
+    """Requests with a NaN initial state and with an empty hard box, served among healthy ones (a
+    spanning 16-scenario request, a warm-started session, single trajectories): each bad request
+    carries its status bit, and every healthy request returns the same bits as on a server
+    without the bad ones."""
+    good = [scpgen.config4_request(14, S=16, N=40), _session_reqs(6, 2)[0], _session_reqs(6, 2)[1],
+            [scpgen.quad_instance(4, 730, N=30, K=4)], [scpgen.mars_instance(3, 731, N=50)]]
+    nan = dict(scpgen.quad_instance(4, 732, N=25, K=3))
+    nan["x_init"] = nan["x_init"].copy()
+    nan["x_init"][2] = math.nan
+    box = dict(scpgen.quad_instance(4, 733, N=35, K=2))
+    box["x_lo"], box["x_hi"] = box["x_lo"].copy(), box["x_hi"].copy()
+    box["x_lo"][3], box["x_hi"][3] = 2.0, -2.0
+
+    def serve(with_bad):
+        srv = _server(B, "f32", scp=2, admm=30)
+        ids = [srv.submit(good[0]), srv.submit(good[1], session=6)]
+        bad_ids = [srv.submit([nan]), srv.submit([box])] if with_bad else []
+        ids += [srv.submit(good[2], session=6), srv.submit(good[3]), srv.submit(good[4])]
+        res = srv.drain(ids + bad_ids)
+        srv.close()
+        return [res[i] for i in ids], [res[i] for i in bad_ids]
+
+    with_bad, bad = serve(True)
+    without, _ = serve(False)
+    assert int(bad[0]["info"][0]["status"]) & B.ST_NONFINITE
+    assert int(bad[1]["info"][0]["status"]) & B.ST_EMPTYSET
+    for a, b in zip(with_bad, without):
+        fail = B.ST_NONFINITE | B.ST_BADPIVOT | B.ST_EMPTYSET | B.ST_SYNC
+        assert all((int(i["status"]) & fail) == 0 for i in a["info"])
+        for m in range(len(a["x"])):
+            np.testing.assert_array_equal(a["x"][m], b["x"][m])
+            np.testing.assert_array_equal(a["u"][m], b["u"][m])
