@@ -119,3 +119,33 @@ def test_foreign_states_are_refused(B):
         a.import_state(bad)
     for p in (a, other, packed, wide):
         p.close()
+
+
+@pytest.mark.parametrize("case", ["spanning_ratio_blowup", "adaptive"])
+def test_resume_carries_per_trajectory_state(B, case):
+    """The per-trajectory state beyond the iterates travels with a checkpoint: the trust radius of
+    the ratio test, the residual blow-up reference and maximum and the spanning groups' layout; a
+    solve with the adaptive penalty (whose factor restarts at 1 with every solve) resumes the
+    same way."""
+    if case == "spanning_ratio_blowup":
+        insts = [scpgen.quad_instance(4, 811, N=20, K=2)] + scpgen.config4_request(12, S=6, N=40) + \
+                [scpgen.quad_instance(4, 812, N=25, K=4)]
+        kw = dict(block=64)
+        prm = B.scp_params(2, 30, rho=3.0, eta0=0.0, shrink=0.5, grow=2.0, delta_max=4.0, detect_blowup=True)
+    else:
+        insts = _mix()
+        kw = {}
+        prm = B.scp_params(2, 30, rho=1.0, adapt_mu=10.0, adapt_tau=2.0)
+    _say("checkpoint", case)
+    a = B.Problem(insts, precision="f32", **kw)
+    a.solve(prm)
+    state = a.export_state()
+    a.solve(prm)
+    want = _arrays(a)
+    b = B.Problem(insts, precision="f32", **kw)
+    b.import_state(state)
+    b.solve(prm)
+    for x, y in zip(_arrays(b), want):
+        np.testing.assert_array_equal(x, y)
+    a.close()
+    b.close()
